@@ -1,0 +1,182 @@
+"""Pins for the oracle's geometry, forces, noise and update (not GPU).
+
+- hexagonal closed form: A = (sqrt 3 / 2) a^2, P = 2 sqrt 3 a, F = 0 for any
+  target shape (symmetry), q = P / sqrt(A) = 2 sqrt 2 3^(1/4);
+- square lattice (degenerate ties): A = a^2, P = 4 a;
+- Voronoi areas tile the torus: sum A = Lx Ly;
+- forces equal central finite differences of Eq. (1) with the topology held
+  fixed (1e-7), and sum to zero (translation invariance);
+- Philox4x64-10 against numpy's independent implementation;
+- Box-Muller normals: moments over many (step, tag);
+- dynamics: with v0 = 0 the energy does not increase (gradient flow); with
+  K_A = K_P = 0 the directors diffuse with <cos(theta_t - theta_0)> = e^(-Dr t)
+  and cells move as active Brownian particles,
+  MSD(t) = (2 v0^2 / Dr) [t - (1 - e^(-Dr t)) / Dr].
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1702_02939_amd import inputs
+
+
+def _prep_random(orc, n, seed):
+    L = float(np.sqrt(n))
+    x, y = inputs.uniform_positions(n, L, L, seed)
+    return orc.prepare(x, y, L, L)
+
+
+def test_hex_lattice_closed_form(orc):
+    a = 1.3
+    x, y, Lx, Ly = inputs.hex_lattice(8, 10, a, offset=(0.37, 0.21))
+    xq, yq, Lx, Ly, q = orc.prepare(x, y, Lx, Ly)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    A, P = orc.geometry(xq, yq, Lx, Ly, off, ring)
+    # the lattice is quantised to the 2^-q grid and Ly carries sqrt(3)/2
+    # rounding: allow 1e-12
+    np.testing.assert_allclose(A, math.sqrt(3) / 2 * a * a, rtol=1e-12)
+    np.testing.assert_allclose(P, 2 * math.sqrt(3) * a, rtol=1e-12)
+    np.testing.assert_allclose(P / np.sqrt(A), 2 * math.sqrt(2) * 3 ** 0.25, rtol=1e-12)
+    for A0, P0 in ((1.0, 3.8), (2.0, 3.0), (0.5, 5.0)):
+        fx, fy = orc.forces(xq, yq, Lx, Ly, off, ring, A0, P0)
+        assert np.abs(fx).max() < 1e-10 and np.abs(fy).max() < 1e-10
+
+
+def test_square_lattice_geometry(orc):
+    x, y, Lx, Ly = inputs.square_lattice(6, 1.5)
+    xq, yq, Lx, Ly, q = orc.prepare(x, y, Lx, Ly)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    A, P = orc.geometry(xq, yq, Lx, Ly, off, ring)
+    np.testing.assert_allclose(A, 2.25, rtol=1e-13)
+    np.testing.assert_allclose(P, 6.0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("n,seed", [(256, 1), (4096, 2)])
+def test_areas_tile_the_torus(orc, n, seed):
+    xq, yq, Lx, Ly, q = _prep_random(orc, n, seed)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    A, P = orc.geometry(xq, yq, Lx, Ly, off, ring)
+    assert abs(A.sum() - Lx * Ly) < 1e-9 * Lx * Ly
+    assert np.all(A > 0) and np.all(P > 0)
+    # isoperimetric bound for polygons: P^2 >= 4 pi A
+    assert np.all(P * P >= 4 * math.pi * A)
+
+
+def test_forces_match_finite_differences(orc):
+    n = 64
+    xq, yq, Lx, Ly, q = _prep_random(orc, n, 3)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    rng = np.random.default_rng(4)
+    A0 = rng.uniform(0.8, 1.2, n)
+    P0 = rng.uniform(3.5, 4.1, n)
+    KA, KP = 1.3, 0.7
+    fx, fy = orc.forces(xq, yq, Lx, Ly, off, ring, A0, P0, KA, KP)
+    h = 1e-6
+
+    def E(xx, yy):
+        A, P = orc.geometry(xx, yy, Lx, Ly, off, ring)
+        return orc.energy(A, P, A0, P0, KA, KP)[0]
+
+    err = 0.0
+    for i in range(n):
+        for comp in (0, 1):
+            xp, yp = xq.copy(), yq.copy()
+            xm, ym = xq.copy(), yq.copy()
+            if comp == 0:
+                xp[i] += h
+                xm[i] -= h
+            else:
+                yp[i] += h
+                ym[i] -= h
+            fd = -(E(xp, yp) - E(xm, ym)) / (2 * h)
+            an = fx[i] if comp == 0 else fy[i]
+            err = max(err, abs(fd - an))
+    assert err < 1e-7 * max(1.0, np.abs(np.concatenate([fx, fy])).max())
+    assert abs(fx.sum()) < 1e-10 and abs(fy.sum()) < 1e-10
+
+
+def test_force_sum_zero_large(orc):
+    xq, yq, Lx, Ly, q = _prep_random(orc, 10000, 5)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    fx, fy = orc.forces(xq, yq, Lx, Ly, off, ring, 1.0, 3.9)
+    scale = np.abs(fx).max()
+    assert abs(fx.sum()) < 1e-11 * scale * 10000 and abs(fy.sum()) < 1e-11 * scale * 10000
+
+
+def test_philox_matches_numpy(orc):
+    """numpy's Philox advances its counter before producing a block, so the
+    block for counter c is the first output of Philox(counter=c-1)."""
+    rng = np.random.default_rng(8)
+    for _ in range(50):
+        ctr = [int(v) for v in rng.integers(1, 2 ** 63, size=4, dtype=np.uint64)]
+        key = [int(v) for v in rng.integers(0, 2 ** 63, size=2, dtype=np.uint64)]
+        prev = list(ctr)
+        prev[0] -= 1
+        g = np.random.Philox(counter=np.array(prev, dtype=np.uint64), key=np.array(key, dtype=np.uint64))
+        want = g.random_raw(4)
+        got = orc.philox4x64(ctr, key)
+        assert list(map(int, got)) == list(map(int, want))
+    # carry across counter words: counter (0, 5, 0, 0) follows (2^64-1, 4, 0, 0)
+    g = np.random.Philox(counter=np.array([2 ** 64 - 1, 4, 0, 0], dtype=np.uint64), key=np.array([3, 0], dtype=np.uint64))
+    assert list(map(int, orc.philox4x64([0, 5, 0, 0], [3, 0]))) == list(map(int, g.random_raw(4)))
+
+
+def test_normals_moments(orc):
+    xs = np.array([orc.normal(99, s, t) for s in range(40) for t in range(500)])
+    assert abs(xs.mean()) < 4 / math.sqrt(len(xs))
+    assert abs(xs.var() - 1) < 0.05
+    assert abs(((xs ** 4).mean()) - 3) < 0.25
+
+
+def test_gradient_flow_energy_decreases(orc):
+    n = 256
+    xq, yq, Lx, Ly, q = _prep_random(orc, n, 6)
+    th = orc.theta0(1, n)
+    out = orc.run(xq, yq, th, Lx, Ly, q, 1.0, 3.8, v0=0.0, Dr=1.0, dt=0.01, seed=1, nsteps=60)
+    E = out["E"]
+    assert np.all(np.diff(E) <= 1e-12 * E[0])
+    assert E[-1] < 0.9 * E[0]
+
+
+def test_active_brownian_limit(orc):
+    """K_A = K_P = 0: no interaction; cells are active Brownian particles."""
+    n, v0, Dr, dt, T = 1024, 0.5, 1.0, 0.01, 100
+    xq, yq, Lx, Ly, q = _prep_random(orc, n, 7)
+    th0 = orc.theta0(5, n)
+    out = orc.run(xq, yq, th0, Lx, Ly, q, 1.0, 3.8, KA=0.0, KP=0.0, v0=v0, Dr=Dr, dt=dt, seed=5, nsteps=T)
+    t = T * dt
+    c = np.cos(out["theta"] - th0).mean()
+    assert abs(c - math.exp(-Dr * t)) < 4 * 0.5 / math.sqrt(n)
+    dx = (out["x"] - xq + Lx / 2) % Lx - Lx / 2
+    dy = (out["y"] - yq + Ly / 2) % Ly - Ly / 2
+    msd = (dx * dx + dy * dy).mean()
+    # discrete-time ABP: sum over steps of v0 dt n(theta_k); exact mean of the
+    # sum of e^{-Dr dt |k-l|} correlations
+    k = np.arange(T)
+    corr = np.exp(-Dr * dt * np.abs(k[:, None] - k[None, :])).sum()
+    want = (v0 * dt) ** 2 * corr
+    want_cont = 2 * v0 ** 2 / Dr * (t - (1 - math.exp(-Dr * t)) / Dr)
+    assert abs(want - want_cont) < 0.02 * want_cont
+    assert abs(msd - want) < 0.1 * want
+
+
+def test_run_update_rule(orc):
+    """One step equals r + dt (mu F + v0 n) on the grid, theta + sqrt(2 Dr dt) xi."""
+    n = 256
+    xq, yq, Lx, Ly, q = _prep_random(orc, n, 9)
+    th = orc.theta0(3, n)
+    mu, v0, Dr, dt = 0.7, 0.3, 0.5, 0.02
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    fx, fy = orc.forces(xq, yq, Lx, Ly, off, ring, 1.0, 3.8)
+    out = orc.run(xq, yq, th, Lx, Ly, q, 1.0, 3.8, mu=mu, v0=v0, Dr=Dr, dt=dt, seed=3, step0=17, nsteps=1)
+    xn = (xq + dt * (mu * fx + v0 * np.cos(th))) % Lx
+    yn = (yq + dt * (mu * fy + v0 * np.sin(th))) % Ly
+    spacing = 2.0 ** -q
+    dxe = (out["x"] - xn + Lx / 2) % Lx - Lx / 2
+    dye = (out["y"] - yn + Ly / 2) % Ly - Ly / 2
+    assert np.abs(dxe).max() <= spacing and np.abs(dye).max() <= spacing
+    xi = np.array([orc.normal(3, 17, t) for t in range(n)])
+    np.testing.assert_allclose(out["theta"], th + math.sqrt(2 * Dr * dt) * xi, rtol=0, atol=1e-15)
+    # grid: every coordinate is an exact multiple of 2^-q
+    assert np.all(np.ldexp(out["x"], q) == np.rint(np.ldexp(out["x"], q)))
