@@ -1,0 +1,143 @@
+/*
+ * spv.h -- C-ABI of the MI355X self-propelled Voronoi (SPV) step library
+ * (libspv.so, HIP for gfx950).
+ *
+ * Model (Sussman, "cellGPU: massively parallel simulations of dynamic vertex
+ * models", arXiv:1702.02939):
+ *   cells are points r_i in a periodic box; their shapes are the Voronoi
+ *   cells of the Delaunay triangulation of the points (Sec. II.A, Fig. 1);
+ *   E = sum_i K_A (A_i - A0_i)^2 + K_P (P_i - P0_i)^2            (Eq. 1)
+ *   F_i = -dE/dr_i, by the chain rule through the Voronoi vertices (App. B)
+ *   dr_i/dt = mu F_i + v0 n_i, n_i = (cos theta_i, sin theta_i)     (Eq. 3)
+ *   d theta_i/dt = eta_i, white noise of variance 2 Dr             (Sec. II.A)
+ * One step = forces and update, then the empty-circumcircle test of every
+ * cell's neighbour ring (Sec. II.C.3) and the local repair of failed rings
+ * (Sec. II.C.4), entirely on the device.
+ *
+ * Conventions shared by every entry point:
+ *   - every call returns spv_status; nothing throws across the ABI; on a
+ *     non-OK status spv_last_error() returns a message (thread-local);
+ *   - array arguments are plain pointers to host memory or to device memory
+ *     of the current HIP device (the library detects which); the caller owns
+ *     them; the library copies inputs and owns its device state;
+ *   - per-cell arrays are indexed by tag = input index (0..N-1), whatever
+ *     order the library keeps internally;
+ *   - positions are kept on the dyadic grid 2^-q, q = 51 - ceil(log2
+ *     max(Lx, Ly)); inputs are rounded to it (and the box sides too);
+ *   - all work is ordered on the HIP stream given at creation; calls that
+ *     return data synchronise that stream;
+ *   - a handle is not thread-safe: one host thread per handle.
+ */
+#ifndef SPV_H
+#define SPV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPV_OK = 0,
+    SPV_EINVAL = -1,     /* bad argument: N < 3, NULL pointer, non-finite or out-of-box input, duplicate cells */
+    SPV_ENOMEM = -2,     /* device or host allocation failed */
+    SPV_EHIP = -3,       /* HIP runtime error */
+    SPV_EPRECOND = -4,   /* a Delaunay circumradius reached min(Lx, Ly)/4 (box too small for the cells) */
+    SPV_ECAPACITY = -5,  /* a ring longer than kcap, or too many repair candidates */
+    SPV_ENONFINITE = -6, /* non-finite force or position */
+    SPV_EREPAIR = -7     /* topology repair did not converge within repair_rounds */
+} spv_status;
+
+enum { SPV_FP64 = 0, SPV_MIXED = 1 };
+
+typedef struct {
+    double KA, KP;          /* area and perimeter moduli (Eq. 1) */
+    double mu;              /* mobility (Eq. 3) */
+    double v0;              /* self-propulsion speed (Eq. 3) */
+    double Dr;              /* rotational diffusion constant (Sec. II.A) */
+    double dt;              /* time step */
+    uint64_t seed;          /* noise seed: Philox4x64-10 key (seed, 0), counter (step, tag, 0, 0) */
+    int32_t precision;      /* SPV_FP64 (only value accepted so far) */
+    int32_t resort_every;   /* steps between spatial re-sorts (0: default 64) */
+    int32_t kcap;           /* ring capacity = max Delaunay degree (0: default 16, at most 64) */
+    int32_t repair_rounds;  /* max test/repair rounds per step (0: default 16) */
+} spv_params;
+
+typedef struct spv_sys spv_sys; /* opaque handle: all device state of one system */
+
+/*
+ * Create a system of N cells at positions (x[i], y[i]) in [0, Lx) x [0, Ly)
+ * and build its periodic Delaunay triangulation on the device.
+ *   A0, P0   per-cell preferred area / perimeter (Eq. 1); A0 == NULL means 1;
+ *            P0 == NULL means P0_i = p0 * sqrt(A0_i)
+ *   theta0   initial directors; NULL means theta_i = 2 pi u with u from
+ *            Philox counter (2^64 - 1, tag, 0, 0)
+ *   stream   hipStream_t to order all work on (NULL: the default stream)
+ * Ownership: *out receives a new handle (free with spv_destroy).  All input
+ * arrays are read during the call only.
+ * Errors: SPV_EINVAL (arguments), SPV_EPRECOND (box too small), SPV_ENOMEM,
+ * SPV_EHIP; *out is then NULL.
+ */
+spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y, double Lx, double Ly,
+                      const double* A0, const double* P0, double p0, const double* theta0,
+                      const spv_params* params, void* stream);
+
+/*
+ * Advance nsteps steps (Sec. II.C): forces and Eq. (3) update, then the
+ * validity test and device-side repair of the triangulation.  The step index
+ * used for the noise counter continues across calls.
+ * Errors: SPV_EPRECOND, SPV_ECAPACITY, SPV_ENONFINITE, SPV_EREPAIR, SPV_EHIP.
+ * After an error the handle holds the state reached when it was detected.
+ */
+spv_status spv_step(spv_sys* s, int64_t nsteps);
+
+/* Box sides after rounding to the grid, and the grid exponent q. */
+spv_status spv_get_box(spv_sys* s, double* Lx, double* Ly, int32_t* q);
+
+/* Current positions / directors, tag order, N entries each. */
+spv_status spv_get_positions(spv_sys* s, double* x, double* y);
+spv_status spv_get_directors(spv_sys* s, double* theta);
+
+/* Forces F = -dE/dr at the current positions and topology, tag order. */
+spv_status spv_get_forces(spv_sys* s, double* fx, double* fy);
+
+/* Voronoi area and perimeter of every cell, tag order. */
+spv_status spv_get_geometry(spv_sys* s, double* A, double* P);
+
+/*
+ * Neighbour lists (Delaunay rings), CSR in tag order: the neighbours of cell
+ * t are nbr[offsets[t] .. offsets[t+1]), counter-clockwise, starting at the
+ * smallest tag.  offsets has N+1 entries; nbr has room for cap entries.
+ * *needed receives the total (3N on the torus).  Host pointers only.
+ * Errors: SPV_ECAPACITY if cap < *needed (offsets are still written).
+ */
+spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t cap, int64_t* needed);
+
+/*
+ * Observables of the current state: E (Eq. 1), qbar = mean of P_i/sqrt(A_i),
+ * sumA = sum of A_i; counters[8] (host pointer, may be NULL):
+ *   [0] steps taken  [1] cells repaired  [2] repair rounds  [3] exact-arithmetic fallbacks
+ *   [4] max ring length written  [5] spatial re-sorts  [6] repair radius retries  [7] error word
+ */
+spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA, int64_t* counters);
+
+/*
+ * Kernel timing.  While enabled, every launch of the listed kernel is
+ * bracketed by HIP events on the handle's stream; spv_kernel_time returns
+ * the summed duration (ms) and launch count since enabling.
+ *   which: 0 = force+update, 1 = geometry+test (all cells), 2 = repair
+ */
+spv_status spv_set_timing(spv_sys* s, int32_t enable);
+spv_status spv_kernel_time(spv_sys* s, int32_t which, double* total_ms, int64_t* launches);
+
+/* Release all device state of the handle. */
+spv_status spv_destroy(spv_sys* s);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* spv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPV_H */

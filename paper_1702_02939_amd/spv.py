@@ -1,0 +1,240 @@
+"""ctypes binding of libspv.so (the C-ABI declared in include/spv.h).
+
+Argument marshalling only: every step of the model runs in the library's HIP
+kernels.  The functions keep the C names (spv_create, spv_step, ...); the
+`System` class is a convenience wrapper used by the tests and the benchmark.
+Arrays may be numpy arrays (host) or torch tensors (host or device); the
+handle's stream is torch's current stream on the current device unless one is
+given.  There is no CPU fallback: importing this module fails if the library
+is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspv.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python __graft_entry__.py` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SPV_OK, SPV_EINVAL, SPV_ENOMEM, SPV_EHIP, SPV_EPRECOND, SPV_ECAPACITY, SPV_ENONFINITE, SPV_EREPAIR = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+SPV_FP64, SPV_MIXED = 0, 1
+STATUS_NAMES = {0: "SPV_OK", -1: "SPV_EINVAL", -2: "SPV_ENOMEM", -3: "SPV_EHIP", -4: "SPV_EPRECOND",
+                -5: "SPV_ECAPACITY", -6: "SPV_ENONFINITE", -7: "SPV_EREPAIR"}
+
+# kernel ids for spv_kernel_time
+K_FORCE, K_GEOM, K_REPAIR = 0, 1, 2
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("KA", ctypes.c_double), ("KP", ctypes.c_double), ("mu", ctypes.c_double),
+                ("v0", ctypes.c_double), ("Dr", ctypes.c_double), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("resort_every", ctypes.c_int32),
+                ("kcap", ctypes.c_int32), ("repair_rounds", ctypes.c_int32)]
+
+    def __init__(self, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=1.0, dt=0.01, seed=0, precision=SPV_FP64,
+                 resort_every=0, kcap=0, repair_rounds=0):
+        super().__init__(KA, KP, mu, v0, Dr, dt, seed, precision, resort_every, kcap, repair_rounds)
+
+
+_P = ctypes.c_void_p
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_H = ctypes.c_void_p
+
+_SIGS = {
+    "spv_create": [ctypes.POINTER(_H), _i64, _P, _P, _d, _d, _P, _P, _d, _P, ctypes.POINTER(Params), _P],
+    "spv_step": [_H, _i64],
+    "spv_get_box": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)],
+    "spv_get_positions": [_H, _P, _P],
+    "spv_get_directors": [_H, _P],
+    "spv_get_forces": [_H, _P, _P],
+    "spv_get_geometry": [_H, _P, _P],
+    "spv_get_neighbors": [_H, _P, _P, _i64, ctypes.POINTER(_i64)],
+    "spv_get_observables": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d), _P],
+    "spv_set_timing": [_H, _i32],
+    "spv_kernel_time": [_H, _i32, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
+    "spv_destroy": [_H],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.spv_last_error.restype = ctypes.c_char_p
+_lib.spv_last_error.argtypes = []
+
+
+class SPVError(RuntimeError):
+    def __init__(self, status, where):
+        msg = _lib.spv_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status, where):
+    if status != SPV_OK:
+        raise SPVError(status, where)
+
+
+def _ptr(a):
+    """Raw pointer of a contiguous float64/int32 numpy array or torch tensor."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        assert a.is_contiguous()
+        return ctypes.c_void_p(a.data_ptr())
+    assert a.flags["C_CONTIGUOUS"]
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _f64(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        import torch
+        return a.to(torch.float64).contiguous()
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return ctypes.c_void_p(0)
+
+
+# ------------------------------------------------------------------ C names
+def spv_create(N, x, y, Lx, Ly, A0=None, P0=None, p0=3.8, theta0=None, params=None, stream=None):
+    params = params if params is not None else Params()
+    h = _H()
+    keep = [_f64(x), _f64(y), _f64(A0), _f64(P0), _f64(theta0)]
+    st = _lib.spv_create(ctypes.byref(h), int(N), _ptr(keep[0]), _ptr(keep[1]), float(Lx), float(Ly),
+                         _ptr(keep[2]), _ptr(keep[3]), float(p0), _ptr(keep[4]), ctypes.byref(params),
+                         stream if stream is not None else _current_stream())
+    _check(st, "spv_create")
+    return h
+
+
+def spv_step(h, nsteps):
+    _check(_lib.spv_step(h, int(nsteps)), "spv_step")
+
+
+def spv_get_box(h):
+    Lx, Ly, q = _d(), _d(), _i32()
+    _check(_lib.spv_get_box(h, ctypes.byref(Lx), ctypes.byref(Ly), ctypes.byref(q)), "spv_get_box")
+    return Lx.value, Ly.value, q.value
+
+
+def spv_get_positions(h, x, y):
+    _check(_lib.spv_get_positions(h, _ptr(x), _ptr(y)), "spv_get_positions")
+
+
+def spv_get_directors(h, th):
+    _check(_lib.spv_get_directors(h, _ptr(th)), "spv_get_directors")
+
+
+def spv_get_forces(h, fx, fy):
+    _check(_lib.spv_get_forces(h, _ptr(fx), _ptr(fy)), "spv_get_forces")
+
+
+def spv_get_geometry(h, A, P):
+    _check(_lib.spv_get_geometry(h, _ptr(A), _ptr(P)), "spv_get_geometry")
+
+
+def spv_get_neighbors(h, N):
+    off = np.zeros(N + 1, dtype=np.int32)
+    need = _i64()
+    st = _lib.spv_get_neighbors(h, _ptr(off), None, 0, ctypes.byref(need))
+    if st not in (SPV_OK, SPV_ECAPACITY):
+        _check(st, "spv_get_neighbors")
+    nbr = np.zeros(max(int(need.value), 1), dtype=np.int32)
+    _check(_lib.spv_get_neighbors(h, _ptr(off), _ptr(nbr), int(need.value), ctypes.byref(need)),
+           "spv_get_neighbors")
+    return off, nbr[: int(need.value)]
+
+
+def spv_get_observables(h):
+    E, q, a = _d(), _d(), _d()
+    cnt = np.zeros(8, dtype=np.int64)
+    _check(_lib.spv_get_observables(h, ctypes.byref(E), ctypes.byref(q), ctypes.byref(a), _ptr(cnt)),
+           "spv_get_observables")
+    return E.value, q.value, a.value, cnt
+
+
+def spv_set_timing(h, enable):
+    _check(_lib.spv_set_timing(h, int(bool(enable))), "spv_set_timing")
+
+
+def spv_kernel_time(h, which):
+    ms, n = _d(), _i64()
+    _check(_lib.spv_kernel_time(h, int(which), ctypes.byref(ms), ctypes.byref(n)), "spv_kernel_time")
+    return ms.value, n.value
+
+
+def spv_destroy(h):
+    _check(_lib.spv_destroy(h), "spv_destroy")
+
+
+# ------------------------------------------------------------------ convenience
+class System:
+    """One SPV system on the current HIP device (see include/spv.h)."""
+
+    def __init__(self, x, y, Lx, Ly, *, p0=3.8, A0=None, P0=None, theta0=None, params=None, stream=None):
+        self.N = len(x)
+        self.params = params if params is not None else Params()
+        self.h = spv_create(self.N, x, y, Lx, Ly, A0=A0, P0=P0, p0=p0, theta0=theta0, params=self.params,
+                            stream=stream)
+
+    def step(self, n=1):
+        spv_step(self.h, n)
+
+    def box(self):
+        return spv_get_box(self.h)
+
+    def positions(self):
+        x, y = np.zeros(self.N), np.zeros(self.N)
+        spv_get_positions(self.h, x, y)
+        return x, y
+
+    def directors(self):
+        th = np.zeros(self.N)
+        spv_get_directors(self.h, th)
+        return th
+
+    def forces(self):
+        fx, fy = np.zeros(self.N), np.zeros(self.N)
+        spv_get_forces(self.h, fx, fy)
+        return fx, fy
+
+    def geometry(self):
+        A, P = np.zeros(self.N), np.zeros(self.N)
+        spv_get_geometry(self.h, A, P)
+        return A, P
+
+    def neighbors(self):
+        return spv_get_neighbors(self.h, self.N)
+
+    def observables(self):
+        return spv_get_observables(self.h)
+
+    def close(self):
+        if self.h:
+            spv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

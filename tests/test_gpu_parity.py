@@ -1,0 +1,257 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Bar: neighbour rings bit-exact (same CCW order, same start); FP64 forces
+within 1e-10 * max(max|F_oracle|, K_P P0) (per system); areas and perimeters
+within 1e-12 relative; one-step positions within 1e-12; trajectory energy and
+mean shape index within 1e-6 over short runs (they diverge chaotically later).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_02939_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spv():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1702_02939_amd import spv as mod
+    return mod
+
+
+def _compare_topology(sysm, x, y):
+    Lx, Ly, q = sysm.box()
+    off, ring, ntri, _ = oracle.triangulate(x, y, Lx, Ly, q)
+    goff, gring = sysm.neighbors()
+    assert ntri == 2 * len(x)
+    assert np.array_equal(goff, off), "degrees differ"
+    assert np.array_equal(gring, ring), "rings differ"
+    return off, ring
+
+
+def _compare_forces(sysm, x, y, off, ring, A0, P0, KA=1.0, KP=1.0):
+    Lx, Ly, q = sysm.box()
+    fx, fy = oracle.forces(x, y, Lx, Ly, off, ring, A0, P0, KA, KP)
+    gfx, gfy = sysm.forces()
+    scale = max(np.abs(np.concatenate([fx, fy])).max(), KP * np.max(P0))
+    err = max(np.abs(gfx - fx).max(), np.abs(gfy - fy).max())
+    assert err <= 1e-10 * scale, f"max |dF| = {err:.3e} (scale {scale:.3e})"
+    A, P = oracle.geometry(x, y, Lx, Ly, off, ring)
+    gA, gP = sysm.geometry()
+    np.testing.assert_allclose(gA, A, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(gP, P, rtol=1e-12, atol=0)
+    return err
+
+
+def _random_case(n, seed, L=None):
+    L = float(math.sqrt(n)) if L is None else L
+    x, y = inputs.uniform_positions(n, L, L, seed)
+    return x, y, L, L
+
+
+CREATE_CASES = [
+    ("uniform_256", lambda: _random_case(256, inputs.BASE_SEED + 1, 16.0)),
+    ("uniform_1000", lambda: _random_case(1000, 31)),
+    ("uniform_4099", lambda: _random_case(4099, 32)),
+    ("uniform_20011", lambda: _random_case(20011, 33)),
+    ("hex_12x12", lambda: inputs.hex_lattice(12, 12, 1.0)),
+    ("square_10x10", lambda: inputs.square_lattice(10, 1.0)),
+    ("rect_box_3000", lambda: (*inputs.uniform_positions(3000, 100.0, 30.0, 34), 100.0, 30.0)),
+]
+
+
+@pytest.mark.parametrize("name,make", CREATE_CASES, ids=[c[0] for c in CREATE_CASES])
+def test_create_topology_and_forces(spv, name, make):
+    x, y, Lx, Ly = make()
+    n = len(x)
+    sysm = spv.System(x, y, Lx, Ly, p0=3.8, params=spv.Params(v0=0.05, seed=1))
+    gx, gy = sysm.positions()
+    xq, yq, _, _, _ = oracle.prepare(x, y, Lx, Ly)
+    assert np.array_equal(gx, xq) and np.array_equal(gy, yq), "grid quantisation differs"
+    off, ring = _compare_topology(sysm, gx, gy)
+    if name.startswith("square"):
+        # exactly at T1 points the perimeter gradient is undefined: geometry only
+        Lxq, Lyq, _ = sysm.box()
+        A, P = oracle.geometry(gx, gy, Lxq, Lyq, off, ring)
+        gA, gP = sysm.geometry()
+        np.testing.assert_allclose(gA, A, rtol=1e-12)
+        np.testing.assert_allclose(gP, P, rtol=1e-12)
+    else:
+        _compare_forces(sysm, gx, gy, off, ring, 1.0, 3.8)
+    E, qbar, sumA, cnt = sysm.observables()
+    Lxq, Lyq, _ = sysm.box()
+    assert abs(sumA - Lxq * Lyq) < 1e-9 * Lxq * Lyq
+    assert cnt[7] == 0
+    sysm.close()
+
+
+def test_hex_lattice_zero_force(spv):
+    x, y, Lx, Ly = inputs.hex_lattice(16, 16, 1.0)
+    sysm = spv.System(x, y, Lx, Ly, p0=3.0, params=spv.Params())
+    fx, fy = sysm.forces()
+    assert np.abs(fx).max() < 1e-10 and np.abs(fy).max() < 1e-10
+    A, P = sysm.geometry()
+    np.testing.assert_allclose(A, math.sqrt(3) / 2, rtol=1e-12)
+    np.testing.assert_allclose(P, 2 * math.sqrt(3), rtol=1e-12)
+    sysm.close()
+
+
+def test_per_cell_targets_and_moduli(spv):
+    n = 2000
+    x, y, Lx, Ly = _random_case(n, 41)
+    rng = np.random.default_rng(5)
+    A0 = rng.uniform(0.8, 1.2, n)
+    P0 = rng.uniform(3.4, 4.2, n)
+    prm = spv.Params(KA=1.7, KP=0.6)
+    sysm = spv.System(x, y, Lx, Ly, A0=A0, P0=P0, params=prm)
+    gx, gy = sysm.positions()
+    off, ring = _compare_topology(sysm, gx, gy)
+    _compare_forces(sysm, gx, gy, off, ring, A0, P0, 1.7, 0.6)
+    sysm.close()
+
+
+def test_one_step_parity(spv):
+    n = 1024
+    x, y, Lx, Ly = _random_case(n, 42)
+    th0 = np.random.default_rng(6).uniform(0, 2 * math.pi, n)
+    mu, v0, Dr, dt, seed = 1.0, 0.1, 1.0, 0.01, 99
+    sysm = spv.System(x, y, Lx, Ly, p0=3.9, theta0=th0, params=spv.Params(mu=mu, v0=v0, Dr=Dr, dt=dt, seed=seed))
+    Lxq, Lyq, q = sysm.box()
+    xq, yq, _, _, _ = oracle.prepare(x, y, Lx, Ly)
+    out = oracle.run(xq, yq, th0, Lxq, Lyq, q, 1.0, 3.9, mu=mu, v0=v0, Dr=Dr, dt=dt, seed=seed, nsteps=1,
+                     want_rings=True, want_forces=True)
+    sysm.step(1)
+    gx, gy = sysm.positions()
+    dx = (gx - out["x"] + Lxq / 2) % Lxq - Lxq / 2
+    dy = (gy - out["y"] + Lyq / 2) % Lyq - Lyq / 2
+    assert np.abs(dx).max() <= 1e-12 and np.abs(dy).max() <= 1e-12
+    np.testing.assert_allclose(sysm.directors(), out["theta"], rtol=0, atol=1e-12)
+    # topology and forces at the new state, evaluated by the oracle on the GPU positions
+    off, ring = _compare_topology(sysm, gx, gy)
+    _compare_forces(sysm, gx, gy, off, ring, 1.0, 3.9)
+    sysm.close()
+
+
+def test_default_directors_match_counter_rule(spv):
+    n = 500
+    x, y, Lx, Ly = _random_case(n, 43)
+    sysm = spv.System(x, y, Lx, Ly, params=spv.Params(seed=1234))
+    np.testing.assert_allclose(sysm.directors(), oracle.theta0(1234, n), rtol=0, atol=1e-14)
+    sysm.close()
+
+
+@pytest.mark.parametrize("n,p0,v0,steps,every", [(256, 3.8, 0.05, 300, 50), (4096, 3.9, 0.1, 200, 40)])
+def test_repair_keeps_exact_topology(spv, n, p0, v0, steps, every):
+    """After every block of steps the device topology equals the oracle's
+    from-scratch triangulation of the device positions, and forces agree."""
+    L = 16.0 if n == 256 else math.sqrt(n)
+    x, y = inputs.uniform_positions(n, L, L, inputs.BASE_SEED + 1 if n == 256 else 44)
+    sysm = spv.System(x, y, L, L, p0=p0, params=spv.Params(v0=v0, Dr=1.0, dt=0.01, seed=3, resort_every=25))
+    done = 0
+    while done < steps:
+        sysm.step(every)
+        done += every
+        gx, gy = sysm.positions()
+        off, ring = _compare_topology(sysm, gx, gy)
+        _compare_forces(sysm, gx, gy, off, ring, 1.0, p0)
+    E, qbar, sumA, cnt = sysm.observables()
+    assert cnt[0] == steps and cnt[1] > 0 and cnt[7] == 0
+    sysm.close()
+
+
+def test_trajectory_energy_and_shape_index(spv):
+    """spv_n256 workload: E and qbar per step against the oracle to 1e-6."""
+    w = inputs.WORKLOADS["spv_n256"]
+    n, L, T = w["N"], w["L"], 150
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    th0 = oracle.theta0(w["seed"], n)
+    prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"])
+    sysm = spv.System(x, y, L, L, p0=w["p0"], theta0=th0, params=prm)
+    Lxq, Lyq, q = sysm.box()
+    xq, yq, _, _, _ = oracle.prepare(x, y, L, L)
+    out = oracle.run(xq, yq, th0, Lxq, Lyq, q, 1.0, w["p0"], mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"],
+                     seed=w["seed"], nsteps=T)
+    Eg, Qg = [], []
+    for t in range(T + 1):
+        E, qbar, _, _ = sysm.observables()
+        Eg.append(E)
+        Qg.append(qbar)
+        if t < T:
+            sysm.step(1)
+    Eg, Qg = np.array(Eg), np.array(Qg)
+    np.testing.assert_allclose(Eg, out["E"], rtol=1e-6)
+    np.testing.assert_allclose(Qg, out["qbar"], rtol=1e-6)
+    sysm.close()
+
+
+def test_determinism(spv):
+    n = 3000
+    x, y, Lx, Ly = _random_case(n, 45)
+    res = []
+    for _ in range(2):
+        s = spv.System(x, y, Lx, Ly, p0=3.9, params=spv.Params(v0=0.1, seed=11, resort_every=10))
+        s.step(60)
+        res.append((*s.positions(), s.directors(), s.observables()[0]))
+        s.close()
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_large_system_sampled(spv):
+    """spv_n100k workload size: full topology and force comparison after steps."""
+    w = inputs.WORKLOADS["spv_n100k"]
+    n, L = w["N"], w["L"]
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    sysm = spv.System(x, y, L, L, p0=w["p0"], params=spv.Params(v0=w["v0"], Dr=w["Dr"], dt=w["dt"],
+                                                                  seed=w["seed"]))
+    gx, gy = sysm.positions()
+    off, ring = _compare_topology(sysm, gx, gy)
+    sysm.step(30)
+    gx, gy = sysm.positions()
+    off, ring = _compare_topology(sysm, gx, gy)
+    _compare_forces(sysm, gx, gy, off, ring, 1.0, w["p0"])
+    sysm.close()
+
+
+def test_precondition_error(spv):
+    x = np.array([1.0, 2.0, 1.5, 7.0, 3.0])
+    y = np.array([1.0, 1.0, 2.0, 7.0, 5.0])
+    with pytest.raises(spv.SPVError) as ei:
+        spv.System(x, y, 10.0, 10.0)
+    assert ei.value.status == spv.SPV_EPRECOND
+
+
+def test_invalid_inputs(spv):
+    x, y, Lx, Ly = _random_case(100, 46)
+    x2 = x.copy()
+    x2[3] = Lx + 1.0
+    with pytest.raises(spv.SPVError) as ei:
+        spv.System(x2, y, Lx, Ly)
+    assert ei.value.status == spv.SPV_EINVAL
+    x3, y3 = x.copy(), y.copy()
+    x3[5], y3[5] = x3[9], y3[9]
+    with pytest.raises(spv.SPVError) as ei:
+        spv.System(x3, y3, Lx, Ly)
+    assert ei.value.status == spv.SPV_EINVAL
+
+
+def test_device_pointer_inputs_and_outputs(spv):
+    import torch
+    n = 700
+    x, y, Lx, Ly = _random_case(n, 47)
+    tx = torch.tensor(x, dtype=torch.float64, device="cuda")
+    ty = torch.tensor(y, dtype=torch.float64, device="cuda")
+    s = spv.System(tx, ty, Lx, Ly)
+    ox = torch.empty(n, dtype=torch.float64, device="cuda")
+    oy = torch.empty(n, dtype=torch.float64, device="cuda")
+    spv.spv_get_positions(s.h, ox, oy)
+    hx, hy = s.positions()
+    assert np.array_equal(ox.cpu().numpy(), hx) and np.array_equal(oy.cpu().numpy(), hy)
+    s.close()
