@@ -219,8 +219,13 @@ spv_status check_err(spv_sys* s)
     const unsigned e = s->h_cnt->err;
     if (!e) return SPV_OK;
     s->err_word |= e;
-    char buf[160];
-    std::snprintf(buf, sizeof buf, "device error word 0x%x at step %llu", e, (unsigned long long)s->step);
+    char buf[400];
+    const DevCounters& c = *s->h_cnt;
+    std::snprintf(buf, sizeof buf,
+                  "device error word 0x%x at step %llu (first repair failure: tag %d, %d candidates, ring %d, "
+                  "closed %d, %d attempts, R %.4g, max circumradius %.4g)",
+                  e, (unsigned long long)s->step, c.fail_set ? c.fail_cell : -1, c.fail_n, c.fail_k, c.fail_closed,
+                  c.fail_attempts, c.fail_R, c.fail_umax);
     if (e & ERR_NONFINITE) return fail(SPV_ENONFINITE, std::string(buf) + ": non-finite force or position");
     if (e & ERR_PRECOND)
         return fail(SPV_EPRECOND, std::string(buf) + ": a Delaunay circumradius reached min(Lx,Ly)/4");

@@ -25,6 +25,9 @@ struct DevCounters {
     int max_deg;             // largest ring written by the repair
     int repaired;            // cells rebuilt
     int retries;             // repair radius enlargements
+    // first repair failure (diagnostics for the error message)
+    int fail_cell, fail_n, fail_k, fail_closed, fail_attempts, fail_set;
+    double fail_R, fail_umax;
 };
 
 // Everything a kernel needs about one system; passed by value.

@@ -143,7 +143,11 @@ __device__ __forceinline__ void geom_test_cell(const View& v, int i, double KA, 
                 double px = mimg(v.x[o] - xi, v.Lx, v.hLx), py = mimg(v.y[o] - yi, v.Ly, v.hLy);
                 fail = incircle_tags(bx, by, cx, cy, px, py, v.tag, i, jm, jn, o, v.scale, exact) > 0;
             }
-            if (!fail && ux * ux + uy * uy >= rlim2) atomicOr(&v.cnt->err, ERR_PRECOND);
+            // a circumradius >= min(L)/4 is either a non-Delaunay triangle that
+            // another cell's test will catch, or a true violation of the box
+            // precondition; the repair tells them apart (it cannot certify a
+            // disk wider than L/2 and then reports the precondition)
+            if (!fail && ux * ux + uy * uy >= rlim2) fail = true;
         }
         if (fail) {
             any_fail = true;
@@ -451,7 +455,10 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
         int k = 0;
         bool ok = false;
         bool at_max = false;
+        int last_n = 0, last_closed = 0, attempts = 0;
+        double last_umax = 0.0;
         for (int attempt = 0; attempt < 16 && !ok; attempt++) {
+            attempts = attempt + 1;
             if (lane == 0) s_n = 0;
             __syncthreads();
             const double Rs = R + drift;
@@ -483,6 +490,7 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
             }
             __syncthreads();
             const int n = s_n;
+            last_n = n;
             if (n > RP_CAP) {
                 if (lane == 0) atomicOr(&v.cnt->err, ERR_CAPACITY);
                 break;
@@ -558,17 +566,30 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
                 for (int off = 32; off >= 1; off >>= 1) umax = fmax(umax, __shfl_xor(umax, off));
                 if (2.0 * umax * (1.0 + 1e-9) <= R) ok = true;
             }
+            last_closed = closed ? 1 : 0;
+            last_umax = umax;
             if (!ok) {
                 if (at_max) break;
-                double Rn = 2.0 * R;
-                if (closed && k >= 3) Rn = fmax(Rn, 2.05 * umax);
-                R = fmin(Rn, Rmax);
+                // an uncertified star may be wrong (outer triangles clipped by
+                // the search disk), so its circumradii say nothing: double R
+                R = fmin(2.0 * R, Rmax);
                 at_max = (R >= Rmax);
                 if (lane == 0) atomicAdd(&v.cnt->retries, 1);
             }
         }
         if (!ok) {
-            if (lane == 0) atomicOr(&v.cnt->err, at_max ? ERR_PRECOND : ERR_REPAIR);
+            if (lane == 0) {
+                atomicOr(&v.cnt->err, at_max ? ERR_PRECOND : ERR_REPAIR);
+                if (atomicCAS(&v.cnt->fail_set, 0, 1) == 0) {
+                    v.cnt->fail_cell = v.tag[i];
+                    v.cnt->fail_n = last_n;
+                    v.cnt->fail_k = k;
+                    v.cnt->fail_closed = last_closed;
+                    v.cnt->fail_attempts = attempts;
+                    v.cnt->fail_R = R;
+                    v.cnt->fail_umax = last_umax;
+                }
+            }
             __syncthreads();
             continue;
         }
