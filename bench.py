@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Throughput of the SPV hot path on one MI355X: cell-steps/s.
+
+A step is one full pass of the hot path through the C-ABI (forces and
+update, geometry and empty-circumcircle test, device repair of failed rings)
+on the synthetic spv_n100k workload: N = 100000 cells uniform-random in a
+periodic box of side sqrt(N), p0 = 3.9, v0 = 0.1, Dr = 1, mu = 1, dt = 0.01,
+FP64.  `value` = N * steps / wall seconds of the timed steps, inputs resident
+in HBM.  The JSON line also carries the roofline of the dominant kernel
+(algorithmic bytes per launch / average launch time from HIP events on the
+library's stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per cell per launch (FP64, mean ring length 6;
+# neighbour gathers served by cache).  See the design doc.
+BYTES_PER_CELL = {
+    # force+update: read x,y,theta (24), deg (1), ring (24), opp (24), own a,b (16), tag (4);
+    # write x,y,theta (24)
+    "force_update": 24 + 1 + 24 + 24 + 16 + 4 + 24,
+    # geometry+test: read x,y (16), deg (1), ring (24), opp (24), A0,P0 (16);
+    # write A,P,a,b (32)
+    "geometry_test": 16 + 1 + 24 + 24 + 16 + 32,
+}
+
+
+# HBM bytes per launch of the dominant kernel from the rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs (calibrated against a plain copy; profiles/), valid only for
+# the kernel sources they were taken on.
+MEASURED_TRAFFIC = {
+    "force_update": {"bytes": 17.91e6, "csrc_sha256": "216fe5a8e184eeb106fde0d3e1c6a3f69db48d67e745c15ddd6973acbfde437b"},
+}
+
+
+def csrc_digest():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1702_02939_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", default="spv_n100k")
+    ap.add_argument("--cpu-sample-steps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, nsteps):
+    """The oracle (serial C: full Bowyer-Watson each step, dual-number forces)
+    on the same workload, a bounded number of steps from the same start."""
+    import numpy as np
+
+    import oracle
+    from paper_1702_02939_amd import inputs
+    n, L = w["N"], w["L"]
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    xq, yq, Lx, Ly, q = oracle.prepare(x, y, L, L)
+    th = oracle.theta0(w["seed"], n)
+    t0 = time.perf_counter()
+    oracle.run(xq, yq, th, Lx, Ly, q, 1.0, w["p0"], mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"],
+               seed=w["seed"], nsteps=nsteps)
+    dt = time.perf_counter() - t0
+    # run() also triangulates the final state once: nsteps + 1 triangulations
+    return {"value": n * nsteps / dt, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w['N']} cells, {nsteps} steps from the random start (serial, 1 thread), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
+                                   "and not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1702_02939_amd import inputs, spv
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        nel = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    w = inputs.WORKLOADS[args.workload]
+    n, L = w["N"], w["L"]
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"])
+    sysm = spv.System(x, y, L, L, p0=w["p0"], params=prm)
+    sysm.step(args.warmup)
+    _, _, _, c0 = sysm.observables()
+    spv.spv_set_timing(sysm.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    E, qbar, sumA, c1 = sysm.observables()
+    kt = {name: spv.spv_kernel_time(sysm.h, k) for name, k in
+          (("force_update", spv.K_FORCE), ("geometry_test", spv.K_GEOM), ("repair", spv.K_REPAIR))}
+    sysm.close()
+
+    value = n * args.steps / wall
+    # dominant streaming kernel: the one with the larger total time
+    dom = max(("force_update", "geometry_test"), key=lambda k: kt[k][0])
+    ms, launches = kt[dom]
+    avg_s = ms / 1e3 / max(launches, 1)
+    bytes_per_launch = BYTES_PER_CELL[dom] * n
+    achieved = bytes_per_launch / avg_s / 1e9
+    mt = MEASURED_TRAFFIC.get(dom)
+    traffic = mt["bytes"] if mt and mt["csrc_sha256"] == csrc_digest() else None
+    out = {
+        "metric": "cell-steps/s",
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": n, "L": L, "p0": w["p0"], "v0": w["v0"], "Dr": w["Dr"],
+                   "mu": w["mu"], "dt": w["dt"], "precision": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
+        "kernels_ms_total": {k: v[0] for k, v in kt.items()},
+        "kernel_launches": {k: v[1] for k, v in kt.items()},
+        "repairs_per_step": float(c1[1] - c0[1]) / args.steps,
+        "observables": {"E": E, "qbar": qbar, "sumA": sumA},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
