@@ -14,16 +14,22 @@
  * cell's neighbour ring (Sec. II.C.3) and the local repair of failed rings
  * (Sec. II.C.4), entirely on the device.
  *
+ * A handle holds one system or a batch of independent systems (each with its
+ * own size, box, target shape, self-propulsion speed and seed) that are
+ * stepped together; a single system is a batch of one.
+ *
  * Conventions shared by every entry point:
  *   - every call returns spv_status; nothing throws across the ABI; on a
  *     non-OK status spv_last_error() returns a message (thread-local);
  *   - array arguments are plain pointers to host memory or to device memory
- *     of the current HIP device (the library detects which); the caller owns
- *     them; the library copies inputs and owns its device state;
- *   - per-cell arrays are indexed by tag = input index (0..N-1), whatever
- *     order the library keeps internally;
+ *     of the current HIP device (hipMemcpyDefault semantics); the caller
+ *     owns them; the library copies inputs and owns its device state;
+ *   - per-cell arrays are in "tag order": system by system, and inside a
+ *     system by input index (tag), whatever order the library keeps
+ *     internally;
  *   - positions are kept on the dyadic grid 2^-q, q = 51 - ceil(log2
- *     max(Lx, Ly)); inputs are rounded to it (and the box sides too);
+ *     max(Lx, Ly)) of their system; inputs are rounded to it (and the box
+ *     sides too);
  *   - all work is ordered on the HIP stream given at creation; calls that
  *     return data synchronise that stream;
  *   - a handle is not thread-safe: one host thread per handle.
@@ -48,25 +54,29 @@ typedef enum {
     SPV_EREPAIR = -7     /* topology repair did not converge within repair_rounds */
 } spv_status;
 
-enum { SPV_FP64 = 0, SPV_MIXED = 1 };
+/* Arithmetic of the geometry and force kernels.  Positions, their update,
+ * the topology predicates (exact) and the noise are FP64 in both. */
+enum { SPV_FP64 = 0, SPV_MIXED = 1 /* FP32 Voronoi geometry, forces and energy coefficients */ };
 
 typedef struct {
     double KA, KP;          /* area and perimeter moduli (Eq. 1) */
     double mu;              /* mobility (Eq. 3) */
-    double v0;              /* self-propulsion speed (Eq. 3) */
+    double v0;              /* self-propulsion speed (Eq. 3); per system in spv_batch_create */
     double Dr;              /* rotational diffusion constant (Sec. II.A) */
     double dt;              /* time step */
-    uint64_t seed;          /* noise seed: Philox4x64-10 key (seed, 0), counter (step, tag, 0, 0) */
-    int32_t precision;      /* SPV_FP64 (only value accepted so far) */
-    int32_t resort_every;   /* steps between spatial re-sorts (0: default 64) */
-    int32_t kcap;           /* ring capacity = max Delaunay degree (0: default 16, at most 64) */
-    int32_t repair_rounds;  /* max test/repair rounds per step (0: default 16) */
+    uint64_t seed;          /* noise: Philox4x64-10, key (seed, 0), counter (step, tag, 0, 0) */
+    int32_t precision;      /* SPV_FP64 or SPV_MIXED */
+    int32_t resort_every;   /* steps between spatial re-sorts, rounded up to even (0: 16) */
+    int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16) */
+    int32_t repair_rounds;  /* max test/repair rounds per step, device and host together (0: 16, max 32) */
+    int32_t device_rounds;  /* repair rounds run on the device inside each step (0: 2) */
+    int32_t no_graphs;      /* 0: replay whole re-sort periods as captured HIP graphs; 1: launch eagerly */
 } spv_params;
 
-typedef struct spv_sys spv_sys; /* opaque handle: all device state of one system */
+typedef struct spv_sys spv_sys; /* opaque handle: all device state of one system or batch */
 
 /*
- * Create a system of N cells at positions (x[i], y[i]) in [0, Lx) x [0, Ly)
+ * Create one system of N cells at positions (x[i], y[i]) in [0, Lx) x [0, Ly)
  * and build its periodic Delaunay triangulation on the device.
  *   A0, P0   per-cell preferred area / perimeter (Eq. 1); A0 == NULL means 1;
  *            P0 == NULL means P0_i = p0 * sqrt(A0_i)
@@ -83,18 +93,45 @@ spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y
                       const spv_params* params, void* stream);
 
 /*
+ * Create a batch of S independent systems, stepped together by every
+ * spv_step call (each with its own noise key, so a system in a batch follows
+ * exactly the trajectory it follows alone).
+ *   N_s[S], Lx_s[S], Ly_s[S]   cells and box of each system
+ *   x, y                        positions, concatenated system by system (sum N_s entries)
+ *   P0                          per-cell target perimeters, concatenated, or NULL:
+ *                               P0 = p0_s[s] * sqrt(A0) with A0 = 1
+ *   p0_s, v0_s, seed_s          per-system target shape index, speed, noise seed
+ *                               (v0_s / seed_s NULL: params->v0 / params->seed)
+ * Other model parameters (K_A, K_P, mu, Dr, dt, precision, ...) are shared.
+ * Errors as spv_create.
+ */
+spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const double* Lx_s, const double* Ly_s,
+                            const double* x, const double* y, const double* P0, const double* p0_s,
+                            const double* v0_s, const uint64_t* seed_s, const spv_params* params, void* stream);
+
+/*
  * Advance nsteps steps (Sec. II.C): forces and Eq. (3) update, then the
  * validity test and device-side repair of the triangulation.  The step index
  * used for the noise counter continues across calls.
  * Errors: SPV_EPRECOND, SPV_ECAPACITY, SPV_ENONFINITE, SPV_EREPAIR, SPV_EHIP.
- * After an error the handle holds the state reached when it was detected.
+ * After an error the handle holds the state reached when it was detected and
+ * every later spv_step returns the same error.
  */
 spv_status spv_step(spv_sys* s, int64_t nsteps);
 
-/* Box sides after rounding to the grid, and the grid exponent q. */
+/* Number of systems and total number of cells of the handle. */
+spv_status spv_get_size(spv_sys* s, int32_t* S, int64_t* N);
+
+/* First cell (in tag order) and cell count of system sys. */
+spv_status spv_get_system_range(spv_sys* s, int32_t sys, int64_t* first, int64_t* n);
+
+/* Box sides of system 0 after rounding to the grid, and the grid exponent q. */
 spv_status spv_get_box(spv_sys* s, double* Lx, double* Ly, int32_t* q);
 
-/* Current positions / directors, tag order, N entries each. */
+/* Box of system sys (batches). */
+spv_status spv_get_system_box(spv_sys* s, int32_t sys, double* Lx, double* Ly, int32_t* q);
+
+/* Current positions / directors, tag order, total-N entries each. */
 spv_status spv_get_positions(spv_sys* s, double* x, double* y);
 spv_status spv_get_directors(spv_sys* s, double* theta);
 
@@ -107,25 +144,31 @@ spv_status spv_get_geometry(spv_sys* s, double* A, double* P);
 /*
  * Neighbour lists (Delaunay rings), CSR in tag order: the neighbours of cell
  * t are nbr[offsets[t] .. offsets[t+1]), counter-clockwise, starting at the
- * smallest tag.  offsets has N+1 entries; nbr has room for cap entries.
- * *needed receives the total (3N on the torus).  Host pointers only.
+ * smallest tag; entries are tag-order indices (system first cell + tag).
+ * offsets has total-N + 1 entries; nbr has room for cap entries.  *needed
+ * receives the total (3 N_s per system on the torus).  Host pointers only.
  * Errors: SPV_ECAPACITY if cap < *needed (offsets are still written).
  */
 spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t cap, int64_t* needed);
 
 /*
- * Observables of the current state: E (Eq. 1), qbar = mean of P_i/sqrt(A_i),
- * sumA = sum of A_i; counters[8] (host pointer, may be NULL):
- *   [0] steps taken  [1] cells repaired  [2] repair rounds  [3] exact-arithmetic fallbacks
+ * Observables of the current state summed over all systems: E (Eq. 1),
+ * qbar = mean of P_i/sqrt(A_i), sumA = sum of A_i; counters[8] (host
+ * pointer, may be NULL):
+ *   [0] steps taken  [1] cells repaired  [2] repair rounds used  [3] exact-arithmetic fallbacks
  *   [4] max ring length written  [5] spatial re-sorts  [6] repair radius retries  [7] error word
  */
 spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA, int64_t* counters);
 
+/* Observables of one system of a batch. */
+spv_status spv_get_system_observables(spv_sys* s, int32_t sys, double* E, double* qbar, double* sumA);
+
 /*
  * Kernel timing.  While enabled, every launch of the listed kernel is
- * bracketed by HIP events on the handle's stream; spv_kernel_time returns
- * the summed duration (ms) and launch count since enabling.
- *   which: 0 = force+update, 1 = geometry+test (all cells), 2 = repair
+ * bracketed by HIP events on the handle's stream (also inside captured
+ * graphs); spv_kernel_time returns the summed duration (ms) and launch count
+ * since enabling.   which: 0 = force+update, 1 = geometry+test (all cells),
+ * 2 = repair (device rounds)
  */
 spv_status spv_set_timing(spv_sys* s, int32_t enable);
 spv_status spv_kernel_time(spv_sys* s, int32_t which, double* total_ms, int64_t* launches);

@@ -1,8 +1,16 @@
 // spv_api.hip -- host runtime and C-ABI of the SPV step library (gfx950).
 //
-// The host side only allocates, orders launches on the handle's stream and
-// reads back one small counter block per repair round; every arithmetic step
-// of the model runs in the kernels of spv_kernels.hpp.
+// The host side allocates, orders launches on the handle's stream, captures
+// whole re-sort periods (resort_every steps + the re-sort) as HIP graphs and
+// reads back one small control block per period; every arithmetic step of
+// the model runs in the kernels of spv_kernels.hpp.
+//
+// State: two full sets of per-cell arrays.  In configuration `cfg` set[cfg]
+// is current and set[cfg ^ 1] is scratch; x, y, theta additionally alternate
+// between the two sets at every step (the update writes the other set, so
+// neighbours read step-start positions).  A period has an even number of
+// steps, so positions are back in set[cfg] when the re-sort gathers
+// everything into set[cfg ^ 1] and the configuration flips.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +41,12 @@ spv_status fail(spv_status st, const std::string& msg)
         hipError_t e_ = (expr);                                                                    \
         if (e_ != hipSuccess)                                                                      \
             return fail(SPV_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+#define ST_TRY(expr)                   \
+    do {                               \
+        spv_status st_ = (expr);       \
+        if (st_ != SPV_OK) return st_; \
     } while (0)
 
 // ceil(log2 L) exactly, from the binary exponent
@@ -67,56 +81,57 @@ int64_t hilbert_index(int64_t n, int64_t x, int64_t y)
 
 enum { T_FORCE = 0, T_GEOM = 1, T_REPAIR = 2, T_COUNT = 3 };
 
-struct TimedLaunch {
-    int which;
-    hipEvent_t a, b;
+struct ArraySet {
+    double *x = nullptr, *y = nullptr, *th = nullptr;
+    int *tag = nullptr, *sys = nullptr;
+    double *A0 = nullptr, *P0 = nullptr;
+    uint8_t* deg = nullptr;
+    int *ring = nullptr, *opp = nullptr;
+    void *A = nullptr, *P = nullptr, *ca = nullptr, *cb = nullptr;  // R-typed
+};
+
+struct EvPair {
+    hipEvent_t a = nullptr, b = nullptr;
 };
 
 }  // namespace
 
 struct spv_sys {
-    int N = 0;
-    int kcap = 16;
-    int repair_rounds = 16;
-    int resort_every = 64;
-    double Lx = 0, Ly = 0;
-    int q = 0;
+    int S = 1, N = 0, KC = 16;
+    int dev_rounds = 2, max_rounds = 16, unit = 16;
+    bool mixed = false, multi = false, use_graphs = true;
+    bool graph_timing_broken = false;  // event records could not be captured: timed runs launch eagerly
     spv_params prm{};
-    hipStream_t stream = nullptr;
-    View v{};   // current buffers
-    View a{};   // alternate buffers (update target, re-sort target)
-    // bins
-    int nbins = 0;
-    double spacing = 1.0;
-    int* d_bin_rank = nullptr;
-    int* d_bin_start = nullptr;
-    int* d_key = nullptr;
-    int* d_hist = nullptr;
-    int* d_fill = nullptr;
-    int* d_perm = nullptr;
-    int* d_inv = nullptr;
-    // scratch
-    DevCounters* d_cnt = nullptr;
-    DevCounters* h_cnt = nullptr;  // pinned
-    double* d_stage = nullptr;     // N doubles
-    double* d_fx = nullptr;
-    double* d_fy = nullptr;
-    double* d_part = nullptr;
-    double* d_obs = nullptr;
+    hipStream_t stream = nullptr;      // caller's stream (all work is ordered on it)
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    std::vector<SysParam> hsp;
+    std::vector<int> cell_off;
+    SysParam* d_sp = nullptr;
+    ArraySet set[2];
+    int cfg = 0, pos = 0;              // configuration and steps done in the current period
+    Work work{};
+    int total_bins = 0;
+    int *d_bin_key = nullptr, *d_bin_start = nullptr, *d_key = nullptr, *d_hist = nullptr, *d_fill = nullptr;
+    int *d_perm = nullptr, *d_inv = nullptr;
+    DevState* d_st = nullptr;
+    DevState* h_st = nullptr;  // pinned copy
+    double *d_stage = nullptr, *d_fx = nullptr, *d_fy = nullptr, *d_obs = nullptr;
     std::vector<void*> allocs;
+    // graphs of one period starting in configuration 0 / 1
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool gtimed[2] = {false, false};
+    std::vector<EvPair> gev[2];  // per step: force, geom, repair(round 0)
     // bookkeeping
     uint64_t step = 0;
-    int64_t steps_since_resort = 0;
-    double drift = 0.0;
-    int64_t repaired = 0, rounds = 0, exact_calls = 0, resorts = 0, retries = 0;
-    int max_deg = 0;
-    unsigned err_word = 0;
+    int64_t resorts = 0;
+    spv_status sticky = SPV_OK;
+    std::string sticky_msg;
     // timing
     bool timing = false;
     double t_ms[T_COUNT] = {0, 0, 0};
     int64_t t_n[T_COUNT] = {0, 0, 0};
-    std::vector<TimedLaunch> pending;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+    std::vector<std::pair<int, EvPair>> pending;  // eager launches
+    std::vector<EvPair> pool;
 };
 
 namespace {
@@ -134,224 +149,342 @@ spv_status dalloc(spv_sys* s, T** p, size_t count)
     return SPV_OK;
 }
 
-#define ST_TRY(expr)                          \
-    do {                                      \
-        spv_status st_ = (expr);              \
-        if (st_ != SPV_OK) return st_;        \
-    } while (0)
-
-spv_status alloc_view(spv_sys* s, View& w)
+spv_status alloc_set(spv_sys* s, ArraySet& a)
 {
-    const size_t N = s->N, K = s->kcap;
-    ST_TRY(dalloc(s, &w.x, N));
-    ST_TRY(dalloc(s, &w.y, N));
-    ST_TRY(dalloc(s, &w.th, N));
-    ST_TRY(dalloc(s, &w.tag, N));
-    ST_TRY(dalloc(s, &w.A0, N));
-    ST_TRY(dalloc(s, &w.P0, N));
-    ST_TRY(dalloc(s, &w.deg, N));
-    ST_TRY(dalloc(s, &w.ring, N * K));
-    ST_TRY(dalloc(s, &w.opp, N * K));
-    ST_TRY(dalloc(s, &w.A, N));
-    ST_TRY(dalloc(s, &w.P, N));
-    ST_TRY(dalloc(s, &w.ca, N));
-    ST_TRY(dalloc(s, &w.cb, N));
-    HIP_TRY(hipMemsetAsync(w.deg, 0, N, s->stream));
-    HIP_TRY(hipMemsetAsync(w.ring, 0, N * K * sizeof(int), s->stream));
-    HIP_TRY(hipMemsetAsync(w.opp, 0xff, N * K * sizeof(int), s->stream));
-    HIP_TRY(hipMemsetAsync(w.ca, 0, N * sizeof(double), s->stream));
-    HIP_TRY(hipMemsetAsync(w.cb, 0, N * sizeof(double), s->stream));
-    HIP_TRY(hipMemsetAsync(w.A, 0, N * sizeof(double), s->stream));
-    HIP_TRY(hipMemsetAsync(w.P, 0, N * sizeof(double), s->stream));
+    const size_t N = s->N, K = s->KC, rs = s->mixed ? sizeof(float) : sizeof(double);
+    ST_TRY(dalloc(s, &a.x, N));
+    ST_TRY(dalloc(s, &a.y, N));
+    ST_TRY(dalloc(s, &a.th, N));
+    ST_TRY(dalloc(s, &a.tag, N));
+    ST_TRY(dalloc(s, &a.sys, N));
+    ST_TRY(dalloc(s, &a.A0, N));
+    ST_TRY(dalloc(s, &a.P0, N));
+    ST_TRY(dalloc(s, &a.deg, N));
+    ST_TRY(dalloc(s, &a.ring, N * K));
+    ST_TRY(dalloc(s, &a.opp, N * K));
+    uint8_t* raw = nullptr;
+    ST_TRY(dalloc(s, &raw, 4 * N * rs));
+    a.A = raw;
+    a.P = raw + N * rs;
+    a.ca = raw + 2 * N * rs;
+    a.cb = raw + 3 * N * rs;
+    HIP_TRY(hipMemsetAsync(a.deg, 0, N, s->stream));
+    HIP_TRY(hipMemsetAsync(a.ring, 0, N * K * sizeof(int), s->stream));
+    HIP_TRY(hipMemsetAsync(a.opp, 0xff, N * K * sizeof(int), s->stream));
+    HIP_TRY(hipMemsetAsync(raw, 0, 4 * N * rs, s->stream));
     return SPV_OK;
+}
+
+template <typename R>
+Cells<R> cells(const spv_sys* s, int cfg, int parity)
+{
+    const ArraySet& P = s->set[cfg];
+    const ArraySet& Q = s->set[cfg ^ 1];
+    Cells<R> c;
+    c.x = parity ? Q.x : P.x;
+    c.y = parity ? Q.y : P.y;
+    c.th = parity ? Q.th : P.th;
+    c.tag = P.tag;
+    c.sys = P.sys;
+    c.A0 = P.A0;
+    c.P0 = P.P0;
+    c.deg = P.deg;
+    c.ring = P.ring;
+    c.opp = P.opp;
+    c.A = static_cast<R*>(P.A);
+    c.P = static_cast<R*>(P.P);
+    c.ca = static_cast<R*>(P.ca);
+    c.cb = static_cast<R*>(P.cb);
+    return c;
+}
+
+// run f.template operator()<R, MULTI, KC>() for the handle's instantiation
+template <class F>
+void dispatch(const spv_sys* s, F&& f)
+{
+    if (s->mixed) {
+        if (s->multi) {
+            if (s->KC == 16) f.template operator()<float, true, 16>();
+            else f.template operator()<float, true, 32>();
+        } else {
+            if (s->KC == 16) f.template operator()<float, false, 16>();
+            else f.template operator()<float, false, 32>();
+        }
+    } else {
+        if (s->multi) {
+            if (s->KC == 16) f.template operator()<double, true, 16>();
+            else f.template operator()<double, true, 32>();
+        } else {
+            if (s->KC == 16) f.template operator()<double, false, 16>();
+            else f.template operator()<double, false, 32>();
+        }
+    }
 }
 
 inline unsigned grid_for(int n, int block) { return (unsigned)std::max(1, (n + block - 1) / block); }
 
+// all-cell grid of the 8-lanes-per-cell kernels, padded to a multiple of 8 XCDs
+inline unsigned cell_grid(const spv_sys* s) { return (grid_for(s->N, CPB) + 7u) & ~7u; }
+inline unsigned list_grid(const spv_sys* s) { return std::min(grid_for(s->N, CPB), 512u); }
+inline unsigned repair_grid(const spv_sys* s) { return (unsigned)std::min(std::max(s->N, 64), 1024); }
+
 // ---------------------------------------------------------------- timing
-void begin_timed(spv_sys* s, int which, hipEvent_t* stop)
+EvPair take_events(spv_sys* s)
 {
-    *stop = nullptr;
-    if (!s->timing) return;
-    std::pair<hipEvent_t, hipEvent_t> ev;
-    if (!s->event_pool.empty()) {
-        ev = s->event_pool.back();
-        s->event_pool.pop_back();
+    EvPair e;
+    if (!s->pool.empty()) {
+        e = s->pool.back();
+        s->pool.pop_back();
     } else {
-        (void)hipEventCreate(&ev.first);
-        (void)hipEventCreate(&ev.second);
+        (void)hipEventCreate(&e.a);
+        (void)hipEventCreate(&e.b);
     }
-    (void)hipEventRecord(ev.first, s->stream);
-    s->pending.push_back({which, ev.first, ev.second});
-    *stop = ev.second;
+    return e;
 }
 
-void end_timed(spv_sys* s, hipEvent_t stop)
-{
-    if (stop) (void)hipEventRecord(stop, s->stream);
-}
-
-void collect_timing(spv_sys* s)
+void collect_eager_timing(spv_sys* s)
 {
     for (auto& t : s->pending) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
-            s->t_ms[t.which] += ms;
-            s->t_n[t.which] += 1;
+        if (hipEventElapsedTime(&ms, t.second.a, t.second.b) == hipSuccess) {
+            s->t_ms[t.first] += ms;
+            s->t_n[t.first] += 1;
         }
-        s->event_pool.push_back({t.a, t.b});
+        s->pool.push_back(t.second);
     }
     s->pending.clear();
 }
 
-// ---------------------------------------------------------------- counters
-spv_status read_counters(spv_sys* s)
+void collect_graph_timing(spv_sys* s, int g)
 {
-    HIP_TRY(hipMemcpyAsync(s->h_cnt, s->d_cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s->stream));
+    if (!s->timing || !s->gtimed[g]) return;
+    for (size_t k = 0; k < s->gev[g].size(); k++) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, s->gev[g][k].a, s->gev[g][k].b) == hipSuccess) {
+            s->t_ms[k % T_COUNT] += ms;
+            s->t_n[k % T_COUNT] += 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launch sequences
+// One step on stream `st` from (cfg, parity).  ev: optional event pairs
+// (force, geom, repair round 0) to record around the kernels.
+template <typename R, bool MULTI, int KC>
+void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair* ev)
+{
+    Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
+    const unsigned cg = cell_grid(s), lg = list_grid(s), rg = repair_grid(s);
+    if (ev) (void)hipEventRecord(ev[0].a, st);
+    hipLaunchKernelGGL((k_force<R, MULTI, KC, true>), dim3(cg), dim3(256), 0, st, cur, nxt.x, nxt.y, nxt.th,
+                       (double*)nullptr, (double*)nullptr, s->d_sp, s->d_st, s->N);
+    if (ev) (void)hipEventRecord(ev[0].b, st);
+    if (ev) (void)hipEventRecord(ev[1].a, st);
+    hipLaunchKernelGGL((k_geom<R, MULTI, KC, false, false>), dim3(cg), dim3(256), 0, st, nxt, s->work, s->d_sp,
+                       s->d_st, s->N, 0);
+    if (ev) (void)hipEventRecord(ev[1].b, st);
+    for (int r = 0; r < s->dev_rounds; r++) {
+        if (ev && r == 0) (void)hipEventRecord(ev[2].a, st);
+        hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, r);
+        if (ev && r == 0) (void)hipEventRecord(ev[2].b, st);
+        hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
+                           s->d_st, s->N, r);
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, s->d_st, s->dev_rounds);
+}
+
+// Re-sort from (cfg, parity 0) into set[cfg ^ 1] (the caller flips cfg).
+template <typename R, bool MULTI, int KC>
+void enqueue_resort(spv_sys* s, hipStream_t st, int cfg)
+{
+    Cells<R> src = cells<R>(s, cfg, 0), dst = cells<R>(s, cfg ^ 1, 0);
+    const int N = s->N, nb = s->total_bins;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_hist, nb, 0);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_fill, nb, 0);
+    hipLaunchKernelGGL((k_bin_keys<R, MULTI>), dim3(grid_for(N, 256)), dim3(256), 0, st, src, s->work, s->d_sp,
+                       s->d_st, N, s->d_key, s->d_hist);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, s->d_hist, s->d_bin_start, nb, s->d_st);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(N, 256)), dim3(256), 0, st, s->d_key, s->d_bin_start, s->d_fill,
+                       s->d_perm, N, s->d_st);
+    hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_bin_start, s->d_perm, src.tag,
+                       nb, s->d_st);
+    hipLaunchKernelGGL(k_inv_perm, dim3(grid_for(N, 256)), dim3(256), 0, st, s->d_perm, s->d_inv, N, s->d_st);
+    hipLaunchKernelGGL((k_gather<R, KC>), dim3(grid_for(N, 256)), dim3(256), 0, st, src, dst, s->d_perm, s->d_inv,
+                       N, s->d_st);
+}
+
+// one host-driven repair round (creation and recovery)
+template <typename R, bool MULTI, int KC>
+void enqueue_round(spv_sys* s, hipStream_t st, int round, unsigned rgrid)
+{
+    Cells<R> cur = cells<R>(s, s->cfg, s->pos & 1);
+    hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rgrid), dim3(64), 0, st, cur, s->work, s->d_sp, s->d_st,
+                       round);
+    hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(std::min(grid_for(s->N, CPB), 4096u)), dim3(256), 0,
+                       st, cur, s->work, s->d_sp, s->d_st, s->N, round);
+}
+
+// ---------------------------------------------------------------- control block
+spv_status read_state(spv_sys* s)
+{
+    HIP_TRY(hipMemcpyAsync(s->h_st, s->d_st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
     HIP_TRY(hipGetLastError());
-    collect_timing(s);
+    collect_eager_timing(s);
     return SPV_OK;
 }
 
-spv_status check_err(spv_sys* s)
+spv_status error_from_word(spv_sys* s)
 {
-    const unsigned e = s->h_cnt->err;
-    if (!e) return SPV_OK;
-    s->err_word |= e;
+    const DevState& d = *s->h_st;
+    const unsigned e = d.err;
     char buf[400];
-    const DevCounters& c = *s->h_cnt;
     std::snprintf(buf, sizeof buf,
                   "device error word 0x%x at step %llu (first repair failure: tag %d, %d candidates, ring %d, "
                   "closed %d, %d attempts, R %.4g, max circumradius %.4g)",
-                  e, (unsigned long long)s->step, c.fail_set ? c.fail_cell : -1, c.fail_n, c.fail_k, c.fail_closed,
-                  c.fail_attempts, c.fail_R, c.fail_umax);
-    if (e & ERR_NONFINITE) return fail(SPV_ENONFINITE, std::string(buf) + ": non-finite force or position");
-    if (e & ERR_PRECOND)
-        return fail(SPV_EPRECOND, std::string(buf) + ": a Delaunay circumradius reached min(Lx,Ly)/4");
-    if (e & ERR_CAPACITY) return fail(SPV_ECAPACITY, std::string(buf) + ": ring longer than kcap");
-    if (e & ERR_DEGREE) return fail(SPV_EREPAIR, std::string(buf) + ": ring with fewer than 3 cells");
-    return fail(SPV_EREPAIR, std::string(buf) + ": ring could not be rebuilt");
+                  e, (unsigned long long)d.step, d.fail_set ? d.fail_cell : -1, d.fail_n, d.fail_k, d.fail_closed,
+                  d.fail_attempts, d.fail_R, d.fail_umax);
+    spv_status st = SPV_EREPAIR;
+    std::string what = ": ring could not be rebuilt";
+    if (e & ERR_NONFINITE) {
+        st = SPV_ENONFINITE;
+        what = ": non-finite force or position";
+    } else if (e & ERR_PRECOND) {
+        st = SPV_EPRECOND;
+        what = ": a Delaunay circumradius reached min(Lx,Ly)/4";
+    } else if (e & ERR_CAPACITY) {
+        st = SPV_ECAPACITY;
+        what = ": ring longer than kcap or too many repair candidates";
+    } else if (e & ERR_DEGREE) {
+        what = ": ring with fewer than 3 cells";
+    }
+    s->sticky = st;
+    s->sticky_msg = std::string(buf) + what;
+    return fail(st, s->sticky_msg);
 }
 
-// ---------------------------------------------------------------- re-sort
-// Permute cells into the Hilbert order of their bins; afterwards bin_start
-// indexes the cells of every bin (stored contiguously).
-spv_status resort(spv_sys* s)
+// Finish the repair of the halted step on the host side: more rounds, each
+// read back, until no flag is left.
+spv_status recover(spv_sys* s)
 {
-    const int N = s->N, nb = s->nbins;
-    HIP_TRY(hipMemsetAsync(s->d_hist, 0, nb * sizeof(int), s->stream));
-    HIP_TRY(hipMemsetAsync(s->d_fill, 0, nb * sizeof(int), s->stream));
-    View v = s->v;
-    hipLaunchKernelGGL(k_bin_keys, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, v, s->d_key, s->d_hist);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s->stream, s->d_hist, s->d_bin_start, nb);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->d_key, s->d_bin_start,
-                       s->d_fill, s->d_perm, N);
-    hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nb, 256)), dim3(256), 0, s->stream, s->d_bin_start, s->d_perm,
-                       v.tag, nb);
-    hipLaunchKernelGGL(k_inv_perm, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->d_perm, s->d_inv, N);
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->v, s->a, s->d_perm,
-                       s->d_inv);
+    if (s->h_st->err) return error_from_word(s);
+    int r = s->h_st->halt_round;
+    hipLaunchKernelGGL(k_set_halt, dim3(1), dim3(64), 0, s->stream, s->d_st, 0);
+    while (true) {
+        if (r >= s->max_rounds || r >= MAX_ROUNDS) {
+            s->sticky = SPV_EREPAIR;
+            s->sticky_msg = "topology repair did not converge within repair_rounds";
+            return fail(SPV_EREPAIR, s->sticky_msg);
+        }
+        const unsigned rg = (unsigned)std::min(std::max(s->h_st->wl_count[r], 1), 65535);
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_round<R, MULTI, KC>(s, s->stream, r, rg); });
+        HIP_TRY(hipGetLastError());
+        ST_TRY(read_state(s));
+        if (s->h_st->err) return error_from_word(s);
+        if (s->h_st->wl_count[r + 1] == 0) break;
+        r++;
+    }
+    hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s->stream, s->d_st);
     HIP_TRY(hipGetLastError());
-    std::swap(s->v.x, s->a.x);
-    std::swap(s->v.y, s->a.y);
-    std::swap(s->v.th, s->a.th);
-    std::swap(s->v.tag, s->a.tag);
-    std::swap(s->v.A0, s->a.A0);
-    std::swap(s->v.P0, s->a.P0);
-    std::swap(s->v.deg, s->a.deg);
-    std::swap(s->v.ring, s->a.ring);
-    std::swap(s->v.opp, s->a.opp);
-    std::swap(s->v.A, s->a.A);
-    std::swap(s->v.P, s->a.P);
-    std::swap(s->v.ca, s->a.ca);
-    std::swap(s->v.cb, s->a.cb);
-    s->drift = 0.0;
-    s->steps_since_resort = 0;
+    return SPV_OK;
+}
+
+spv_status capture_graph(spv_sys* s, int g)
+{
+    if (s->gexec[g]) {
+        (void)hipGraphExecDestroy(s->gexec[g]);
+        s->gexec[g] = nullptr;
+    }
+    const bool timed = s->timing;
+    if (timed && s->gev[g].empty()) {
+        s->gev[g].resize((size_t)s->unit * T_COUNT);
+        for (auto& e : s->gev[g]) {
+            HIP_TRY(hipEventCreate(&e.a));
+            HIP_TRY(hipEventCreate(&e.b));
+        }
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+    for (int k = 0; k < s->unit; k++) {
+        const EvPair* ev = timed ? &s->gev[g][(size_t)k * T_COUNT] : nullptr;
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, ev); });
+    }
+    dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->cap_stream, g); });
+    hipError_t e0 = hipGetLastError();
+    hipError_t e1 = hipStreamEndCapture(s->cap_stream, &graph);
+    if (e1 == hipSuccess && e0 != hipSuccess) e1 = e0;
+    if (e1 != hipSuccess) return fail(SPV_EHIP, std::string("graph capture: ") + hipGetErrorString(e1));
+    hipError_t e2 = hipGraphInstantiate(&s->gexec[g], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return fail(SPV_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    s->gtimed[g] = timed;
+    return SPV_OK;
+}
+
+spv_status do_resort_eager(spv_sys* s)
+{
+    dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->stream, s->cfg); });
+    HIP_TRY(hipGetLastError());
+    s->cfg ^= 1;
+    s->pos = 0;
     s->resorts++;
     return SPV_OK;
 }
 
-// ---------------------------------------------------------------- repair rounds
-// Loop until the validity test raises no flag: compact the flags into a
-// worklist, rebuild those rings, rebuild opp and re-test every cell whose
-// neighbourhood changed.  `fail_count` is the number of failing cells of the
-// last test (already read back).
-spv_status repair_loop(spv_sys* s, int fail_count, double R0)
+spv_status run_steps(spv_sys* s, int64_t n)
 {
-    int rounds = 0;
-    const int N = s->N;
-    while (fail_count > 0) {
-        if (++rounds > s->repair_rounds)
-            return fail(SPV_EREPAIR, "topology repair did not converge within repair_rounds");
-        View v = s->v;
-        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s->stream, s->d_cnt, 1, 0);
-        const unsigned cg = std::min(grid_for(N, 256), 2048u);
-        hipLaunchKernelGGL(k_compact, dim3(cg), dim3(256), 0, s->stream, v.flag, N, v.worklist, &s->d_cnt->wl_count);
-        const unsigned rg = (unsigned)std::min(std::max(4 * fail_count + 64, 64), std::max(N, 64));
-        hipEvent_t stop;
-        begin_timed(s, T_REPAIR, &stop);
-        hipLaunchKernelGGL(k_repair, dim3(std::min(rg, 65535u)), dim3(64), 0, s->stream, v, R0, s->drift);
-        end_timed(s, stop);
-        hipLaunchKernelGGL(k_compact, dim3(cg), dim3(256), 0, s->stream, v.touched, N, v.list2,
-                           &s->d_cnt->touched_count);
-        const unsigned lg = std::min(grid_for(N, 256), 1024u);
-        hipLaunchKernelGGL(k_opp<true>, dim3(lg), dim3(256), 0, s->stream, v);
-        hipLaunchKernelGGL(k_geom_test<true>, dim3(lg), dim3(256), 0, s->stream, v, s->prm.KA, s->prm.KP);
-        HIP_TRY(hipGetLastError());
-        ST_TRY(read_counters(s));
-        s->rounds++;
-        ST_TRY(check_err(s));
-        fail_count = s->h_cnt->fail_count;
+    if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
+    while (n > 0) {
+        if (s->pos == s->unit) ST_TRY(do_resort_eager(s));
+        if (s->pos == 0 && n >= s->unit && s->use_graphs && !(s->timing && s->graph_timing_broken)) {
+            const int g = s->cfg;
+            if (!s->gexec[g] || s->gtimed[g] != s->timing) {
+                const spv_status cst = capture_graph(s, g);
+                if (cst != SPV_OK) {
+                    if (!s->timing) return cst;
+                    s->graph_timing_broken = true;  // retry this period eagerly
+                    (void)hipGetLastError();
+                    continue;
+                }
+            }
+            const uint64_t before = s->step;
+            HIP_TRY(hipGraphLaunch(s->gexec[g], s->stream));
+            ST_TRY(read_state(s));
+            const uint64_t done = s->h_st->step - before;
+            if (s->h_st->halt) {
+                // the period stopped after `done` steps (the last one unfinished);
+                // later kernels, including its re-sort, did nothing
+                s->step += done;
+                n -= (int64_t)done;
+                s->pos = (int)done;
+                ST_TRY(recover(s));
+                continue;
+            }
+            collect_graph_timing(s, g);
+            s->step += done;
+            n -= (int64_t)done;
+            s->cfg ^= 1;
+            s->resorts++;
+        } else {
+            EvPair ev[T_COUNT];
+            const EvPair* evp = nullptr;
+            if (s->timing) {
+                for (int k = 0; k < T_COUNT; k++) {
+                    ev[k] = take_events(s);
+                    s->pending.push_back({k, ev[k]});
+                }
+                evp = ev;
+            }
+            const int cfg = s->cfg, par = s->pos & 1;
+            dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, evp); });
+            HIP_TRY(hipGetLastError());
+            ST_TRY(read_state(s));
+            s->step += 1;
+            s->pos += 1;
+            n -= 1;
+            if (s->h_st->halt) ST_TRY(recover(s));
+        }
     }
-    return SPV_OK;
-}
-
-double default_radius(const spv_sys* s) { return 2.5 * s->spacing; }
-
-spv_status one_step(spv_sys* s)
-{
-    const int N = s->N;
-    const double min_bs = std::min(s->v.bsx, s->v.bsy);
-    if (s->steps_since_resort >= s->resort_every || s->drift > 0.5 * min_bs) ST_TRY(resort(s));
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s->stream, s->d_cnt, 0, 0);
-    StepParams sp;
-    sp.mu = s->prm.mu;
-    sp.v0 = s->prm.v0;
-    sp.dt = s->prm.dt;
-    sp.amp = std::sqrt(2.0 * s->prm.Dr * s->prm.dt);
-    sp.KA = s->prm.KA;
-    sp.KP = s->prm.KP;
-    sp.seed = s->prm.seed;
-    sp.step = s->step;
-    hipEvent_t stop;
-    begin_timed(s, T_FORCE, &stop);
-    hipLaunchKernelGGL(k_force<true>, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->v, s->a.x, s->a.y, s->a.th,
-                       (double*)nullptr, (double*)nullptr, sp);
-    end_timed(s, stop);
-    std::swap(s->v.x, s->a.x);
-    std::swap(s->v.y, s->a.y);
-    std::swap(s->v.th, s->a.th);
-    begin_timed(s, T_GEOM, &stop);
-    hipLaunchKernelGGL(k_geom_test<false>, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->v, s->prm.KA,
-                       s->prm.KP);
-    end_timed(s, stop);
-    HIP_TRY(hipGetLastError());
-    ST_TRY(read_counters(s));
-    s->step++;
-    s->steps_since_resort++;
-    s->drift += __builtin_bit_cast(double, s->h_cnt->disp_bits);
-    ST_TRY(check_err(s));
-    return repair_loop(s, s->h_cnt->fail_count, default_radius(s));
-}
-
-spv_status copy_out_tag_order(spv_sys* s, const double* dsrc, double* dst)
-{
-    hipLaunchKernelGGL(k_to_tag_order, dim3(grid_for(s->N, 256)), dim3(256), 0, s->stream, dsrc, s->v.tag,
-                       s->d_stage, s->N);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(hipMemcpyAsync(dst, s->d_stage, s->N * sizeof(double), hipMemcpyDefault, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
     return SPV_OK;
 }
 
@@ -366,160 +499,245 @@ void destroy_all(spv_sys* s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    for (void* p : s->allocs) (void)hipFree(p);
-    if (s->h_cnt) (void)hipHostFree(s->h_cnt);
-    for (auto& e : s->event_pool) {
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
+    for (int g = 0; g < 2; g++) {
+        if (s->gexec[g]) (void)hipGraphExecDestroy(s->gexec[g]);
+        for (auto& e : s->gev[g]) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+    }
+    for (auto& e : s->pool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
     }
     for (auto& t : s->pending) {
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
+        (void)hipEventDestroy(t.second.a);
+        (void)hipEventDestroy(t.second.b);
     }
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    for (void* p : s->allocs) (void)hipFree(p);
+    if (s->h_st) (void)hipHostFree(s->h_st);
     delete s;
 }
 
-spv_status create_impl(spv_sys* s, int64_t N64, const double* x, const double* y, double Lx, double Ly,
-                       const double* A0, const double* P0, double p0, const double* theta0)
-{
-    const int N = (int)N64;
-    s->N = N;
-    // grid and box
-    s->q = grid_exponent(std::max(Lx, Ly));
-    const double scale = std::ldexp(1.0, s->q);
-    const double LXu = std::rint(Lx * scale), LYu = std::rint(Ly * scale);
-    s->Lx = LXu / scale;
-    s->Ly = LYu / scale;
-    // host copies of the inputs (host or device pointers)
-    std::vector<double> hx, hy, hA0, hP0, hth;
-    ST_TRY(copy_in(x, hx, N));
-    ST_TRY(copy_in(y, hy, N));
-    for (int i = 0; i < N; i++) {
-        if (!std::isfinite(hx[i]) || !std::isfinite(hy[i]) || hx[i] < 0.0 || hx[i] >= Lx || hy[i] < 0.0 ||
-            hy[i] >= Ly)
-            return fail(SPV_EINVAL, "positions must be finite and inside [0,Lx) x [0,Ly)");
-        double X = std::rint(hx[i] * scale), Y = std::rint(hy[i] * scale);
-        if (X >= LXu) X -= LXu;
-        if (Y >= LYu) Y -= LYu;
-        hx[i] = X / scale;
-        hy[i] = Y / scale;
-    }
-    {
-        std::vector<std::pair<double, double>> pts(N);
-        for (int i = 0; i < N; i++) pts[i] = {hx[i], hy[i]};
-        std::sort(pts.begin(), pts.end());
-        for (int i = 1; i < N; i++)
-            if (pts[i] == pts[i - 1]) return fail(SPV_EINVAL, "two cells share a position on the grid");
-    }
-    if (A0) ST_TRY(copy_in(A0, hA0, N));
-    else hA0.assign(N, 1.0);
-    if (P0) ST_TRY(copy_in(P0, hP0, N));
-    else {
-        hP0.resize(N);
-        for (int i = 0; i < N; i++) hP0[i] = p0 * std::sqrt(hA0[i]);
-    }
-    for (int i = 0; i < N; i++)
-        if (!std::isfinite(hA0[i]) || !std::isfinite(hP0[i]) || hA0[i] <= 0.0)
-            return fail(SPV_EINVAL, "A0 must be positive and finite, P0 finite");
-    if (theta0) {
-        ST_TRY(copy_in(theta0, hth, N));
-        for (int i = 0; i < N; i++)
-            if (!std::isfinite(hth[i])) return fail(SPV_EINVAL, "theta0 must be finite");
-    }
+struct SysInput {
+    int64_t n;
+    double Lx, Ly;
+    double v0;
+    uint64_t seed;
+};
 
-    // bins of side >= mean spacing, ordered along a Hilbert curve
-    s->spacing = std::sqrt(s->Lx * s->Ly / N);
-    const int nbx = std::max(1, (int)std::floor(s->Lx / s->spacing));
-    const int nby = std::max(1, (int)std::floor(s->Ly / s->spacing));
-    s->nbins = nbx * nby;
-    std::vector<int> rank(s->nbins);
-    {
+// Shared creation: hx, hy, hA0, hP0 are host arrays concatenated by system;
+// hth empty means default directors.
+spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<double>& hx,
+                       std::vector<double>& hy, const std::vector<double>& hA0, const std::vector<double>& hP0,
+                       const std::vector<double>& hth)
+{
+    const int S = (int)in.size();
+    s->S = S;
+    s->multi = S > 1;
+    int64_t Ntot = 0;
+    for (auto& v : in) Ntot += v.n;
+    if (Ntot > (int64_t)1 << 30) return fail(SPV_EINVAL, "too many cells");
+    s->N = (int)Ntot;
+    const int N = s->N;
+    std::vector<int> htag(N), hsys(N);
+    std::vector<int> hbinkey;
+    s->hsp.resize(S);
+    s->cell_off.resize(S + 1);
+    int off = 0, boff = 0;
+    for (int k = 0; k < S; k++) {
+        const SysInput& v = in[k];
+        SysParam& P = s->hsp[k];
+        std::memset(&P, 0, sizeof P);
+        const int q = grid_exponent(std::max(v.Lx, v.Ly));
+        P.scale = std::ldexp(1.0, q);
+        P.inv_scale = 1.0 / P.scale;
+        P.LXu = std::rint(v.Lx * P.scale);
+        P.LYu = std::rint(v.Ly * P.scale);
+        P.Lx = P.LXu / P.scale;
+        P.Ly = P.LYu / P.scale;
+        P.hLx = 0.5 * P.Lx;
+        P.hLy = 0.5 * P.Ly;
+        P.mu = s->prm.mu;
+        P.v0 = v.v0;
+        P.dt = s->prm.dt;
+        P.amp = std::sqrt(2.0 * s->prm.Dr * s->prm.dt);
+        P.KA = s->prm.KA;
+        P.KP = s->prm.KP;
+        P.seed = v.seed;
+        P.cell_off = off;
+        P.n = (int)v.n;
+        const double spacing = std::sqrt(P.Lx * P.Ly / (double)v.n);
+        P.R0 = 2.5 * spacing;
+        P.nbx = std::max(1, (int)std::floor(P.Lx / spacing));
+        P.nby = std::max(1, (int)std::floor(P.Ly / spacing));
+        P.bsx = P.Lx / P.nbx;
+        P.bsy = P.Ly / P.nby;
+        P.bin_off = boff;
+        // quantise, validate, reject duplicates
+        std::vector<std::pair<double, double>> pts((size_t)v.n);
+        for (int64_t t = 0; t < v.n; t++) {
+            double& x = hx[off + t];
+            double& y = hy[off + t];
+            if (!std::isfinite(x) || !std::isfinite(y) || x < 0.0 || x >= v.Lx || y < 0.0 || y >= v.Ly)
+                return fail(SPV_EINVAL, "positions must be finite and inside [0,Lx) x [0,Ly)");
+            double X = std::rint(x * P.scale), Y = std::rint(y * P.scale);
+            if (X >= P.LXu) X -= P.LXu;
+            if (Y >= P.LYu) Y -= P.LYu;
+            x = X / P.scale;
+            y = Y / P.scale;
+            pts[t] = {x, y};
+            htag[off + t] = (int)t;
+            hsys[off + t] = k;
+        }
+        std::sort(pts.begin(), pts.end());
+        for (size_t t = 1; t < pts.size(); t++)
+            if (pts[t] == pts[t - 1]) return fail(SPV_EINVAL, "two cells share a position on the grid");
+        // bins of this system ranked along a Hilbert curve
+        const int nb = P.nbx * P.nby;
         int64_t n2 = 1;
-        while (n2 < std::max(nbx, nby)) n2 *= 2;
-        std::vector<std::pair<int64_t, int>> key(s->nbins);
-        for (int by = 0; by < nby; by++)
-            for (int bx = 0; bx < nbx; bx++) key[by * nbx + bx] = {hilbert_index(n2, bx, by), by * nbx + bx};
+        while (n2 < std::max(P.nbx, P.nby)) n2 *= 2;
+        std::vector<std::pair<int64_t, int>> key(nb);
+        for (int by = 0; by < P.nby; by++)
+            for (int bx = 0; bx < P.nbx; bx++) key[by * P.nbx + bx] = {hilbert_index(n2, bx, by), by * P.nbx + bx};
         std::sort(key.begin(), key.end());
-        for (int r = 0; r < s->nbins; r++) rank[key[r].second] = r;
+        hbinkey.resize(boff + nb);
+        for (int r = 0; r < nb; r++) hbinkey[boff + key[r].second] = boff + r;
+        off += (int)v.n;
+        boff += nb;
     }
+    s->cell_off[S] = off;
+    for (int k = 0; k < S; k++) s->cell_off[k] = s->hsp[k].cell_off;
+    s->total_bins = boff;
 
     // device state
-    ST_TRY(alloc_view(s, s->v));
-    ST_TRY(alloc_view(s, s->a));
-    ST_TRY(dalloc(s, &s->v.flag, N));
-    ST_TRY(dalloc(s, &s->v.touched, N));
-    ST_TRY(dalloc(s, &s->v.worklist, N));
-    ST_TRY(dalloc(s, &s->v.list2, N));
-    ST_TRY(dalloc(s, &s->d_cnt, 1));
-    ST_TRY(dalloc(s, &s->d_bin_rank, s->nbins));
-    ST_TRY(dalloc(s, &s->d_bin_start, s->nbins + 1));
+    ST_TRY(alloc_set(s, s->set[0]));
+    ST_TRY(alloc_set(s, s->set[1]));
+    const size_t nwords = (N + 31) / 32;
+    ST_TRY(dalloc(s, &s->work.flagbits, nwords));
+    ST_TRY(dalloc(s, &s->work.touchbits, nwords));
+    for (int k = 0; k < 2; k++) {
+        ST_TRY(dalloc(s, &s->work.wl[k], N));
+        ST_TRY(dalloc(s, &s->work.tl[k], N));
+    }
+    ST_TRY(dalloc(s, &s->d_bin_key, s->total_bins));
+    ST_TRY(dalloc(s, &s->d_bin_start, s->total_bins + 1));
+    s->work.bin_key = s->d_bin_key;
+    s->work.bin_start = s->d_bin_start;
     ST_TRY(dalloc(s, &s->d_key, N));
-    ST_TRY(dalloc(s, &s->d_hist, s->nbins));
-    ST_TRY(dalloc(s, &s->d_fill, s->nbins));
+    ST_TRY(dalloc(s, &s->d_hist, s->total_bins));
+    ST_TRY(dalloc(s, &s->d_fill, s->total_bins));
     ST_TRY(dalloc(s, &s->d_perm, N));
     ST_TRY(dalloc(s, &s->d_inv, N));
+    ST_TRY(dalloc(s, &s->d_st, 1));
+    ST_TRY(dalloc(s, &s->d_sp, S));
     ST_TRY(dalloc(s, &s->d_stage, N));
     ST_TRY(dalloc(s, &s->d_fx, N));
     ST_TRY(dalloc(s, &s->d_fy, N));
-    ST_TRY(dalloc(s, &s->d_part, 3 * 1024));
-    ST_TRY(dalloc(s, &s->d_obs, 3));
-    HIP_TRY(hipHostMalloc((void**)&s->h_cnt, sizeof(DevCounters), hipHostMallocDefault));
-    HIP_TRY(hipMemsetAsync(s->d_cnt, 0, sizeof(DevCounters), s->stream));
-    HIP_TRY(hipMemsetAsync(s->v.flag, 0, N, s->stream));
-    HIP_TRY(hipMemsetAsync(s->v.touched, 0, N, s->stream));
-    for (View* w : {&s->v, &s->a}) {
-        View& vv = *w;
-        vv.N = N;
-        vv.kcap = s->kcap;
-        vv.Lx = s->Lx;
-        vv.Ly = s->Ly;
-        vv.hLx = 0.5 * s->Lx;
-        vv.hLy = 0.5 * s->Ly;
-        vv.scale = scale;
-        vv.inv_scale = 1.0 / scale;
-        vv.LXu = LXu;
-        vv.LYu = LYu;
-        vv.flag = s->v.flag;
-        vv.touched = s->v.touched;
-        vv.worklist = s->v.worklist;
-        vv.list2 = s->v.list2;
-        vv.cnt = s->d_cnt;
-        vv.nbx = nbx;
-        vv.nby = nby;
-        vv.bsx = s->Lx / nbx;
-        vv.bsy = s->Ly / nby;
-        vv.bin_rank = s->d_bin_rank;
-        vv.bin_start = s->d_bin_start;
-    }
-    HIP_TRY(hipMemcpyAsync(s->v.x, hx.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemcpyAsync(s->v.y, hy.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemcpyAsync(s->v.A0, hA0.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemcpyAsync(s->v.P0, hP0.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
-    HIP_TRY(hipMemcpyAsync(s->d_bin_rank, rank.data(), s->nbins * sizeof(int), hipMemcpyHostToDevice, s->stream));
-    hipLaunchKernelGGL(k_iota, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->v.tag, N);
-    if (theta0)
-        HIP_TRY(hipMemcpyAsync(s->v.th, hth.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    ST_TRY(dalloc(s, &s->d_obs, 3 * S));
+    HIP_TRY(hipHostMalloc((void**)&s->h_st, sizeof(DevState), hipHostMallocDefault));
+    HIP_TRY(hipMemsetAsync(s->d_st, 0, sizeof(DevState), s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.flagbits, 0, nwords * sizeof(unsigned), s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.touchbits, 0, nwords * sizeof(unsigned), s->stream));
+    ArraySet& A = s->set[0];
+    HIP_TRY(hipMemcpyAsync(s->d_sp, s->hsp.data(), S * sizeof(SysParam), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->d_bin_key, hbinkey.data(), s->total_bins * sizeof(int), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(A.x, hx.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(A.y, hy.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(A.A0, hA0.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(A.P0, hP0.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(A.tag, htag.data(), N * sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(A.sys, hsys.data(), N * sizeof(int), hipMemcpyHostToDevice, s->stream));
+    if (!hth.empty())
+        HIP_TRY(hipMemcpyAsync(A.th, hth.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
     else
-        hipLaunchKernelGGL(k_theta0, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->v.th, s->v.tag, N,
-                           (uint64_t)s->prm.seed);
+        hipLaunchKernelGGL(k_theta0, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, A.th, A.tag, A.sys, s->d_sp, N);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s->stream));  // host vectors die at return
+    HIP_TRY(hipStreamCreate(&s->cap_stream));
 
     // spatial order, then the triangulation from scratch: every cell repaired
-    ST_TRY(resort(s));
-    View v = s->v;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s->stream, s->d_cnt, 2, N);
-    hipLaunchKernelGGL(k_iota, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, v.worklist, N);
-    hipLaunchKernelGGL(k_repair, dim3(std::min(N, 65535)), dim3(64), 0, s->stream, v, default_radius(s), 0.0);
-    hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, v.touched, N, (uint8_t)0);
-    hipLaunchKernelGGL(k_opp<false>, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, v);
-    hipLaunchKernelGGL(k_geom_test<false>, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, v, s->prm.KA,
-                       s->prm.KP);
+    s->cfg = 0;
+    s->pos = 0;
+    ST_TRY(do_resort_eager(s));
+    s->resorts = 0;
+    hipLaunchKernelGGL(k_all_to_worklist, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->work, s->d_st, N);
+    int r = 0;
+    while (true) {
+        if (r >= MAX_ROUNDS) return fail(SPV_EREPAIR, "initial triangulation did not converge");
+        const unsigned rg = (r == 0) ? (unsigned)std::min(N, 65535) : 4096u;
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_round<R, MULTI, KC>(s, s->stream, r, rg); });
+        HIP_TRY(hipGetLastError());
+        ST_TRY(read_state(s));
+        if (s->h_st->err) {
+            spv_status st = error_from_word(s);
+            return st;
+        }
+        if (s->h_st->wl_count[r + 1] == 0) break;
+        r++;
+    }
+    hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s->stream, s->d_st);
     HIP_TRY(hipGetLastError());
-    ST_TRY(read_counters(s));
-    ST_TRY(check_err(s));
-    ST_TRY(repair_loop(s, s->h_cnt->fail_count, default_radius(s)));
+    ST_TRY(read_state(s));
     return SPV_OK;
+}
+
+spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
+{
+    const spv_params& p = *params;
+    if (p.precision != SPV_FP64 && p.precision != SPV_MIXED) return fail(SPV_EINVAL, "precision must be FP64 or MIXED");
+    if (!(p.dt > 0.0) || !(p.Dr >= 0.0) || !std::isfinite(p.dt) || !std::isfinite(p.Dr) || !std::isfinite(p.mu) ||
+        !std::isfinite(p.v0) || !std::isfinite(p.KA) || !std::isfinite(p.KP))
+        return fail(SPV_EINVAL, "invalid model parameters");
+    s->prm = p;
+    s->mixed = p.precision == SPV_MIXED;
+    s->KC = p.kcap > 0 ? p.kcap : 16;
+    if (s->KC != 16 && s->KC != 32) return fail(SPV_EINVAL, "kcap must be 16 or 32");
+    s->max_rounds = p.repair_rounds > 0 ? std::min(p.repair_rounds, MAX_ROUNDS) : 16;
+    s->dev_rounds = p.device_rounds > 0 ? std::min(p.device_rounds, s->max_rounds) : 2;
+    if (s->dev_rounds > s->max_rounds) return fail(SPV_EINVAL, "device_rounds exceeds repair_rounds");
+    s->unit = p.resort_every > 0 ? p.resort_every : 16;
+    if (s->unit & 1) s->unit += 1;
+    s->use_graphs = p.no_graphs == 0;
+    s->stream = (hipStream_t)stream;
+    return SPV_OK;
+}
+
+spv_status finish_create(spv_sys* s, spv_status st, spv_sys** out)
+{
+    if (st != SPV_OK) {
+        std::string keep = g_err;
+        destroy_all(s);
+        g_err = keep;
+        return st;
+    }
+    *out = s;
+    return SPV_OK;
+}
+
+template <typename F>
+spv_status with_tag_order(spv_sys* s, F&& launch_into_stage, double* dst)
+{
+    launch_into_stage(s->d_stage);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(dst, s->d_stage, (size_t)s->N * sizeof(double), hipMemcpyDefault, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SPV_OK;
+}
+
+template <typename T>
+spv_status out_tag_order(spv_sys* s, const T* src, double* dst)
+{
+    const ArraySet& P = s->set[s->cfg];
+    return with_tag_order(
+        s,
+        [&](double* stage) {
+            hipLaunchKernelGGL(k_to_tag_order<T>, dim3(grid_for(s->N, 256)), dim3(256), 0, s->stream, src, P.tag,
+                               P.sys, s->d_sp, stage, s->N);
+        },
+        dst);
 }
 
 }  // namespace
@@ -539,131 +757,231 @@ spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y
     if (!x || !y || !params) return fail(SPV_EINVAL, "x, y and params are required");
     if (!(Lx > 0.0) || !(Ly > 0.0) || !std::isfinite(Lx) || !std::isfinite(Ly))
         return fail(SPV_EINVAL, "box sides must be positive and finite");
-    const spv_params& p = *params;
-    if (p.precision != SPV_FP64) return fail(SPV_EINVAL, "precision must be SPV_FP64");
-    if (!(p.dt > 0.0) || !(p.Dr >= 0.0) || !std::isfinite(p.mu) || !std::isfinite(p.v0) || !std::isfinite(p.KA) ||
-        !std::isfinite(p.KP))
-        return fail(SPV_EINVAL, "invalid model parameters");
     if (!A0 && !P0 && !std::isfinite(p0)) return fail(SPV_EINVAL, "p0 must be finite");
     spv_sys* s = new spv_sys();
-    s->prm = p;
-    s->kcap = p.kcap > 0 ? p.kcap : 16;
-    if (s->kcap < 3 || s->kcap > RP_KMAX) {
-        delete s;
-        return fail(SPV_EINVAL, "kcap must be in [3, 64]");
+    spv_status st = setup_params(s, params, stream);
+    if (st != SPV_OK) return finish_create(s, st, out);
+    std::vector<double> hx, hy, hA0, hP0, hth;
+    if ((st = copy_in(x, hx, N)) != SPV_OK || (st = copy_in(y, hy, N)) != SPV_OK) return finish_create(s, st, out);
+    if (A0) {
+        if ((st = copy_in(A0, hA0, N)) != SPV_OK) return finish_create(s, st, out);
+    } else {
+        hA0.assign(N, 1.0);
     }
-    s->repair_rounds = p.repair_rounds > 0 ? p.repair_rounds : 16;
-    s->resort_every = p.resort_every > 0 ? p.resort_every : 64;
-    s->stream = (hipStream_t)stream;
-    spv_status st = create_impl(s, N, x, y, Lx, Ly, A0, P0, p0, theta0);
-    if (st != SPV_OK) {
-        std::string keep = g_err;
-        destroy_all(s);
-        g_err = keep;
-        return st;
+    if (P0) {
+        if ((st = copy_in(P0, hP0, N)) != SPV_OK) return finish_create(s, st, out);
+    } else {
+        hP0.resize(N);
+        for (int64_t i = 0; i < N; i++) hP0[i] = p0 * std::sqrt(hA0[i]);
     }
-    *out = s;
-    return SPV_OK;
+    for (int64_t i = 0; i < N; i++)
+        if (!std::isfinite(hA0[i]) || !std::isfinite(hP0[i]) || hA0[i] <= 0.0)
+            return finish_create(s, fail(SPV_EINVAL, "A0 must be positive and finite, P0 finite"), out);
+    if (theta0) {
+        if ((st = copy_in(theta0, hth, N)) != SPV_OK) return finish_create(s, st, out);
+        for (int64_t i = 0; i < N; i++)
+            if (!std::isfinite(hth[i])) return finish_create(s, fail(SPV_EINVAL, "theta0 must be finite"), out);
+    }
+    std::vector<SysInput> in{{N, Lx, Ly, params->v0, params->seed}};
+    return finish_create(s, create_impl(s, in, hx, hy, hA0, hP0, hth), out);
+}
+
+spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const double* Lx_s, const double* Ly_s,
+                            const double* x, const double* y, const double* P0, const double* p0_s,
+                            const double* v0_s, const uint64_t* seed_s, const spv_params* params, void* stream)
+{
+    if (!out) return fail(SPV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (S < 1 || !N_s || !Lx_s || !Ly_s || !x || !y || !params || (!P0 && !p0_s))
+        return fail(SPV_EINVAL, "bad batch arguments");
+    std::vector<SysInput> in(S);
+    int64_t Ntot = 0;
+    for (int k = 0; k < S; k++) {
+        if (N_s[k] < 3 || !(Lx_s[k] > 0.0) || !(Ly_s[k] > 0.0) || !std::isfinite(Lx_s[k]) || !std::isfinite(Ly_s[k]))
+            return fail(SPV_EINVAL, "every system needs N >= 3 and a positive finite box");
+        in[k] = {N_s[k], Lx_s[k], Ly_s[k], v0_s ? v0_s[k] : params->v0, seed_s ? seed_s[k] : params->seed};
+        if (!std::isfinite(in[k].v0)) return fail(SPV_EINVAL, "v0 must be finite");
+        Ntot += N_s[k];
+        if (Ntot > (int64_t)1 << 30) return fail(SPV_EINVAL, "too many cells");
+    }
+    spv_sys* s = new spv_sys();
+    spv_status st = setup_params(s, params, stream);
+    if (st != SPV_OK) return finish_create(s, st, out);
+    std::vector<double> hx, hy, hA0(Ntot, 1.0), hP0, hth;
+    if ((st = copy_in(x, hx, Ntot)) != SPV_OK || (st = copy_in(y, hy, Ntot)) != SPV_OK)
+        return finish_create(s, st, out);
+    if (P0) {
+        if ((st = copy_in(P0, hP0, Ntot)) != SPV_OK) return finish_create(s, st, out);
+    } else {
+        hP0.resize(Ntot);
+        int64_t o = 0;
+        for (int k = 0; k < S; k++)
+            for (int64_t t = 0; t < N_s[k]; t++) hP0[o++] = p0_s[k];
+    }
+    for (int64_t i = 0; i < Ntot; i++)
+        if (!std::isfinite(hP0[i])) return finish_create(s, fail(SPV_EINVAL, "P0 must be finite"), out);
+    return finish_create(s, create_impl(s, in, hx, hy, hA0, hP0, hth), out);
 }
 
 spv_status spv_step(spv_sys* s, int64_t nsteps)
 {
     if (!s || nsteps < 0) return fail(SPV_EINVAL, "bad handle or nsteps");
-    for (int64_t k = 0; k < nsteps; k++) ST_TRY(one_step(s));
+    return run_steps(s, nsteps);
+}
+
+spv_status spv_get_size(spv_sys* s, int32_t* S, int64_t* N)
+{
+    if (!s) return fail(SPV_EINVAL, "bad handle");
+    if (S) *S = s->S;
+    if (N) *N = s->N;
     return SPV_OK;
 }
 
-spv_status spv_get_box(spv_sys* s, double* Lx, double* Ly, int32_t* q)
+spv_status spv_get_system_range(spv_sys* s, int32_t sys, int64_t* first, int64_t* n)
 {
-    if (!s) return fail(SPV_EINVAL, "bad handle");
-    if (Lx) *Lx = s->Lx;
-    if (Ly) *Ly = s->Ly;
-    if (q) *q = s->q;
+    if (!s || sys < 0 || sys >= s->S) return fail(SPV_EINVAL, "bad handle or system index");
+    if (first) *first = s->hsp[sys].cell_off;
+    if (n) *n = s->hsp[sys].n;
     return SPV_OK;
 }
+
+spv_status spv_get_system_box(spv_sys* s, int32_t sys, double* Lx, double* Ly, int32_t* q)
+{
+    if (!s || sys < 0 || sys >= s->S) return fail(SPV_EINVAL, "bad handle or system index");
+    if (Lx) *Lx = s->hsp[sys].Lx;
+    if (Ly) *Ly = s->hsp[sys].Ly;
+    if (q) *q = grid_exponent(std::max(s->hsp[sys].Lx, s->hsp[sys].Ly));
+    return SPV_OK;
+}
+
+spv_status spv_get_box(spv_sys* s, double* Lx, double* Ly, int32_t* q) { return spv_get_system_box(s, 0, Lx, Ly, q); }
 
 spv_status spv_get_positions(spv_sys* s, double* x, double* y)
 {
     if (!s || !x || !y) return fail(SPV_EINVAL, "bad argument");
-    ST_TRY(copy_out_tag_order(s, s->v.x, x));
-    return copy_out_tag_order(s, s->v.y, y);
+    const int par = s->pos & 1;
+    const ArraySet& cur = s->set[par ? s->cfg ^ 1 : s->cfg];
+    ST_TRY(out_tag_order(s, cur.x, x));
+    return out_tag_order(s, cur.y, y);
 }
 
 spv_status spv_get_directors(spv_sys* s, double* theta)
 {
     if (!s || !theta) return fail(SPV_EINVAL, "bad argument");
-    return copy_out_tag_order(s, s->v.th, theta);
+    const int par = s->pos & 1;
+    const ArraySet& cur = s->set[par ? s->cfg ^ 1 : s->cfg];
+    return out_tag_order(s, cur.th, theta);
 }
 
 spv_status spv_get_forces(spv_sys* s, double* fx, double* fy)
 {
     if (!s || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
-    StepParams sp{};
-    hipLaunchKernelGGL(k_force<false>, dim3(grid_for(s->N, 256)), dim3(256), 0, s->stream, s->v, (double*)nullptr,
-                       (double*)nullptr, (double*)nullptr, s->d_fx, s->d_fy, sp);
+    dispatch(s, [&]<typename R, bool MULTI, int KC>() {
+        Cells<R> c = cells<R>(s, s->cfg, s->pos & 1);
+        hipLaunchKernelGGL((k_force<R, MULTI, KC, false>), dim3(cell_grid(s)), dim3(256), 0, s->stream, c,
+                           (double*)nullptr, (double*)nullptr, (double*)nullptr, s->d_fx, s->d_fy, s->d_sp, s->d_st,
+                           s->N);
+    });
     HIP_TRY(hipGetLastError());
-    ST_TRY(copy_out_tag_order(s, s->d_fx, fx));
-    return copy_out_tag_order(s, s->d_fy, fy);
+    ST_TRY(out_tag_order(s, s->d_fx, fx));
+    return out_tag_order(s, s->d_fy, fy);
 }
 
 spv_status spv_get_geometry(spv_sys* s, double* A, double* P)
 {
     if (!s || !A || !P) return fail(SPV_EINVAL, "bad argument");
-    ST_TRY(copy_out_tag_order(s, s->v.A, A));
-    return copy_out_tag_order(s, s->v.P, P);
+    const ArraySet& cur = s->set[s->cfg];
+    if (s->mixed) {
+        ST_TRY(out_tag_order(s, static_cast<const float*>(cur.A), A));
+        return out_tag_order(s, static_cast<const float*>(cur.P), P);
+    }
+    ST_TRY(out_tag_order(s, static_cast<const double*>(cur.A), A));
+    return out_tag_order(s, static_cast<const double*>(cur.P), P);
 }
 
 spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t cap, int64_t* needed)
 {
     if (!s || !offsets) return fail(SPV_EINVAL, "bad argument");
-    const int N = s->N, K = s->kcap;
+    const int N = s->N, K = s->KC;
+    const ArraySet& cur = s->set[s->cfg];
     std::vector<uint8_t> deg(N);
-    std::vector<int> ring((size_t)N * K), tag(N);
-    HIP_TRY(hipMemcpyAsync(deg.data(), s->v.deg, N, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipMemcpyAsync(ring.data(), s->v.ring, (size_t)N * K * sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipMemcpyAsync(tag.data(), s->v.tag, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    std::vector<int> ring((size_t)N * K), tag(N), sys(N);
+    HIP_TRY(hipMemcpyAsync(deg.data(), cur.deg, N, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(ring.data(), cur.ring, (size_t)N * K * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(tag.data(), cur.tag, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(sys.data(), cur.sys, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    std::vector<int> slot_of_tag(N);
-    for (int i = 0; i < N; i++) slot_of_tag[tag[i]] = i;
+    std::vector<int> gid(N), slot_of(N);
+    for (int i = 0; i < N; i++) {
+        gid[i] = s->hsp[sys[i]].cell_off + tag[i];
+        slot_of[gid[i]] = i;
+    }
     int64_t tot = 0;
     for (int t = 0; t < N; t++) {
         offsets[t] = (int32_t)tot;
-        tot += deg[slot_of_tag[t]];
+        tot += deg[slot_of[t]];
     }
     offsets[N] = (int32_t)tot;
     if (needed) *needed = tot;
     if (!nbr || cap < tot) return fail(SPV_ECAPACITY, "nbr buffer too small");
     for (int t = 0; t < N; t++) {
-        const int i = slot_of_tag[t];
-        for (int m = 0; m < deg[i]; m++) nbr[offsets[t] + m] = tag[ring[(size_t)m * N + i]];
+        const int i = slot_of[t];
+        for (int m = 0; m < deg[i]; m++) nbr[offsets[t] + m] = gid[ring[(size_t)i * K + m]];
     }
     return SPV_OK;
+}
+
+static spv_status observables_all(spv_sys* s, std::vector<double>& h)
+{
+    const ArraySet& cur = s->set[s->cfg];
+    if (s->mixed)
+        hipLaunchKernelGGL(k_observables<float>, dim3(s->S), dim3(256), 0, s->stream, (const float*)cur.A,
+                           (const float*)cur.P, cur.A0, cur.P0, s->d_sp, s->d_obs);
+    else
+        hipLaunchKernelGGL(k_observables<double>, dim3(s->S), dim3(256), 0, s->stream, (const double*)cur.A,
+                           (const double*)cur.P, cur.A0, cur.P0, s->d_sp, s->d_obs);
+    HIP_TRY(hipGetLastError());
+    h.resize(3 * s->S);
+    HIP_TRY(hipMemcpyAsync(h.data(), s->d_obs, 3 * s->S * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    return read_state(s);
 }
 
 spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA, int64_t* counters)
 {
     if (!s) return fail(SPV_EINVAL, "bad handle");
-    const int nb = 1024;
-    hipLaunchKernelGGL(k_obs_partial, dim3(nb), dim3(256), 0, s->stream, s->v, s->prm.KA, s->prm.KP, s->d_part);
-    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(256), 0, s->stream, s->d_part, nb, s->d_obs);
-    HIP_TRY(hipGetLastError());
-    double h[3];
-    HIP_TRY(hipMemcpyAsync(h, s->d_obs, sizeof h, hipMemcpyDeviceToHost, s->stream));
-    ST_TRY(read_counters(s));
-    if (E) *E = h[0];
-    if (qbar) *qbar = h[1] / s->N;
-    if (sumA) *sumA = h[2];
-    if (counters) {
-        const DevCounters& c = *s->h_cnt;
-        counters[0] = (int64_t)s->step;
-        counters[1] = c.repaired;
-        counters[2] = s->rounds;
-        counters[3] = c.exact_calls;
-        counters[4] = c.max_deg;
-        counters[5] = s->resorts;
-        counters[6] = c.retries;
-        counters[7] = (int64_t)(c.err | s->err_word);
+    std::vector<double> h;
+    ST_TRY(observables_all(s, h));
+    double e = 0, q = 0, a = 0;
+    for (int k = 0; k < s->S; k++) {
+        e += h[3 * k];
+        q += h[3 * k + 1];
+        a += h[3 * k + 2];
     }
+    if (E) *E = e;
+    if (qbar) *qbar = q / s->N;
+    if (sumA) *sumA = a;
+    if (counters) {
+        const DevState& d = *s->h_st;
+        counters[0] = (int64_t)s->step;
+        counters[1] = (int64_t)d.repaired;
+        counters[2] = (int64_t)d.rounds;
+        counters[3] = (int64_t)d.exact_calls;
+        counters[4] = d.max_deg;
+        counters[5] = s->resorts;
+        counters[6] = (int64_t)d.retries;
+        counters[7] = (int64_t)d.err;
+    }
+    return SPV_OK;
+}
+
+spv_status spv_get_system_observables(spv_sys* s, int32_t sys, double* E, double* qbar, double* sumA)
+{
+    if (!s || sys < 0 || sys >= s->S) return fail(SPV_EINVAL, "bad handle or system index");
+    std::vector<double> h;
+    ST_TRY(observables_all(s, h));
+    if (E) *E = h[3 * sys];
+    if (qbar) *qbar = h[3 * sys + 1] / s->hsp[sys].n;
+    if (sumA) *sumA = h[3 * sys + 2];
     return SPV_OK;
 }
 
@@ -671,7 +989,7 @@ spv_status spv_set_timing(spv_sys* s, int32_t enable)
 {
     if (!s) return fail(SPV_EINVAL, "bad handle");
     HIP_TRY(hipStreamSynchronize(s->stream));
-    collect_timing(s);
+    collect_eager_timing(s);
     s->timing = enable != 0;
     for (int k = 0; k < T_COUNT; k++) {
         s->t_ms[k] = 0.0;
@@ -684,7 +1002,7 @@ spv_status spv_kernel_time(spv_sys* s, int32_t which, double* total_ms, int64_t*
 {
     if (!s || which < 0 || which >= T_COUNT) return fail(SPV_EINVAL, "bad argument");
     HIP_TRY(hipStreamSynchronize(s->stream));
-    collect_timing(s);
+    collect_eager_timing(s);
     if (total_ms) *total_ms = s->t_ms[which];
     if (launches) *launches = s->t_n[which];
     return SPV_OK;

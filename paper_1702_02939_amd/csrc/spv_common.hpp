@@ -1,4 +1,4 @@
-// spv_common.hpp -- device state view, small device helpers, Philox noise.
+// spv_common.hpp -- device data structures, small helpers, Philox noise.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -7,61 +7,80 @@ namespace spv {
 
 // error-word bits (device -> host)
 enum : unsigned {
-    ERR_PRECOND = 1u,    // a Delaunay circumradius reached min(Lx, Ly)/4, or search radius >= L/2
-    ERR_CAPACITY = 2u,   // ring degree above kcap or too many repair candidates
+    ERR_PRECOND = 1u,    // a Delaunay circumradius reached min(Lx, Ly)/4 (search disk would exceed L/2)
+    ERR_CAPACITY = 2u,   // ring longer than kcap or too many repair candidates
     ERR_NONFINITE = 4u,  // non-finite force or position
     ERR_REPAIR = 8u,     // a ring could not be rebuilt
     ERR_DEGREE = 16u,    // ring with fewer than 3 members
 };
 
-// counters read back by the host once per repair round
-struct DevCounters {
-    int fail_count;          // cells flagged by the validity test
-    int wl_count;            // repair worklist size
-    int touched_count;       // cells whose neighbourhood changed
-    unsigned err;            // error word
-    unsigned long long disp_bits;  // max |displacement| of the last update (bits of a non-negative double)
-    int exact_calls;         // exact-arithmetic fallbacks of the in-circle filter
-    int max_deg;             // largest ring written by the repair
-    int repaired;            // cells rebuilt
-    int retries;             // repair radius enlargements
+constexpr int MAX_ROUNDS = 32;  // repair rounds per step (device rounds + host recovery rounds)
+
+// Per-system constants (a batch holds several independent systems laid out
+// one after the other; a single system is a batch of one).
+struct SysParam {
+    double Lx, Ly, hLx, hLy;  // box (on the grid) and half box
+    double scale, inv_scale;  // 2^q and 2^-q
+    double LXu, LYu;          // box in grid units (exact doubles)
+    double bsx, bsy;          // bin sides
+    double R0;                // first repair search radius
+    double mu, v0, dt, amp;   // Eq. 3 and the noise amplitude sqrt(2 Dr dt)
+    double KA, KP;            // Eq. 1 moduli
+    uint64_t seed;            // Philox key
+    int nbx, nby;             // bins per side
+    int bin_off;              // first global bin of this system
+    int cell_off, n;          // cells [cell_off, cell_off + n)
+    int pad;
+};
+
+// Device-side control block of one batch.
+struct DevState {
+    int wl_count[MAX_ROUNDS + 1];  // size of the repair worklist of round r (list r & 1)
+    int tl_count[MAX_ROUNDS];      // size of the touched list of round r (list r & 1)
+    unsigned err;                  // error word
+    int halt;                      // a step did not converge on the device: later kernels do nothing
+    int halt_round;                // first round whose worklist is still pending
+    int pad0;
+    unsigned long long disp_bits;  // max |displacement| of the current step (bits of a non-negative double)
+    double drift;                  // sum of per-step max displacements since the last re-sort
+    unsigned long long step;       // completed steps (noise counter of the next step)
+    // statistics
+    unsigned long long repaired, exact_calls, retries, rounds;
+    int max_deg;
     // first repair failure (diagnostics for the error message)
-    int fail_cell, fail_n, fail_k, fail_closed, fail_attempts, fail_set;
+    int fail_set, fail_cell, fail_n, fail_k, fail_closed, fail_attempts;
     double fail_R, fail_umax;
 };
 
-// Everything a kernel needs about one system; passed by value.
-struct View {
-    int N;
-    int kcap;
-    double Lx, Ly, hLx, hLy;  // box and half box
-    double scale, inv_scale;  // 2^q and 2^-q
-    double LXu, LYu;          // box in grid units (exact doubles)
-    // per-cell state, current buffers
+// Per-cell arrays of one configuration (the library keeps two and swaps them
+// at every re-sort; x, y, theta additionally alternate at every step).
+template <typename R>
+struct Cells {
     double* x;
     double* y;
     double* th;
-    int* tag;
+    int* tag;    // index of the cell inside its system
+    int* sys;    // system of the cell
     double* A0;
     double* P0;
     uint8_t* deg;
-    int* ring;  // [kcap][N]
-    int* opp;   // [kcap][N]
-    double* A;
-    double* P;
-    double* ca;  // 2 K_A (A - A0)
-    double* cb;  // 2 K_P (P - P0)
-    // scratch
-    uint8_t* flag;
-    uint8_t* touched;
-    int* worklist;
-    int* list2;
-    DevCounters* cnt;
-    // bins (cells are stored in bin order of the last re-sort)
-    int nbx, nby;
-    double bsx, bsy;          // bin sides
-    const int* bin_rank;      // spatial bin -> position along the Hilbert curve
-    const int* bin_start;     // [nbins + 1], indexed by Hilbert position
+    int* ring;   // [N][kcap], counter-clockwise, starting at the smallest tag
+    int* opp;    // [N][kcap], third vertex across edge (ring[m], ring[m+1])
+    R* A;
+    R* P;
+    R* ca;       // 2 K_A (A - A0)
+    R* cb;       // 2 K_P (P - P0)
+};
+
+// Work lists and bitmaps shared by both configurations.
+struct Work {
+    unsigned* flagbits;   // cell is in the pending repair worklist
+    unsigned* touchbits;  // cell is in the pending touched list
+    int* wl[2];
+    int* tl[2];
+    // bins (cells are stored in the order of their global bin at the last re-sort)
+    const int* bin_key;    // [sum of bins] spatial bin of a system -> global key
+    const int* bin_start;  // [total bins + 1]
 };
 
 __device__ __forceinline__ double mimg(double d, double L, double hL)

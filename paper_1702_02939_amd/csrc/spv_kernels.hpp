@@ -6,37 +6,51 @@
 //                  director turns by sqrt(2 Dr dt) xi (Sec. II.A);
 //   geometry+test  Voronoi area / perimeter of every cell (Sec. II.C.1) fused
 //                  with the empty-circumcircle test of its ring (Sec. II.C.3);
-//   repair         flagged rings rebuilt on the device from the candidate
+//   repair rounds  flagged rings rebuilt on the device from the candidate
 //                  neighbours inside a search disk (locality lemma, Sec.
-//                  II.C.4), by exact gift-wrapping around the cell.
-// Layout: structure of arrays, one thread per cell for the streaming passes,
-// one 64-lane wavefront per cell for the repair; neighbour rings are
-// slot-major int32 [kcap][N] so that slot m of 64 consecutive cells is one
-// coalesced load.
+//                  II.C.4) by exact gift-wrapping, then the touched cells get
+//                  their opposite vertices rebuilt and are re-tested; repeated
+//                  until no flag is raised (cf. the repeat-until-no-change rule
+//                  of Sec. II.D).
+// Streaming passes use GL = 8 lanes per cell: lane l handles ring slots
+// l, l + 8, ...; per-slot values (displacements, Voronoi vertices, unit edge
+// vectors, neighbour coefficients) are staged in LDS so that a slot can read
+// its ring neighbours m +- 1 for any ring length.  Rings are cell-major
+// [N][KC]; a cell's 8 lanes read one contiguous 32-byte row segment.
+// Every kernel first checks the device halt flag, so that a step whose
+// repair did not converge turns the rest of a captured graph into no-ops.
 #pragma once
 #include "spv_common.hpp"
 #include "spv_exact.hpp"
 
 namespace spv {
 
-constexpr int RP_CAP = 1024;  // max candidate neighbours of one repaired cell
-constexpr int RP_KMAX = 64;   // max ring length during the gift wrap
+constexpr int GL = 8;          // lanes per cell in the streaming kernels
+constexpr int CPB = 256 / GL;  // cells per 256-thread block
+constexpr int RP_CAP = 1024;   // max candidate neighbours of one repaired cell
 
-struct StepParams {
-    double mu, v0, dt, amp;  // amp = sqrt(2 Dr dt)
-    double KA, KP;
-    uint64_t seed, step;
-};
+// ---------------------------------------------------------------- helpers
 
-// ---------------------------------------------------------------- small helpers
-
-__device__ __forceinline__ void circumcentre(double bx, double by, double cx, double cy, double s, double& ux,
-                                             double& uy)
+template <typename R>
+__device__ __forceinline__ void circumcentre(R bx, R by, R cx, R cy, R& ux, R& uy)
 {
-    double nb = bx * bx + by * by, nc = cx * cx + cy * cy;
-    double inv = 0.5 / s;
+    const R nb = bx * bx + by * by, nc = cx * cx + cy * cy;
+    const R inv = R(0.5) / (bx * cy - by * cx);
     ux = (cy * nb - by * nc) * inv;
     uy = (bx * nc - cx * nb) * inv;
+}
+
+template <typename R>
+__device__ __forceinline__ void unit(R ex, R ey, R& tx, R& ty)
+{
+    const R l2 = ex * ex + ey * ey;
+    if (l2 > R(0)) {
+        const R r = R(1) / sqrt(l2);
+        tx = ex * r;
+        ty = ey * r;
+    } else {  // zero-length Voronoi edge (exact T1 configuration)
+        tx = ty = R(0);
+    }
 }
 
 // In-circle with lazily loaded tags (the tie-break almost never runs).
@@ -44,56 +58,222 @@ __device__ __forceinline__ int incircle_tags(double bx, double by, double cx, do
                                              const int* tag, int gi, int gb, int gc, int gp, double scale,
                                              int* exact_count)
 {
-    double nb = bx * bx + by * by, nc = cx * cx + cy * cy, np = px * px + py * py;
-    double t1 = cx * py, t2 = cy * px, t3 = px * by, t4 = py * bx, t5 = bx * cy, t6 = by * cx;
-    double det = nb * (t1 - t2) + nc * (t3 - t4) + np * (t5 - t6);
-    double perm = nb * (fabs(t1) + fabs(t2)) + nc * (fabs(t3) + fabs(t4)) + np * (fabs(t5) + fabs(t6));
-    double bound = 2.0e-15 * perm;
+    const double nb = bx * bx + by * by, nc = cx * cx + cy * cy, np = px * px + py * py;
+    const double t1 = cx * py, t2 = cy * px, t3 = px * by, t4 = py * bx, t5 = bx * cy, t6 = by * cx;
+    const double det = nb * (t1 - t2) + nc * (t3 - t4) + np * (t5 - t6);
+    const double perm = nb * (fabs(t1) + fabs(t2)) + nc * (fabs(t3) + fabs(t4)) + np * (fabs(t5) + fabs(t6));
+    const double bound = 2.0e-15 * perm;
     if (det > bound) return -1;
     if (det < -bound) return 1;
     return incircle_sos(bx, by, cx, cy, px, py, tag[gi], tag[gb], tag[gc], tag[gp], scale, exact_count);
 }
 
-__device__ __forceinline__ void flag_cell(const View& v, int c) { v.flag[c] = 1; }
-
-// ---------------------------------------------------------------- initial directors
-__global__ void k_theta0(double* th, const int* tag, int n, uint64_t seed)
+// append c to the repair worklist of round r (once per round)
+__device__ __forceinline__ void push_flag(const Work& w, DevState* st, int r, int c)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t r[4];
-    philox4x64(~0ull, (uint64_t)tag[i], 0, 0, seed, 0, r);
-    th[i] = 2.0 * 3.14159265358979323846 * u01(r[0]);
-}
-
-__global__ void k_iota(int* a, int n)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = i;
-}
-
-__global__ void k_fill_u8(uint8_t* a, int n, uint8_t val)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = val;
-}
-
-__global__ void k_fill_i32(int* a, int n, int val)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) a[i] = val;
-}
-
-// counters: mode 0 = step start, 1 = repair round start, 2 = worklist preset to n
-__global__ void k_reset(DevCounters* c, int mode, int n)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    c->fail_count = 0;
-    if (mode == 0) c->disp_bits = 0ull;
-    if (mode >= 1) {
-        c->wl_count = (mode == 2) ? n : 0;
-        c->touched_count = 0;
+    const unsigned bit = 1u << (c & 31);
+    if (!(atomicOr(&w.flagbits[c >> 5], bit) & bit)) {
+        const int slot = atomicAdd(&st->wl_count[r], 1);
+        w.wl[r & 1][slot] = c;
     }
+}
+
+// append c to the touched list of round r (once per round)
+__device__ __forceinline__ void push_touch(const Work& w, DevState* st, int r, int c)
+{
+    const unsigned bit = 1u << (c & 31);
+    if (!(atomicOr(&w.touchbits[c >> 5], bit) & bit)) {
+        const int slot = atomicAdd(&st->tl_count[r], 1);
+        w.tl[r & 1][slot] = c;
+    }
+}
+
+// XCD-aware block order: the 8 XCDs receive consecutive workgroups in turn;
+// remap so that each XCD works on one contiguous range of cells (neighbour
+// gathers then hit that XCD's L2).  The grid is padded to a multiple of 8.
+__device__ __forceinline__ int xcd_block(int b, int grid)
+{
+    const int per = grid >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------- force (+ update)
+// Vertex h_m (circumcentre of i, j_m, j_{m+1}, frame of i) is shared by cells
+// i, j_m, j_{m+1}; its neighbours in those polygons are h_{m-1}, h_{m+1} and
+// h'_m = circumcentre(j_m, opp_m, j_{m+1}).  With unit edge vectors
+//   t1 = (h_m - h_{m-1})/|.|, t2 = (h_{m+1} - h_m)/|.|, t3 = (h'_m - h_m)/|.|
+// the vertex gradient of E (App. A; perimeter term incoming minus outgoing) is
+//   g_m = a_i dA_i + b_i (t1 - t2) + a_jm dA_jm + b_jm (t1 - t3)
+//       + a_jn dA_jn + b_jn (-t2 - t3),
+// dA_c = 1/2 (h+_y - h-_y, h-_x - h+_x) for the CCW neighbours (h-, h+) of h_m
+// in cell c, and F_i = -sum_m J_m^T g_m with the circumcentre Jacobian of
+// App. B (Eq. B4), read with s = b x c in the denominator and its gradient.
+template <typename R, bool MULTI, int KC, bool UPDATE>
+__global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
+                                               double* __restrict__ tho, double* __restrict__ fxo,
+                                               double* __restrict__ fyo, const SysParam* __restrict__ sp,
+                                               DevState* st, int N)
+{
+    constexpr int NS = KC / GL;
+    __shared__ R sD[CPB][KC][2];  // displacement of ring cell m
+    __shared__ R sH[CPB][KC][2];  // Voronoi vertex m
+    __shared__ R sE[CPB][KC][2];  // unit edge vector h_m -> h_{m+1}
+    __shared__ R sC[CPB][KC][2];  // (a, b) of ring cell m
+    if (st->halt) return;
+    const int g = threadIdx.x / GL, l = threadIdx.x % GL;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * CPB + g;
+    const bool valid = i < N;
+    const int ii = valid ? i : 0;
+    const SysParam& P = sp[MULTI ? c.sys[ii] : 0];
+    int k = valid ? c.deg[ii] : 0;
+    if (k < 3 || k > KC) k = 0;  // reported by the validity test
+    const double xi = c.x[ii], yi = c.y[ii];
+    const R* __restrict__ ca = c.ca;
+    const R* __restrict__ cb = c.cb;
+
+    double dmx[NS], dmy[NS], odx[NS], ody[NS];
+    bool hasopp[NS];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int m = l + s * GL;
+        dmx[s] = dmy[s] = odx[s] = ody[s] = 0.0;
+        hasopp[s] = false;
+        if (m < k) {
+            const int j = c.ring[ii * KC + m];
+            dmx[s] = mimg(c.x[j] - xi, P.Lx, P.hLx);
+            dmy[s] = mimg(c.y[j] - yi, P.Ly, P.hLy);
+            sD[g][m][0] = (R)dmx[s];
+            sD[g][m][1] = (R)dmy[s];
+            sC[g][m][0] = ca[j];
+            sC[g][m][1] = cb[j];
+            const int o = c.opp[ii * KC + m];
+            if (o >= 0) {
+                hasopp[s] = true;
+                odx[s] = mimg(c.x[o] - xi, P.Lx, P.hLx);
+                ody[s] = mimg(c.y[o] - yi, P.Ly, P.hLy);
+            }
+        }
+    }
+    __syncthreads();
+    R hqx[NS], hqy[NS];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int m = l + s * GL;
+        hqx[s] = hqy[s] = R(0);
+        if (m < k) {
+            const int mn = (m + 1 == k) ? 0 : m + 1;
+            const R bx = sD[g][m][0], by = sD[g][m][1], cx = sD[g][mn][0], cy = sD[g][mn][1];
+            R hx, hy;
+            circumcentre(bx, by, cx, cy, hx, hy);
+            sH[g][m][0] = hx;
+            sH[g][m][1] = hy;
+            hqx[s] = hx;
+            hqy[s] = hy;
+            if (hasopp[s]) {
+                // third vertex of edge (j_m, j_{m+1}): circumcentre of (j_m, opp_m, j_{m+1})
+                const R ex = (R)(odx[s] - dmx[s]), ey = (R)(ody[s] - dmy[s]);
+                R qx, qy;
+                circumcentre(ex, ey, cx - bx, cy - by, qx, qy);
+                hqx[s] = qx + bx;
+                hqy[s] = qy + by;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int m = l + s * GL;
+        if (m < k) {
+            const int mn = (m + 1 == k) ? 0 : m + 1;
+            R tx, ty;
+            unit(sH[g][mn][0] - sH[g][m][0], sH[g][mn][1] - sH[g][m][1], tx, ty);
+            sE[g][m][0] = tx;
+            sE[g][m][1] = ty;
+        }
+    }
+    __syncthreads();
+    R fx = R(0), fy = R(0);
+    const R ai = valid ? ca[ii] : R(0), bi = valid ? cb[ii] : R(0);
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int m = l + s * GL;
+        if (m < k) {
+            const int mn = (m + 1 == k) ? 0 : m + 1, mp = (m == 0) ? k - 1 : m - 1;
+            const R hpx = sH[g][mp][0], hpy = sH[g][mp][1];
+            const R hcx = sH[g][m][0], hcy = sH[g][m][1];
+            const R hnx = sH[g][mn][0], hny = sH[g][mn][1];
+            const R t1x = sE[g][mp][0], t1y = sE[g][mp][1];
+            const R t2x = sE[g][m][0], t2y = sE[g][m][1];
+            R t3x, t3y;
+            unit(hqx[s] - hcx, hqy[s] - hcy, t3x, t3y);
+            const R am = sC[g][m][0], bm = sC[g][m][1], an = sC[g][mn][0], bn = sC[g][mn][1];
+            const R qx = hqx[s], qy = hqy[s];
+            R gx = ai * R(0.5) * (hny - hpy) + bi * (t1x - t2x);
+            R gy = ai * R(0.5) * (hpx - hnx) + bi * (t1y - t2y);
+            gx += am * R(0.5) * (hpy - qy) + bm * (t1x - t3x);
+            gy += am * R(0.5) * (qx - hpx) + bm * (t1y - t3y);
+            gx += an * R(0.5) * (qy - hny) + bn * (-t2x - t3x);
+            gy += an * R(0.5) * (hnx - qx) + bn * (-t2y - t3y);
+            // J_m^T g, b = d_m, c = d_{m+1}, e = c - b
+            const R Bx = sD[g][m][0], By = sD[g][m][1], Cx = sD[g][mn][0], Cy = sD[g][mn][1];
+            const R ex = Cx - Bx, ey = Cy - By;
+            const R sc = Bx * Cy - By * Cx;
+            const R be = Bx * ex + By * ey, ce = Cx * ex + Cy * ey;
+            const R nb = Bx * Bx + By * By, nc = Cx * Cx + Cy * Cy;
+            const R betaD = -nc * be, gammaD = nb * ce;
+            const R zx = betaD * Bx + gammaD * Cx, zy = betaD * By + gammaD * Cy;
+            const R gbx = R(2) * be * Cx + nc * ex, gby = R(2) * be * Cy + nc * ey;    // grad(beta D)
+            const R ggx = R(-2) * ce * Bx - nb * ex, ggy = R(-2) * ce * By - nb * ey;  // grad(gamma D)
+            const R is = R(1) / sc;
+            const R gdx = R(2) * is * (-ey), gdy = R(2) * is * ex;                     // grad(D) / D
+            const R invD = R(0.5) * is * is;                                           // 1 / (2 s^2)
+            const R gB = gx * Bx + gy * By, gC = gx * Cx + gy * Cy, gZ = gx * zx + gy * zy;
+            fx -= gx + invD * (gB * gbx + gC * ggx - (betaD + gammaD) * gx - gZ * gdx);
+            fy -= gy + invD * (gB * gby + gC * ggy - (betaD + gammaD) * gy - gZ * gdy);
+        }
+    }
+#pragma unroll
+    for (int off = GL / 2; off > 0; off >>= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+    }
+    if (!UPDATE) {
+        if (valid && l == 0) {
+            fxo[i] = (double)fx;
+            fyo[i] = (double)fy;
+        }
+        return;
+    }
+    double disp = 0.0;
+    if (valid && l == 0) {
+        const double th = c.th[i];
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        const double xn = xi + P.dt * (P.mu * (double)fx + P.v0 * cs);
+        const double yn = yi + P.dt * (P.mu * (double)fy + P.v0 * sn);
+        double X = rint(xn * P.scale), Y = rint(yn * P.scale);
+        if (X < 0.0) X += P.LXu;
+        else if (X >= P.LXu) X -= P.LXu;
+        if (Y < 0.0) Y += P.LYu;
+        else if (Y >= P.LYu) Y -= P.LYu;
+        if (!(X >= 0.0 && X < P.LXu && Y >= 0.0 && Y < P.LYu)) {
+            atomicOr(&st->err, ERR_NONFINITE);
+            X = rint(xi * P.scale);  // keep the stored state finite and inside the box
+            Y = rint(yi * P.scale);
+        }
+        const double xq = X * P.inv_scale, yq = Y * P.inv_scale;
+        xo[i] = xq;
+        yo[i] = yq;
+        tho[i] = th + P.amp * normal_for(P.seed, st->step, (uint64_t)c.tag[i]);
+        const double ddx = mimg(xq - xi, P.Lx, P.hLx), ddy = mimg(yq - yi, P.Ly, P.hLy);
+        disp = sqrt(ddx * ddx + ddy * ddy);
+    }
+    unsigned long long b = __double_as_longlong(disp);
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long o = __shfl_xor(b, off);
+        b = o > b ? o : b;
+    }
+    if ((threadIdx.x & 63) == 0 && b) atomicMax(&st->disp_bits, b);
 }
 
 // ---------------------------------------------------------------- geometry + validity test
@@ -102,388 +282,201 @@ __global__ void k_reset(DevCounters* c, int mode, int n)
 //   A_i = 1/2 sum u_m x u_{m+1},  P_i = sum |u_{m+1} - u_m|
 // and the ring is valid when every (i, j_m, j_{m+1}) is counter-clockwise and
 // the cell opp_m across edge (j_m, j_{m+1}) is not strictly inside its
-// circumcircle (local Delaunay property of every edge).
-__device__ __forceinline__ void geom_test_cell(const View& v, int i, double KA, double KP, int* exact)
+// circumcircle (local Delaunay property of every edge).  The predicates use
+// the exact FP64 displacements whatever R is.
+// LIST: process the touched list of round `round` (clearing its bits) and
+// push failures to round + 1; otherwise all cells, failures to round 0.
+// OPP: rebuild opp first -- in the CCW ring of j_m the pattern
+// ..., opp_m, j_{m+1}, i, ... must appear; otherwise the rings disagree and
+// the cells are flagged.
+template <typename R, bool MULTI, int KC, bool LIST, bool OPP>
+__global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
+                                              int N, int round)
 {
-    const int N = v.N;
-    const double xi = v.x[i], yi = v.y[i];
-    const int k = v.deg[i];
-    if (k < 3) {
-        atomicOr(&v.cnt->err, ERR_DEGREE);
-        return;
-    }
-    const int j0 = v.ring[i];
-    const double b0x = mimg(v.x[j0] - xi, v.Lx, v.hLx), b0y = mimg(v.y[j0] - yi, v.Ly, v.hLy);
-    int jm = j0;
-    double bx = b0x, by = b0y;
-    double a2 = 0.0, per = 0.0, u0x = 0.0, u0y = 0.0, upx = 0.0, upy = 0.0;
-    const double rlim2 = 0.0625 * fmin(v.Lx, v.Ly) * fmin(v.Lx, v.Ly);
-    bool any_fail = false;
-    for (int m = 0; m < k; m++) {
-        int jn;
-        double cx, cy;
-        if (m + 1 < k) {
-            jn = v.ring[(m + 1) * N + i];
-            cx = mimg(v.x[jn] - xi, v.Lx, v.hLx);
-            cy = mimg(v.y[jn] - yi, v.Ly, v.hLy);
-        } else {
-            jn = j0;
-            cx = b0x;
-            cy = b0y;
-        }
-        const double s = bx * cy - by * cx;
-        double ux, uy;
-        circumcentre(bx, by, cx, cy, s, ux, uy);
-        const int o = v.opp[m * N + i];
-        bool fail = cross_sign(bx, by, cx, cy, s, v.scale) <= 0;
-        if (!fail) {
-            if (o < 0) {
-                fail = true;
-            } else {
-                double px = mimg(v.x[o] - xi, v.Lx, v.hLx), py = mimg(v.y[o] - yi, v.Ly, v.hLy);
-                fail = incircle_tags(bx, by, cx, cy, px, py, v.tag, i, jm, jn, o, v.scale, exact) > 0;
-            }
-            // a circumradius >= min(L)/4 is either a non-Delaunay triangle that
-            // another cell's test will catch, or a true violation of the box
-            // precondition; the repair tells them apart (it cannot certify a
-            // disk wider than L/2 and then reports the precondition)
-            if (!fail && ux * ux + uy * uy >= rlim2) fail = true;
-        }
-        if (fail) {
-            any_fail = true;
-            flag_cell(v, i);
-            flag_cell(v, jm);
-            flag_cell(v, jn);
-            if (o >= 0) flag_cell(v, o);
-        }
-        if (m == 0) {
-            u0x = ux;
-            u0y = uy;
-        } else {
-            a2 += upx * uy - upy * ux;
-            per += sqrt((ux - upx) * (ux - upx) + (uy - upy) * (uy - upy));
-        }
-        upx = ux;
-        upy = uy;
-        jm = jn;
-        bx = cx;
-        by = cy;
-    }
-    a2 += upx * u0y - upy * u0x;
-    per += sqrt((u0x - upx) * (u0x - upx) + (u0y - upy) * (u0y - upy));
-    const double A = 0.5 * a2;
-    v.A[i] = A;
-    v.P[i] = per;
-    v.ca[i] = 2.0 * KA * (A - v.A0[i]);
-    v.cb[i] = 2.0 * KP * (per - v.P0[i]);
-    if (any_fail) atomicAdd(&v.cnt->fail_count, 1);
-}
-
-template <bool LIST>
-__global__ __launch_bounds__(256) void k_geom_test(View v, double KA, double KP)
-{
-    const int n = LIST ? v.cnt->touched_count : v.N;
+    constexpr int NS = KC / GL;
+    __shared__ double sD[CPB][KC][2];
+    __shared__ R sU[CPB][KC][2];
+    __shared__ int sJ[CPB][KC];
+    if (st->halt) return;
+    const int g = threadIdx.x / GL, l = threadIdx.x % GL;
+    const int n = LIST ? st->tl_count[round] : N;
+    const int rnext = LIST ? round + 1 : 0;
+    const int* __restrict__ list = w.tl[round & 1];
+    const int bstart = LIST ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
     int exact = 0;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        const int i = LIST ? v.list2[t] : t;
-        geom_test_cell(v, i, KA, KP, &exact);
-    }
-    if (exact) atomicAdd(&v.cnt->exact_calls, exact);
-}
-
-// ---------------------------------------------------------------- force (+ update)
-// Vertex h_m = r_i + u(d_m, d_{m+1}) is shared by cells i, j_m, j_{m+1}; its
-// neighbours in the three polygons are h_{m-1}, h_{m+1} and h'_m, the
-// circumcentre of (j_m, opp_m, j_{m+1}).  With unit edge vectors
-//   t1 = (h_m - h_{m-1})/|.|, t2 = (h_{m+1} - h_m)/|.|, t3 = (h'_m - h_m)/|.|
-// the vertex gradient of E (App. A, perimeter term with the incoming-minus-
-// outgoing sign) is
-//   g_m = a_i dA_i + b_i (t1 - t2) + a_jm dA_jm + b_jm (t1 - t3)
-//       + a_jn dA_jn + b_jn (-t2 - t3),
-// dA_c = 1/2 (h+_y - h-_y, h-_x - h+_x) for the CCW neighbours (h-, h+) of h_m
-// in cell c, and F_i = -sum_m J_m^T g_m with the circumcentre Jacobian of
-// App. B (Eq. B4).
-__device__ __forceinline__ void unit(double ex, double ey, double& tx, double& ty)
-{
-    double l2 = ex * ex + ey * ey;
-    if (l2 > 0.0) {
-        double r = 1.0 / sqrt(l2);
-        tx = ex * r;
-        ty = ey * r;
-    } else {
-        tx = ty = 0.0;
-    }
-}
-
-__device__ __forceinline__ void force_cell(const View& v, int i, double& Fx, double& Fy)
-{
-    const int N = v.N;
-    const double xi = v.x[i], yi = v.y[i];
-    const int k = v.deg[i];
-    Fx = Fy = 0.0;
-    if (k < 3) return;  // reported by the validity test
-    const int jl = v.ring[(k - 1) * N + i];
-    const int j0 = v.ring[i];
-    const int j1 = v.ring[N + i];
-    const double dlx = mimg(v.x[jl] - xi, v.Lx, v.hLx), dly = mimg(v.y[jl] - yi, v.Ly, v.hLy);
-    const double d0x = mimg(v.x[j0] - xi, v.Lx, v.hLx), d0y = mimg(v.y[j0] - yi, v.Ly, v.hLy);
-    const double d1x = mimg(v.x[j1] - xi, v.Lx, v.hLx), d1y = mimg(v.y[j1] - yi, v.Ly, v.hLy);
-    double hlx, hly, h0x, h0y;
-    circumcentre(dlx, dly, d0x, d0y, dlx * d0y - dly * d0x, hlx, hly);
-    circumcentre(d0x, d0y, d1x, d1y, d0x * d1y - d0y * d1x, h0x, h0y);
-    const double ai = v.ca[i], bi = v.cb[i];
-    const double a0 = v.ca[j0], b0 = v.cb[j0];
-    const double a1 = v.ca[j1], b1 = v.cb[j1];
-
-    double hpx = hlx, hpy = hly;   // h_{m-1}
-    double hcx = h0x, hcy = h0y;   // h_m
-    double dmx = d0x, dmy = d0y;   // d_m
-    double dnx = d1x, dny = d1y;   // d_{m+1}
-    double am = a0, bm = b0, an = a1, bn = b1;
-    double t1x, t1y;
-    unit(hcx - hpx, hcy - hpy, t1x, t1y);
-    double fx = 0.0, fy = 0.0;
-    for (int m = 0; m < k; m++) {
-        double hnx, hny, dnnx = 0.0, dnny = 0.0, ann = 0.0, bnn = 0.0;
-        if (m == k - 1) {
-            hnx = h0x;
-            hny = h0y;
-        } else if (m == k - 2) {
-            hnx = hlx;
-            hny = hly;
-            dnnx = d0x;
-            dnny = d0y;
-            ann = a0;
-            bnn = b0;
-        } else {
-            const int jnn = v.ring[(m + 2) * N + i];
-            dnnx = mimg(v.x[jnn] - xi, v.Lx, v.hLx);
-            dnny = mimg(v.y[jnn] - yi, v.Ly, v.hLy);
-            ann = v.ca[jnn];
-            bnn = v.cb[jnn];
-            circumcentre(dnx, dny, dnnx, dnny, dnx * dnny - dny * dnnx, hnx, hny);
+    for (int base = bstart * CPB; base < n; base += gridDim.x * CPB) {
+        const int t = base + g;
+        const bool valid = t < n;
+        const int i = valid ? (LIST ? list[t] : t) : 0;
+        if (LIST && valid && l == 0) atomicAnd(&w.touchbits[i >> 5], ~(1u << (i & 31)));
+        const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+        int k = valid ? c.deg[i] : 0;
+        if (valid && (k < 3 || k > KC)) {
+            if (l == 0) atomicOr(&st->err, ERR_DEGREE);
+            k = 0;
         }
-        // third vertex h'_m of edge (j_m, j_{m+1}): circumcentre of (j_m, opp_m, j_{m+1})
-        const int o = v.opp[m * N + i];
-        double qx = hcx, qy = hcy;  // a missing opp (inconsistent ring) is reported by the test
-        if (o >= 0) {
-            const double dox = mimg(v.x[o] - xi, v.Lx, v.hLx), doy = mimg(v.y[o] - yi, v.Ly, v.hLy);
-            const double ex = dox - dmx, ey = doy - dmy, fx2 = dnx - dmx, fy2 = dny - dmy;
-            circumcentre(ex, ey, fx2, fy2, ex * fy2 - ey * fx2, qx, qy);
-            qx += dmx;
-            qy += dmy;
+        const double xi = c.x[i], yi = c.y[i];
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const int m = l + s * GL;
+            if (m < k) {
+                const int j = c.ring[i * KC + m];
+                sJ[g][m] = j;
+                sD[g][m][0] = mimg(c.x[j] - xi, P.Lx, P.hLx);
+                sD[g][m][1] = mimg(c.y[j] - yi, P.Ly, P.hLy);
+            }
         }
-        double t2x, t2y, t3x, t3y;
-        unit(hnx - hcx, hny - hcy, t2x, t2y);
-        unit(qx - hcx, qy - hcy, t3x, t3y);
-        double gx = ai * 0.5 * (hny - hpy) + bi * (t1x - t2x);
-        double gy = ai * 0.5 * (hpx - hnx) + bi * (t1y - t2y);
-        gx += am * 0.5 * (hpy - qy) + bm * (t1x - t3x);
-        gy += am * 0.5 * (qx - hpx) + bm * (t1y - t3y);
-        gx += an * 0.5 * (qy - hny) + bn * (-t2x - t3x);
-        gy += an * 0.5 * (hnx - qx) + bn * (-t2y - t3y);
-
-        // J_m^T g with b = d_m, c = d_{m+1}, e = c - b (App. B, with the
-        // cross product s = b x c in both the denominator and its gradient)
-        {
-            const double Bx = dmx, By = dmy, Cx = dnx, Cy = dny;
-            const double ex = Cx - Bx, ey = Cy - By;
-            const double s = Bx * Cy - By * Cx;
-            const double D = 2.0 * s * s;
-            const double be = Bx * ex + By * ey, ce = Cx * ex + Cy * ey;
-            const double nb = Bx * Bx + By * By, nc = Cx * Cx + Cy * Cy;
-            const double betaD = -nc * be, gammaD = nb * ce;
-            const double zx = betaD * Bx + gammaD * Cx, zy = betaD * By + gammaD * Cy;
-            const double gbx = 2.0 * be * Cx + nc * ex, gby = 2.0 * be * Cy + nc * ey;        // grad(beta D)
-            const double ggx = -2.0 * ce * Bx - nb * ex, ggy = -2.0 * ce * By - nb * ey;      // grad(gamma D)
-            const double gdx = (2.0 / s) * (-ey), gdy = (2.0 / s) * ex;                      // grad(D)/D
-            const double invD = 1.0 / D;
-            const double gB = gx * Bx + gy * By, gC = gx * Cx + gy * Cy, gZ = gx * zx + gy * zy;
-            const double jx = gx + invD * (gB * gbx + gC * ggx - (betaD + gammaD) * gx - gZ * gdx);
-            const double jy = gy + invD * (gB * gby + gC * ggy - (betaD + gammaD) * gy - gZ * gdy);
-            fx -= jx;
-            fy -= jy;
-        }
-        // advance the window
-        hpx = hcx; hpy = hcy;
-        hcx = hnx; hcy = hny;
-        t1x = t2x; t1y = t2y;
-        dmx = dnx; dmy = dny;
-        dnx = dnnx; dny = dnny;
-        am = an; bm = bn;
-        an = ann; bn = bnn;
-    }
-    Fx = fx;
-    Fy = fy;
-}
-
-// UPDATE: r += dt (mu F + v0 n), re-quantised and wrapped; theta += amp xi.
-// Writes the new state into (xo, yo, tho); the old buffers stay untouched so
-// that neighbours read step-start positions.  Without UPDATE only the force
-// is written (tag order is handled by the caller).
-template <bool UPDATE>
-__global__ __launch_bounds__(256) void k_force(View v, double* xo, double* yo, double* tho, double* fxo,
-                                               double* fyo, StepParams sp)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    double disp = 0.0;
-    if (i < v.N) {
-        double Fx, Fy;
-        force_cell(v, i, Fx, Fy);
-        if (!UPDATE) {
-            fxo[i] = Fx;
-            fyo[i] = Fy;
-        } else {
-            const double xi = v.x[i], yi = v.y[i], th = v.th[i];
-            double sn, cs;
-            sincos(th, &sn, &cs);
-            const double xn = xi + sp.dt * (sp.mu * Fx + sp.v0 * cs);
-            const double yn = yi + sp.dt * (sp.mu * Fy + sp.v0 * sn);
-            double X = rint(xn * v.scale), Y = rint(yn * v.scale);
-            if (X < 0.0) X += v.LXu;
-            else if (X >= v.LXu) X -= v.LXu;
-            if (Y < 0.0) Y += v.LYu;
-            else if (Y >= v.LYu) Y -= v.LYu;
-            const double xq = X * v.inv_scale, yq = Y * v.inv_scale;
-            if (!(X >= 0.0 && X < v.LXu && Y >= 0.0 && Y < v.LYu)) atomicOr(&v.cnt->err, ERR_NONFINITE);
-            xo[i] = xq;
-            yo[i] = yq;
-            tho[i] = th + sp.amp * normal_for(sp.seed, sp.step, (uint64_t)v.tag[i]);
-            const double ddx = mimg(xq - xi, v.Lx, v.hLx), ddy = mimg(yq - yi, v.Ly, v.hLy);
-            disp = sqrt(ddx * ddx + ddy * ddy);
-        }
-    }
-    if (UPDATE) {
-        // wave max of a non-negative double through its bit pattern
-        unsigned long long b = __double_as_longlong(disp);
-        for (int off = 32; off >= 1; off >>= 1) {
-            unsigned long long o = __shfl_xor(b, off);
-            b = o > b ? o : b;
-        }
-        if ((threadIdx.x & 63) == 0 && b) atomicMax(&v.cnt->disp_bits, b);
-    }
-}
-
-// ---------------------------------------------------------------- compaction
-// Wave-aggregated stream compaction: out <- { i : a[i] != 0 }, a[i] cleared.
-__global__ __launch_bounds__(256) void k_compact(uint8_t* a, int n, int* out, int* count)
-{
-    const int lane = threadIdx.x & 63;
-    const int stride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int i = base + threadIdx.x;
-        bool f = false;
-        if (i < n) {
-            f = a[i] != 0;
-            if (f) a[i] = 0;
-        }
-        const unsigned long long mask = __ballot(f);
-        const int cnt = __popcll(mask);
-        int slot = 0;
-        if (lane == 0 && cnt) slot = atomicAdd(count, cnt);
-        slot = __shfl(slot, 0);
-        if (f) out[slot + __popcll(mask & ((1ull << lane) - 1ull))] = i;
-    }
-}
-
-// ---------------------------------------------------------------- opp rebuild
-// opp_m(i) is the third vertex of the triangle across edge (j_m, j_{m+1}):
-// in the CCW ring of j_m the sequence ..., opp_m, j_{m+1}, i, ... appears.  A
-// ring that does not contain that pattern is inconsistent: flag the cells.
-template <bool LIST>
-__global__ __launch_bounds__(256) void k_opp(View v)
-{
-    const int N = v.N;
-    const int n = LIST ? v.cnt->touched_count : N;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-        const int i = LIST ? v.list2[t] : t;
-        const int k = v.deg[i];
-        bool bad = false;
-        for (int m = 0; m < k; m++) {
-            const int j = v.ring[m * N + i];
-            const int jn = v.ring[((m + 1 == k) ? 0 : m + 1) * N + i];
-            const int kj = v.deg[j];
-            int o = -1;
-            for (int p = 0; p < kj; p++) {
-                if (v.ring[p * N + j] == i) {
-                    const int pm1 = (p + kj - 1) % kj, pm2 = (p + kj - 2) % kj;
-                    if (v.ring[pm1 * N + j] == jn) o = v.ring[pm2 * N + j];
-                    break;
+        __syncthreads();
+        const double rlim2 = 0.0625 * fmin(P.Lx, P.Ly) * fmin(P.Lx, P.Ly);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const int m = l + s * GL;
+            if (m < k) {
+                const int mn = (m + 1 == k) ? 0 : m + 1;
+                const int jm = sJ[g][m], jn = sJ[g][mn];
+                int o;
+                if (OPP) {
+                    o = -1;
+                    const int kj = min((int)c.deg[jm], KC);
+                    for (int p = 0; p < kj; p++) {
+                        if (c.ring[jm * KC + p] == i) {
+                            const int pm1 = (p == 0) ? kj - 1 : p - 1;
+                            const int pm2 = (pm1 == 0) ? kj - 1 : pm1 - 1;
+                            if (c.ring[jm * KC + pm1] == jn) o = c.ring[jm * KC + pm2];
+                            break;
+                        }
+                    }
+                    c.opp[i * KC + m] = o;
+                } else {
+                    o = c.opp[i * KC + m];
                 }
+                const double bx = sD[g][m][0], by = sD[g][m][1], cx = sD[g][mn][0], cy = sD[g][mn][1];
+                bool fail = cross_sign(bx, by, cx, cy, bx * cy - by * cx, P.scale) <= 0;
+                R ux, uy;
+                circumcentre((R)bx, (R)by, (R)cx, (R)cy, ux, uy);
+                if (!fail) {
+                    if (o < 0) {
+                        fail = true;
+                    } else {
+                        const double px = mimg(c.x[o] - xi, P.Lx, P.hLx), py = mimg(c.y[o] - yi, P.Ly, P.hLy);
+                        fail = incircle_tags(bx, by, cx, cy, px, py, c.tag, i, jm, jn, o, P.scale, &exact) > 0;
+                    }
+                    // a circumradius >= min(L)/4 is either a non-Delaunay triangle
+                    // or a true violation of the box precondition; the repair
+                    // tells them apart (it cannot certify a disk wider than L/2)
+                    if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
+                }
+                if (fail) {
+                    push_flag(w, st, rnext, i);
+                    push_flag(w, st, rnext, jm);
+                    push_flag(w, st, rnext, jn);
+                    if (o >= 0) push_flag(w, st, rnext, o);
+                }
+                sU[g][m][0] = ux;
+                sU[g][m][1] = uy;
             }
-            if (o < 0) {
-                bad = true;
-                flag_cell(v, j);
-                flag_cell(v, jn);
+        }
+        __syncthreads();
+        R a2 = R(0), per = R(0);
+#pragma unroll
+        for (int s = 0; s < NS; s++) {
+            const int m = l + s * GL;
+            if (m < k) {
+                const int mn = (m + 1 == k) ? 0 : m + 1;
+                const R ux = sU[g][m][0], uy = sU[g][m][1], vx = sU[g][mn][0], vy = sU[g][mn][1];
+                a2 += ux * vy - uy * vx;
+                per += sqrt((vx - ux) * (vx - ux) + (vy - uy) * (vy - uy));
             }
-            v.opp[m * N + i] = o;
         }
-        if (bad) {
-            flag_cell(v, i);
-            atomicAdd(&v.cnt->fail_count, 1);
+#pragma unroll
+        for (int off = GL / 2; off > 0; off >>= 1) {
+            a2 += __shfl_xor(a2, off);
+            per += __shfl_xor(per, off);
         }
+        if (valid && l == 0 && k >= 3) {
+            const R A = R(0.5) * a2;
+            c.A[i] = A;
+            c.P[i] = per;
+            c.ca[i] = (R)(2.0 * P.KA * ((double)A - c.A0[i]));
+            c.cb[i] = (R)(2.0 * P.KP * ((double)per - c.P0[i]));
+        }
+        __syncthreads();  // LDS is reused by the next group of cells
     }
+    if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
 }
 
 // ---------------------------------------------------------------- repair
 // One 64-lane wavefront rebuilds the Delaunay ring of one flagged cell i.
-// Candidates: every cell within distance R of i, gathered from the bins of
-// the last re-sort (searched with R + drift, drift bounding the motion since
-// then).  The ring is traced counter-clockwise by gift-wrapping: from the
-// nearest candidate (always a Delaunay neighbour), the next neighbour after
-// c is the left-side candidate p whose circle through (i, c, p) contains no
-// other left-side candidate -- an arg-min under the exact in-circle order,
-// taken per lane and then across the wave.  The result is certified when
-// every new circumdisk lies inside the search disk (2 |u_m| <= R), which
-// makes each new triangle empty with respect to all cells; otherwise R grows.
-__global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
+// Candidates: every cell of i's system within distance R, gathered from the
+// bins of the last re-sort (searched with R + drift, drift bounding the
+// motion since then).  The ring is traced counter-clockwise by gift-wrapping:
+// from the nearest candidate (always a Delaunay neighbour) the next neighbour
+// after c is the left-side candidate p whose circle through (i, c, p)
+// contains no other left-side candidate -- an arg-min under the exact
+// in-circle order, per lane and then across the wave.  The ring is certified
+// when every new circumdisk lies inside the search disk (2 |u_m| <= R), which
+// makes each new triangle empty with respect to all cells; otherwise R doubles.
+template <typename R, bool MULTI, int KC>
+__global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
+                                               int round)
 {
+    constexpr int KMAX = 64;
     __shared__ double sx[RP_CAP], sy[RP_CAP];
     __shared__ int sid[RP_CAP];
     __shared__ int s_n;
-    __shared__ int s_ring[RP_KMAX + 1];
+    __shared__ int s_ring[KMAX + 1];
+    if (st->halt) return;
     const int lane = threadIdx.x;
-    const int N = v.N;
-    const int nw = v.cnt->wl_count;
-    const double Rmax = 0.5 * fmin(v.Lx, v.Ly) * (1.0 - 1e-9);
+    const int nw = st->wl_count[round];
+    const int* __restrict__ wl = w.wl[round & 1];
+    const double drift = st->drift;
     int exact = 0;
-    for (int w = blockIdx.x; w < nw; w += gridDim.x) {
-        const int i = v.worklist[w];
-        const double xi = v.x[i], yi = v.y[i];
-        const int kold = v.deg[i];
-        double R = fmin(R0, Rmax);
+    for (int wi = blockIdx.x; wi < nw; wi += gridDim.x) {
+        const int i = wl[wi];
+        if (lane == 0) atomicAnd(&w.flagbits[i >> 5], ~(1u << (i & 31)));
+        const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+        const double xi = c.x[i], yi = c.y[i];
+        const int kold = min((int)c.deg[i], KC);
+        const double Rmax = 0.5 * fmin(P.Lx, P.Ly) * (1.0 - 1e-9);
+        double Rs = fmin(P.R0, Rmax);
         int k = 0;
-        bool ok = false;
-        bool at_max = false;
+        bool ok = false, at_max = false;
         int last_n = 0, last_closed = 0, attempts = 0;
         double last_umax = 0.0;
         for (int attempt = 0; attempt < 16 && !ok; attempt++) {
             attempts = attempt + 1;
             if (lane == 0) s_n = 0;
             __syncthreads();
-            const double Rs = R + drift;
-            int rbx = (int)ceil(Rs / v.bsx), rby = (int)ceil(Rs / v.bsy);
+            const double Rw = Rs + drift;
+            int rbx = (int)ceil(Rw / P.bsx), rby = (int)ceil(Rw / P.bsy);
             int wx = 2 * rbx + 1, wy = 2 * rby + 1;
-            int cbx = min((int)(xi / v.bsx), v.nbx - 1), cby = min((int)(yi / v.bsy), v.nby - 1);
+            const int cbx = min((int)(xi / P.bsx), P.nbx - 1), cby = min((int)(yi / P.bsy), P.nby - 1);
             int bx0 = cbx - rbx, by0 = cby - rby;
-            if (wx >= v.nbx) { wx = v.nbx; bx0 = 0; }
-            if (wy >= v.nby) { wy = v.nby; by0 = 0; }
-            const double R2 = R * R * (1.0 + 1e-12);
+            if (wx >= P.nbx) {
+                wx = P.nbx;
+                bx0 = 0;
+            }
+            if (wy >= P.nby) {
+                wy = P.nby;
+                by0 = 0;
+            }
+            const double R2 = Rs * Rs * (1.0 + 1e-12);
+            const int lo = P.cell_off, hi = P.cell_off + P.n;
             for (int b = lane; b < wx * wy; b += 64) {
                 int bx = bx0 + b % wx, by = by0 + b / wx;
-                bx = ((bx % v.nbx) + v.nbx) % v.nbx;
-                by = ((by % v.nby) + v.nby) % v.nby;
-                const int r = v.bin_rank[by * v.nbx + bx];
-                const int c1 = min(v.bin_start[r + 1], N);
-                for (int c = max(v.bin_start[r], 0); c < c1; c++) {
-                    if (c == i) continue;
-                    const double dx = mimg(v.x[c] - xi, v.Lx, v.hLx), dy = mimg(v.y[c] - yi, v.Ly, v.hLy);
+                bx = ((bx % P.nbx) + P.nbx) % P.nbx;
+                by = ((by % P.nby) + P.nby) % P.nby;
+                const int key = w.bin_key[P.bin_off + by * P.nbx + bx];
+                const int c1 = min(w.bin_start[key + 1], hi);
+                for (int q = max(w.bin_start[key], lo); q < c1; q++) {
+                    if (q == i) continue;
+                    const double dx = mimg(c.x[q] - xi, P.Lx, P.hLx), dy = mimg(c.y[q] - yi, P.Ly, P.hLy);
                     if (dx * dx + dy * dy <= R2) {
                         const int slot = atomicAdd(&s_n, 1);
                         if (slot < RP_CAP) {
                             sx[slot] = dx;
                             sy[slot] = dy;
-                            sid[slot] = c;
+                            sid[slot] = q;
                         }
                     }
                 }
@@ -492,19 +485,19 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
             const int n = s_n;
             last_n = n;
             if (n > RP_CAP) {
-                if (lane == 0) atomicOr(&v.cnt->err, ERR_CAPACITY);
+                if (lane == 0) atomicOr(&st->err, ERR_CAPACITY);
                 break;
             }
             // nearest candidate: exact squared distance in grid units, ties by tag
             unsigned long long bh = ~0ull, bl = ~0ull;
             int best = -1;
             for (int q = lane; q < n; q += 64) {
-                const __int128 X = to_units(sx[q], v.scale), Y = to_units(sy[q], v.scale);
+                const __int128 X = to_units(sx[q], P.scale), Y = to_units(sy[q], P.scale);
                 const unsigned __int128 d2 = (unsigned __int128)(X * X + Y * Y);
-                const unsigned long long h = (unsigned long long)(d2 >> 64), l = (unsigned long long)d2;
-                if (best < 0 || h < bh || (h == bh && (l < bl || (l == bl && v.tag[sid[q]] < v.tag[sid[best]])))) {
+                const unsigned long long h = (unsigned long long)(d2 >> 64), lw = (unsigned long long)d2;
+                if (best < 0 || h < bh || (h == bh && (lw < bl || (lw == bl && c.tag[sid[q]] < c.tag[sid[best]])))) {
                     bh = h;
-                    bl = l;
+                    bl = lw;
                     best = q;
                 }
             }
@@ -512,7 +505,7 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
                 const unsigned long long oh = __shfl_xor(bh, off), ol = __shfl_xor(bl, off);
                 const int ob = __shfl_xor(best, off);
                 if (ob >= 0 && (best < 0 || oh < bh ||
-                                (oh == bh && (ol < bl || (ol == bl && v.tag[sid[ob]] < v.tag[sid[best]]))))) {
+                                (oh == bh && (ol < bl || (ol == bl && c.tag[sid[ob]] < c.tag[sid[best]]))))) {
                     bh = oh;
                     bl = ol;
                     best = ob;
@@ -520,8 +513,8 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
             }
             if (best < 0) {  // no candidate at all
                 if (at_max) break;
-                R = fmin(2.0 * R, Rmax);
-                at_max = (R >= Rmax);
+                Rs = fmin(2.0 * Rs, Rmax);
+                at_max = (Rs >= Rmax);
                 continue;
             }
             const int start = best;
@@ -529,27 +522,30 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
             k = 1;
             int cur = start;
             bool closed = false;
-            while (k <= RP_KMAX) {
+            while (k <= KMAX) {
                 const double cx = sx[cur], cy = sy[cur];
                 const int gc = sid[cur];
                 int nb = -1;
                 for (int q = lane; q < n; q += 64) {
                     if (q == cur) continue;
                     const double px = sx[q], py = sy[q];
-                    if (cross_sign(cx, cy, px, py, cx * py - cy * px, v.scale) <= 0) continue;
-                    if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, v.tag, i, gc, sid[nb], sid[q],
-                                                v.scale, &exact) > 0)
+                    if (cross_sign(cx, cy, px, py, cx * py - cy * px, P.scale) <= 0) continue;
+                    if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, c.tag, i, gc, sid[nb], sid[q],
+                                                P.scale, &exact) > 0)
                         nb = q;
                 }
                 for (int off = 32; off >= 1; off >>= 1) {
                     const int ob = __shfl_xor(nb, off);
                     if (ob >= 0 && ob != nb &&
-                        (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], v.tag, i, gc, sid[nb],
-                                                 sid[ob], v.scale, &exact) > 0))
+                        (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], c.tag, i, gc, sid[nb],
+                                                 sid[ob], P.scale, &exact) > 0))
                         nb = ob;
                 }
-                if (nb < 0) break;               // star open: search disk too small
-                if (nb == start) { closed = true; break; }
+                if (nb < 0) break;  // star open: search disk too small
+                if (nb == start) {
+                    closed = true;
+                    break;
+                }
                 if (lane == 0) s_ring[k] = nb;
                 k++;
                 cur = nb;
@@ -560,11 +556,11 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
                 for (int m = lane; m < k; m += 64) {
                     const int p = s_ring[m], q = s_ring[(m + 1 == k) ? 0 : m + 1];
                     double ux, uy;
-                    circumcentre(sx[p], sy[p], sx[q], sy[q], sx[p] * sy[q] - sy[p] * sx[q], ux, uy);
+                    circumcentre(sx[p], sy[p], sx[q], sy[q], ux, uy);
                     umax = fmax(umax, sqrt(ux * ux + uy * uy));
                 }
                 for (int off = 32; off >= 1; off >>= 1) umax = fmax(umax, __shfl_xor(umax, off));
-                if (2.0 * umax * (1.0 + 1e-9) <= R) ok = true;
+                if (2.0 * umax * (1.0 + 1e-9) <= Rs) ok = true;
             }
             last_closed = closed ? 1 : 0;
             last_umax = umax;
@@ -572,84 +568,153 @@ __global__ __launch_bounds__(64) void k_repair(View v, double R0, double drift)
                 if (at_max) break;
                 // an uncertified star may be wrong (outer triangles clipped by
                 // the search disk), so its circumradii say nothing: double R
-                R = fmin(2.0 * R, Rmax);
-                at_max = (R >= Rmax);
-                if (lane == 0) atomicAdd(&v.cnt->retries, 1);
+                Rs = fmin(2.0 * Rs, Rmax);
+                at_max = (Rs >= Rmax);
+                if (lane == 0) atomicAdd(&st->retries, 1ull);
             }
         }
-        if (!ok) {
+        if (!ok || k > KC) {
             if (lane == 0) {
-                atomicOr(&v.cnt->err, at_max ? ERR_PRECOND : ERR_REPAIR);
-                if (atomicCAS(&v.cnt->fail_set, 0, 1) == 0) {
-                    v.cnt->fail_cell = v.tag[i];
-                    v.cnt->fail_n = last_n;
-                    v.cnt->fail_k = k;
-                    v.cnt->fail_closed = last_closed;
-                    v.cnt->fail_attempts = attempts;
-                    v.cnt->fail_R = R;
-                    v.cnt->fail_umax = last_umax;
+                atomicOr(&st->err, !ok ? (at_max ? ERR_PRECOND : ERR_REPAIR) : ERR_CAPACITY);
+                if (atomicCAS(&st->fail_set, 0, 1) == 0) {
+                    st->fail_cell = c.tag[i];
+                    st->fail_n = last_n;
+                    st->fail_k = k;
+                    st->fail_closed = last_closed;
+                    st->fail_attempts = attempts;
+                    st->fail_R = Rs;
+                    st->fail_umax = last_umax;
                 }
             }
-            __syncthreads();
-            continue;
-        }
-        if (k > v.kcap) {
-            if (lane == 0) atomicOr(&v.cnt->err, ERR_CAPACITY);
             __syncthreads();
             continue;
         }
         // canonical rotation: start at the smallest tag
         int mt = 0x7fffffff, mi = 0;
         for (int m = lane; m < k; m += 64) {
-            const int t = v.tag[sid[s_ring[m]]];
-            if (t < mt) { mt = t; mi = m; }
+            const int t = c.tag[sid[s_ring[m]]];
+            if (t < mt) {
+                mt = t;
+                mi = m;
+            }
         }
         for (int off = 32; off >= 1; off >>= 1) {
             const int ot = __shfl_xor(mt, off), oi = __shfl_xor(mi, off);
-            if (ot < mt) { mt = ot; mi = oi; }
+            if (ot < mt) {
+                mt = ot;
+                mi = oi;
+            }
         }
         // touch the old neighbourhood before overwriting it
-        for (int m = lane; m < kold; m += 64) v.touched[v.ring[m * N + i]] = 1;
+        for (int m = lane; m < kold; m += 64) push_touch(w, st, round, c.ring[i * KC + m]);
         __syncthreads();
         for (int m = lane; m < k; m += 64) {
-            const int c = sid[s_ring[(mi + m) % k]];
-            v.ring[m * N + i] = c;
-            v.touched[c] = 1;
+            const int q = sid[s_ring[(mi + m) % k]];
+            c.ring[i * KC + m] = q;
+            push_touch(w, st, round, q);
         }
         if (lane == 0) {
-            v.deg[i] = (uint8_t)k;
-            v.touched[i] = 1;
-            atomicAdd(&v.cnt->repaired, 1);
-            atomicMax(&v.cnt->max_deg, k);
+            c.deg[i] = (uint8_t)k;
+            push_touch(w, st, round, i);
+            atomicAdd(&st->repaired, 1ull);
+            atomicMax(&st->max_deg, k);
         }
         __syncthreads();
     }
-    if (exact) atomicAdd(&v.cnt->exact_calls, exact);
+    if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
+}
+
+// ---------------------------------------------------------------- step bookkeeping
+// After the last device repair round: count the step, accumulate the drift,
+// halt if rounds remain (the host finishes them) or an error was raised, and
+// clear the per-step counters otherwise.
+__global__ void k_finalize(DevState* st, int rounds)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (st->halt) return;
+    st->step += 1ull;
+    st->drift += __longlong_as_double((long long)st->disp_bits);
+    st->disp_bits = 0ull;
+    int used = 0;
+    for (int r = 0; r < rounds; r++) used += st->wl_count[r] > 0;
+    st->rounds += (unsigned long long)used;
+    if (st->err || st->wl_count[rounds] > 0) {
+        st->halt = 1;
+        st->halt_round = rounds;
+        return;
+    }
+    for (int r = 0; r <= rounds; r++) st->wl_count[r] = 0;
+    for (int r = 0; r < rounds; r++) st->tl_count[r] = 0;
+}
+
+// host recovery finished: clear the per-step counters and resume
+__global__ void k_resume(DevState* st)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int r = 0; r <= MAX_ROUNDS; r++) st->wl_count[r] = 0;
+    for (int r = 0; r < MAX_ROUNDS; r++) st->tl_count[r] = 0;
+    st->halt = 0;
+}
+
+__global__ void k_set_halt(DevState* st, int v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->halt = v;
+}
+
+// worklist of round 0 = every cell (initial triangulation)
+__global__ void k_all_to_worklist(Work w, DevState* st, int N)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        w.wl[0][i] = i;
+        atomicOr(&w.flagbits[i >> 5], 1u << (i & 31));
+    }
+    if (i == 0) st->wl_count[0] = N;
 }
 
 // ---------------------------------------------------------------- spatial re-sort
-__global__ void k_bin_keys(View v, int* key, int* hist)
+__global__ void k_fill_i32(int* a, int n, int val)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= v.N) return;
-    const int bx = min((int)(v.x[i] / v.bsx), v.nbx - 1), by = min((int)(v.y[i] / v.bsy), v.nby - 1);
-    const int r = v.bin_rank[by * v.nbx + bx];
-    key[i] = r;
-    atomicAdd(&hist[r], 1);
+    if (i < n) a[i] = val;
 }
 
-// exclusive scan of n ints by one 1024-thread block; out has n + 1 entries
-__global__ __launch_bounds__(1024) void k_scan(const int* in, int* out, int n)
+template <typename R, bool MULTI>
+__global__ void k_bin_keys(Cells<R> c, Work w, const SysParam* __restrict__ sp, const DevState* st, int N,
+                           int* key, int* hist)
 {
-    __shared__ int part[1024 / 64];
+    if (st->halt) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+    const int bx = min((int)(c.x[i] / P.bsx), P.nbx - 1), by = min((int)(c.y[i] / P.bsy), P.nby - 1);
+    const int kk = w.bin_key[P.bin_off + by * P.nbx + bx];
+    key[i] = kk;
+    atomicAdd(&hist[kk], 1);
+}
+
+// exclusive scan of n ints by one 1024-thread block (16 items per thread per
+// pass); out has n + 1 entries
+__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ in, int* __restrict__ out, int n,
+                                               const DevState* st)
+{
+    constexpr int IPT = 16, CH = 1024 * IPT;
+    __shared__ int part[16];
     __shared__ int carry;
+    if (st->halt) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) carry = 0;
     __syncthreads();
-    for (int base = 0; base < n; base += 1024) {
-        const int i = base + tid;
-        const int val = i < n ? in[i] : 0;
-        int inc = val;
+    for (int base = 0; base < n; base += CH) {
+        const int i0 = base + tid * IPT;
+        int v[IPT];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            v[k] = (i0 + k < n) ? in[i0 + k] : 0;
+            sum += v[k];
+        }
+        int inc = sum;
         for (int off = 1; off < 64; off <<= 1) {
             const int o = __shfl_up(inc, off);
             if (lane >= off) inc += o;
@@ -665,17 +730,22 @@ __global__ __launch_bounds__(1024) void k_scan(const int* in, int* out, int n)
             if (lane < 16) part[lane] = p;
         }
         __syncthreads();
-        const int wbase = wid ? part[wid - 1] : 0;
-        if (i < n) out[i] = carry + wbase + inc - val;
+        int run = carry + (wid ? part[wid - 1] : 0) + inc - sum;
+#pragma unroll
+        for (int k = 0; k < IPT; k++) {
+            if (i0 + k < n) out[i0 + k] = run;
+            run += v[k];
+        }
         __syncthreads();
-        if (tid == 1023) carry += wbase + inc;
+        if (tid == 1023) carry = run;
         __syncthreads();
     }
     if (tid == 0) out[n] = carry;
 }
 
-__global__ void k_bin_scatter(const int* key, const int* start, int* fill, int* perm, int n)
+__global__ void k_bin_scatter(const int* key, const int* start, int* fill, int* perm, int n, const DevState* st)
 {
+    if (st->halt) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int r = key[i];
@@ -683,67 +753,83 @@ __global__ void k_bin_scatter(const int* key, const int* start, int* fill, int* 
 }
 
 // order the few cells of each bin by tag so the permutation is deterministic
-__global__ void k_bin_sort(const int* start, int* perm, const int* tag, int nb)
+__global__ void k_bin_sort(const int* start, int* perm, const int* tag, int nb, const DevState* st)
 {
+    if (st->halt) return;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nb) return;
     const int s = start[r], e = start[r + 1];
     for (int a = s + 1; a < e; a++) {
-        const int c = perm[a];
-        const int tc = tag[c];
+        const int cc = perm[a];
+        const int tc = tag[cc];
         int b = a - 1;
         while (b >= s && tag[perm[b]] > tc) {
             perm[b + 1] = perm[b];
             b--;
         }
-        perm[b + 1] = c;
+        perm[b + 1] = cc;
     }
 }
 
-__global__ void k_inv_perm(const int* perm, int* inv, int n)
+__global__ void k_inv_perm(const int* perm, int* inv, int n, const DevState* st)
 {
+    if (st->halt) return;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < n) inv[perm[p]] = p;
 }
 
 // new slot p holds old cell perm[p]; neighbour indices go through inv
-__global__ void k_gather(View src, View dst, const int* perm, const int* inv)
+template <typename R, int KC>
+__global__ void k_gather(Cells<R> src, Cells<R> dst, const int* perm, const int* inv, int N, DevState* st)
 {
+    if (st->halt) return;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= src.N) return;
-    const int N = src.N;
+    if (p == 0) st->drift = 0.0;
+    if (p >= N) return;
     const int i = perm[p];
     dst.x[p] = src.x[i];
     dst.y[p] = src.y[i];
     dst.th[p] = src.th[i];
     dst.tag[p] = src.tag[i];
+    dst.sys[p] = src.sys[i];
     dst.A0[p] = src.A0[i];
     dst.P0[p] = src.P0[i];
     dst.A[p] = src.A[i];
     dst.P[p] = src.P[i];
     dst.ca[p] = src.ca[i];
     dst.cb[p] = src.cb[i];
-    const int k = src.deg[i];
+    const int k = min((int)src.deg[i], KC);
     dst.deg[p] = (uint8_t)k;
     for (int m = 0; m < k; m++) {
-        dst.ring[m * N + p] = inv[src.ring[m * N + i]];
-        const int o = src.opp[m * N + i];
-        dst.opp[m * N + p] = o >= 0 ? inv[o] : -1;
+        dst.ring[p * KC + m] = inv[src.ring[i * KC + m]];
+        const int o = src.opp[i * KC + m];
+        dst.opp[p * KC + m] = o >= 0 ? inv[o] : -1;
     }
 }
 
-// ---------------------------------------------------------------- observables
-// Deterministic two-level reduction: fixed grid, fixed in-block tree.
-__global__ __launch_bounds__(256) void k_obs_partial(View v, double KA, double KP, double* part)
+// ---------------------------------------------------------------- outputs and observables
+// out[cell_off(sys) + tag] = in[i]
+template <typename T>
+__global__ void k_to_tag_order(const T* in, const int* tag, const int* sys, const SysParam* sp, double* out, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[sp[sys[i]].cell_off + tag[i]] = (double)in[i];
+}
+
+// one block per system; fixed in-block tree (deterministic)
+template <typename R>
+__global__ __launch_bounds__(256) void k_observables(const R* A, const R* P, const double* A0, const double* P0,
+                                                     const SysParam* sp, double* out)
 {
     __shared__ double s[3][256];
+    const SysParam& S = sp[blockIdx.x];
     double e = 0.0, q = 0.0, a = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < v.N; i += gridDim.x * blockDim.x) {
-        const double A = v.A[i], P = v.P[i];
-        const double dA = A - v.A0[i], dP = P - v.P0[i];
-        e += KA * dA * dA + KP * dP * dP;
-        q += P / sqrt(A);
-        a += A;
+    for (int i = S.cell_off + threadIdx.x; i < S.cell_off + S.n; i += 256) {
+        const double Ai = (double)A[i], Pi = (double)P[i];
+        const double dA = Ai - A0[i], dP = Pi - P0[i];
+        e += S.KA * dA * dA + S.KP * dP * dP;
+        q += Pi / sqrt(Ai);
+        a += Ai;
     }
     s[0][threadIdx.x] = e;
     s[1][threadIdx.x] = q;
@@ -751,36 +837,20 @@ __global__ __launch_bounds__(256) void k_obs_partial(View v, double KA, double K
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if (threadIdx.x < h)
-            for (int c = 0; c < 3; c++) s[c][threadIdx.x] += s[c][threadIdx.x + h];
+            for (int k = 0; k < 3; k++) s[k][threadIdx.x] += s[k][threadIdx.x + h];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int c = 0; c < 3; c++) part[c * gridDim.x + blockIdx.x] = s[c][0];
+        for (int k = 0; k < 3; k++) out[3 * blockIdx.x + k] = s[k][0];
 }
 
-__global__ __launch_bounds__(256) void k_obs_final(const double* part, int nb, double* out)
-{
-    __shared__ double s[3][256];
-    for (int c = 0; c < 3; c++) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nb; b += 256) acc += part[c * nb + b];
-        s[c][threadIdx.x] = acc;
-    }
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h)
-            for (int c = 0; c < 3; c++) s[c][threadIdx.x] += s[c][threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int c = 0; c < 3; c++) out[c] = s[c][0];
-}
-
-// out[tag[i]] = in[i]
-__global__ void k_to_tag_order(const double* in, const int* tag, double* out, int n)
+__global__ void k_theta0(double* th, const int* tag, const int* sys, const SysParam* sp, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[tag[i]] = in[i];
+    if (i >= n) return;
+    uint64_t r[4];
+    philox4x64(~0ull, (uint64_t)tag[i], 0, 0, sp[sys[i]].seed, 0, r);
+    th[i] = 2.0 * 3.14159265358979323846 * u01(r[0]);
 }
 
 }  // namespace spv

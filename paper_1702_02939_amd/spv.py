@@ -37,11 +37,13 @@ class Params(ctypes.Structure):
     _fields_ = [("KA", ctypes.c_double), ("KP", ctypes.c_double), ("mu", ctypes.c_double),
                 ("v0", ctypes.c_double), ("Dr", ctypes.c_double), ("dt", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("resort_every", ctypes.c_int32),
-                ("kcap", ctypes.c_int32), ("repair_rounds", ctypes.c_int32)]
+                ("kcap", ctypes.c_int32), ("repair_rounds", ctypes.c_int32), ("device_rounds", ctypes.c_int32),
+                ("no_graphs", ctypes.c_int32)]
 
     def __init__(self, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=1.0, dt=0.01, seed=0, precision=SPV_FP64,
-                 resort_every=0, kcap=0, repair_rounds=0):
-        super().__init__(KA, KP, mu, v0, Dr, dt, seed, precision, resort_every, kcap, repair_rounds)
+                 resort_every=0, kcap=0, repair_rounds=0, device_rounds=0, no_graphs=0):
+        super().__init__(KA, KP, mu, v0, Dr, dt, seed, precision, resort_every, kcap, repair_rounds,
+                         device_rounds, no_graphs)
 
 
 _P = ctypes.c_void_p
@@ -52,8 +54,13 @@ _H = ctypes.c_void_p
 
 _SIGS = {
     "spv_create": [ctypes.POINTER(_H), _i64, _P, _P, _d, _d, _P, _P, _d, _P, ctypes.POINTER(Params), _P],
+    "spv_batch_create": [ctypes.POINTER(_H), _i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Params), _P],
     "spv_step": [_H, _i64],
+    "spv_get_size": [_H, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
+    "spv_get_system_range": [_H, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "spv_get_box": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)],
+    "spv_get_system_box": [_H, _i32, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)],
+    "spv_get_system_observables": [_H, _i32, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d)],
     "spv_get_positions": [_H, _P, _P],
     "spv_get_directors": [_H, _P],
     "spv_get_forces": [_H, _P, _P],
@@ -126,6 +133,48 @@ def spv_create(N, x, y, Lx, Ly, A0=None, P0=None, p0=3.8, theta0=None, params=No
     return h
 
 
+def spv_batch_create(N_s, L_s, x, y, p0_s, v0_s=None, seed_s=None, P0=None, params=None, stream=None):
+    """S independent systems (square boxes of side L_s) stepped together."""
+    params = params if params is not None else Params()
+    S = len(N_s)
+    N_s = np.ascontiguousarray(N_s, dtype=np.int64)
+    L_s = np.ascontiguousarray(L_s, dtype=np.float64)
+    keep = [N_s, L_s, _f64(x), _f64(y), _f64(P0), _f64(p0_s), _f64(v0_s),
+            None if seed_s is None else np.ascontiguousarray(seed_s, dtype=np.uint64)]
+    h = _H()
+    st = _lib.spv_batch_create(ctypes.byref(h), S, _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[1]), _ptr(keep[2]),
+                               _ptr(keep[3]), _ptr(keep[4]), _ptr(keep[5]), _ptr(keep[6]), _ptr(keep[7]),
+                               ctypes.byref(params), stream if stream is not None else _current_stream())
+    _check(st, "spv_batch_create")
+    return h
+
+
+def spv_get_size(h):
+    S, N = _i32(), _i64()
+    _check(_lib.spv_get_size(h, ctypes.byref(S), ctypes.byref(N)), "spv_get_size")
+    return S.value, N.value
+
+
+def spv_get_system_range(h, s):
+    a, n = _i64(), _i64()
+    _check(_lib.spv_get_system_range(h, int(s), ctypes.byref(a), ctypes.byref(n)), "spv_get_system_range")
+    return a.value, n.value
+
+
+def spv_get_system_box(h, s):
+    Lx, Ly, q = _d(), _d(), _i32()
+    _check(_lib.spv_get_system_box(h, int(s), ctypes.byref(Lx), ctypes.byref(Ly), ctypes.byref(q)),
+           "spv_get_system_box")
+    return Lx.value, Ly.value, q.value
+
+
+def spv_get_system_observables(h, s):
+    E, q, a = _d(), _d(), _d()
+    _check(_lib.spv_get_system_observables(h, int(s), ctypes.byref(E), ctypes.byref(q), ctypes.byref(a)),
+           "spv_get_system_observables")
+    return E.value, q.value, a.value
+
+
 def spv_step(h, nsteps):
     _check(_lib.spv_step(h, int(nsteps)), "spv_step")
 
@@ -188,13 +237,37 @@ def spv_destroy(h):
 
 # ------------------------------------------------------------------ convenience
 class System:
-    """One SPV system on the current HIP device (see include/spv.h)."""
+    """One SPV system (or a batch, see `System.batch`) on the current HIP
+    device (see include/spv.h)."""
 
-    def __init__(self, x, y, Lx, Ly, *, p0=3.8, A0=None, P0=None, theta0=None, params=None, stream=None):
-        self.N = len(x)
+    def __init__(self, x, y, Lx, Ly, *, p0=3.8, A0=None, P0=None, theta0=None, params=None, stream=None,
+                 _handle=None):
         self.params = params if params is not None else Params()
+        if _handle is not None:
+            self.h = _handle
+            self.N = spv_get_size(self.h)[1]
+            return
+        self.N = len(x)
         self.h = spv_create(self.N, x, y, Lx, Ly, A0=A0, P0=P0, p0=p0, theta0=theta0, params=self.params,
                             stream=stream)
+
+    @classmethod
+    def batch(cls, N_s, L_s, x, y, p0_s, v0_s=None, seed_s=None, P0=None, params=None, stream=None):
+        params = params if params is not None else Params()
+        h = spv_batch_create(N_s, L_s, x, y, p0_s, v0_s=v0_s, seed_s=seed_s, P0=P0, params=params, stream=stream)
+        return cls(None, None, None, None, params=params, _handle=h)
+
+    def size(self):
+        return spv_get_size(self.h)
+
+    def system_range(self, s):
+        return spv_get_system_range(self.h, s)
+
+    def system_box(self, s):
+        return spv_get_system_box(self.h, s)
+
+    def system_observables(self, s):
+        return spv_get_system_observables(self.h, s)
 
     def step(self, n=1):
         spv_step(self.h, n)

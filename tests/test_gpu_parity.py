@@ -255,3 +255,107 @@ def test_device_pointer_inputs_and_outputs(spv):
     hx, hy = s.positions()
     assert np.array_equal(ox.cpu().numpy(), hx) and np.array_equal(oy.cpu().numpy(), hy)
     s.close()
+
+
+# ---------------------------------------------------------------- launch paths, batches, precision
+
+def _run(spv, x, y, L, steps_seq, **kw):
+    s = spv.System(x, y, L, L, p0=3.9, params=spv.Params(v0=0.1, seed=21, **kw))
+    for k in steps_seq:
+        s.step(k)
+    out = (*s.positions(), s.directors(), *s.neighbors())
+    s.close()
+    return out
+
+
+def test_graph_and_eager_paths_bitwise_equal(spv):
+    n = 2000
+    x, y, L, _ = _random_case(n, 51)
+    a = _run(spv, x, y, L, [37], resort_every=8)                 # 4 graph periods + 5 eager steps
+    b = _run(spv, x, y, L, [37], resort_every=8, no_graphs=1)    # all eager
+    c = _run(spv, x, y, L, [1, 2, 3, 31], resort_every=8)       # mixed boundaries
+    for u, v, w in zip(a, b, c):
+        assert np.array_equal(u, v) and np.array_equal(u, w)
+
+
+def test_host_recovery_rounds_bitwise_equal(spv):
+    """One device round per step forces the host to finish most repairs; the
+    result must not depend on where the rounds run."""
+    n = 3000
+    x, y, L, _ = _random_case(n, 52)
+    a = _run(spv, x, y, L, [48], resort_every=16)
+    b = _run(spv, x, y, L, [48], resort_every=16, device_rounds=1)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+
+
+def _batch_inputs(S, seed):
+    rng = np.random.default_rng(seed)
+    N_s = [64, 300, 1000, 257, 4096][:S]
+    L_s = [math.sqrt(nn) for nn in N_s]
+    xs, ys = [], []
+    for k, nn in enumerate(N_s):
+        x, y = inputs.uniform_positions(nn, L_s[k], L_s[k], seed + 1 + k)
+        xs.append(x)
+        ys.append(y)
+    p0_s = rng.uniform(3.6, 4.0, S)
+    v0_s = rng.uniform(0.01, 0.2, S)
+    seed_s = np.arange(S, dtype=np.uint64) + 1000
+    return N_s, L_s, xs, ys, p0_s, v0_s, seed_s
+
+
+def test_batch_equals_systems_run_alone(spv):
+    S = 5
+    N_s, L_s, xs, ys, p0_s, v0_s, seed_s = _batch_inputs(S, 60)
+    steps = 40
+    b = spv.System.batch(N_s, L_s, np.concatenate(xs), np.concatenate(ys), p0_s, v0_s=v0_s, seed_s=seed_s,
+                         params=spv.Params(Dr=1.0, dt=0.01, resort_every=8))
+    b.step(steps)
+    bx, by = b.positions()
+    boff, bnb = b.neighbors()
+    for k in range(S):
+        first, nn = b.system_range(k)
+        assert nn == N_s[k]
+        s = spv.System(xs[k], ys[k], L_s[k], L_s[k], p0=p0_s[k],
+                       params=spv.Params(v0=v0_s[k], seed=int(seed_s[k]), Dr=1.0, dt=0.01, resort_every=8))
+        s.step(steps)
+        sx, sy = s.positions()
+        assert np.array_equal(bx[first:first + nn], sx) and np.array_equal(by[first:first + nn], sy)
+        soff, snb = s.neighbors()
+        ring_b = bnb[boff[first]:boff[first + nn]] - first
+        assert np.array_equal(ring_b, snb)
+        Eb, qb, ab = b.system_observables(k)
+        Es, qs, as_, _ = s.observables()
+        assert abs(Eb - Es) <= 1e-12 * max(1.0, abs(Es)) and abs(ab - as_) <= 1e-9 * as_
+        # and each system's topology is its exact Delaunay triangulation
+        Lx, Ly, q = b.system_box(k)
+        off, ring, _, _ = oracle.triangulate(sx, sy, Lx, Ly, q)
+        assert np.array_equal(soff, off) and np.array_equal(snb, ring)
+        s.close()
+    b.close()
+
+
+def test_mixed_precision_forces_and_topology(spv):
+    """FP32 geometry/forces: topology stays exact (FP64 predicates); the force
+    error against the FP64 oracle is reported and bounded."""
+    n = 20000
+    x, y, L, _ = _random_case(n, 61)
+    s = spv.System(x, y, L, L, p0=3.9, params=spv.Params(v0=0.1, seed=5, precision=spv.SPV_MIXED))
+    s.step(50)
+    gx, gy = s.positions()
+    Lx, Ly, q = s.box()
+    off, ring = _compare_topology(s, gx, gy)
+    fx, fy = oracle.forces(gx, gy, Lx, Ly, off, ring, 1.0, 3.9)
+    gfx, gfy = s.forces()
+    F = np.hypot(fx, fy)
+    dF = np.hypot(gfx - fx, gfy - fy)
+    scale = max(F.max(), 3.9)
+    rel = dF.max() / scale
+    l2 = np.sqrt((dF ** 2).sum() / (F ** 2).sum())
+    print(f"mixed precision: max|dF|/scale = {rel:.3e}, |dF|_2/|F|_2 = {l2:.3e}, p99.9 = "
+          f"{np.quantile(dF, 0.999) / scale:.3e}")
+    assert rel < 1e-4 and l2 < 1e-5
+    A, P = oracle.geometry(gx, gy, Lx, Ly, off, ring)
+    gA, gP = s.geometry()
+    assert np.abs(gA - A).max() < 1e-5 and np.abs(gP - P).max() < 1e-5
+    s.close()
