@@ -59,6 +59,11 @@ def parse():
     ap.add_argument("--workload", default="spv_n100k")
     ap.add_argument("--cpu-sample-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="skip the mixed / batched / 1e6 runs")
+    ap.add_argument("--no-timing", action="store_true", help="skip the kernel-timing pass")
+    ap.add_argument("--timing-steps", type=int, default=2000)
+    ap.add_argument("--batch-steps", type=int, default=5000)
+    ap.add_argument("--big-steps", type=int, default=400)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -84,13 +89,67 @@ def cpu_baseline(w, nsteps):
             "sample": f"{w['N']} cells, {nsteps} steps from the random start (serial, 1 thread), {dt:.1f} s"}
 
 
+def timed_run(spv, make, steps, warmup, timing=True):
+    """Create via make(), warm up, time `steps` steps; returns a dict."""
+    import torch
+    sysm, ncells = make()
+    sysm.step(warmup)
+    _, _, _, c0 = sysm.observables()
+    if timing:
+        spv.spv_set_timing(sysm.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysm.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    E, qbar, sumA, c1 = sysm.observables()
+    kt = {name: spv.spv_kernel_time(sysm.h, k) for name, k in
+          (("force_update", spv.K_FORCE), ("geometry_test", spv.K_GEOM), ("repair", spv.K_REPAIR))}
+    sysm.close()
+    return {"value": ncells * steps / wall, "ms_per_step": wall * 1e3 / steps, "cells": ncells, "steps": steps,
+            "kernels": kt, "repairs_per_step": float(c1[1] - c0[1]) / steps,
+            "rounds_per_step": float(c1[2] - c0[2]) / steps, "E": E, "qbar": qbar, "sumA": sumA}
+
+
+def single(spv, inputs, name, precision):
+    w = inputs.WORKLOADS[name]
+
+    def make():
+        x, y = inputs.uniform_positions(w["N"], w["L"], w["L"], w["seed"])
+        prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"], precision=precision)
+        return spv.System(x, y, w["L"], w["L"], p0=w["p0"], params=prm), w["N"]
+    return make
+
+
+def batched(spv, inputs, precision):
+    def make():
+        systems = inputs.batch_systems()
+        N_s = [s_["N"] for s_ in systems]
+        L_s = [s_["L"] for s_ in systems]
+        x = __import__("numpy").concatenate([s_["x"] for s_ in systems])
+        y = __import__("numpy").concatenate([s_["y"] for s_ in systems])
+        prm = spv.Params(mu=1.0, Dr=1.0, dt=0.01, precision=precision)
+        sysm = spv.System.batch(N_s, L_s, x, y, [s_["p0"] for s_ in systems], v0_s=[s_["v0"] for s_ in systems],
+                                seed_s=[s_["seed"] for s_ in systems], params=prm)
+        return sysm, sum(N_s)
+    return make
+
+
+def roofline_of(kt, ncells):
+    dom = max(("force_update", "geometry_test"), key=lambda k: kt[k][0])
+    ms, launches = kt[dom]
+    avg_s = ms / 1e3 / max(launches, 1)
+    bytes_per_launch = BYTES_PER_CELL[dom] * ncells
+    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    return dom, avg_s, bytes_per_launch, achieved
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
                                    "and not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_1702_02939_amd import inputs, spv
@@ -104,55 +163,62 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = inputs.WORKLOADS[args.workload]
-    n, L = w["N"], w["L"]
-    x, y = inputs.uniform_positions(n, L, L, w["seed"])
-    prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"])
-    sysm = spv.System(x, y, L, L, p0=w["p0"], params=prm)
-    sysm.step(args.warmup)
-    _, _, _, c0 = sysm.observables()
-    spv.spv_set_timing(sysm.h, 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sysm.step(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    E, qbar, sumA, c1 = sysm.observables()
-    kt = {name: spv.spv_kernel_time(sysm.h, k) for name, k in
-          (("force_update", spv.K_FORCE), ("geometry_test", spv.K_GEOM), ("repair", spv.K_REPAIR))}
-    sysm.close()
-
-    value = n * args.steps / wall
-    # dominant streaming kernel: the one with the larger total time
-    dom = max(("force_update", "geometry_test"), key=lambda k: kt[k][0])
-    ms, launches = kt[dom]
-    avg_s = ms / 1e3 / max(launches, 1)
-    bytes_per_launch = BYTES_PER_CELL[dom] * n
-    achieved = bytes_per_launch / avg_s / 1e9
+    # timed region 1: throughput (steps replayed as captured graphs, no events)
+    head = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.steps, args.warmup, timing=False)
+    n = head["cells"]
+    # timed region 2: kernel durations from HIP events around every launch
+    # (timing mode launches each step's kernels one by one on the same stream)
+    kt = {k: (0.0, 0) for k in ("force_update", "geometry_test", "repair")}
+    if not args.no_timing:
+        kt = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.timing_steps, args.warmup,
+                       timing=True)["kernels"]
+    dom, avg_s, bytes_per_launch, achieved = roofline_of(kt, n)
     mt = MEASURED_TRAFFIC.get(dom)
     traffic = mt["bytes"] if mt and mt["csrc_sha256"] == csrc_digest() else None
     out = {
         "metric": "cell-steps/s",
-        "value": value,
+        "value": head["value"],
         "unit": "cell-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "N": n, "L": L, "p0": w["p0"], "v0": w["v0"], "Dr": w["Dr"],
+        "config": {"workload": args.workload, "N": n, "L": w["L"], "p0": w["p0"], "v0": w["v0"], "Dr": w["Dr"],
                    "mu": w["mu"], "dt": w["dt"], "precision": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
         "kernels_ms_total": {k: v[0] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
-        "repairs_per_step": float(c1[1] - c0[1]) / args.steps,
-        "observables": {"E": E, "qbar": qbar, "sumA": sumA},
+        "repairs_per_step": head["repairs_per_step"],
+        "observables": {"E": head["E"], "qbar": head["qbar"], "sumA": head["sumA"]},
     }
+    if not args.headline_only:
+        extra = {}
+        runs = [
+            ("spv_n100k_mixed", single(spv, inputs, "spv_n100k", spv.SPV_MIXED), args.steps, args.warmup),
+            ("batched_sweep_256_mixed", batched(spv, inputs, spv.SPV_MIXED), args.batch_steps, 200),
+            ("batched_sweep_256_fp64", batched(spv, inputs, spv.SPV_FP64), args.batch_steps, 200),
+            ("spv_n1m_fp64", single(spv, inputs, "spv_n1m", spv.SPV_FP64), args.big_steps, 100),
+            ("spv_n1m_mixed", single(spv, inputs, "spv_n1m", spv.SPV_MIXED), args.big_steps, 100),
+        ]
+        for name, make, steps, warm in runs:
+            r = timed_run(spv, make, steps, warm, timing=False)
+            r["kernels"] = timed_run(spv, make, max(steps // 10, 50), warm, timing=True)["kernels"]
+            d, a_s, bpl, ach = roofline_of(r["kernels"], r["cells"])
+            extra[name] = {"value": r["value"], "unit": "cell-steps/s", "ms_per_step": r["ms_per_step"],
+                           "cells": r["cells"], "steps": steps, "warmup": warm,
+                           "repairs_per_step": r["repairs_per_step"],
+                           "kernel_avg_us": {k: (v[0] * 1e3 / max(v[1], 1)) for k, v in r["kernels"].items()},
+                           "roofline_frac_hbm": ach / HBM_PEAK_GBS, "dominant_kernel": d}
+            print(f"[bench] {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)
+        extra["mixed_vs_fp64_speedup_n100k"] = extra["spv_n100k_mixed"]["value"] / head["value"]
+        out["extra"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
     print(json.dumps(out))

@@ -66,7 +66,7 @@ typedef struct {
     double dt;              /* time step */
     uint64_t seed;          /* noise: Philox4x64-10, key (seed, 0), counter (step, tag, 0, 0) */
     int32_t precision;      /* SPV_FP64 or SPV_MIXED */
-    int32_t resort_every;   /* steps between spatial re-sorts, rounded up to even (0: 16) */
+    int32_t resort_every;   /* steps between spatial re-sorts, rounded up to even (0: 32) */
     int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16) */
     int32_t repair_rounds;  /* max test/repair rounds per step, device and host together (0: 16, max 32) */
     int32_t device_rounds;  /* repair rounds run on the device inside each step (0: 2) */
@@ -164,11 +164,12 @@ spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA
 spv_status spv_get_system_observables(spv_sys* s, int32_t sys, double* E, double* qbar, double* sumA);
 
 /*
- * Kernel timing.  While enabled, every launch of the listed kernel is
- * bracketed by HIP events on the handle's stream (also inside captured
- * graphs); spv_kernel_time returns the summed duration (ms) and launch count
- * since enabling.   which: 0 = force+update, 1 = geometry+test (all cells),
- * 2 = repair (device rounds)
+ * Kernel timing.  While enabled, steps are launched one by one (not as
+ * captured graphs) and every launch of the listed kernel is bracketed by HIP
+ * events on the handle's stream; spv_kernel_time returns the summed duration
+ * (ms) and number of timed launches since enabling.
+ *   which: 0 = force+update, 1 = geometry+test (all cells),
+ *          2 = repair (first device round)
  */
 spv_status spv_set_timing(spv_sys* s, int32_t enable);
 spv_status spv_kernel_time(spv_sys* s, int32_t which, double* total_ms, int64_t* launches);

@@ -100,7 +100,6 @@ struct spv_sys {
     int S = 1, N = 0, KC = 16;
     int dev_rounds = 2, max_rounds = 16, unit = 16;
     bool mixed = false, multi = false, use_graphs = true;
-    bool graph_timing_broken = false;  // event records could not be captured: timed runs launch eagerly
     spv_params prm{};
     hipStream_t stream = nullptr;      // caller's stream (all work is ordered on it)
     hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
@@ -112,15 +111,14 @@ struct spv_sys {
     Work work{};
     int total_bins = 0;
     int *d_bin_key = nullptr, *d_bin_start = nullptr, *d_key = nullptr, *d_hist = nullptr, *d_fill = nullptr;
-    int *d_perm = nullptr, *d_inv = nullptr;
+    int *d_perm = nullptr, *d_inv = nullptr, *d_chunk = nullptr;
     DevState* d_st = nullptr;
     DevState* h_st = nullptr;  // pinned copy
-    double *d_stage = nullptr, *d_fx = nullptr, *d_fy = nullptr, *d_obs = nullptr;
+    double *d_stage = nullptr, *d_fx = nullptr, *d_fy = nullptr, *d_obs = nullptr, *d_blockmax = nullptr;
     std::vector<void*> allocs;
     // graphs of one period starting in configuration 0 / 1
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    bool gtimed[2] = {false, false};
-    std::vector<EvPair> gev[2];  // per step: force, geom, repair(round 0)
+
     // bookkeeping
     uint64_t step = 0;
     int64_t resorts = 0;
@@ -255,18 +253,6 @@ void collect_eager_timing(spv_sys* s)
     s->pending.clear();
 }
 
-void collect_graph_timing(spv_sys* s, int g)
-{
-    if (!s->timing || !s->gtimed[g]) return;
-    for (size_t k = 0; k < s->gev[g].size(); k++) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, s->gev[g][k].a, s->gev[g][k].b) == hipSuccess) {
-            s->t_ms[k % T_COUNT] += ms;
-            s->t_n[k % T_COUNT] += 1;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- launch sequences
 // One step on stream `st` from (cfg, parity).  ev: optional event pairs
 // (force, geom, repair round 0) to record around the kernels.
@@ -277,7 +263,7 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
     const unsigned cg = cell_grid(s), lg = list_grid(s), rg = repair_grid(s);
     if (ev) (void)hipEventRecord(ev[0].a, st);
     hipLaunchKernelGGL((k_force<R, MULTI, KC, true>), dim3(cg), dim3(256), 0, st, cur, nxt.x, nxt.y, nxt.th,
-                       (double*)nullptr, (double*)nullptr, s->d_sp, s->d_st, s->N);
+                       (double*)nullptr, (double*)nullptr, s->d_sp, s->d_st, s->N, s->d_blockmax);
     if (ev) (void)hipEventRecord(ev[0].b, st);
     if (ev) (void)hipEventRecord(ev[1].a, st);
     hipLaunchKernelGGL((k_geom<R, MULTI, KC, false, false>), dim3(cg), dim3(256), 0, st, nxt, s->work, s->d_sp,
@@ -287,10 +273,13 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
         if (ev && r == 0) (void)hipEventRecord(ev[2].a, st);
         hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, r);
         if (ev && r == 0) (void)hipEventRecord(ev[2].b, st);
-        hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
-                           s->d_st, s->N, r);
+        if (r + 1 < s->dev_rounds)
+            hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
+                               s->d_st, s->N, r, (const double*)nullptr, 0);
+        else  // the last re-test also closes the step (last block done)
+            hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work,
+                               s->d_sp, s->d_st, s->N, r, (const double*)s->d_blockmax, (int)cg);
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, s->d_st, s->dev_rounds);
 }
 
 // Re-sort from (cfg, parity 0) into set[cfg ^ 1] (the caller flips cfg).
@@ -303,7 +292,11 @@ void enqueue_resort(spv_sys* s, hipStream_t st, int cfg)
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_fill, nb, 0);
     hipLaunchKernelGGL((k_bin_keys<R, MULTI>), dim3(grid_for(N, 256)), dim3(256), 0, st, src, s->work, s->d_sp,
                        s->d_st, N, s->d_key, s->d_hist);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, s->d_hist, s->d_bin_start, nb, s->d_st);
+    const unsigned nchunk = grid_for(nb, SCAN_CHUNK);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nchunk), dim3(256), 0, st, s->d_hist, nb, s->d_chunk, s->d_st);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(256), 0, st, s->d_chunk, (int)nchunk, s->d_st);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nchunk), dim3(256), 0, st, s->d_hist, s->d_bin_start, nb,
+                       (const int*)s->d_chunk, s->d_st);
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(N, 256)), dim3(256), 0, st, s->d_key, s->d_bin_start, s->d_fill,
                        s->d_perm, N, s->d_st);
     hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_bin_start, s->d_perm, src.tag,
@@ -395,20 +388,12 @@ spv_status capture_graph(spv_sys* s, int g)
         (void)hipGraphExecDestroy(s->gexec[g]);
         s->gexec[g] = nullptr;
     }
-    const bool timed = s->timing;
-    if (timed && s->gev[g].empty()) {
-        s->gev[g].resize((size_t)s->unit * T_COUNT);
-        for (auto& e : s->gev[g]) {
-            HIP_TRY(hipEventCreate(&e.a));
-            HIP_TRY(hipEventCreate(&e.b));
-        }
-    }
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-    for (int k = 0; k < s->unit; k++) {
-        const EvPair* ev = timed ? &s->gev[g][(size_t)k * T_COUNT] : nullptr;
-        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, ev); });
-    }
+    for (int k = 0; k < s->unit; k++)
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() {
+            enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, nullptr);
+        });
     dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->cap_stream, g); });
     hipError_t e0 = hipGetLastError();
     hipError_t e1 = hipStreamEndCapture(s->cap_stream, &graph);
@@ -417,7 +402,6 @@ spv_status capture_graph(spv_sys* s, int g)
     hipError_t e2 = hipGraphInstantiate(&s->gexec[g], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e2 != hipSuccess) return fail(SPV_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
-    s->gtimed[g] = timed;
     return SPV_OK;
 }
 
@@ -436,17 +420,9 @@ spv_status run_steps(spv_sys* s, int64_t n)
     if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
     while (n > 0) {
         if (s->pos == s->unit) ST_TRY(do_resort_eager(s));
-        if (s->pos == 0 && n >= s->unit && s->use_graphs && !(s->timing && s->graph_timing_broken)) {
+        if (s->pos == 0 && n >= s->unit && s->use_graphs && !s->timing) {
             const int g = s->cfg;
-            if (!s->gexec[g] || s->gtimed[g] != s->timing) {
-                const spv_status cst = capture_graph(s, g);
-                if (cst != SPV_OK) {
-                    if (!s->timing) return cst;
-                    s->graph_timing_broken = true;  // retry this period eagerly
-                    (void)hipGetLastError();
-                    continue;
-                }
-            }
+            if (!s->gexec[g]) ST_TRY(capture_graph(s, g));
             const uint64_t before = s->step;
             HIP_TRY(hipGraphLaunch(s->gexec[g], s->stream));
             ST_TRY(read_state(s));
@@ -460,7 +436,6 @@ spv_status run_steps(spv_sys* s, int64_t n)
                 ST_TRY(recover(s));
                 continue;
             }
-            collect_graph_timing(s, g);
             s->step += done;
             n -= (int64_t)done;
             s->cfg ^= 1;
@@ -499,13 +474,8 @@ void destroy_all(spv_sys* s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    for (int g = 0; g < 2; g++) {
+    for (int g = 0; g < 2; g++)
         if (s->gexec[g]) (void)hipGraphExecDestroy(s->gexec[g]);
-        for (auto& e : s->gev[g]) {
-            (void)hipEventDestroy(e.a);
-            (void)hipEventDestroy(e.b);
-        }
-    }
     for (auto& e : s->pool) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -629,6 +599,7 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     ST_TRY(dalloc(s, &s->d_hist, s->total_bins));
     ST_TRY(dalloc(s, &s->d_fill, s->total_bins));
     ST_TRY(dalloc(s, &s->d_perm, N));
+    ST_TRY(dalloc(s, &s->d_chunk, grid_for(s->total_bins, SCAN_CHUNK) + 1));
     ST_TRY(dalloc(s, &s->d_inv, N));
     ST_TRY(dalloc(s, &s->d_st, 1));
     ST_TRY(dalloc(s, &s->d_sp, S));
@@ -636,6 +607,7 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     ST_TRY(dalloc(s, &s->d_fx, N));
     ST_TRY(dalloc(s, &s->d_fy, N));
     ST_TRY(dalloc(s, &s->d_obs, 3 * S));
+    ST_TRY(dalloc(s, &s->d_blockmax, cell_grid(s)));
     HIP_TRY(hipHostMalloc((void**)&s->h_st, sizeof(DevState), hipHostMallocDefault));
     HIP_TRY(hipMemsetAsync(s->d_st, 0, sizeof(DevState), s->stream));
     HIP_TRY(hipMemsetAsync(s->work.flagbits, 0, nwords * sizeof(unsigned), s->stream));
@@ -698,7 +670,7 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     s->max_rounds = p.repair_rounds > 0 ? std::min(p.repair_rounds, MAX_ROUNDS) : 16;
     s->dev_rounds = p.device_rounds > 0 ? std::min(p.device_rounds, s->max_rounds) : 2;
     if (s->dev_rounds > s->max_rounds) return fail(SPV_EINVAL, "device_rounds exceeds repair_rounds");
-    s->unit = p.resort_every > 0 ? p.resort_every : 16;
+    s->unit = p.resort_every > 0 ? p.resort_every : 32;
     if (s->unit & 1) s->unit += 1;
     s->use_graphs = p.no_graphs == 0;
     s->stream = (hipStream_t)stream;
@@ -880,7 +852,7 @@ spv_status spv_get_forces(spv_sys* s, double* fx, double* fy)
         Cells<R> c = cells<R>(s, s->cfg, s->pos & 1);
         hipLaunchKernelGGL((k_force<R, MULTI, KC, false>), dim3(cell_grid(s)), dim3(256), 0, s->stream, c,
                            (double*)nullptr, (double*)nullptr, (double*)nullptr, s->d_fx, s->d_fy, s->d_sp, s->d_st,
-                           s->N);
+                           s->N, s->d_blockmax);
     });
     HIP_TRY(hipGetLastError());
     ST_TRY(out_tag_order(s, s->d_fx, fx));
@@ -966,7 +938,11 @@ spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA
         counters[1] = (int64_t)d.repaired;
         counters[2] = (int64_t)d.rounds;
         counters[3] = (int64_t)d.exact_calls;
-        counters[4] = d.max_deg;
+        {
+            std::vector<uint8_t> deg(s->N);
+            HIP_TRY(hipMemcpy(deg.data(), s->set[s->cfg].deg, s->N, hipMemcpyDeviceToHost));
+            counters[4] = *std::max_element(deg.begin(), deg.end());
+        }
         counters[5] = s->resorts;
         counters[6] = (int64_t)d.retries;
         counters[7] = (int64_t)d.err;

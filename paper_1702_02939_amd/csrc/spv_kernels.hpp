@@ -68,24 +68,41 @@ __device__ __forceinline__ int incircle_tags(double bx, double by, double cx, do
     return incircle_sos(bx, by, cx, cy, px, py, tag[gi], tag[gb], tag[gc], tag[gp], scale, exact_count);
 }
 
-// append c to the repair worklist of round r (once per round)
-__device__ __forceinline__ void push_flag(const Work& w, DevState* st, int r, int c)
+// Wave-aggregated append: the active lanes with `want` write c to list, one
+// counter atomic per wave (same-address atomics from many waves serialise at
+// the device coherence point across the XCDs).
+__device__ __forceinline__ void wave_append(int* list, int* count, int c, bool want)
 {
-    const unsigned bit = 1u << (c & 31);
-    if (!(atomicOr(&w.flagbits[c >> 5], bit) & bit)) {
-        const int slot = atomicAdd(&st->wl_count[r], 1);
-        w.wl[r & 1][slot] = c;
-    }
+    const unsigned long long mask = __ballot(want);
+    if (!mask) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(mask));
+    base = __shfl(base, leader);
+    if (want) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = c;
 }
 
-// append c to the touched list of round r (once per round)
+// append c (if >= 0) to the repair worklist of round r, once per round
+__device__ __forceinline__ void push_flag(const Work& w, DevState* st, int r, int c)
+{
+    bool want = false;
+    if (c >= 0) {
+        const unsigned bit = 1u << (c & 31);
+        want = !(atomicOr(&w.flagbits[c >> 5], bit) & bit);
+    }
+    wave_append(w.wl[r & 1], &st->wl_count[r], c, want);
+}
+
+// append c (if >= 0) to the touched list of round r, once per round
 __device__ __forceinline__ void push_touch(const Work& w, DevState* st, int r, int c)
 {
-    const unsigned bit = 1u << (c & 31);
-    if (!(atomicOr(&w.touchbits[c >> 5], bit) & bit)) {
-        const int slot = atomicAdd(&st->tl_count[r], 1);
-        w.tl[r & 1][slot] = c;
+    bool want = false;
+    if (c >= 0) {
+        const unsigned bit = 1u << (c & 31);
+        want = !(atomicOr(&w.touchbits[c >> 5], bit) & bit);
     }
+    wave_append(w.tl[r & 1], &st->tl_count[r], c, want);
 }
 
 // XCD-aware block order: the 8 XCDs receive consecutive workgroups in turn;
@@ -112,7 +129,7 @@ template <typename R, bool MULTI, int KC, bool UPDATE>
 __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
                                                double* __restrict__ tho, double* __restrict__ fxo,
                                                double* __restrict__ fyo, const SysParam* __restrict__ sp,
-                                               DevState* st, int N)
+                                               DevState* st, int N, double* __restrict__ blockmax)
 {
     constexpr int NS = KC / GL;
     __shared__ R sD[CPB][KC][2];  // displacement of ring cell m
@@ -244,36 +261,46 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
         }
         return;
     }
+    // the update (noise, trigonometry) runs on the first CPB threads -- one
+    // half-wave per block -- instead of one lane per 8-lane group
+    __shared__ double sF[CPB][2];
+    if (l == 0) {
+        sF[g][0] = (double)fx;
+        sF[g][1] = (double)fy;
+    }
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
     double disp = 0.0;
-    if (valid && l == 0) {
-        const double th = c.th[i];
+    const int iu = xcd_block(blockIdx.x, gridDim.x) * CPB + (int)threadIdx.x;
+    if (threadIdx.x < CPB && iu < N) {
+        const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
+        const double xu = c.x[iu], yu = c.y[iu];
+        const double Fx = sF[threadIdx.x][0], Fy = sF[threadIdx.x][1];
+        const double th = c.th[iu];
         double sn, cs;
         sincos(th, &sn, &cs);
-        const double xn = xi + P.dt * (P.mu * (double)fx + P.v0 * cs);
-        const double yn = yi + P.dt * (P.mu * (double)fy + P.v0 * sn);
-        double X = rint(xn * P.scale), Y = rint(yn * P.scale);
-        if (X < 0.0) X += P.LXu;
-        else if (X >= P.LXu) X -= P.LXu;
-        if (Y < 0.0) Y += P.LYu;
-        else if (Y >= P.LYu) Y -= P.LYu;
-        if (!(X >= 0.0 && X < P.LXu && Y >= 0.0 && Y < P.LYu)) {
+        const double xn = xu + Q.dt * (Q.mu * Fx + Q.v0 * cs);
+        const double yn = yu + Q.dt * (Q.mu * Fy + Q.v0 * sn);
+        double X = rint(xn * Q.scale), Y = rint(yn * Q.scale);
+        if (X < 0.0) X += Q.LXu;
+        else if (X >= Q.LXu) X -= Q.LXu;
+        if (Y < 0.0) Y += Q.LYu;
+        else if (Y >= Q.LYu) Y -= Q.LYu;
+        if (!(X >= 0.0 && X < Q.LXu && Y >= 0.0 && Y < Q.LYu)) {
             atomicOr(&st->err, ERR_NONFINITE);
-            X = rint(xi * P.scale);  // keep the stored state finite and inside the box
-            Y = rint(yi * P.scale);
+            X = rint(xu * Q.scale);  // keep the stored state finite and inside the box
+            Y = rint(yu * Q.scale);
         }
-        const double xq = X * P.inv_scale, yq = Y * P.inv_scale;
-        xo[i] = xq;
-        yo[i] = yq;
-        tho[i] = th + P.amp * normal_for(P.seed, st->step, (uint64_t)c.tag[i]);
-        const double ddx = mimg(xq - xi, P.Lx, P.hLx), ddy = mimg(yq - yi, P.Ly, P.hLy);
+        const double xq = X * Q.inv_scale, yq = Y * Q.inv_scale;
+        xo[iu] = xq;
+        yo[iu] = yq;
+        tho[iu] = th + Q.amp * normal_for(Q.seed, st->step, (uint64_t)c.tag[iu]);
+        const double ddx = mimg(xq - xu, Q.Lx, Q.hLx), ddy = mimg(yq - yu, Q.Ly, Q.hLy);
         disp = sqrt(ddx * ddx + ddy * ddy);
     }
-    unsigned long long b = __double_as_longlong(disp);
-    for (int off = 32; off >= 1; off >>= 1) {
-        const unsigned long long o = __shfl_xor(b, off);
-        b = o > b ? o : b;
-    }
-    if ((threadIdx.x & 63) == 0 && b) atomicMax(&st->disp_bits, b);
+    // block max of the displacement -> blockmax[block] (reduced by k_finalize)
+    for (int off = 32; off >= 1; off >>= 1) disp = fmax(disp, __shfl_xor(disp, off));
+    if (threadIdx.x == 0) blockmax[blockIdx.x] = disp;
 }
 
 // ---------------------------------------------------------------- geometry + validity test
@@ -289,9 +316,11 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
 // OPP: rebuild opp first -- in the CCW ring of j_m the pattern
 // ..., opp_m, j_{m+1}, i, ... must appear; otherwise the rings disagree and
 // the cells are flagged.
-template <typename R, bool MULTI, int KC, bool LIST, bool OPP>
+__device__ void finalize_block(DevState* st, int rounds, const double* blockmax, int nblk);
+
+template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool FINAL = false>
 __global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
-                                              int N, int round)
+                                              int N, int round, const double* blockmax = nullptr, int nblk = 0)
 {
     constexpr int NS = KC / GL;
     __shared__ double sD[CPB][KC][2];
@@ -403,6 +432,21 @@ __global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam
         __syncthreads();  // LDS is reused by the next group of cells
     }
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
+    if (FINAL) {
+        // the last block to finish closes the step (no separate launch)
+        __shared__ int s_last;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            s_last = atomicAdd(&st->done, 1) == (int)gridDim.x - 1;
+        }
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            if (threadIdx.x == 0) st->done = 0;
+            finalize_block(st, round + 1, blockmax, nblk);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- repair
@@ -430,7 +474,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
     const int nw = st->wl_count[round];
     const int* __restrict__ wl = w.wl[round & 1];
     const double drift = st->drift;
-    int exact = 0;
+    int exact = 0, nrep = 0;
     for (int wi = blockIdx.x; wi < nw; wi += gridDim.x) {
         const int i = wl[wi];
         if (lane == 0) atomicAnd(&w.flagbits[i >> 5], ~(1u << (i & 31)));
@@ -438,7 +482,9 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
         const double xi = c.x[i], yi = c.y[i];
         const int kold = min((int)c.deg[i], KC);
         const double Rmax = 0.5 * fmin(P.Lx, P.Ly) * (1.0 - 1e-9);
-        double Rs = fmin(P.R0, Rmax);
+        // first radius: at least R0, and as large as the 7x7 bin window
+        // around the cell covers after the drift since the last re-sort
+        double Rs = fmin(fmax(P.R0, 3.0 * fmin(P.bsx, P.bsy) - drift), Rmax);
         int k = 0;
         bool ok = false, at_max = false;
         int last_n = 0, last_closed = 0, attempts = 0;
@@ -525,21 +571,67 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
             while (k <= KMAX) {
                 const double cx = sx[cur], cy = sy[cur];
                 const int gc = sid[cur];
+                // Next neighbour after c: the left-side candidate whose circle
+                // through (i, c, p) is first met when the circle centre
+                // c/2 + t perp(c) moves left; t_p = (|p|^2 - c.p) / (2 c x p).
+                // p strictly inside circle(i, c, q)  <=>  t_p < t_q.  The keys
+                // are double estimates with a per-key error bound; the exact
+                // in-circle order decides whenever the two best keys overlap.
+                double t1 = INFINITY, e1 = 0.0, t2 = INFINITY, e2 = 0.0;
                 int nb = -1;
                 for (int q = lane; q < n; q += 64) {
                     if (q == cur) continue;
                     const double px = sx[q], py = sy[q];
-                    if (cross_sign(cx, cy, px, py, cx * py - cy * px, P.scale) <= 0) continue;
-                    if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, c.tag, i, gc, sid[nb], sid[q],
-                                                P.scale, &exact) > 0)
-                        nb = q;
+                    const double cr = cx * py - cy * px;
+                    if (cross_sign(cx, cy, px, py, cr, P.scale) <= 0) continue;
+                    const double num = px * px + py * py - (cx * px + cy * py);
+                    const double t = num / (2.0 * cr);
+                    // rounding bounds: |d num| <= 4e-15 (|p|^2 + |c.p|), |d cr| <= ecr
+                    const double ecr = 1e-15 * (fabs(cx * py) + fabs(cy * px));
+                    const double bnd =
+                        (ecr > 0.25 * fabs(cr))
+                            ? INFINITY
+                            : 4e-15 * (px * px + py * py + fabs(cx * px) + fabs(cy * py)) / (2.0 * fabs(cr)) +
+                                  fabs(t) * (2.0 * ecr / fabs(cr) + 4e-15);
+                    if (t < t1) {
+                        t2 = t1; e2 = e1;
+                        t1 = t; e1 = bnd; nb = q;
+                    } else if (t < t2) {
+                        t2 = t; e2 = bnd;
+                    }
                 }
+                // wave arg-min of (t1, nb) keeping the runner-up key
                 for (int off = 32; off >= 1; off >>= 1) {
-                    const int ob = __shfl_xor(nb, off);
-                    if (ob >= 0 && ob != nb &&
-                        (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], c.tag, i, gc, sid[nb],
-                                                 sid[ob], P.scale, &exact) > 0))
-                        nb = ob;
+                    const double ot1 = __shfl_xor(t1, off), oe1 = __shfl_xor(e1, off);
+                    const double ot2 = __shfl_xor(t2, off), oe2 = __shfl_xor(e2, off);
+                    const int onb = __shfl_xor(nb, off);
+                    if (ot1 < t1 || (ot1 == t1 && onb >= 0 && (nb < 0 || onb < nb))) {
+                        // other side wins: my best becomes a runner-up candidate
+                        if (t1 < ot2) { t2 = t1; e2 = e1; } else { t2 = ot2; e2 = oe2; }
+                        t1 = ot1; e1 = oe1; nb = onb;
+                    } else {
+                        if (ot1 < t2) { t2 = ot1; e2 = oe1; }
+                    }
+                }
+                if (nb >= 0 && t2 - e2 <= t1 + e1) {
+                    // the keys cannot separate the best from the runner-up:
+                    // exact arg-min under the in-circle order (rare)
+                    nb = -1;
+                    for (int q = lane; q < n; q += 64) {
+                        if (q == cur) continue;
+                        const double px = sx[q], py = sy[q];
+                        if (cross_sign(cx, cy, px, py, cx * py - cy * px, P.scale) <= 0) continue;
+                        if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, c.tag, i, gc, sid[nb], sid[q],
+                                                    P.scale, &exact) > 0)
+                            nb = q;
+                    }
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const int ob = __shfl_xor(nb, off);
+                        if (ob >= 0 && ob != nb &&
+                            (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], c.tag, i, gc, sid[nb],
+                                                     sid[ob], P.scale, &exact) > 0))
+                            nb = ob;
+                    }
                 }
                 if (nb < 0) break;  // star open: search disk too small
                 if (nb == start) {
@@ -605,36 +697,44 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
                 mi = oi;
             }
         }
-        // touch the old neighbourhood before overwriting it
-        for (int m = lane; m < kold; m += 64) push_touch(w, st, round, c.ring[i * KC + m]);
+        // touch the old neighbourhood before overwriting it (k, kold <= 64:
+        // one pass of the wave)
+        push_touch(w, st, round, lane < kold ? c.ring[i * KC + lane] : -1);
         __syncthreads();
-        for (int m = lane; m < k; m += 64) {
-            const int q = sid[s_ring[(mi + m) % k]];
-            c.ring[i * KC + m] = q;
+        {
+            const int q = lane < k ? sid[s_ring[(mi + lane) % k]] : -1;
+            if (lane < k) c.ring[i * KC + lane] = q;
             push_touch(w, st, round, q);
         }
-        if (lane == 0) {
-            c.deg[i] = (uint8_t)k;
-            push_touch(w, st, round, i);
-            atomicAdd(&st->repaired, 1ull);
-            atomicMax(&st->max_deg, k);
-        }
+        push_touch(w, st, round, lane == 0 ? i : -1);
+        if (lane == 0) c.deg[i] = (uint8_t)k;
+        nrep++;
         __syncthreads();
     }
+    if (lane == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
 }
 
 // ---------------------------------------------------------------- step bookkeeping
 // After the last device repair round: count the step, accumulate the drift,
 // halt if rounds remain (the host finishes them) or an error was raised, and
-// clear the per-step counters otherwise.
-__global__ void k_finalize(DevState* st, int rounds)
+// clear the per-step counters otherwise.  Run by one 256-thread block: the
+// last block of the step's final re-test.
+__device__ void finalize_block(DevState* st, int rounds, const double* blockmax, int nblk)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (st->halt) return;
+    __shared__ double smax[256];
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) m = fmax(m, blockmax[b]);
+    smax[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
     st->step += 1ull;
-    st->drift += __longlong_as_double((long long)st->disp_bits);
-    st->disp_bits = 0ull;
+    st->drift += smax[0];
+    st->disp_bits = __double_as_longlong(smax[0]);
     int used = 0;
     for (int r = 0; r < rounds; r++) used += st->wl_count[r] > 0;
     st->rounds += (unsigned long long)used;
@@ -693,54 +793,79 @@ __global__ void k_bin_keys(Cells<R> c, Work w, const SysParam* __restrict__ sp, 
     atomicAdd(&hist[kk], 1);
 }
 
-// exclusive scan of n ints by one 1024-thread block (16 items per thread per
-// pass); out has n + 1 entries
-__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ in, int* __restrict__ out, int n,
-                                               const DevState* st)
+// exclusive scan of n ints into out[0..n] (out[n] = total) in three passes:
+// per-chunk sums, scan of the chunk sums, chunk scans with their offsets
+constexpr int SCAN_CHUNK = 4096;  // elements per 256-thread block (16 per thread)
+
+__device__ __forceinline__ int block_inclusive_scan256(int v, int* part)
 {
-    constexpr int IPT = 16, CH = 1024 * IPT;
-    __shared__ int part[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(v, off);
+        if (lane >= off) v += o;
+    }
+    if (lane == 63) part[wid] = v;
+    __syncthreads();
+    int add = 0;
+    for (int k = 0; k < wid; k++) add += part[k];
+    __syncthreads();
+    return v + add;
+}
+
+__global__ __launch_bounds__(256) void k_scan_sums(const int* __restrict__ in, int n, int* __restrict__ sums,
+                                                   const DevState* st)
+{
+    __shared__ int part[4];
+    if (st->halt) return;
+    const int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) v += (base + k < n) ? in[base + k] : 0;
+    const int tot = block_inclusive_scan256(v, part);
+    if (threadIdx.x == 255) sums[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of nb chunk sums in place (any nb, 256 at a time)
+__global__ __launch_bounds__(256) void k_scan_offsets(int* sums, int nb, const DevState* st)
+{
+    __shared__ int part[4];
     __shared__ int carry;
     if (st->halt) return;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0) carry = 0;
+    if (threadIdx.x == 0) carry = 0;
     __syncthreads();
-    for (int base = 0; base < n; base += CH) {
-        const int i0 = base + tid * IPT;
-        int v[IPT];
-        int sum = 0;
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            v[k] = (i0 + k < n) ? in[i0 + k] : 0;
-            sum += v[k];
-        }
-        int inc = sum;
-        for (int off = 1; off < 64; off <<= 1) {
-            const int o = __shfl_up(inc, off);
-            if (lane >= off) inc += o;
-        }
-        if (lane == 63) part[wid] = inc;
+    for (int b0 = 0; b0 < nb; b0 += 256) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nb ? sums[b] : 0;
+        const int inc = block_inclusive_scan256(v, part);
+        const int c0 = carry;
+        if (b < nb) sums[b] = c0 + inc - v;
         __syncthreads();
-        if (wid == 0) {
-            int p = lane < 16 ? part[lane] : 0;
-            for (int off = 1; off < 16; off <<= 1) {
-                const int o = __shfl_up(p, off);
-                if (lane >= off) p += o;
-            }
-            if (lane < 16) part[lane] = p;
-        }
-        __syncthreads();
-        int run = carry + (wid ? part[wid - 1] : 0) + inc - sum;
-#pragma unroll
-        for (int k = 0; k < IPT; k++) {
-            if (i0 + k < n) out[i0 + k] = run;
-            run += v[k];
-        }
-        __syncthreads();
-        if (tid == 1023) carry = run;
+        if (threadIdx.x == 255) carry = c0 + inc;
         __syncthreads();
     }
-    if (tid == 0) out[n] = carry;
+    if (threadIdx.x == 0) sums[nb] = carry;  // grand total
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int* __restrict__ in, int* __restrict__ out, int n,
+                                                    const int* __restrict__ offs, const DevState* st)
+{
+    __shared__ int part[4];
+    if (st->halt) return;
+    const int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
+    int v[16];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        sum += v[k];
+    }
+    int run = offs[blockIdx.x] + block_inclusive_scan256(sum, part) - sum;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = offs[gridDim.x];  // total
 }
 
 __global__ void k_bin_scatter(const int* key, const int* start, int* fill, int* perm, int n, const DevState* st)
