@@ -135,6 +135,43 @@ def batched(spv, inputs, precision):
     return make
 
 
+def adjoint_cost(spv, inputs):
+    """spv_n4096_adjoint workload: gradient of the time-averaged mean shape
+    index over T steps (checkpoint every k) w.r.t. per-cell p0; cost of
+    forward+backward relative to the plain FP64 forward of the same T steps."""
+    import numpy as np
+    import torch
+    w = inputs.WORKLOADS["spv_n4096_adjoint"]
+    n, L, T, k = w["N"], w["L"], w["steps"], w["ckpt"]
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    p0 = inputs.per_cell_p0(n, w["p0"], w["p0_sigma"], w["seed"])
+    prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"])
+
+    def fresh():
+        s = spv.System(x, y, L, L, P0=p0, params=prm)
+        s.step(200)  # leave the random-start transient
+        return s
+    s = fresh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(T)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    s.close()
+    s = fresh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Q = s.traj_forward(T, k)
+    t1 = time.perf_counter()
+    g = s.traj_backward(1.0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.close()
+    return {"cells": n, "steps": T, "ckpt_every": k, "Q": Q, "grad_norm": float(np.linalg.norm(g)),
+            "plain_forward_ms": t_plain * 1e3, "traj_forward_ms": (t1 - t0) * 1e3,
+            "traj_backward_ms": (t2 - t1) * 1e3, "adjoint_over_forward": (t2 - t0) / t_plain}
+
+
 def roofline_of(kt, ncells):
     dom = max(("force_update", "geometry_test"), key=lambda k: kt[k][0])
     ms, launches = kt[dom]
@@ -218,6 +255,9 @@ def main():
                            "roofline_frac_hbm": ach / HBM_PEAK_GBS, "dominant_kernel": d}
             print(f"[bench] {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)
         extra["mixed_vs_fp64_speedup_n100k"] = extra["spv_n100k_mixed"]["value"] / head["value"]
+        extra["adjoint_n4096"] = adjoint_cost(spv, inputs)
+        print(f"[bench] adjoint/forward: {extra['adjoint_n4096']['adjoint_over_forward']:.2f}", file=sys.stderr,
+              flush=True)
         out["extra"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)

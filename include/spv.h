@@ -174,6 +174,34 @@ spv_status spv_get_system_observables(spv_sys* s, int32_t sys, double* E, double
 spv_status spv_set_timing(spv_sys* s, int32_t enable);
 spv_status spv_kernel_time(spv_sys* s, int32_t which, double* total_ms, int64_t* launches);
 
+/*
+ * Trajectory adjoint (single FP64 system).  Gradient of the time-averaged
+ * mean shape index Q = (1/T) sum_{t=1..T} qbar(r_t), qbar = mean P_i/sqrt(A_i),
+ * with respect to the per-cell target shape index p0_i (P0_i = p0_i sqrt(A0_i)).
+ *
+ * spv_traj_forward runs T steps from the current state (noise counter
+ * continuing), checkpointing the full state every ckpt_every steps, and
+ * returns Q.  spv_traj_backward(dQ) recomputes every segment from its
+ * checkpoint (bit-reproducibly, with the same topology) and propagates the
+ * adjoint backwards: lambda_{t-1} = lambda_t + dt mu dF(r_{t-1})[lambda_t]
+ * (+ dQ/dr_{t-1}), dQ/dP0 += dt mu 2 K_P dP(r_{t-1})[lambda_t], where dF[v] =
+ * -H v is the Hessian-vector product of Eq. 1 through the Voronoi geometry
+ * with the recorded topology (App. A/B derivatives in forward-mode tangent
+ * arithmetic).  The quantisation of positions is not differentiated.
+ * dQ_dp0 receives dQ * dQ/dp0 (N entries, tag order, host or device).
+ * The handle ends in the state reached by spv_traj_forward.  Any spv_step
+ * between the two calls invalidates the record (SPV_EINVAL).
+ */
+spv_status spv_traj_forward(spv_sys* s, int64_t T, int64_t ckpt_every, double* Q);
+spv_status spv_traj_backward(spv_sys* s, double dQ, double* dQ_dp0);
+
+/*
+ * Directional derivative of the forces along v at the current state with the
+ * current topology: dF[v] = -H v (Hessian-vector product of Eq. 1), tag
+ * order (v and the result: N entries per component).  FP64 handles.
+ */
+spv_status spv_force_tangent(spv_sys* s, const double* vx, const double* vy, double* fx, double* fy);
+
 /* Release all device state of the handle. */
 spv_status spv_destroy(spv_sys* s);
 

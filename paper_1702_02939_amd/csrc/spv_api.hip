@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/spv.h"
+#include "spv_adjoint.hpp"
 #include "spv_kernels.hpp"
 
 using namespace spv;
@@ -94,6 +95,21 @@ struct EvPair {
     hipEvent_t a = nullptr, b = nullptr;
 };
 
+// Device copy of the dynamic state of a single-system handle (positions,
+// directors, topology, geometry and energy coefficients), FP64.
+struct Snapshot {
+    double *x = nullptr, *y = nullptr, *th = nullptr;
+    uint8_t* deg = nullptr;
+    int *ring = nullptr, *opp = nullptr;
+    double *A = nullptr, *P = nullptr, *ca = nullptr, *cb = nullptr;
+};
+
+struct TrajCheckpoint {
+    Snapshot snap;
+    int pos = 0;
+    uint64_t step = 0;
+};
+
 }  // namespace
 
 struct spv_sys {
@@ -130,6 +146,14 @@ struct spv_sys {
     int64_t t_n[T_COUNT] = {0, 0, 0};
     std::vector<std::pair<int, EvPair>> pending;  // eager launches
     std::vector<EvPair> pool;
+    // trajectory adjoint
+    bool no_resort = false;       // keep the memory order fixed during a recorded trajectory
+    int64_t traj_T = 0, traj_k = 0;
+    bool traj_valid = false;
+    std::vector<TrajCheckpoint> ckpt;  // state at steps 0, k, 2k, ... and at T (last)
+    std::vector<Snapshot> seg;         // per-step states of the segment being differentiated
+    double *d_lx = nullptr, *d_ly = nullptr, *d_g = nullptr, *d_dA = nullptr, *d_dP = nullptr;
+    double *d_fdx = nullptr, *d_fdy = nullptr, *d_aq = nullptr, *d_bq = nullptr, *d_acc = nullptr;
 };
 
 namespace {
@@ -419,8 +443,8 @@ spv_status run_steps(spv_sys* s, int64_t n)
 {
     if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
     while (n > 0) {
-        if (s->pos == s->unit) ST_TRY(do_resort_eager(s));
-        if (s->pos == 0 && n >= s->unit && s->use_graphs && !s->timing) {
+        if (s->pos >= s->unit && !(s->pos & 1) && !s->no_resort) ST_TRY(do_resort_eager(s));
+        if (s->pos == 0 && n >= s->unit && s->use_graphs && !s->timing && !s->no_resort) {
             const int g = s->cfg;
             if (!s->gexec[g]) ST_TRY(capture_graph(s, g));
             const uint64_t before = s->step;
@@ -712,6 +736,239 @@ spv_status out_tag_order(spv_sys* s, const T* src, double* dst)
         dst);
 }
 
+// ---------------------------------------------------------------- trajectory adjoint
+spv_status snap_alloc(spv_sys* s, Snapshot& z)
+{
+    if (z.x) return SPV_OK;
+    const size_t N = s->N, K = s->KC;
+    ST_TRY(dalloc(s, &z.x, N));
+    ST_TRY(dalloc(s, &z.y, N));
+    ST_TRY(dalloc(s, &z.th, N));
+    ST_TRY(dalloc(s, &z.deg, N));
+    ST_TRY(dalloc(s, &z.ring, N * K));
+    ST_TRY(dalloc(s, &z.opp, N * K));
+    ST_TRY(dalloc(s, &z.A, N));
+    ST_TRY(dalloc(s, &z.P, N));
+    ST_TRY(dalloc(s, &z.ca, N));
+    ST_TRY(dalloc(s, &z.cb, N));
+    return SPV_OK;
+}
+
+// copy between the live state (current configuration and parity) and z
+spv_status snap_copy(spv_sys* s, Snapshot& z, bool take)
+{
+    const size_t N = s->N, K = s->KC;
+    const ArraySet& cur = s->set[s->cfg];
+    const ArraySet& par = s->set[(s->pos & 1) ? s->cfg ^ 1 : s->cfg];
+    auto cp = [&](void* live, void* snap, size_t bytes) {
+        return take ? hipMemcpyAsync(snap, live, bytes, hipMemcpyDeviceToDevice, s->stream)
+                    : hipMemcpyAsync(live, snap, bytes, hipMemcpyDeviceToDevice, s->stream);
+    };
+    HIP_TRY(cp(par.x, z.x, N * 8));
+    HIP_TRY(cp(par.y, z.y, N * 8));
+    HIP_TRY(cp(par.th, z.th, N * 8));
+    HIP_TRY(cp(cur.deg, z.deg, N));
+    HIP_TRY(cp(cur.ring, z.ring, N * K * 4));
+    HIP_TRY(cp(cur.opp, z.opp, N * K * 4));
+    HIP_TRY(cp(cur.A, z.A, N * 8));
+    HIP_TRY(cp(cur.P, z.P, N * 8));
+    HIP_TRY(cp(cur.ca, z.ca, N * 8));
+    HIP_TRY(cp(cur.cb, z.cb, N * 8));
+    return SPV_OK;
+}
+
+Cells<double> snap_cells(const spv_sys* s, const Snapshot& z)
+{
+    Cells<double> c = cells<double>(s, s->cfg, 0);
+    c.x = z.x;
+    c.y = z.y;
+    c.th = z.th;
+    c.deg = z.deg;
+    c.ring = z.ring;
+    c.opp = z.opp;
+    c.A = z.A;
+    c.P = z.P;
+    c.ca = z.ca;
+    c.cb = z.cb;
+    return c;
+}
+
+spv_status traj_buffers(spv_sys* s)
+{
+    if (s->d_lx) return SPV_OK;
+    const size_t N = s->N;
+    for (double** p : {&s->d_lx, &s->d_ly, &s->d_g, &s->d_dA, &s->d_dP, &s->d_fdx, &s->d_fdy, &s->d_aq, &s->d_bq})
+        ST_TRY(dalloc(s, p, N));
+    ST_TRY(dalloc(s, &s->d_acc, 1));
+    return SPV_OK;
+}
+
+spv_status take_checkpoint(spv_sys* s, TrajCheckpoint& c)
+{
+    ST_TRY(snap_alloc(s, c.snap));
+    ST_TRY(snap_copy(s, c.snap, true));
+    c.pos = s->pos;
+    c.step = s->step;
+    return SPV_OK;
+}
+
+// restore a checkpoint, including the device noise counter
+spv_status restore_checkpoint(spv_sys* s, const TrajCheckpoint& c)
+{
+    s->pos = c.pos;
+    s->step = c.step;
+    ST_TRY(snap_copy(s, const_cast<Snapshot&>(c.snap), false));
+    ST_TRY(read_state(s));
+    s->h_st->step = c.step;
+    HIP_TRY(hipMemcpyAsync(&s->d_st->step, &s->h_st->step, sizeof(unsigned long long), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return SPV_OK;
+}
+
+spv_status traj_forward(spv_sys* s, int64_t T, int64_t k, double* Q)
+{
+    if (s->S != 1 || s->mixed) return fail(SPV_EINVAL, "the trajectory adjoint needs a single FP64 system");
+    if (T < 1 || k < 1) return fail(SPV_EINVAL, "T and ckpt_every must be positive");
+    if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
+    ST_TRY(traj_buffers(s));
+    const int64_t nck = (T + k - 1) / k;
+    s->ckpt.resize(nck + 1);
+    s->traj_valid = false;
+    s->no_resort = true;
+    HIP_TRY(hipMemsetAsync(s->d_acc, 0, sizeof(double), s->stream));
+    const double w = 1.0 / (double)T;
+    spv_status st = SPV_OK;
+    for (int64_t t = 0; t < T && st == SPV_OK; t++) {
+        if (t % k == 0) st = take_checkpoint(s, s->ckpt[t / k]);
+        if (st == SPV_OK) st = run_steps(s, 1);
+        if (st == SPV_OK) {
+            const ArraySet& cur = s->set[s->cfg];
+            hipLaunchKernelGGL(k_qbar_accum, dim3(1), dim3(256), 0, s->stream, (const double*)cur.A,
+                               (const double*)cur.P, s->N, w, s->d_acc);
+        }
+    }
+    if (st == SPV_OK) st = take_checkpoint(s, s->ckpt[nck]);
+    s->no_resort = false;
+    if (st != SPV_OK) return st;
+    double q = 0.0;
+    HIP_TRY(hipMemcpyAsync(&q, s->d_acc, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (Q) *Q = q;
+    s->traj_T = T;
+    s->traj_k = k;
+    s->traj_valid = true;
+    return SPV_OK;
+}
+
+template <int KC>
+void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_prev, bool add_grad)
+{
+    const int N = s->N;
+    const unsigned g256 = grid_for(N, 256);
+    const double w = 1.0 / (double)s->traj_T;
+    if (add_grad) {
+        // lambda += d(w qbar)/dr at r_t: the force kernel with the qbar coefficients
+        Cells<double> ct = snap_cells(s, at_t);
+        hipLaunchKernelGGL(k_qbar_coef, dim3(g256), dim3(256), 0, s->stream, (const double*)ct.A,
+                           (const double*)ct.P, N, w, s->d_aq, s->d_bq);
+        ct.ca = s->d_aq;
+        ct.cb = s->d_bq;
+        hipLaunchKernelGGL((k_force<double, false, KC, false>), dim3(cell_grid(s)), dim3(256), 0, s->stream, ct,
+                           (double*)nullptr, (double*)nullptr, (double*)nullptr, s->d_fdx, s->d_fdy, s->d_sp,
+                           s->d_st, N, s->d_blockmax);
+        hipLaunchKernelGGL(k_adj_add_grad, dim3(g256), dim3(256), 0, s->stream, s->d_lx, s->d_ly,
+                           (const double*)s->d_fdx, (const double*)s->d_fdy, N);
+    }
+    // step r_{t-1} -> r_t: g += dt mu 2 K_P dP[lambda], lambda += dt mu dF[lambda]
+    Cells<double> cp = snap_cells(s, at_prev);
+    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(g256), dim3(256), 0, s->stream, cp, (const double*)s->d_lx,
+                       (const double*)s->d_ly, s->d_sp, N, s->d_dA, s->d_dP);
+    hipLaunchKernelGGL((k_tangent_force<KC>), dim3(g256), dim3(256), 0, s->stream, cp, (const double*)s->d_lx,
+                       (const double*)s->d_ly, (const double*)s->d_dA, (const double*)s->d_dP, s->d_sp, N, s->d_fdx,
+                       s->d_fdy);
+    hipLaunchKernelGGL(k_adj_step, dim3(g256), dim3(256), 0, s->stream, s->d_lx, s->d_ly, (const double*)s->d_fdx,
+                       (const double*)s->d_fdy, (const double*)s->d_dP, s->d_g, s->d_sp, (const int*)cp.sys, N);
+}
+
+__global__ void k_adj_out(const double* g, const double* A0, const int* tag, double scale, double* out, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[tag[i]] = scale * g[i] * sqrt(A0[i]);
+}
+
+spv_status traj_backward(spv_sys* s, double dQ, double* dQ_dp0)
+{
+    if (!s->traj_valid) return fail(SPV_EINVAL, "spv_traj_forward must precede spv_traj_backward");
+    const int64_t T = s->traj_T, k = s->traj_k, nck = (T + k - 1) / k;
+    const size_t N = s->N;
+    s->seg.resize(k + 1);
+    for (auto& z : s->seg) ST_TRY(snap_alloc(s, z));
+    HIP_TRY(hipMemsetAsync(s->d_lx, 0, N * 8, s->stream));
+    HIP_TRY(hipMemsetAsync(s->d_ly, 0, N * 8, s->stream));
+    HIP_TRY(hipMemsetAsync(s->d_g, 0, N * 8, s->stream));
+    s->no_resort = true;
+    spv_status st = SPV_OK;
+    for (int64_t c = nck - 1; c >= 0 && st == SPV_OK; c--) {
+        // recompute the segment from its checkpoint, recording every state
+        st = restore_checkpoint(s, s->ckpt[c]);
+        if (st == SPV_OK) st = snap_copy(s, s->seg[0], true);
+        const int64_t m = std::min<int64_t>(k, T - c * k);
+        for (int64_t j = 1; j <= m && st == SPV_OK; j++) {
+            st = run_steps(s, 1);
+            if (st == SPV_OK) st = snap_copy(s, s->seg[j], true);
+        }
+        for (int64_t j = m; j >= 1 && st == SPV_OK; j--) {
+            if (s->KC == 16) enqueue_adjoint_step<16>(s, s->seg[j], s->seg[j - 1], true);
+            else enqueue_adjoint_step<32>(s, s->seg[j], s->seg[j - 1], true);
+            if (hipGetLastError() != hipSuccess) st = fail(SPV_EHIP, "adjoint kernel launch failed");
+        }
+    }
+    // back to the state reached by the forward pass
+    if (st == SPV_OK) st = restore_checkpoint(s, s->ckpt[nck]);
+    s->no_resort = false;
+    if (st != SPV_OK) return st;
+    const ArraySet& cur = s->set[s->cfg];
+    return with_tag_order(
+        s,
+        [&](double* stage) {
+            hipLaunchKernelGGL(k_adj_out, dim3(grid_for(s->N, 256)), dim3(256), 0, s->stream, (const double*)s->d_g,
+                               (const double*)cur.A0, (const int*)cur.tag, dQ, stage, s->N);
+        },
+        dQ_dp0);
+}
+
+// H v for tests: dF[v] at the current state (v and the result in tag order)
+template <int KC>
+spv_status hvp_impl(spv_sys* s, const double* vx, const double* vy, double* hx, double* hy)
+{
+    const int N = s->N;
+    ST_TRY(traj_buffers(s));
+    const ArraySet& cur = s->set[s->cfg];
+    std::vector<double> hvx, hvy;
+    ST_TRY(copy_in(vx, hvx, N));
+    ST_TRY(copy_in(vy, hvy, N));
+    std::vector<int> tag(N);
+    HIP_TRY(hipMemcpy(tag.data(), cur.tag, N * sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<double> mx(N), my(N);
+    for (int i = 0; i < N; i++) {
+        mx[i] = hvx[tag[i]];
+        my[i] = hvy[tag[i]];
+    }
+    HIP_TRY(hipMemcpyAsync(s->d_lx, mx.data(), N * 8, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->d_ly, my.data(), N * 8, hipMemcpyHostToDevice, s->stream));
+    Cells<double> c = cells<double>(s, s->cfg, s->pos & 1);
+    const unsigned g256 = grid_for(N, 256);
+    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(g256), dim3(256), 0, s->stream, c, (const double*)s->d_lx,
+                       (const double*)s->d_ly, s->d_sp, N, s->d_dA, s->d_dP);
+    hipLaunchKernelGGL((k_tangent_force<KC>), dim3(g256), dim3(256), 0, s->stream, c, (const double*)s->d_lx,
+                       (const double*)s->d_ly, (const double*)s->d_dA, (const double*)s->d_dP, s->d_sp, N, s->d_fdx,
+                       s->d_fdy);
+    HIP_TRY(hipGetLastError());
+    ST_TRY(out_tag_order(s, s->d_fdx, hx));
+    return out_tag_order(s, s->d_fdy, hy);
+}
+
 }  // namespace
 
 // ====================================================================== C-ABI
@@ -798,6 +1055,7 @@ spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const 
 spv_status spv_step(spv_sys* s, int64_t nsteps)
 {
     if (!s || nsteps < 0) return fail(SPV_EINVAL, "bad handle or nsteps");
+    s->traj_valid = false;  // the recorded trajectory no longer ends at the current state
     return run_steps(s, nsteps);
 }
 
@@ -982,6 +1240,25 @@ spv_status spv_kernel_time(spv_sys* s, int32_t which, double* total_ms, int64_t*
     if (total_ms) *total_ms = s->t_ms[which];
     if (launches) *launches = s->t_n[which];
     return SPV_OK;
+}
+
+spv_status spv_traj_forward(spv_sys* s, int64_t T, int64_t ckpt_every, double* Q)
+{
+    if (!s) return fail(SPV_EINVAL, "bad handle");
+    return traj_forward(s, T, ckpt_every, Q);
+}
+
+spv_status spv_traj_backward(spv_sys* s, double dQ, double* dQ_dp0)
+{
+    if (!s || !dQ_dp0) return fail(SPV_EINVAL, "bad argument");
+    return traj_backward(s, dQ, dQ_dp0);
+}
+
+spv_status spv_force_tangent(spv_sys* s, const double* vx, const double* vy, double* fx, double* fy)
+{
+    if (!s || !vx || !vy || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
+    if (s->mixed) return fail(SPV_EINVAL, "the force tangent needs an FP64 handle");
+    return s->KC == 16 ? hvp_impl<16>(s, vx, vy, fx, fy) : hvp_impl<32>(s, vx, vy, fx, fy);
 }
 
 spv_status spv_destroy(spv_sys* s)

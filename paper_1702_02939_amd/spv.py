@@ -69,6 +69,9 @@ _SIGS = {
     "spv_get_observables": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d), _P],
     "spv_set_timing": [_H, _i32],
     "spv_kernel_time": [_H, _i32, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
+    "spv_traj_forward": [_H, _i64, _i64, ctypes.POINTER(_d)],
+    "spv_traj_backward": [_H, _d, _P],
+    "spv_force_tangent": [_H, _P, _P, _P, _P],
     "spv_destroy": [_H],
 }
 for _name, _args in _SIGS.items():
@@ -231,6 +234,21 @@ def spv_kernel_time(h, which):
     return ms.value, n.value
 
 
+def spv_traj_forward(h, T, ckpt_every):
+    Q = _d()
+    _check(_lib.spv_traj_forward(h, int(T), int(ckpt_every), ctypes.byref(Q)), "spv_traj_forward")
+    return Q.value
+
+
+def spv_traj_backward(h, dQ, out):
+    _check(_lib.spv_traj_backward(h, float(dQ), _ptr(out)), "spv_traj_backward")
+
+
+def spv_force_tangent(h, vx, vy, fx, fy):
+    keep = [_f64(vx), _f64(vy)]
+    _check(_lib.spv_force_tangent(h, _ptr(keep[0]), _ptr(keep[1]), _ptr(fx), _ptr(fy)), "spv_force_tangent")
+
+
 def spv_destroy(h):
     _check(_lib.spv_destroy(h), "spv_destroy")
 
@@ -300,6 +318,19 @@ class System:
 
     def observables(self):
         return spv_get_observables(self.h)
+
+    def traj_forward(self, T, ckpt_every):
+        return spv_traj_forward(self.h, T, ckpt_every)
+
+    def traj_backward(self, dQ=1.0):
+        g = np.zeros(self.N)
+        spv_traj_backward(self.h, dQ, g)
+        return g
+
+    def force_tangent(self, vx, vy):
+        fx, fy = np.zeros(self.N), np.zeros(self.N)
+        spv_force_tangent(self.h, vx, vy, fx, fy)
+        return fx, fy
 
     def close(self):
         if self.h:

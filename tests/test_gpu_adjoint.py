@@ -1,0 +1,115 @@
+"""Adjoint pieces of the HIP path against the CPU oracle.
+
+- Hessian-vector product dF[v] = -H v against central finite differences of
+  the oracle's forces (topology held fixed), its symmetry v.Hw = w.Hv and
+  translation invariance H 1 = 0;
+- dQ/dp0 of the time-averaged mean shape index against central finite
+  differences of the oracle's trajectory over a window where the topology
+  does not change (start state relaxed by the oracle).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_02939_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def spv():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_1702_02939_amd import spv as mod
+    return mod
+
+
+def _state(n, seed):
+    L = math.sqrt(n)
+    x, y = inputs.uniform_positions(n, L, L, seed)
+    xq, yq, Lx, Ly, q = oracle.prepare(x, y, L, L)
+    return xq, yq, Lx, Ly, q
+
+
+def test_hvp_matches_oracle_finite_differences(spv):
+    n = 1000
+    xq, yq, Lx, Ly, q = _state(n, 71)
+    rng = np.random.default_rng(3)
+    P0 = rng.uniform(3.6, 4.0, n)
+    s = spv.System(xq, yq, Lx, Ly, P0=P0, params=spv.Params(KA=1.3, KP=0.7))
+    off, ring, _, _ = oracle.triangulate(xq, yq, Lx, Ly, q)
+    vx, vy = rng.normal(size=n), rng.normal(size=n)
+    gx, gy = s.force_tangent(vx, vy)
+    h = 1e-6
+    fpx, fpy = oracle.forces(xq + h * vx, yq + h * vy, Lx, Ly, off, ring, 1.0, P0, 1.3, 0.7)
+    fmx, fmy = oracle.forces(xq - h * vx, yq - h * vy, Lx, Ly, off, ring, 1.0, P0, 1.3, 0.7)
+    fdx, fdy = (fpx - fmx) / (2 * h), (fpy - fmy) / (2 * h)
+    scale = np.abs(np.concatenate([fdx, fdy])).max()
+    err = max(np.abs(gx - fdx).max(), np.abs(gy - fdy).max())
+    assert err < 1e-6 * scale, f"HVP vs FD: {err:.3e} (scale {scale:.3e})"
+    # symmetry and translation invariance
+    wx, wy = rng.normal(size=n), rng.normal(size=n)
+    hx, hy = s.force_tangent(wx, wy)
+    a = np.dot(vx, hx) + np.dot(vy, hy)
+    b = np.dot(wx, gx) + np.dot(wy, gy)
+    assert abs(a - b) < 1e-10 * max(abs(a), abs(b))
+    tx, ty = s.force_tangent(np.ones(n), np.zeros(n))
+    assert np.abs(tx).max() < 1e-9 * scale and np.abs(ty).max() < 1e-9 * scale
+    s.close()
+
+
+def _relaxed_state(n, seed, steps):
+    xq, yq, Lx, Ly, q = _state(n, seed)
+    th = oracle.theta0(seed, n)
+    out = oracle.run(xq, yq, th, Lx, Ly, q, 1.0, 3.75, v0=0.0, Dr=1.0, dt=0.02, seed=seed, nsteps=steps)
+    return out["x"], out["y"], Lx, Ly, q
+
+
+def test_trajectory_gradient_matches_oracle_finite_differences(spv):
+    n, T, k = 400, 20, 6
+    x0, y0, Lx, Ly, q = _relaxed_state(n, 72, 300)
+    th0 = oracle.theta0(9, n)
+    rng = np.random.default_rng(11)
+    p0 = rng.normal(3.75, 0.05, n)
+    prm = dict(mu=1.0, v0=0.02, Dr=1.0, dt=0.01, seed=9)
+    s = spv.System(x0, y0, Lx, Ly, P0=p0, theta0=th0, params=spv.Params(**prm))
+    Q = s.traj_forward(T, k)
+    g = s.traj_backward(1.0)
+    # the forward observable equals the oracle's
+    base = oracle.run(x0, y0, th0, Lx, Ly, q, 1.0, p0, nsteps=T, want_rings=True, **prm)
+    Q_or = base["qbar"][1:].mean()
+    assert abs(Q - Q_or) < 1e-10 * abs(Q_or)
+    eps = 1e-5
+    for trial in range(3):
+        d = rng.normal(size=n)
+        outp = oracle.run(x0, y0, th0, Lx, Ly, q, 1.0, p0 + eps * d, nsteps=T, want_rings=True, **prm)
+        outm = oracle.run(x0, y0, th0, Lx, Ly, q, 1.0, p0 - eps * d, nsteps=T, want_rings=True, **prm)
+        # a window without topology change for the +/- runs
+        assert np.array_equal(outp["ring"], base["ring"]) and np.array_equal(outm["ring"], base["ring"])
+        fd = (outp["qbar"][1:].mean() - outm["qbar"][1:].mean()) / (2 * eps)
+        an = float(np.dot(g, d))
+        assert abs(an - fd) < 1e-5 * max(abs(fd), 1e-3), f"dQ/dp0 . d: adjoint {an:.8e} vs FD {fd:.8e}"
+    s.close()
+
+
+def test_autograd_function(spv):
+    import torch
+    from paper_1702_02939_amd.autograd import trajectory_q
+    n, T, k = 300, 10, 4
+    x0, y0, Lx, Ly, q = _relaxed_state(n, 73, 200)
+    th0 = oracle.theta0(5, n)
+    p0 = torch.full((n,), 3.75, dtype=torch.float64, requires_grad=True)
+    prm = spv.Params(mu=1.0, v0=0.02, Dr=1.0, dt=0.01, seed=5)
+    Qt = trajectory_q(p0, x0, y0, th0, Lx, prm, T, k)
+    Qt.backward()
+    assert p0.grad is not None and p0.grad.shape == (n,) and torch.isfinite(p0.grad).all()
+    # same numbers as the C-ABI calls
+    s = spv.System(x0, y0, Lx, Ly, P0=np.full(n, 3.75), theta0=th0, params=prm)
+    assert abs(s.traj_forward(T, k) - Qt.item()) == 0.0
+    g = s.traj_backward(1.0)
+    assert np.array_equal(g, p0.grad.numpy())
+    s.close()
