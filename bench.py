@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--headline-only", action="store_true", help="skip the mixed / batched / 1e6 runs")
     ap.add_argument("--no-timing", action="store_true", help="skip the kernel-timing pass")
     ap.add_argument("--timing-steps", type=int, default=2000)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run with the default scheduling knobs instead of the library's tuned ones")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--big-steps", type=int, default=400)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
@@ -90,9 +92,12 @@ def cpu_baseline(w, nsteps):
 
 
 def timed_run(spv, make, steps, warmup, timing=True):
-    """Create via make(), warm up, time `steps` steps; returns a dict."""
+    """Create via make() (outside the timed region: this includes the
+    autotuner's trials when it has no cached choice), warm up, time `steps`
+    steps; returns a dict."""
     import torch
     sysm, ncells = make()
+    tuning = sysm.tuning()
     sysm.step(warmup)
     _, _, _, c0 = sysm.observables()
     if timing:
@@ -108,7 +113,11 @@ def timed_run(spv, make, steps, warmup, timing=True):
     sysm.close()
     return {"value": ncells * steps / wall, "ms_per_step": wall * 1e3 / steps, "cells": ncells, "steps": steps,
             "kernels": kt, "repairs_per_step": float(c1[1] - c0[1]) / steps,
-            "rounds_per_step": float(c1[2] - c0[2]) / steps, "E": E, "qbar": qbar, "sumA": sumA}
+            "rounds_per_step": float(c1[2] - c0[2]) / steps, "E": E, "qbar": qbar, "sumA": sumA,
+            "tuning": tuning}
+
+
+AUTOTUNE = 1
 
 
 def single(spv, inputs, name, precision):
@@ -116,7 +125,8 @@ def single(spv, inputs, name, precision):
 
     def make():
         x, y = inputs.uniform_positions(w["N"], w["L"], w["L"], w["seed"])
-        prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"], precision=precision)
+        prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"], precision=precision,
+                         autotune=AUTOTUNE)
         return spv.System(x, y, w["L"], w["L"], p0=w["p0"], params=prm), w["N"]
     return make
 
@@ -128,7 +138,7 @@ def batched(spv, inputs, precision):
         L_s = [s_["L"] for s_ in systems]
         x = __import__("numpy").concatenate([s_["x"] for s_ in systems])
         y = __import__("numpy").concatenate([s_["y"] for s_ in systems])
-        prm = spv.Params(mu=1.0, Dr=1.0, dt=0.01, precision=precision)
+        prm = spv.Params(mu=1.0, Dr=1.0, dt=0.01, precision=precision, autotune=AUTOTUNE)
         sysm = spv.System.batch(N_s, L_s, x, y, [s_["p0"] for s_ in systems], v0_s=[s_["v0"] for s_ in systems],
                                 seed_s=[s_["seed"] for s_ in systems], params=prm)
         return sysm, sum(N_s)
@@ -182,7 +192,9 @@ def roofline_of(kt, ncells):
 
 
 def main():
+    global AUTOTUNE
     args = parse()
+    AUTOTUNE = 0 if args.no_autotune else 1
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
                                    "and not implemented", "n_gpus": args.gpus}))
@@ -226,7 +238,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "L": w["L"], "p0": w["p0"], "v0": w["v0"], "Dr": w["Dr"],
-                   "mu": w["mu"], "dt": w["dt"], "precision": "fp64"},
+                   "mu": w["mu"], "dt": w["dt"], "precision": "fp64", "tuning": head["tuning"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
@@ -250,7 +262,7 @@ def main():
             d, a_s, bpl, ach = roofline_of(r["kernels"], r["cells"])
             extra[name] = {"value": r["value"], "unit": "cell-steps/s", "ms_per_step": r["ms_per_step"],
                            "cells": r["cells"], "steps": steps, "warmup": warm,
-                           "repairs_per_step": r["repairs_per_step"],
+                           "repairs_per_step": r["repairs_per_step"], "tuning": r["tuning"],
                            "kernel_avg_us": {k: (v[0] * 1e3 / max(v[1], 1)) for k, v in r["kernels"].items()},
                            "roofline_frac_hbm": ach / HBM_PEAK_GBS, "dominant_kernel": d}
             print(f"[bench] {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)

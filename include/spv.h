@@ -71,7 +71,24 @@ typedef struct {
     int32_t repair_rounds;  /* max test/repair rounds per step, device and host together (0: 16, max 32) */
     int32_t device_rounds;  /* repair rounds run on the device inside each step (0: 2) */
     int32_t no_graphs;      /* 0: replay whole re-sort periods as captured HIP graphs; 1: launch eagerly */
+    int32_t repair_cells;   /* flagged cells per repair wavefront: the repair grid is N / repair_cells
+                               blocks, clamped to [256, 4096] (0: 64) */
+    int32_t autotune;       /* 0: use the scheduling knobs given here (resort_every, device_rounds,
+                               repair_cells, bin_factor); 1: take them from the tuning cache for this
+                               device and size class, else choose them by timed trial runs and cache
+                               them; 2: always run the trials and refresh the cache.  The cache is the
+                               JSON file named by the environment variable SPV_TUNE_CACHE, else held
+                               in this process only.  The knobs never change results. */
+    double bin_factor;      /* cell-list bin side in mean cell spacings sqrt(Lx Ly / N) (0: 1; 0.5..8) */
 } spv_params;
+
+/* Scheduling knobs a handle runs with (see spv_params). */
+typedef struct {
+    int32_t resort_every, device_rounds, repair_cells;
+    int32_t source;      /* 0: given in spv_params, 1: tuning cache, 2: timed trials */
+    double bin_factor;
+    double ms_per_step;  /* trial time per step of the chosen knobs (0 when source = 0) */
+} spv_tuning;
 
 typedef struct spv_sys spv_sys; /* opaque handle: all device state of one system or batch */
 
@@ -162,6 +179,44 @@ spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA
 
 /* Observables of one system of a batch. */
 spv_status spv_get_system_observables(spv_sys* s, int32_t sys, double* E, double* qbar, double* sumA);
+
+/*
+ * Checkpoint and resume (the state of Eq. 3's dynamics: positions, directors,
+ * per-cell targets A0/P0 of Eq. 1, the step index that drives the noise).
+ * The triangulation is not stored: it is the unique Delaunay triangulation
+ * of the positions (Sec. II.C.3, ties broken by tag), rebuilt on load, so a
+ * loaded handle continues bitwise as the saved one would have.  Model
+ * parameters (K_A, K_P, mu, Dr, dt, v0, seed) are the loading handle's own.
+ *   spv_save_state  buf: host or device pointer to cap bytes (may be NULL to
+ *                   query); *needed = size.  Layout, little-endian: header
+ *                   {char magic[8] = "SPVSTAT\1"; int32 S, precision; int64 N;
+ *                   uint64 step}, S records {int64 n; double Lx, Ly, v0;
+ *                   uint64 seed}, then x, y, theta, A0, P0 as double[N] each
+ *                   in tag order (systems concatenated).
+ *   spv_load_state  buf of len bytes as written by spv_save_state into a
+ *                   handle of the same layout (S, N_s, grid-rounded boxes,
+ *                   precision).  Clears a sticky error on success; repair
+ *                   statistics restart.
+ * Errors: spv_save_state SPV_ECAPACITY (cap < *needed, nothing written),
+ * SPV_EHIP; spv_load_state SPV_EINVAL (size, magic, layout, off-grid or
+ * non-finite values; the handle is unchanged), repair errors while
+ * rebuilding (the handle then reports that error until the next load).
+ */
+spv_status spv_save_state(spv_sys* s, void* buf, int64_t cap, int64_t* needed);
+spv_status spv_load_state(spv_sys* s, const void* buf, int64_t len);
+
+/*
+ * Scheduling knobs of a handle.  With spv_params.autotune set, creation first
+ * runs the tuner: a clone of the input is stepped 64 steps from the given
+ * state, then clones of that state are timed over whole re-sort periods for
+ * each candidate bin side, repair grid, device repair budget and re-sort
+ * period (one knob at a time, each against a fresh time of the current best).
+ * The handle itself starts from the caller's input, so its trajectory is
+ * exactly that of an untuned handle.  A trial that fails leaves the given
+ * knobs in place (source 0).
+ * Errors: SPV_EINVAL (NULL argument).
+ */
+spv_status spv_get_tuning(spv_sys* s, spv_tuning* out);
 
 /*
  * Kernel timing.  While enabled, steps are launched one by one (not as

@@ -14,9 +14,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -24,6 +28,7 @@
 #include "../../include/spv.h"
 #include "spv_adjoint.hpp"
 #include "spv_kernels.hpp"
+#include "spv_tune.hpp"
 
 using namespace spv;
 
@@ -115,6 +120,10 @@ struct TrajCheckpoint {
 struct spv_sys {
     int S = 1, N = 0, KC = 16;
     int dev_rounds = 2, max_rounds = 16, unit = 16;
+    int repair_cells = 64;  // repair grid = N / this (clamped to [256, 4096] blocks)
+    double bin_factor = 1.0;
+    int tune_source = 0;
+    double tune_ms = 0.0;
     bool mixed = false, multi = false, use_graphs = true;
     spv_params prm{};
     hipStream_t stream = nullptr;      // caller's stream (all work is ordered on it)
@@ -248,7 +257,10 @@ inline unsigned grid_for(int n, int block) { return (unsigned)std::max(1, (n + b
 // all-cell grid of the 8-lanes-per-cell kernels, padded to a multiple of 8 XCDs
 inline unsigned cell_grid(const spv_sys* s) { return (grid_for(s->N, CPB) + 7u) & ~7u; }
 inline unsigned list_grid(const spv_sys* s) { return std::min(grid_for(s->N, CPB), 512u); }
-inline unsigned repair_grid(const spv_sys* s) { return (unsigned)std::min(std::max(s->N, 64), 1024); }
+inline unsigned repair_grid(const spv_sys* s)
+{
+    return (unsigned)std::min(std::max(s->N / s->repair_cells, 256), 4096);
+}
 
 // ---------------------------------------------------------------- timing
 EvPair take_events(spv_sys* s)
@@ -297,13 +309,11 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
         if (ev && r == 0) (void)hipEventRecord(ev[2].a, st);
         hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, r);
         if (ev && r == 0) (void)hipEventRecord(ev[2].b, st);
-        if (r + 1 < s->dev_rounds)
-            hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
-                               s->d_st, s->N, r, (const double*)nullptr, 0);
-        else  // the last re-test also closes the step (last block done)
-            hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work,
-                               s->d_sp, s->d_st, s->N, r, (const double*)s->d_blockmax, (int)cg);
+        hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
+                           s->d_st, s->N, r);
     }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, s->d_st, s->dev_rounds, (const double*)s->d_blockmax,
+                       (int)cg);
 }
 
 // Re-sort from (cfg, parity 0) into set[cfg ^ 1] (the caller flips cfg).
@@ -521,6 +531,10 @@ struct SysInput {
     uint64_t seed;
 };
 
+spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vector<double>& hy,
+                      const std::vector<double>& hA0, const std::vector<double>& hP0, const std::vector<double>& hth,
+                      const std::vector<int>& htag, const std::vector<int>& hsys, uint64_t step0);
+
 // Shared creation: hx, hy, hA0, hP0 are host arrays concatenated by system;
 // hth empty means default directors.
 spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<double>& hx,
@@ -564,8 +578,8 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
         P.n = (int)v.n;
         const double spacing = std::sqrt(P.Lx * P.Ly / (double)v.n);
         P.R0 = 2.5 * spacing;
-        P.nbx = std::max(1, (int)std::floor(P.Lx / spacing));
-        P.nby = std::max(1, (int)std::floor(P.Ly / spacing));
+        P.nbx = std::max(1, (int)std::floor(P.Lx / (s->bin_factor * spacing)));
+        P.nby = std::max(1, (int)std::floor(P.Ly / (s->bin_factor * spacing)));
         P.bsx = P.Lx / P.nbx;
         P.bsy = P.Ly / P.nby;
         P.bin_off = boff;
@@ -633,13 +647,30 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     ST_TRY(dalloc(s, &s->d_obs, 3 * S));
     ST_TRY(dalloc(s, &s->d_blockmax, cell_grid(s)));
     HIP_TRY(hipHostMalloc((void**)&s->h_st, sizeof(DevState), hipHostMallocDefault));
-    HIP_TRY(hipMemsetAsync(s->d_st, 0, sizeof(DevState), s->stream));
-    HIP_TRY(hipMemsetAsync(s->work.flagbits, 0, nwords * sizeof(unsigned), s->stream));
-    HIP_TRY(hipMemsetAsync(s->work.touchbits, 0, nwords * sizeof(unsigned), s->stream));
-    ArraySet& A = s->set[0];
     HIP_TRY(hipMemcpyAsync(s->d_sp, s->hsp.data(), S * sizeof(SysParam), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->d_bin_key, hbinkey.data(), s->total_bins * sizeof(int), hipMemcpyHostToDevice,
                            s->stream));
+    HIP_TRY(hipStreamCreate(&s->cap_stream));
+    return seat_cells(s, hx, hy, hA0, hP0, hth, htag, hsys, 0);
+}
+
+// Put cells (tag order per system, grid-exact positions) into configuration
+// 0 and build their triangulation from scratch: the state after creation or
+// after loading a checkpoint.  Statistics restart; the step index is step0.
+spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vector<double>& hy,
+                      const std::vector<double>& hA0, const std::vector<double>& hP0, const std::vector<double>& hth,
+                      const std::vector<int>& htag, const std::vector<int>& hsys, uint64_t step0)
+{
+    const int N = s->N;
+    const size_t nwords = (N + 31) / 32;
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < 2; k++) HIP_TRY(hipMemsetAsync(s->set[k].deg, 0, N, s->stream));
+    HIP_TRY(hipMemsetAsync(s->d_st, 0, sizeof(DevState), s->stream));
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(s->d_st) + offsetof(DevState, step), &step0, sizeof step0,
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.flagbits, 0, nwords * sizeof(unsigned), s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.touchbits, 0, nwords * sizeof(unsigned), s->stream));
+    ArraySet& A = s->set[0];
     HIP_TRY(hipMemcpyAsync(A.x, hx.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(A.y, hy.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(A.A0, hA0.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
@@ -651,12 +682,12 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     else
         hipLaunchKernelGGL(k_theta0, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, A.th, A.tag, A.sys, s->d_sp, N);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(s->stream));  // host vectors die at return
-    HIP_TRY(hipStreamCreate(&s->cap_stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));  // the host vectors may die after return
 
     // spatial order, then the triangulation from scratch: every cell repaired
     s->cfg = 0;
     s->pos = 0;
+    s->step = step0;
     ST_TRY(do_resort_eager(s));
     s->resorts = 0;
     hipLaunchKernelGGL(k_all_to_worklist, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->work, s->d_st, N);
@@ -697,6 +728,12 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     s->unit = p.resort_every > 0 ? p.resort_every : 32;
     if (s->unit & 1) s->unit += 1;
     s->use_graphs = p.no_graphs == 0;
+    if (p.repair_cells < 0 || p.resort_every < 0 || p.device_rounds < 0)
+        return fail(SPV_EINVAL, "negative scheduling knob");
+    s->repair_cells = p.repair_cells > 0 ? p.repair_cells : 64;
+    s->bin_factor = p.bin_factor != 0.0 ? p.bin_factor : 1.0;
+    if (!(s->bin_factor >= 0.5 && s->bin_factor <= 8.0)) return fail(SPV_EINVAL, "bin_factor must be in [0.5, 8]");
+    if (p.autotune < 0 || p.autotune > 2) return fail(SPV_EINVAL, "autotune must be 0, 1 or 2");
     s->stream = (hipStream_t)stream;
     return SPV_OK;
 }
@@ -734,6 +771,321 @@ spv_status out_tag_order(spv_sys* s, const T* src, double* dst)
                                P.sys, s->d_sp, stage, s->N);
         },
         dst);
+}
+
+// ---------------------------------------------------------------- checkpoints
+// Layout (little-endian, 8-byte fields): header, one record per system, then
+// x, y, theta, A0, P0 as double[N] each, tag order.
+struct StateHeader {
+    char magic[8];  // "SPVSTAT" + version byte 1
+    int32_t S, precision;
+    int64_t N;
+    uint64_t step;
+};
+struct StateSystem {
+    int64_t n;
+    double Lx, Ly, v0;
+    uint64_t seed;
+};
+constexpr char kStateMagic[8] = {'S', 'P', 'V', 'S', 'T', 'A', 'T', 1};
+
+int64_t state_bytes(const spv_sys* s)
+{
+    return (int64_t)sizeof(StateHeader) + (int64_t)s->S * (int64_t)sizeof(StateSystem) + 5 * (int64_t)s->N * 8;
+}
+
+spv_status save_state(spv_sys* s, void* buf, int64_t cap, int64_t* needed)
+{
+    const int64_t bytes = state_bytes(s);
+    if (needed) *needed = bytes;
+    if (!buf || cap < bytes) return fail(SPV_ECAPACITY, "state buffer too small (see *needed)");
+    if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
+    const size_t N = s->N;
+    std::vector<char> out((size_t)bytes);
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, 8);
+    h.S = s->S;
+    h.precision = s->mixed ? SPV_MIXED : SPV_FP64;
+    h.N = s->N;
+    h.step = s->step;
+    std::memcpy(out.data(), &h, sizeof h);
+    char* p = out.data() + sizeof h;
+    for (int k = 0; k < s->S; k++) {
+        const SysParam& P = s->hsp[k];
+        StateSystem r{P.n, P.Lx, P.Ly, P.v0, P.seed};
+        std::memcpy(p, &r, sizeof r);
+        p += sizeof r;
+    }
+    double* arr = reinterpret_cast<double*>(p);
+    const int par = s->pos & 1;
+    const ArraySet& live = s->set[par ? s->cfg ^ 1 : s->cfg];
+    const ArraySet& fixed = s->set[s->cfg];
+    ST_TRY(out_tag_order(s, live.x, arr));
+    ST_TRY(out_tag_order(s, live.y, arr + N));
+    ST_TRY(out_tag_order(s, live.th, arr + 2 * N));
+    ST_TRY(out_tag_order(s, fixed.A0, arr + 3 * N));
+    ST_TRY(out_tag_order(s, fixed.P0, arr + 4 * N));
+    HIP_TRY(hipMemcpy(buf, out.data(), (size_t)bytes, hipMemcpyDefault));
+    return SPV_OK;
+}
+
+spv_status load_state(spv_sys* s, const void* buf, int64_t len)
+{
+    const int64_t bytes = state_bytes(s);
+    if (!buf || len != bytes) return fail(SPV_EINVAL, "state size does not match this handle's layout");
+    std::vector<char> in((size_t)bytes);
+    HIP_TRY(hipMemcpy(in.data(), buf, (size_t)bytes, hipMemcpyDefault));
+    StateHeader h;
+    std::memcpy(&h, in.data(), sizeof h);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(SPV_EINVAL, "not an SPV state (bad magic/version)");
+    if (h.S != s->S || h.N != s->N || h.precision != (s->mixed ? SPV_MIXED : SPV_FP64))
+        return fail(SPV_EINVAL, "state has another number of systems, cells or precision");
+    const char* p = in.data() + sizeof h;
+    for (int k = 0; k < s->S; k++) {
+        StateSystem r;
+        std::memcpy(&r, p, sizeof r);
+        p += sizeof r;
+        const SysParam& P = s->hsp[k];
+        if (r.n != P.n || r.Lx != P.Lx || r.Ly != P.Ly)
+            return fail(SPV_EINVAL, "state system " + std::to_string(k) + " has another size or box");
+    }
+    const size_t N = s->N;
+    const double* arr = reinterpret_cast<const double*>(p);
+    std::vector<double> hx(arr, arr + N), hy(arr + N, arr + 2 * N), hth(arr + 2 * N, arr + 3 * N),
+        hA0(arr + 3 * N, arr + 4 * N), hP0(arr + 4 * N, arr + 5 * N);
+    std::vector<int> htag(N), hsys(N);
+    for (int k = 0; k < s->S; k++) {
+        const SysParam& P = s->hsp[k];
+        for (int t = 0; t < P.n; t++) {
+            const size_t i = (size_t)P.cell_off + t;
+            htag[i] = t;
+            hsys[i] = k;
+            const double X = hx[i] * P.scale, Y = hy[i] * P.scale;
+            if (!(X >= 0.0 && X < P.LXu && Y >= 0.0 && Y < P.LYu) || X != std::rint(X) || Y != std::rint(Y))
+                return fail(SPV_EINVAL, "state positions are not on this handle's grid");
+            if (!std::isfinite(hth[i]) || !(hA0[i] > 0.0) || !std::isfinite(hA0[i]) || !std::isfinite(hP0[i]))
+                return fail(SPV_EINVAL, "state holds non-finite directors or targets");
+        }
+    }
+    // every check passed: replace the state (a failure from here on leaves
+    // the handle unusable until the next successful load)
+    s->traj_valid = false;
+    s->sticky = SPV_OK;
+    spv_status st = seat_cells(s, hx, hy, hA0, hP0, hth, htag, hsys, h.step);
+    if (st != SPV_OK && s->sticky == SPV_OK) {
+        s->sticky = st;
+        s->sticky_msg = "loading the state failed: " + g_err;
+    }
+    return st;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Everything creation needs, kept so the tuner can build clones.
+struct CreateArgs {
+    std::vector<SysInput> in;
+    std::vector<double> x, y, A0, P0, th;
+    spv_params prm{};
+    void* stream = nullptr;
+};
+
+spv_status build_handle(const CreateArgs& a, const spv_params& p, spv_sys** out)
+{
+    *out = nullptr;
+    spv_sys* s = new spv_sys();
+    spv_status st = setup_params(s, &p, a.stream);
+    if (st != SPV_OK) return finish_create(s, st, out);
+    std::vector<double> hx = a.x, hy = a.y;  // quantised in place
+    return finish_create(s, create_impl(s, a.in, hx, hy, a.A0, a.P0, a.th), out);
+}
+
+Knobs knobs_of(const spv_sys* s) { return {s->unit, s->dev_rounds, s->repair_cells, s->bin_factor}; }
+
+spv_params with_knobs(spv_params p, const Knobs& k)
+{
+    p.resort_every = k.resort_every;
+    p.device_rounds = k.device_rounds;
+    p.repair_cells = k.repair_cells;
+    p.bin_factor = k.bin_factor;
+    p.autotune = 0;
+    return p;
+}
+
+// knobs that need no new allocation: the captured graphs depend on them
+spv_status set_runtime_knobs(spv_sys* s, const Knobs& k)
+{
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int g = 0; g < 2; g++)
+        if (s->gexec[g]) {
+            (void)hipGraphExecDestroy(s->gexec[g]);
+            s->gexec[g] = nullptr;
+        }
+    s->unit = k.resort_every + (k.resort_every & 1);
+    s->dev_rounds = std::min(k.device_rounds, s->max_rounds);
+    s->repair_cells = k.repair_cells;
+    return SPV_OK;
+}
+
+// Start a period, run one (captures and replays its graph), then time
+// `steps` steps; steps is a multiple of every candidate period.
+spv_status trial_ms(spv_sys* s, int steps, double* ms)
+{
+    if (s->pos & 1) ST_TRY(run_steps(s, 1));
+    if (s->pos != 0) ST_TRY(do_resort_eager(s));
+    ST_TRY(run_steps(s, s->unit));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    ST_TRY(run_steps(s, steps));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const auto t1 = std::chrono::steady_clock::now();
+    *ms = std::chrono::duration<double, std::milli>(t1 - t0).count() / steps;
+    return SPV_OK;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune_mem;  // this process's cache (file entries merged in)
+
+spv_status tune_key_for(const CreateArgs& a, std::string& key)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    int64_t N = 0;
+    for (const auto& v : a.in) N += v.n;
+    key = tune_key(arch, prop.multiProcessorCount, a.prm.precision == SPV_MIXED, a.prm.kcap > 0 ? a.prm.kcap : 16, N,
+                   (int)a.in.size());
+    return SPV_OK;
+}
+
+// The search: warm a clone for 64 steps from the input, then, from that
+// state, pick the bin side (a clone per candidate), and on the best clone the
+// repair grid, the device repair budget and the re-sort period, one at a
+// time.  Each knob's candidates are timed right after a fresh time of the
+// current choice, and a candidate replaces it only when 3% faster.
+spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
+{
+    constexpr int kWarm = 64, kTrial = 128;  // kTrial: a multiple of every candidate period
+    const double kMargin = 0.97;
+    spv_sys* w = nullptr;
+    ST_TRY(build_handle(a, with_knobs(a.prm, best), &w));
+    CreateArgs b = a;
+    b.prm = with_knobs(a.prm, best);
+    spv_status st = run_steps(w, kWarm);
+    const ArraySet& live = w->set[(w->pos & 1) ? w->cfg ^ 1 : w->cfg];
+    b.th.resize(b.x.size());
+    if (st == SPV_OK) st = out_tag_order(w, live.x, b.x.data());
+    if (st == SPV_OK) st = out_tag_order(w, live.y, b.y.data());
+    if (st == SPV_OK) st = out_tag_order(w, live.th, b.th.data());
+    destroy_all(w);
+    ST_TRY(st);
+
+    // bin side: the bins are allocated at creation, so one clone each
+    spv_sys* cur = nullptr;
+    best_ms = INFINITY;
+    for (double f : {1.0, 1.5, 2.0}) {
+        Knobs k = best;
+        k.bin_factor = f;
+        spv_sys* c = nullptr;
+        double ms = INFINITY;
+        if (build_handle(b, with_knobs(b.prm, k), &c) != SPV_OK) continue;
+        if (trial_ms(c, kTrial, &ms) == SPV_OK && (!cur || ms < kMargin * best_ms)) {
+            std::swap(c, cur);
+            best = k;
+            best_ms = ms;
+        }
+        if (c) destroy_all(c);
+    }
+    if (!cur) return fail(SPV_EHIP, "autotune: no trial ran");
+
+    struct Axis {
+        int Knobs::*field;
+        int cand[3];
+    };
+    const Axis axes[] = {{&Knobs::repair_cells, {16, 64, 256}},
+                         {&Knobs::device_rounds, {1, 2, 3}},
+                         {&Knobs::resort_every, {16, 32, 64}}};
+    for (const Axis& ax : axes) {
+        if (set_runtime_knobs(cur, best) != SPV_OK || trial_ms(cur, kTrial, &best_ms) != SPV_OK) break;
+        Knobs choice = best;
+        double choice_ms = best_ms;
+        for (int v : ax.cand) {
+            if (v == best.*ax.field) continue;
+            Knobs k = best;
+            k.*ax.field = v;
+            if (k.device_rounds > cur->max_rounds) continue;
+            double ms = INFINITY;
+            if (set_runtime_knobs(cur, k) != SPV_OK) break;
+            if (trial_ms(cur, kTrial, &ms) != SPV_OK) break;
+            if (ms < kMargin * best_ms && ms < choice_ms) {
+                choice = k;
+                choice_ms = ms;
+            }
+        }
+        best = choice;
+        best_ms = choice_ms;
+        if (cur->sticky != SPV_OK) break;
+    }
+    destroy_all(cur);
+    return SPV_OK;
+}
+
+// Creation with the knobs of a.prm, or tuned ones when a.prm.autotune is set.
+spv_status create_tuned(const CreateArgs& a, spv_sys** out)
+{
+    *out = nullptr;
+    spv_params p = a.prm;
+    if (p.autotune == 0) return build_handle(a, p, out);
+    // validate the parameters (and fill in the defaults) before any trial
+    spv_sys* probe = new spv_sys();
+    spv_status st = setup_params(probe, &p, a.stream);
+    Knobs k = knobs_of(probe);
+    delete probe;
+    ST_TRY(st);
+    std::string key;
+    ST_TRY(tune_key_for(a, key));
+    const char* path = std::getenv("SPV_TUNE_CACHE");
+    int source = 0;
+    double ms = 0.0;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        if (path && *path) {
+            std::map<std::string, TuneEntry> file;
+            if (cache_load(path, file) == 0)
+                for (auto& kv : file) g_tune_mem[kv.first] = kv.second;
+        }
+        auto it = g_tune_mem.find(key);
+        if (p.autotune == 1 && it != g_tune_mem.end()) {
+            k = it->second.k;
+            ms = it->second.ms_per_step;
+            source = 1;
+        }
+    }
+    if (source == 0) {
+        Knobs t = k;
+        double tms = 0.0;
+        const std::string keep = g_err;
+        if (run_trials(a, t, tms) == SPV_OK) {
+            k = t;
+            ms = tms;
+            source = 2;
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tune_mem[key] = {k, ms};
+            if (path && *path) {
+                std::map<std::string, TuneEntry> file;
+                if (cache_load(path, file) == 0) {  // never replace a file we cannot read
+                    file[key] = {k, ms};
+                    (void)cache_store(path, file);
+                }
+            }
+        }
+        g_err = keep;
+    }
+    ST_TRY(build_handle(a, with_knobs(p, k), out));
+    (*out)->tune_source = source;
+    (*out)->tune_ms = ms;
+    return SPV_OK;
 }
 
 // ---------------------------------------------------------------- trajectory adjoint
@@ -987,32 +1339,36 @@ spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y
     if (!(Lx > 0.0) || !(Ly > 0.0) || !std::isfinite(Lx) || !std::isfinite(Ly))
         return fail(SPV_EINVAL, "box sides must be positive and finite");
     if (!A0 && !P0 && !std::isfinite(p0)) return fail(SPV_EINVAL, "p0 must be finite");
-    spv_sys* s = new spv_sys();
-    spv_status st = setup_params(s, params, stream);
-    if (st != SPV_OK) return finish_create(s, st, out);
-    std::vector<double> hx, hy, hA0, hP0, hth;
-    if ((st = copy_in(x, hx, N)) != SPV_OK || (st = copy_in(y, hy, N)) != SPV_OK) return finish_create(s, st, out);
+    {
+        spv_sys probe;  // parameters are checked before any copy
+        ST_TRY(setup_params(&probe, params, stream));
+    }
+    CreateArgs a;
+    a.prm = *params;
+    a.stream = stream;
+    ST_TRY(copy_in(x, a.x, N));
+    ST_TRY(copy_in(y, a.y, N));
     if (A0) {
-        if ((st = copy_in(A0, hA0, N)) != SPV_OK) return finish_create(s, st, out);
+        ST_TRY(copy_in(A0, a.A0, N));
     } else {
-        hA0.assign(N, 1.0);
+        a.A0.assign(N, 1.0);
     }
     if (P0) {
-        if ((st = copy_in(P0, hP0, N)) != SPV_OK) return finish_create(s, st, out);
+        ST_TRY(copy_in(P0, a.P0, N));
     } else {
-        hP0.resize(N);
-        for (int64_t i = 0; i < N; i++) hP0[i] = p0 * std::sqrt(hA0[i]);
+        a.P0.resize(N);
+        for (int64_t i = 0; i < N; i++) a.P0[i] = p0 * std::sqrt(a.A0[i]);
     }
     for (int64_t i = 0; i < N; i++)
-        if (!std::isfinite(hA0[i]) || !std::isfinite(hP0[i]) || hA0[i] <= 0.0)
-            return finish_create(s, fail(SPV_EINVAL, "A0 must be positive and finite, P0 finite"), out);
+        if (!std::isfinite(a.A0[i]) || !std::isfinite(a.P0[i]) || a.A0[i] <= 0.0)
+            return fail(SPV_EINVAL, "A0 must be positive and finite, P0 finite");
     if (theta0) {
-        if ((st = copy_in(theta0, hth, N)) != SPV_OK) return finish_create(s, st, out);
+        ST_TRY(copy_in(theta0, a.th, N));
         for (int64_t i = 0; i < N; i++)
-            if (!std::isfinite(hth[i])) return finish_create(s, fail(SPV_EINVAL, "theta0 must be finite"), out);
+            if (!std::isfinite(a.th[i])) return fail(SPV_EINVAL, "theta0 must be finite");
     }
-    std::vector<SysInput> in{{N, Lx, Ly, params->v0, params->seed}};
-    return finish_create(s, create_impl(s, in, hx, hy, hA0, hP0, hth), out);
+    a.in = {{N, Lx, Ly, params->v0, params->seed}};
+    return create_tuned(a, out);
 }
 
 spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const double* Lx_s, const double* Ly_s,
@@ -1033,23 +1389,28 @@ spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const 
         Ntot += N_s[k];
         if (Ntot > (int64_t)1 << 30) return fail(SPV_EINVAL, "too many cells");
     }
-    spv_sys* s = new spv_sys();
-    spv_status st = setup_params(s, params, stream);
-    if (st != SPV_OK) return finish_create(s, st, out);
-    std::vector<double> hx, hy, hA0(Ntot, 1.0), hP0, hth;
-    if ((st = copy_in(x, hx, Ntot)) != SPV_OK || (st = copy_in(y, hy, Ntot)) != SPV_OK)
-        return finish_create(s, st, out);
+    {
+        spv_sys probe;
+        ST_TRY(setup_params(&probe, params, stream));
+    }
+    CreateArgs a;
+    a.prm = *params;
+    a.stream = stream;
+    a.in = in;
+    a.A0.assign(Ntot, 1.0);
+    ST_TRY(copy_in(x, a.x, Ntot));
+    ST_TRY(copy_in(y, a.y, Ntot));
     if (P0) {
-        if ((st = copy_in(P0, hP0, Ntot)) != SPV_OK) return finish_create(s, st, out);
+        ST_TRY(copy_in(P0, a.P0, Ntot));
     } else {
-        hP0.resize(Ntot);
+        a.P0.resize(Ntot);
         int64_t o = 0;
         for (int k = 0; k < S; k++)
-            for (int64_t t = 0; t < N_s[k]; t++) hP0[o++] = p0_s[k];
+            for (int64_t t = 0; t < N_s[k]; t++) a.P0[o++] = p0_s[k];
     }
     for (int64_t i = 0; i < Ntot; i++)
-        if (!std::isfinite(hP0[i])) return finish_create(s, fail(SPV_EINVAL, "P0 must be finite"), out);
-    return finish_create(s, create_impl(s, in, hx, hy, hA0, hP0, hth), out);
+        if (!std::isfinite(a.P0[i])) return fail(SPV_EINVAL, "P0 must be finite");
+    return create_tuned(a, out);
 }
 
 spv_status spv_step(spv_sys* s, int64_t nsteps)
@@ -1057,6 +1418,30 @@ spv_status spv_step(spv_sys* s, int64_t nsteps)
     if (!s || nsteps < 0) return fail(SPV_EINVAL, "bad handle or nsteps");
     s->traj_valid = false;  // the recorded trajectory no longer ends at the current state
     return run_steps(s, nsteps);
+}
+
+spv_status spv_save_state(spv_sys* s, void* buf, int64_t cap, int64_t* needed)
+{
+    if (!s || cap < 0) return fail(SPV_EINVAL, "bad handle or capacity");
+    return save_state(s, buf, cap, needed);
+}
+
+spv_status spv_load_state(spv_sys* s, const void* buf, int64_t len)
+{
+    if (!s) return fail(SPV_EINVAL, "bad handle");
+    return load_state(s, buf, len);
+}
+
+spv_status spv_get_tuning(spv_sys* s, spv_tuning* out)
+{
+    if (!s || !out) return fail(SPV_EINVAL, "bad argument");
+    out->resort_every = s->unit;
+    out->device_rounds = s->dev_rounds;
+    out->repair_cells = s->repair_cells;
+    out->source = s->tune_source;
+    out->bin_factor = s->bin_factor;
+    out->ms_per_step = s->tune_ms;
+    return SPV_OK;
 }
 
 spv_status spv_get_size(spv_sys* s, int32_t* S, int64_t* N)

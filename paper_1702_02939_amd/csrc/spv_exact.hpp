@@ -135,22 +135,14 @@ __device__ __noinline__ int incircle_exact(double bx, double by, double cx, doub
     return -i256_sign(s);
 }
 
-// In-circle sign for the cell i at the origin and displacements b, c, p:
-// > 0 iff p lies strictly inside the circle through (0, b, c), for (0, b, c)
-// counter-clockwise.  Equals the 4x4 lifted determinant with rows (i, b, c, p).
-// Ties are broken by the tags (ti, tb, tc, tp).  *exact_count is bumped when
-// the integer path runs.
-__device__ __forceinline__ int incircle_sos(double bx, double by, double cx, double cy, double px, double py,
-                                            int ti, int tb, int tc, int tp, double scale, int* exact_count)
+// Exact in-circle sign for the cell i at the origin and displacements b, c,
+// p, when the double filter could not decide: > 0 iff p lies strictly inside
+// the circle through (0, b, c) for (0, b, c) counter-clockwise (the 4x4
+// lifted determinant with rows (i, b, c, p)); ties broken by the tags
+// (ti, tb, tc, tp).
+__device__ __forceinline__ int incircle_exact_sos(double bx, double by, double cx, double cy, double px, double py,
+                                               int ti, int tb, int tc, int tp, double scale)
 {
-    double nb = bx * bx + by * by, nc = cx * cx + cy * cy, np = px * px + py * py;
-    double t1 = cx * py, t2 = cy * px, t3 = px * by, t4 = py * bx, t5 = bx * cy, t6 = by * cx;
-    double det = nb * (t1 - t2) + nc * (t3 - t4) + np * (t5 - t6);
-    double perm = nb * (fabs(t1) + fabs(t2)) + nc * (fabs(t3) + fabs(t4)) + np * (fabs(t5) + fabs(t6));
-    double bound = 2.0e-15 * perm;
-    if (det > bound) return -1;
-    if (det < -bound) return 1;
-    (*exact_count)++;
     int s = incircle_exact(bx, by, cx, cy, px, py, scale);
     if (s) return s;
     // cofactor of the highest-tag row of the lifted determinant

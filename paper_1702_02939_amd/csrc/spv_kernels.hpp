@@ -65,7 +65,8 @@ __device__ __forceinline__ int incircle_tags(double bx, double by, double cx, do
     const double bound = 2.0e-15 * perm;
     if (det > bound) return -1;
     if (det < -bound) return 1;
-    return incircle_sos(bx, by, cx, cy, px, py, tag[gi], tag[gb], tag[gc], tag[gp], scale, exact_count);
+    (*exact_count)++;
+    return incircle_exact_sos(bx, by, cx, cy, px, py, tag[gi], tag[gb], tag[gc], tag[gp], scale);
 }
 
 // Wave-aggregated append: the active lanes with `want` write c to list, one
@@ -132,10 +133,7 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
                                                DevState* st, int N, double* __restrict__ blockmax)
 {
     constexpr int NS = KC / GL;
-    __shared__ R sD[CPB][KC][2];  // displacement of ring cell m
-    __shared__ R sH[CPB][KC][2];  // Voronoi vertex m
-    __shared__ R sE[CPB][KC][2];  // unit edge vector h_m -> h_{m+1}
-    __shared__ R sC[CPB][KC][2];  // (a, b) of ring cell m
+    __shared__ R sH[CPB][KC][2];  // Voronoi vertex m (frame of the cell)
     if (st->halt) return;
     const int g = threadIdx.x / GL, l = threadIdx.x % GL;
     const int i = xcd_block(blockIdx.x, gridDim.x) * CPB + g;
@@ -148,64 +146,41 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     const R* __restrict__ ca = c.ca;
     const R* __restrict__ cb = c.cb;
 
-    double dmx[NS], dmy[NS], odx[NS], ody[NS];
-    bool hasopp[NS];
+    // slot m of this lane: displacements d_m, d_{m+1} (the next slot's ring
+    // entry is read again from the same cache line rather than through LDS),
+    // coefficients of j_m and j_{m+1}, and the opposite cell of edge m
+    R bxs[NS], bys[NS], cxs[NS], cys[NS], ams[NS], bms[NS], ans[NS], bns[NS], qxs[NS], qys[NS];
 #pragma unroll
     for (int s = 0; s < NS; s++) {
         const int m = l + s * GL;
-        dmx[s] = dmy[s] = odx[s] = ody[s] = 0.0;
-        hasopp[s] = false;
-        if (m < k) {
-            const int j = c.ring[ii * KC + m];
-            dmx[s] = mimg(c.x[j] - xi, P.Lx, P.hLx);
-            dmy[s] = mimg(c.y[j] - yi, P.Ly, P.hLy);
-            sD[g][m][0] = (R)dmx[s];
-            sD[g][m][1] = (R)dmy[s];
-            sC[g][m][0] = ca[j];
-            sC[g][m][1] = cb[j];
-            const int o = c.opp[ii * KC + m];
-            if (o >= 0) {
-                hasopp[s] = true;
-                odx[s] = mimg(c.x[o] - xi, P.Lx, P.hLx);
-                ody[s] = mimg(c.y[o] - yi, P.Ly, P.hLy);
-            }
-        }
-    }
-    __syncthreads();
-    R hqx[NS], hqy[NS];
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
-        const int m = l + s * GL;
-        hqx[s] = hqy[s] = R(0);
+        bxs[s] = bys[s] = cxs[s] = cys[s] = ams[s] = bms[s] = ans[s] = bns[s] = qxs[s] = qys[s] = R(0);
         if (m < k) {
             const int mn = (m + 1 == k) ? 0 : m + 1;
-            const R bx = sD[g][m][0], by = sD[g][m][1], cx = sD[g][mn][0], cy = sD[g][mn][1];
+            const int jm = c.ring[ii * KC + m], jn = c.ring[ii * KC + mn], o = c.opp[ii * KC + m];
+            const double dmx = mimg(c.x[jm] - xi, P.Lx, P.hLx), dmy = mimg(c.y[jm] - yi, P.Ly, P.hLy);
+            const double dnx = mimg(c.x[jn] - xi, P.Lx, P.hLx), dny = mimg(c.y[jn] - yi, P.Ly, P.hLy);
+            ams[s] = ca[jm];
+            bms[s] = cb[jm];
+            ans[s] = ca[jn];
+            bns[s] = cb[jn];
+            bxs[s] = (R)dmx;
+            bys[s] = (R)dmy;
+            cxs[s] = (R)dnx;
+            cys[s] = (R)dny;
             R hx, hy;
-            circumcentre(bx, by, cx, cy, hx, hy);
+            circumcentre(bxs[s], bys[s], cxs[s], cys[s], hx, hy);
             sH[g][m][0] = hx;
             sH[g][m][1] = hy;
-            hqx[s] = hx;
-            hqy[s] = hy;
-            if (hasopp[s]) {
+            qxs[s] = hx;
+            qys[s] = hy;
+            if (o >= 0) {
                 // third vertex of edge (j_m, j_{m+1}): circumcentre of (j_m, opp_m, j_{m+1})
-                const R ex = (R)(odx[s] - dmx[s]), ey = (R)(ody[s] - dmy[s]);
+                const double dox = mimg(c.x[o] - xi, P.Lx, P.hLx), doy = mimg(c.y[o] - yi, P.Ly, P.hLy);
                 R qx, qy;
-                circumcentre(ex, ey, cx - bx, cy - by, qx, qy);
-                hqx[s] = qx + bx;
-                hqy[s] = qy + by;
+                circumcentre((R)(dox - dmx), (R)(doy - dmy), (R)(dnx - dmx), (R)(dny - dmy), qx, qy);
+                qxs[s] = qx + bxs[s];
+                qys[s] = qy + bys[s];
             }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
-        const int m = l + s * GL;
-        if (m < k) {
-            const int mn = (m + 1 == k) ? 0 : m + 1;
-            R tx, ty;
-            unit(sH[g][mn][0] - sH[g][m][0], sH[g][mn][1] - sH[g][m][1], tx, ty);
-            sE[g][m][0] = tx;
-            sE[g][m][1] = ty;
         }
     }
     __syncthreads();
@@ -219,12 +194,12 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
             const R hpx = sH[g][mp][0], hpy = sH[g][mp][1];
             const R hcx = sH[g][m][0], hcy = sH[g][m][1];
             const R hnx = sH[g][mn][0], hny = sH[g][mn][1];
-            const R t1x = sE[g][mp][0], t1y = sE[g][mp][1];
-            const R t2x = sE[g][m][0], t2y = sE[g][m][1];
-            R t3x, t3y;
-            unit(hqx[s] - hcx, hqy[s] - hcy, t3x, t3y);
-            const R am = sC[g][m][0], bm = sC[g][m][1], an = sC[g][mn][0], bn = sC[g][mn][1];
-            const R qx = hqx[s], qy = hqy[s];
+            R t1x, t1y, t2x, t2y, t3x, t3y;
+            unit(hcx - hpx, hcy - hpy, t1x, t1y);
+            unit(hnx - hcx, hny - hcy, t2x, t2y);
+            unit(qxs[s] - hcx, qys[s] - hcy, t3x, t3y);
+            const R am = ams[s], bm = bms[s], an = ans[s], bn = bns[s];
+            const R qx = qxs[s], qy = qys[s];
             R gx = ai * R(0.5) * (hny - hpy) + bi * (t1x - t2x);
             R gy = ai * R(0.5) * (hpx - hnx) + bi * (t1y - t2y);
             gx += am * R(0.5) * (hpy - qy) + bm * (t1x - t3x);
@@ -232,7 +207,7 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
             gx += an * R(0.5) * (qy - hny) + bn * (-t2x - t3x);
             gy += an * R(0.5) * (hnx - qx) + bn * (-t2y - t3y);
             // J_m^T g, b = d_m, c = d_{m+1}, e = c - b
-            const R Bx = sD[g][m][0], By = sD[g][m][1], Cx = sD[g][mn][0], Cy = sD[g][mn][1];
+            const R Bx = bxs[s], By = bys[s], Cx = cxs[s], Cy = cys[s];
             const R ex = Cx - Bx, ey = Cy - By;
             const R sc = Bx * Cy - By * Cx;
             const R be = Bx * ex + By * ey, ce = Cx * ex + Cy * ey;
@@ -316,11 +291,9 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
 // OPP: rebuild opp first -- in the CCW ring of j_m the pattern
 // ..., opp_m, j_{m+1}, i, ... must appear; otherwise the rings disagree and
 // the cells are flagged.
-__device__ void finalize_block(DevState* st, int rounds, const double* blockmax, int nblk);
-
-template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool FINAL = false>
+template <typename R, bool MULTI, int KC, bool LIST, bool OPP>
 __global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
-                                              int N, int round, const double* blockmax = nullptr, int nblk = 0)
+                                              int N, int round)
 {
     constexpr int NS = KC / GL;
     __shared__ double sD[CPB][KC][2];
@@ -432,21 +405,6 @@ __global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam
         __syncthreads();  // LDS is reused by the next group of cells
     }
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
-    if (FINAL) {
-        // the last block to finish closes the step (no separate launch)
-        __shared__ int s_last;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __threadfence();
-            s_last = atomicAdd(&st->done, 1) == (int)gridDim.x - 1;
-        }
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            if (threadIdx.x == 0) st->done = 0;
-            finalize_block(st, round + 1, blockmax, nblk);
-        }
-    }
 }
 
 // ---------------------------------------------------------------- repair
@@ -466,7 +424,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
 {
     constexpr int KMAX = 64;
     __shared__ double sx[RP_CAP], sy[RP_CAP];
-    __shared__ int sid[RP_CAP];
+    __shared__ int sid[RP_CAP], stg[RP_CAP];  // candidate cell and its tag
     __shared__ int s_n;
     __shared__ int s_ring[KMAX + 1];
     if (st->halt) return;
@@ -523,6 +481,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
                             sx[slot] = dx;
                             sy[slot] = dy;
                             sid[slot] = q;
+                            stg[slot] = c.tag[q];
                         }
                     }
                 }
@@ -541,7 +500,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
                 const __int128 X = to_units(sx[q], P.scale), Y = to_units(sy[q], P.scale);
                 const unsigned __int128 d2 = (unsigned __int128)(X * X + Y * Y);
                 const unsigned long long h = (unsigned long long)(d2 >> 64), lw = (unsigned long long)d2;
-                if (best < 0 || h < bh || (h == bh && (lw < bl || (lw == bl && c.tag[sid[q]] < c.tag[sid[best]])))) {
+                if (best < 0 || h < bh || (h == bh && (lw < bl || (lw == bl && stg[q] < stg[best])))) {
                     bh = h;
                     bl = lw;
                     best = q;
@@ -551,7 +510,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
                 const unsigned long long oh = __shfl_xor(bh, off), ol = __shfl_xor(bl, off);
                 const int ob = __shfl_xor(best, off);
                 if (ob >= 0 && (best < 0 || oh < bh ||
-                                (oh == bh && (ol < bl || (ol == bl && c.tag[sid[ob]] < c.tag[sid[best]]))))) {
+                                (oh == bh && (ol < bl || (ol == bl && stg[ob] < stg[best]))))) {
                     bh = oh;
                     bl = ol;
                     best = ob;
@@ -684,7 +643,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
         // canonical rotation: start at the smallest tag
         int mt = 0x7fffffff, mi = 0;
         for (int m = lane; m < k; m += 64) {
-            const int t = c.tag[sid[s_ring[m]]];
+            const int t = stg[s_ring[m]];
             if (t < mt) {
                 mt = t;
                 mi = m;
@@ -697,16 +656,19 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
                 mi = oi;
             }
         }
-        // touch the old neighbourhood before overwriting it (k, kold <= 64:
-        // one pass of the wave)
-        push_touch(w, st, round, lane < kold ? c.ring[i * KC + lane] : -1);
-        __syncthreads();
+        // touch the old neighbourhood (lanes 0..31), the new one (lanes
+        // 32..63) and the cell itself in one wave-wide append (k, kold <= 32)
         {
-            const int q = lane < k ? sid[s_ring[(mi + lane) % k]] : -1;
-            if (lane < k) c.ring[i * KC + lane] = q;
-            push_touch(w, st, round, q);
+            const int qnew = (lane >= 32 && lane - 32 < k) ? sid[s_ring[(mi + lane - 32) % k]] : -1;
+            const int qold = lane < kold ? c.ring[i * KC + lane] : -1;
+            __syncthreads();  // every lane has read the old ring
+            if (qnew >= 0) c.ring[i * KC + (lane - 32)] = qnew;
+            int t = lane < 32 ? qold : qnew;
+            const bool self_lane = (lane == 31 && kold < 32) || (lane == 63 && k < 32);
+            if (self_lane && t < 0) t = i;
+            push_touch(w, st, round, t);
+            if (kold >= 32 && k >= 32) push_touch(w, st, round, lane == 0 ? i : -1);
         }
-        push_touch(w, st, round, lane == 0 ? i : -1);
         if (lane == 0) c.deg[i] = (uint8_t)k;
         nrep++;
         __syncthreads();
@@ -718,11 +680,11 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
 // ---------------------------------------------------------------- step bookkeeping
 // After the last device repair round: count the step, accumulate the drift,
 // halt if rounds remain (the host finishes them) or an error was raised, and
-// clear the per-step counters otherwise.  Run by one 256-thread block: the
-// last block of the step's final re-test.
-__device__ void finalize_block(DevState* st, int rounds, const double* blockmax, int nblk)
+// clear the per-step counters otherwise (one 256-thread block).
+__global__ __launch_bounds__(256) void k_finalize(DevState* st, int rounds, const double* blockmax, int nblk)
 {
     __shared__ double smax[256];
+    if (st->halt) return;
     double m = 0.0;
     for (int b = threadIdx.x; b < nblk; b += 256) m = fmax(m, blockmax[b]);
     smax[threadIdx.x] = m;

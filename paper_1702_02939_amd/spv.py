@@ -38,12 +38,23 @@ class Params(ctypes.Structure):
                 ("v0", ctypes.c_double), ("Dr", ctypes.c_double), ("dt", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32), ("resort_every", ctypes.c_int32),
                 ("kcap", ctypes.c_int32), ("repair_rounds", ctypes.c_int32), ("device_rounds", ctypes.c_int32),
-                ("no_graphs", ctypes.c_int32)]
+                ("no_graphs", ctypes.c_int32), ("repair_cells", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("bin_factor", ctypes.c_double)]
 
     def __init__(self, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=1.0, dt=0.01, seed=0, precision=SPV_FP64,
-                 resort_every=0, kcap=0, repair_rounds=0, device_rounds=0, no_graphs=0):
+                 resort_every=0, kcap=0, repair_rounds=0, device_rounds=0, no_graphs=0, repair_cells=0,
+                 autotune=0, bin_factor=0.0):
         super().__init__(KA, KP, mu, v0, Dr, dt, seed, precision, resort_every, kcap, repair_rounds,
-                         device_rounds, no_graphs)
+                         device_rounds, no_graphs, repair_cells, autotune, bin_factor)
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("resort_every", ctypes.c_int32), ("device_rounds", ctypes.c_int32),
+                ("repair_cells", ctypes.c_int32), ("source", ctypes.c_int32), ("bin_factor", ctypes.c_double),
+                ("ms_per_step", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _P = ctypes.c_void_p
@@ -56,6 +67,9 @@ _SIGS = {
     "spv_create": [ctypes.POINTER(_H), _i64, _P, _P, _d, _d, _P, _P, _d, _P, ctypes.POINTER(Params), _P],
     "spv_batch_create": [ctypes.POINTER(_H), _i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Params), _P],
     "spv_step": [_H, _i64],
+    "spv_get_tuning": [_H, ctypes.POINTER(Tuning)],
+    "spv_save_state": [_H, _P, _i64, ctypes.POINTER(_i64)],
+    "spv_load_state": [_H, _P, _i64],
     "spv_get_size": [_H, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
     "spv_get_system_range": [_H, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "spv_get_box": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)],
@@ -224,6 +238,28 @@ def spv_get_observables(h):
     return E.value, q.value, a.value, cnt
 
 
+def spv_save_state(h):
+    """The handle's state as a uint8 array (host)."""
+    need = _i64()
+    st = _lib.spv_save_state(h, None, 0, ctypes.byref(need))
+    if st != SPV_ECAPACITY:
+        _check(st, "spv_save_state")
+    buf = np.zeros(int(need.value), dtype=np.uint8)
+    _check(_lib.spv_save_state(h, _ptr(buf), int(need.value), ctypes.byref(need)), "spv_save_state")
+    return buf
+
+
+def spv_load_state(h, buf):
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    _check(_lib.spv_load_state(h, _ptr(buf), int(buf.size)), "spv_load_state")
+
+
+def spv_get_tuning(h):
+    t = Tuning()
+    _check(_lib.spv_get_tuning(h, ctypes.byref(t)), "spv_get_tuning")
+    return t.as_dict()
+
+
 def spv_set_timing(h, enable):
     _check(_lib.spv_set_timing(h, int(bool(enable))), "spv_set_timing")
 
@@ -318,6 +354,15 @@ class System:
 
     def observables(self):
         return spv_get_observables(self.h)
+
+    def tuning(self):
+        return spv_get_tuning(self.h)
+
+    def save_state(self):
+        return spv_save_state(self.h)
+
+    def load_state(self, buf):
+        spv_load_state(self.h, buf)
 
     def traj_forward(self, T, ckpt_every):
         return spv_traj_forward(self.h, T, ckpt_every)
