@@ -245,6 +245,7 @@ def main():
         "kernels_ms_total": {k: v[0] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "repairs_per_step": head["repairs_per_step"],
+        "repair_rounds_per_step": head["rounds_per_step"],
         "observables": {"E": head["E"], "qbar": head["qbar"], "sumA": head["sumA"]},
     }
     if not args.headline_only:

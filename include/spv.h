@@ -69,22 +69,25 @@ typedef struct {
     int32_t resort_every;   /* steps between spatial re-sorts, rounded up to even (0: 32) */
     int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16) */
     int32_t repair_rounds;  /* max test/repair rounds per step, device and host together (0: 16, max 32) */
-    int32_t device_rounds;  /* repair rounds run on the device inside each step (0: 2) */
+    int32_t device_rounds;  /* repair rounds run on the device inside each step: round 0 over the whole
+                               grid, later ones in one block (0: 8) */
     int32_t no_graphs;      /* 0: replay whole re-sort periods as captured HIP graphs; 1: launch eagerly */
     int32_t repair_cells;   /* flagged cells per repair wavefront: the repair grid is N / repair_cells
                                blocks, clamped to [256, 4096] (0: 64) */
     int32_t autotune;       /* 0: use the scheduling knobs given here (resort_every, device_rounds,
-                               repair_cells, bin_factor); 1: take them from the tuning cache for this
+                               repair_cells, tail_items, bin_factor); 1: take them from the tuning cache for this
                                device and size class, else choose them by timed trial runs and cache
                                them; 2: always run the trials and refresh the cache.  The cache is the
                                JSON file named by the environment variable SPV_TUNE_CACHE, else held
                                in this process only.  The knobs never change results. */
+    int32_t tail_items;     /* a later round with more flagged cells than this is handed to the host
+                               (full-grid rounds) instead of the one-block tail (0: 64) */
     double bin_factor;      /* cell-list bin side in mean cell spacings sqrt(Lx Ly / N) (0: 1; 0.5..8) */
 } spv_params;
 
 /* Scheduling knobs a handle runs with (see spv_params). */
 typedef struct {
-    int32_t resort_every, device_rounds, repair_cells;
+    int32_t resort_every, device_rounds, repair_cells, tail_items;
     int32_t source;      /* 0: given in spv_params, 1: tuning cache, 2: timed trials */
     double bin_factor;
     double ms_per_step;  /* trial time per step of the chosen knobs (0 when source = 0) */

@@ -121,6 +121,7 @@ struct spv_sys {
     int S = 1, N = 0, KC = 16;
     int dev_rounds = 2, max_rounds = 16, unit = 16;
     int repair_cells = 64;  // repair grid = N / this (clamped to [256, 4096] blocks)
+    int tail_items = 64;    // largest later round the one-block tail takes
     double bin_factor = 1.0;
     int tune_source = 0;
     double tune_ms = 0.0;
@@ -137,9 +138,12 @@ struct spv_sys {
     int total_bins = 0;
     int *d_bin_key = nullptr, *d_bin_start = nullptr, *d_key = nullptr, *d_hist = nullptr, *d_fill = nullptr;
     int *d_perm = nullptr, *d_inv = nullptr, *d_chunk = nullptr;
+    int2* d_bin_range = nullptr;
     DevState* d_st = nullptr;
     DevState* h_st = nullptr;  // pinned copy
     double *d_stage = nullptr, *d_fx = nullptr, *d_fy = nullptr, *d_obs = nullptr, *d_blockmax = nullptr;
+    double* d_obs_part = nullptr;  // [S][obs_chunks][3]
+    int obs_chunks = 1;
     std::vector<void*> allocs;
     // graphs of one period starting in configuration 0 / 1
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -302,18 +306,17 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
                        (double*)nullptr, (double*)nullptr, s->d_sp, s->d_st, s->N, s->d_blockmax);
     if (ev) (void)hipEventRecord(ev[0].b, st);
     if (ev) (void)hipEventRecord(ev[1].a, st);
-    hipLaunchKernelGGL((k_geom<R, MULTI, KC, false, false>), dim3(cg), dim3(256), 0, st, nxt, s->work, s->d_sp,
-                       s->d_st, s->N, 0);
+    hipLaunchKernelGGL((k_geom<R, MULTI, KC, false, false, true>), dim3(cg), dim3(256), 0, st, nxt, s->work,
+                       s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax, (int)cg);
     if (ev) (void)hipEventRecord(ev[1].b, st);
-    for (int r = 0; r < s->dev_rounds; r++) {
-        if (ev && r == 0) (void)hipEventRecord(ev[2].a, st);
-        hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, r);
-        if (ev && r == 0) (void)hipEventRecord(ev[2].b, st);
-        hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
-                           s->d_st, s->N, r);
-    }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, s->d_st, s->dev_rounds, (const double*)s->d_blockmax,
-                       (int)cg);
+    // round 0 over the whole grid, later rounds and the step's close in one block
+    if (ev) (void)hipEventRecord(ev[2].a, st);
+    hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, 0);
+    if (ev) (void)hipEventRecord(ev[2].b, st);
+    hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
+                       s->d_st, s->N, 0, (const double*)nullptr, 0);
+    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(1), dim3(TAIL_THREADS), 0, st, nxt, s->work, s->d_sp, s->d_st,
+                       s->dev_rounds, s->tail_items);
 }
 
 // Re-sort from (cfg, parity 0) into set[cfg ^ 1] (the caller flips cfg).
@@ -333,8 +336,8 @@ void enqueue_resort(spv_sys* s, hipStream_t st, int cfg)
                        (const int*)s->d_chunk, s->d_st);
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(N, 256)), dim3(256), 0, st, s->d_key, s->d_bin_start, s->d_fill,
                        s->d_perm, N, s->d_st);
-    hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_bin_start, s->d_perm, src.tag,
-                       nb, s->d_st);
+    hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_bin_start,
+                       (const int*)s->d_bin_key, s->d_bin_range, s->d_perm, src.tag, nb, s->d_st);
     hipLaunchKernelGGL(k_inv_perm, dim3(grid_for(N, 256)), dim3(256), 0, st, s->d_perm, s->d_inv, N, s->d_st);
     hipLaunchKernelGGL((k_gather<R, KC>), dim3(grid_for(N, 256)), dim3(256), 0, st, src, dst, s->d_perm, s->d_inv,
                        N, s->d_st);
@@ -348,7 +351,7 @@ void enqueue_round(spv_sys* s, hipStream_t st, int round, unsigned rgrid)
     hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rgrid), dim3(64), 0, st, cur, s->work, s->d_sp, s->d_st,
                        round);
     hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(std::min(grid_for(s->N, CPB), 4096u)), dim3(256), 0,
-                       st, cur, s->work, s->d_sp, s->d_st, s->N, round);
+                       st, cur, s->work, s->d_sp, s->d_st, s->N, round, (const double*)nullptr, 0);
 }
 
 // ---------------------------------------------------------------- control block
@@ -631,8 +634,10 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     }
     ST_TRY(dalloc(s, &s->d_bin_key, s->total_bins));
     ST_TRY(dalloc(s, &s->d_bin_start, s->total_bins + 1));
+    ST_TRY(dalloc(s, &s->d_bin_range, s->total_bins));
     s->work.bin_key = s->d_bin_key;
     s->work.bin_start = s->d_bin_start;
+    s->work.bin_range = s->d_bin_range;
     ST_TRY(dalloc(s, &s->d_key, N));
     ST_TRY(dalloc(s, &s->d_hist, s->total_bins));
     ST_TRY(dalloc(s, &s->d_fill, s->total_bins));
@@ -645,6 +650,10 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     ST_TRY(dalloc(s, &s->d_fx, N));
     ST_TRY(dalloc(s, &s->d_fy, N));
     ST_TRY(dalloc(s, &s->d_obs, 3 * S));
+    int64_t nmax = 1;
+    for (const auto& v : in) nmax = std::max<int64_t>(nmax, v.n);
+    s->obs_chunks = (int)((nmax + OBS_CHUNK - 1) / OBS_CHUNK);
+    ST_TRY(dalloc(s, &s->d_obs_part, (size_t)3 * S * s->obs_chunks));
     ST_TRY(dalloc(s, &s->d_blockmax, cell_grid(s)));
     HIP_TRY(hipHostMalloc((void**)&s->h_st, sizeof(DevState), hipHostMallocDefault));
     HIP_TRY(hipMemcpyAsync(s->d_sp, s->hsp.data(), S * sizeof(SysParam), hipMemcpyHostToDevice, s->stream));
@@ -723,7 +732,7 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     s->KC = p.kcap > 0 ? p.kcap : 16;
     if (s->KC != 16 && s->KC != 32) return fail(SPV_EINVAL, "kcap must be 16 or 32");
     s->max_rounds = p.repair_rounds > 0 ? std::min(p.repair_rounds, MAX_ROUNDS) : 16;
-    s->dev_rounds = p.device_rounds > 0 ? std::min(p.device_rounds, s->max_rounds) : 2;
+    s->dev_rounds = p.device_rounds > 0 ? std::min(p.device_rounds, s->max_rounds) : std::min(8, s->max_rounds);
     if (s->dev_rounds > s->max_rounds) return fail(SPV_EINVAL, "device_rounds exceeds repair_rounds");
     s->unit = p.resort_every > 0 ? p.resort_every : 32;
     if (s->unit & 1) s->unit += 1;
@@ -731,6 +740,8 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     if (p.repair_cells < 0 || p.resort_every < 0 || p.device_rounds < 0)
         return fail(SPV_EINVAL, "negative scheduling knob");
     s->repair_cells = p.repair_cells > 0 ? p.repair_cells : 64;
+    if (p.tail_items < 0) return fail(SPV_EINVAL, "negative scheduling knob");
+    s->tail_items = p.tail_items > 0 ? p.tail_items : 64;
     s->bin_factor = p.bin_factor != 0.0 ? p.bin_factor : 1.0;
     if (!(s->bin_factor >= 0.5 && s->bin_factor <= 8.0)) return fail(SPV_EINVAL, "bin_factor must be in [0.5, 8]");
     if (p.autotune < 0 || p.autotune > 2) return fail(SPV_EINVAL, "autotune must be 0, 1 or 2");
@@ -898,13 +909,14 @@ spv_status build_handle(const CreateArgs& a, const spv_params& p, spv_sys** out)
     return finish_create(s, create_impl(s, a.in, hx, hy, a.A0, a.P0, a.th), out);
 }
 
-Knobs knobs_of(const spv_sys* s) { return {s->unit, s->dev_rounds, s->repair_cells, s->bin_factor}; }
+Knobs knobs_of(const spv_sys* s) { return {s->unit, s->dev_rounds, s->repair_cells, s->tail_items, s->bin_factor}; }
 
 spv_params with_knobs(spv_params p, const Knobs& k)
 {
     p.resort_every = k.resort_every;
     p.device_rounds = k.device_rounds;
     p.repair_cells = k.repair_cells;
+    p.tail_items = k.tail_items;
     p.bin_factor = k.bin_factor;
     p.autotune = 0;
     return p;
@@ -922,6 +934,7 @@ spv_status set_runtime_knobs(spv_sys* s, const Knobs& k)
     s->unit = k.resort_every + (k.resort_every & 1);
     s->dev_rounds = std::min(k.device_rounds, s->max_rounds);
     s->repair_cells = k.repair_cells;
+    s->tail_items = k.tail_items;
     return SPV_OK;
 }
 
@@ -1004,7 +1017,8 @@ spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
         int cand[3];
     };
     const Axis axes[] = {{&Knobs::repair_cells, {16, 64, 256}},
-                         {&Knobs::device_rounds, {1, 2, 3}},
+                         {&Knobs::tail_items, {16, 64, 256}},
+                         {&Knobs::device_rounds, {2, 4, 8}},
                          {&Knobs::resort_every, {16, 32, 64}}};
     for (const Axis& ax : axes) {
         if (set_runtime_knobs(cur, best) != SPV_OK || trial_ms(cur, kTrial, &best_ms) != SPV_OK) break;
@@ -1438,6 +1452,7 @@ spv_status spv_get_tuning(spv_sys* s, spv_tuning* out)
     out->resort_every = s->unit;
     out->device_rounds = s->dev_rounds;
     out->repair_cells = s->repair_cells;
+    out->tail_items = s->tail_items;
     out->source = s->tune_source;
     out->bin_factor = s->bin_factor;
     out->ms_per_step = s->tune_ms;
@@ -1549,12 +1564,15 @@ spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t
 static spv_status observables_all(spv_sys* s, std::vector<double>& h)
 {
     const ArraySet& cur = s->set[s->cfg];
+    const int ch = s->obs_chunks;
     if (s->mixed)
-        hipLaunchKernelGGL(k_observables<float>, dim3(s->S), dim3(256), 0, s->stream, (const float*)cur.A,
-                           (const float*)cur.P, cur.A0, cur.P0, s->d_sp, s->d_obs);
+        hipLaunchKernelGGL(k_observables<float>, dim3(s->S * ch), dim3(256), 0, s->stream, (const float*)cur.A,
+                           (const float*)cur.P, cur.A0, cur.P0, s->d_sp, ch, s->d_obs_part);
     else
-        hipLaunchKernelGGL(k_observables<double>, dim3(s->S), dim3(256), 0, s->stream, (const double*)cur.A,
-                           (const double*)cur.P, cur.A0, cur.P0, s->d_sp, s->d_obs);
+        hipLaunchKernelGGL(k_observables<double>, dim3(s->S * ch), dim3(256), 0, s->stream, (const double*)cur.A,
+                           (const double*)cur.P, cur.A0, cur.P0, s->d_sp, ch, s->d_obs_part);
+    hipLaunchKernelGGL(k_observables_sum, dim3(s->S), dim3(64), 0, s->stream, (const double*)s->d_obs_part, ch,
+                       s->d_obs);
     HIP_TRY(hipGetLastError());
     h.resize(3 * s->S);
     HIP_TRY(hipMemcpyAsync(h.data(), s->d_obs, 3 * s->S * sizeof(double), hipMemcpyDeviceToHost, s->stream));

@@ -79,8 +79,9 @@ struct Work {
     int* wl[2];
     int* tl[2];
     // bins (cells are stored in the order of their global bin at the last re-sort)
-    const int* bin_key;    // [sum of bins] spatial bin of a system -> global key
-    const int* bin_start;  // [total bins + 1]
+    const int* bin_key;     // [sum of bins] spatial bin of a system -> global key
+    const int* bin_start;   // [total bins + 1], by key
+    const int2* bin_range;  // [sum of bins] cells [x, y) of a spatial bin
 };
 
 __device__ __forceinline__ double mimg(double d, double L, double hL)

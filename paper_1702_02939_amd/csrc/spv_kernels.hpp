@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
         const double ddx = mimg(xq - xu, Q.Lx, Q.hLx), ddy = mimg(yq - yu, Q.Ly, Q.hLy);
         disp = sqrt(ddx * ddx + ddy * ddy);
     }
-    // block max of the displacement -> blockmax[block] (reduced by k_finalize)
+    // block max of the displacement -> blockmax[block] (reduced by the all-cells geometry pass)
     for (int off = 32; off >= 1; off >>= 1) disp = fmax(disp, __shfl_xor(disp, off));
     if (threadIdx.x == 0) blockmax[blockIdx.x] = disp;
 }
@@ -291,120 +291,160 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
 // OPP: rebuild opp first -- in the CCW ring of j_m the pattern
 // ..., opp_m, j_{m+1}, i, ... must appear; otherwise the rings disagree and
 // the cells are flagged.
+template <typename R, int KC>
+struct GeomLds {
+    double (*sD)[KC][2];  // displacements of ring slot m (cell group g)
+    R (*sU)[KC][2];       // Voronoi vertices
+    int (*sJ)[KC];        // ring members
+};
+
+// One pass over cells t = base + g (g = threadIdx.x / GL) of a list (LIST)
+// or of all cells; every thread of the block takes part (block barriers).
 template <typename R, bool MULTI, int KC, bool LIST, bool OPP>
-__global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
-                                              int N, int round)
+__device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, const SysParam* __restrict__ sp,
+                                          DevState* st, int base, int n, const int* __restrict__ list, int rnext,
+                                          const GeomLds<R, KC>& S, int& exact)
 {
     constexpr int NS = KC / GL;
+    const int g = threadIdx.x / GL, l = threadIdx.x % GL;
+    double (*sD)[KC][2] = S.sD;
+    R (*sU)[KC][2] = S.sU;
+    int (*sJ)[KC] = S.sJ;
+    const int t = base + g;
+    const bool valid = t < n;
+    const int i = valid ? (LIST ? list[t] : t) : 0;
+    if (LIST && valid && l == 0) atomicAnd(&w.touchbits[i >> 5], ~(1u << (i & 31)));
+    const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+    int k = valid ? c.deg[i] : 0;
+    if (valid && (k < 3 || k > KC)) {
+        if (l == 0) atomicOr(&st->err, ERR_DEGREE);
+        k = 0;
+    }
+    const double xi = c.x[i], yi = c.y[i];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int m = l + s * GL;
+        if (m < k) {
+            const int j = c.ring[i * KC + m];
+            sJ[g][m] = j;
+            sD[g][m][0] = mimg(c.x[j] - xi, P.Lx, P.hLx);
+            sD[g][m][1] = mimg(c.y[j] - yi, P.Ly, P.hLy);
+        }
+    }
+    __syncthreads();
+    const double rlim2 = 0.0625 * fmin(P.Lx, P.Ly) * fmin(P.Lx, P.Ly);
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int m = l + s * GL;
+        if (m < k) {
+            const int mn = (m + 1 == k) ? 0 : m + 1;
+            const int jm = sJ[g][m], jn = sJ[g][mn];
+            int o;
+            if (OPP) {
+                o = -1;
+                const int kj = min((int)c.deg[jm], KC);
+                for (int p = 0; p < kj; p++) {
+                    if (c.ring[jm * KC + p] == i) {
+                        const int pm1 = (p == 0) ? kj - 1 : p - 1;
+                        const int pm2 = (pm1 == 0) ? kj - 1 : pm1 - 1;
+                        if (c.ring[jm * KC + pm1] == jn) o = c.ring[jm * KC + pm2];
+                        break;
+                    }
+                }
+                c.opp[i * KC + m] = o;
+            } else {
+                o = c.opp[i * KC + m];
+            }
+            const double bx = sD[g][m][0], by = sD[g][m][1], cx = sD[g][mn][0], cy = sD[g][mn][1];
+            bool fail = cross_sign(bx, by, cx, cy, bx * cy - by * cx, P.scale) <= 0;
+            R ux, uy;
+            circumcentre((R)bx, (R)by, (R)cx, (R)cy, ux, uy);
+            if (!fail) {
+                if (o < 0) {
+                    fail = true;
+                } else {
+                    const double px = mimg(c.x[o] - xi, P.Lx, P.hLx), py = mimg(c.y[o] - yi, P.Ly, P.hLy);
+                    fail = incircle_tags(bx, by, cx, cy, px, py, c.tag, i, jm, jn, o, P.scale, &exact) > 0;
+                }
+                // a circumradius >= min(L)/4 is either a non-Delaunay triangle
+                // or a true violation of the box precondition; the repair
+                // tells them apart (it cannot certify a disk wider than L/2)
+                if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
+            }
+            if (fail) {
+                push_flag(w, st, rnext, i);
+                push_flag(w, st, rnext, jm);
+                push_flag(w, st, rnext, jn);
+                if (o >= 0) push_flag(w, st, rnext, o);
+            }
+            sU[g][m][0] = ux;
+            sU[g][m][1] = uy;
+        }
+    }
+    __syncthreads();
+    R a2 = R(0), per = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int m = l + s * GL;
+        if (m < k) {
+            const int mn = (m + 1 == k) ? 0 : m + 1;
+            const R ux = sU[g][m][0], uy = sU[g][m][1], vx = sU[g][mn][0], vy = sU[g][mn][1];
+            a2 += ux * vy - uy * vx;
+            per += sqrt((vx - ux) * (vx - ux) + (vy - uy) * (vy - uy));
+        }
+    }
+#pragma unroll
+    for (int off = GL / 2; off > 0; off >>= 1) {
+        a2 += __shfl_xor(a2, off);
+        per += __shfl_xor(per, off);
+    }
+    if (valid && l == 0 && k >= 3) {
+        const R A = R(0.5) * a2;
+        c.A[i] = A;
+        c.P[i] = per;
+        c.ca[i] = (R)(2.0 * P.KA * ((double)A - c.A0[i]));
+        c.cb[i] = (R)(2.0 * P.KP * ((double)per - c.P0[i]));
+    }
+    __syncthreads();  // LDS is reused by the next pass
+}
+
+// Geometry + test kernel.  LIST: the touched list of round `round` (its bits
+// cleared), failures to round + 1; otherwise all cells, failures to round 0.
+// STEP (all-cells pass of a step): block 0 also counts the step and adds the
+// step's largest displacement (block maxima of the force kernel) to the drift
+// bound that the repair rounds of this step search with.
+template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool STEP = false>
+__global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
+                                              int N, int round, const double* __restrict__ blockmax = nullptr,
+                                              int nblk = 0)
+{
     __shared__ double sD[CPB][KC][2];
     __shared__ R sU[CPB][KC][2];
     __shared__ int sJ[CPB][KC];
     if (st->halt) return;
-    const int g = threadIdx.x / GL, l = threadIdx.x % GL;
     const int n = LIST ? st->tl_count[round] : N;
     const int rnext = LIST ? round + 1 : 0;
     const int* __restrict__ list = w.tl[round & 1];
     const int bstart = LIST ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+    const GeomLds<R, KC> S{sD, sU, sJ};
     int exact = 0;
-    for (int base = bstart * CPB; base < n; base += gridDim.x * CPB) {
-        const int t = base + g;
-        const bool valid = t < n;
-        const int i = valid ? (LIST ? list[t] : t) : 0;
-        if (LIST && valid && l == 0) atomicAnd(&w.touchbits[i >> 5], ~(1u << (i & 31)));
-        const SysParam& P = sp[MULTI ? c.sys[i] : 0];
-        int k = valid ? c.deg[i] : 0;
-        if (valid && (k < 3 || k > KC)) {
-            if (l == 0) atomicOr(&st->err, ERR_DEGREE);
-            k = 0;
-        }
-        const double xi = c.x[i], yi = c.y[i];
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-            const int m = l + s * GL;
-            if (m < k) {
-                const int j = c.ring[i * KC + m];
-                sJ[g][m] = j;
-                sD[g][m][0] = mimg(c.x[j] - xi, P.Lx, P.hLx);
-                sD[g][m][1] = mimg(c.y[j] - yi, P.Ly, P.hLy);
-            }
-        }
-        __syncthreads();
-        const double rlim2 = 0.0625 * fmin(P.Lx, P.Ly) * fmin(P.Lx, P.Ly);
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-            const int m = l + s * GL;
-            if (m < k) {
-                const int mn = (m + 1 == k) ? 0 : m + 1;
-                const int jm = sJ[g][m], jn = sJ[g][mn];
-                int o;
-                if (OPP) {
-                    o = -1;
-                    const int kj = min((int)c.deg[jm], KC);
-                    for (int p = 0; p < kj; p++) {
-                        if (c.ring[jm * KC + p] == i) {
-                            const int pm1 = (p == 0) ? kj - 1 : p - 1;
-                            const int pm2 = (pm1 == 0) ? kj - 1 : pm1 - 1;
-                            if (c.ring[jm * KC + pm1] == jn) o = c.ring[jm * KC + pm2];
-                            break;
-                        }
-                    }
-                    c.opp[i * KC + m] = o;
-                } else {
-                    o = c.opp[i * KC + m];
-                }
-                const double bx = sD[g][m][0], by = sD[g][m][1], cx = sD[g][mn][0], cy = sD[g][mn][1];
-                bool fail = cross_sign(bx, by, cx, cy, bx * cy - by * cx, P.scale) <= 0;
-                R ux, uy;
-                circumcentre((R)bx, (R)by, (R)cx, (R)cy, ux, uy);
-                if (!fail) {
-                    if (o < 0) {
-                        fail = true;
-                    } else {
-                        const double px = mimg(c.x[o] - xi, P.Lx, P.hLx), py = mimg(c.y[o] - yi, P.Ly, P.hLy);
-                        fail = incircle_tags(bx, by, cx, cy, px, py, c.tag, i, jm, jn, o, P.scale, &exact) > 0;
-                    }
-                    // a circumradius >= min(L)/4 is either a non-Delaunay triangle
-                    // or a true violation of the box precondition; the repair
-                    // tells them apart (it cannot certify a disk wider than L/2)
-                    if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
-                }
-                if (fail) {
-                    push_flag(w, st, rnext, i);
-                    push_flag(w, st, rnext, jm);
-                    push_flag(w, st, rnext, jn);
-                    if (o >= 0) push_flag(w, st, rnext, o);
-                }
-                sU[g][m][0] = ux;
-                sU[g][m][1] = uy;
-            }
-        }
-        __syncthreads();
-        R a2 = R(0), per = R(0);
-#pragma unroll
-        for (int s = 0; s < NS; s++) {
-            const int m = l + s * GL;
-            if (m < k) {
-                const int mn = (m + 1 == k) ? 0 : m + 1;
-                const R ux = sU[g][m][0], uy = sU[g][m][1], vx = sU[g][mn][0], vy = sU[g][mn][1];
-                a2 += ux * vy - uy * vx;
-                per += sqrt((vx - ux) * (vx - ux) + (vy - uy) * (vy - uy));
-            }
-        }
-#pragma unroll
-        for (int off = GL / 2; off > 0; off >>= 1) {
-            a2 += __shfl_xor(a2, off);
-            per += __shfl_xor(per, off);
-        }
-        if (valid && l == 0 && k >= 3) {
-            const R A = R(0.5) * a2;
-            c.A[i] = A;
-            c.P[i] = per;
-            c.ca[i] = (R)(2.0 * P.KA * ((double)A - c.A0[i]));
-            c.cb[i] = (R)(2.0 * P.KP * ((double)per - c.P0[i]));
-        }
-        __syncthreads();  // LDS is reused by the next group of cells
-    }
+    for (int base = bstart * CPB; base < n; base += gridDim.x * CPB)
+        geom_pass<R, MULTI, KC, LIST, OPP>(c, w, sp, st, base, n, list, rnext, S, exact);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
+    if (STEP && blockIdx.x == 0) {
+        __shared__ double swm[256 / 64];
+        double m = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = fmax(m, blockmax[b]);
+        for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0) swm[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int v = 1; v < (int)(blockDim.x >> 6); v++) m = fmax(m, swm[v]);
+            st->step += 1ull;
+            st->drift += m;
+            st->disp_bits = __double_as_longlong(m);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- repair
@@ -418,295 +458,418 @@ __global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam
 // in-circle order, per lane and then across the wave.  The ring is certified
 // when every new circumdisk lies inside the search disk (2 |u_m| <= R), which
 // makes each new triangle empty with respect to all cells; otherwise R doubles.
+
+// LDS of one repairing wavefront
+struct RepairLds {
+    double* sx;   // candidate displacements
+    double* sy;
+    int* sid;     // candidate cell
+    int* stg;     // candidate tag
+    int* s_n;     // candidate count
+    int* s_ring;  // ring under construction (candidate slots), 65 entries
+    int cap;      // capacity of sx .. stg
+};
+
+constexpr int KMAX = 64;  // longest ring a repair may trace
+
+// Wave-level barrier: the lanes of one wavefront exchange LDS data with no
+// workgroup barrier (several wavefronts of a block repair different cells).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Rebuild the ring of cell i (all 64 lanes of the calling wavefront).
+// defer_on_cap: more candidates than L.cap leave the cell untouched and
+// return false (the caller hands the round to a larger kernel); otherwise
+// that is a capacity error.  Returns true when the ring was rewritten.
+template <typename R, bool MULTI, int KC>
+__device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __restrict__ sp, DevState* st, int round,
+                           int i, double drift, const RepairLds& L, bool defer_on_cap, bool& deferred, int& exact)
+{
+    const int lane = threadIdx.x & 63;
+    double* __restrict__ sx = L.sx;
+    double* __restrict__ sy = L.sy;
+    int* __restrict__ sid = L.sid;
+    int* __restrict__ stg = L.stg;
+    int* __restrict__ s_ring = L.s_ring;
+    if (lane == 0) atomicAnd(&w.flagbits[i >> 5], ~(1u << (i & 31)));
+    const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+    const double xi = c.x[i], yi = c.y[i];
+    const int kold = min((int)c.deg[i], KC);
+    // the old ring row (touched at the end), read while the search runs
+    const int qrow = lane < KC ? c.ring[i * KC + lane] : -1;
+    const double Rmax = 0.5 * fmin(P.Lx, P.Ly) * (1.0 - 1e-9);
+    // first radius: at least R0, and as large as the 7x7 bin window
+    // around the cell covers after the drift since the last re-sort
+    double Rs = fmin(fmax(P.R0, 3.0 * fmin(P.bsx, P.bsy) - drift), Rmax);
+    int k = 0;
+    bool ok = false, at_max = false;
+    int last_n = 0, last_closed = 0, attempts = 0;
+    double last_umax = 0.0;
+    for (int attempt = 0; attempt < 16 && !ok; attempt++) {
+        attempts = attempt + 1;
+        if (lane == 0) *L.s_n = 0;
+        wave_sync();
+        const double Rw = Rs + drift;
+        int rbx = (int)ceil(Rw / P.bsx), rby = (int)ceil(Rw / P.bsy);
+        int wx = 2 * rbx + 1, wy = 2 * rby + 1;
+        const int cbx = min((int)(xi / P.bsx), P.nbx - 1), cby = min((int)(yi / P.bsy), P.nby - 1);
+        int bx0 = cbx - rbx, by0 = cby - rby;
+        if (wx >= P.nbx) {
+            wx = P.nbx;
+            bx0 = 0;
+        }
+        if (wy >= P.nby) {
+            wy = P.nby;
+            by0 = 0;
+        }
+        const double R2 = Rs * Rs * (1.0 + 1e-12);
+        const int lo = P.cell_off, hi = P.cell_off + P.n;
+        for (int b = lane; b < wx * wy; b += 64) {
+            int bx = bx0 + b % wx, by = by0 + b / wx;
+            bx = ((bx % P.nbx) + P.nbx) % P.nbx;
+            by = ((by % P.nby) + P.nby) % P.nby;
+            const int2 br = w.bin_range[P.bin_off + by * P.nbx + bx];
+            const int c1 = min(br.y, hi);
+            for (int q = max(br.x, lo); q < c1; q++) {
+                if (q == i) continue;
+                const double dx = mimg(c.x[q] - xi, P.Lx, P.hLx), dy = mimg(c.y[q] - yi, P.Ly, P.hLy);
+                if (dx * dx + dy * dy <= R2) {
+                    const int slot = atomicAdd(L.s_n, 1);
+                    if (slot < L.cap) {
+                        sx[slot] = dx;
+                        sy[slot] = dy;
+                        sid[slot] = q;
+                        stg[slot] = c.tag[q];
+                    }
+                }
+            }
+        }
+        wave_sync();
+        const int n = *L.s_n;
+        last_n = n;
+        if (n > L.cap) {
+            if (defer_on_cap) {
+                deferred = true;
+                return false;
+            }
+            if (lane == 0) atomicOr(&st->err, ERR_CAPACITY);
+            break;
+        }
+        // nearest candidate: exact squared distance in grid units, ties by tag
+        unsigned long long bh = ~0ull, bl = ~0ull;
+        int best = -1;
+        for (int q = lane; q < n; q += 64) {
+            const __int128 X = to_units(sx[q], P.scale), Y = to_units(sy[q], P.scale);
+            const unsigned __int128 d2 = (unsigned __int128)(X * X + Y * Y);
+            const unsigned long long h = (unsigned long long)(d2 >> 64), lw = (unsigned long long)d2;
+            if (best < 0 || h < bh || (h == bh && (lw < bl || (lw == bl && stg[q] < stg[best])))) {
+                bh = h;
+                bl = lw;
+                best = q;
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const unsigned long long oh = __shfl_xor(bh, off), ol = __shfl_xor(bl, off);
+            const int ob = __shfl_xor(best, off);
+            if (ob >= 0 && (best < 0 || oh < bh || (oh == bh && (ol < bl || (ol == bl && stg[ob] < stg[best]))))) {
+                bh = oh;
+                bl = ol;
+                best = ob;
+            }
+        }
+        if (best < 0) {  // no candidate at all
+            if (at_max) break;
+            Rs = fmin(2.0 * Rs, Rmax);
+            at_max = (Rs >= Rmax);
+            continue;
+        }
+        const int start = best;
+        if (lane == 0) s_ring[0] = start;
+        k = 1;
+        int cur = start;
+        bool closed = false;
+        while (k <= KMAX) {
+            const double cx = sx[cur], cy = sy[cur];
+            const int gc = sid[cur];
+            // Next neighbour after c: the left-side candidate whose circle
+            // through (i, c, p) is first met when the circle centre
+            // c/2 + t perp(c) moves left; t_p = (|p|^2 - c.p) / (2 c x p).
+            // p strictly inside circle(i, c, q)  <=>  t_p < t_q.  The keys
+            // are double estimates with a per-key error bound; the exact
+            // in-circle order decides whenever the two best keys overlap.
+            double t1 = INFINITY, e1 = 0.0, t2 = INFINITY, e2 = 0.0;
+            int nb = -1;
+            for (int q = lane; q < n; q += 64) {
+                if (q == cur) continue;
+                const double px = sx[q], py = sy[q];
+                const double cr = cx * py - cy * px;
+                if (cross_sign(cx, cy, px, py, cr, P.scale) <= 0) continue;
+                const double num = px * px + py * py - (cx * px + cy * py);
+                const double t = num / (2.0 * cr);
+                // rounding bounds: |d num| <= 4e-15 (|p|^2 + |c.p|), |d cr| <= ecr
+                const double ecr = 1e-15 * (fabs(cx * py) + fabs(cy * px));
+                const double bnd = (ecr > 0.25 * fabs(cr))
+                                       ? INFINITY
+                                       : 4e-15 * (px * px + py * py + fabs(cx * px) + fabs(cy * py)) /
+                                                 (2.0 * fabs(cr)) +
+                                             fabs(t) * (2.0 * ecr / fabs(cr) + 4e-15);
+                if (t < t1) {
+                    t2 = t1;
+                    e2 = e1;
+                    t1 = t;
+                    e1 = bnd;
+                    nb = q;
+                } else if (t < t2) {
+                    t2 = t;
+                    e2 = bnd;
+                }
+            }
+            // wave arg-min of (t1, nb) keeping the runner-up key
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ot1 = __shfl_xor(t1, off), oe1 = __shfl_xor(e1, off);
+                const double ot2 = __shfl_xor(t2, off), oe2 = __shfl_xor(e2, off);
+                const int onb = __shfl_xor(nb, off);
+                if (ot1 < t1 || (ot1 == t1 && onb >= 0 && (nb < 0 || onb < nb))) {
+                    // other side wins: my best becomes a runner-up candidate
+                    if (t1 < ot2) {
+                        t2 = t1;
+                        e2 = e1;
+                    } else {
+                        t2 = ot2;
+                        e2 = oe2;
+                    }
+                    t1 = ot1;
+                    e1 = oe1;
+                    nb = onb;
+                } else {
+                    if (ot1 < t2) {
+                        t2 = ot1;
+                        e2 = oe1;
+                    }
+                }
+            }
+            if (nb >= 0 && t2 - e2 <= t1 + e1) {
+                // the keys cannot separate the best from the runner-up:
+                // exact arg-min under the in-circle order (rare)
+                nb = -1;
+                for (int q = lane; q < n; q += 64) {
+                    if (q == cur) continue;
+                    const double px = sx[q], py = sy[q];
+                    if (cross_sign(cx, cy, px, py, cx * py - cy * px, P.scale) <= 0) continue;
+                    if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, c.tag, i, gc, sid[nb], sid[q],
+                                                P.scale, &exact) > 0)
+                        nb = q;
+                }
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const int ob = __shfl_xor(nb, off);
+                    if (ob >= 0 && ob != nb &&
+                        (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], c.tag, i, gc, sid[nb],
+                                                 sid[ob], P.scale, &exact) > 0))
+                        nb = ob;
+                }
+            }
+            if (nb < 0) break;  // star open: search disk too small
+            if (nb == start) {
+                closed = true;
+                break;
+            }
+            if (lane == 0) s_ring[k] = nb;
+            k++;
+            cur = nb;
+        }
+        wave_sync();
+        double umax = 0.0;
+        if (closed && k >= 3) {
+            for (int m = lane; m < k; m += 64) {
+                const int p = s_ring[m], q = s_ring[(m + 1 == k) ? 0 : m + 1];
+                double ux, uy;
+                circumcentre(sx[p], sy[p], sx[q], sy[q], ux, uy);
+                umax = fmax(umax, sqrt(ux * ux + uy * uy));
+            }
+            for (int off = 32; off >= 1; off >>= 1) umax = fmax(umax, __shfl_xor(umax, off));
+            if (2.0 * umax * (1.0 + 1e-9) <= Rs) ok = true;
+        }
+        last_closed = closed ? 1 : 0;
+        last_umax = umax;
+        if (!ok) {
+            if (at_max) break;
+            // an uncertified star may be wrong (outer triangles clipped by
+            // the search disk), so its circumradii say nothing: double R
+            Rs = fmin(2.0 * Rs, Rmax);
+            at_max = (Rs >= Rmax);
+            if (lane == 0) atomicAdd(&st->retries, 1ull);
+        }
+    }
+    if (!ok || k > KC) {
+        if (lane == 0) {
+            atomicOr(&st->err, !ok ? (at_max ? ERR_PRECOND : ERR_REPAIR) : ERR_CAPACITY);
+            if (atomicCAS(&st->fail_set, 0, 1) == 0) {
+                st->fail_cell = c.tag[i];
+                st->fail_n = last_n;
+                st->fail_k = k;
+                st->fail_closed = last_closed;
+                st->fail_attempts = attempts;
+                st->fail_R = Rs;
+                st->fail_umax = last_umax;
+            }
+        }
+        wave_sync();
+        return false;
+    }
+    // canonical rotation: start at the smallest tag
+    int mt = 0x7fffffff, mi = 0;
+    for (int m = lane; m < k; m += 64) {
+        const int t = stg[s_ring[m]];
+        if (t < mt) {
+            mt = t;
+            mi = m;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int ot = __shfl_xor(mt, off), oi = __shfl_xor(mi, off);
+        if (ot < mt) {
+            mt = ot;
+            mi = oi;
+        }
+    }
+    // touch the old neighbourhood (lanes 0..31), the new one (lanes 32..63)
+    // and the cell itself in one wave-wide append (k, kold <= 32); the old
+    // ring is consumed by the append (a data dependence) before the new one
+    // is stored over it
+    const int qnew = (lane >= 32 && lane - 32 < k) ? sid[s_ring[(mi + lane - 32) % k]] : -1;
+    const int qold = lane < kold ? qrow : -1;
+    int t = lane < 32 ? qold : qnew;
+    const bool self_lane = (lane == 31 && kold < 32) || (lane == 63 && k < 32);
+    if (self_lane && t < 0) t = i;
+    push_touch(w, st, round, t);
+    if (kold >= 32 && k >= 32) push_touch(w, st, round, lane == 0 ? i : -1);
+    wave_sync();
+    if (qnew >= 0) c.ring[i * KC + (lane - 32)] = qnew;
+    if (lane == 0) c.deg[i] = (uint8_t)k;
+    wave_sync();
+    return true;
+}
+
+// Repair round `round`: one wavefront per flagged cell of the worklist.
 template <typename R, bool MULTI, int KC>
 __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
                                                int round)
 {
-    constexpr int KMAX = 64;
     __shared__ double sx[RP_CAP], sy[RP_CAP];
-    __shared__ int sid[RP_CAP], stg[RP_CAP];  // candidate cell and its tag
+    __shared__ int sid[RP_CAP], stg[RP_CAP];
     __shared__ int s_n;
     __shared__ int s_ring[KMAX + 1];
     if (st->halt) return;
-    const int lane = threadIdx.x;
     const int nw = st->wl_count[round];
     const int* __restrict__ wl = w.wl[round & 1];
     const double drift = st->drift;
+    const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, RP_CAP};
     int exact = 0, nrep = 0;
-    for (int wi = blockIdx.x; wi < nw; wi += gridDim.x) {
-        const int i = wl[wi];
-        if (lane == 0) atomicAnd(&w.flagbits[i >> 5], ~(1u << (i & 31)));
-        const SysParam& P = sp[MULTI ? c.sys[i] : 0];
-        const double xi = c.x[i], yi = c.y[i];
-        const int kold = min((int)c.deg[i], KC);
-        const double Rmax = 0.5 * fmin(P.Lx, P.Ly) * (1.0 - 1e-9);
-        // first radius: at least R0, and as large as the 7x7 bin window
-        // around the cell covers after the drift since the last re-sort
-        double Rs = fmin(fmax(P.R0, 3.0 * fmin(P.bsx, P.bsy) - drift), Rmax);
-        int k = 0;
-        bool ok = false, at_max = false;
-        int last_n = 0, last_closed = 0, attempts = 0;
-        double last_umax = 0.0;
-        for (int attempt = 0; attempt < 16 && !ok; attempt++) {
-            attempts = attempt + 1;
-            if (lane == 0) s_n = 0;
-            __syncthreads();
-            const double Rw = Rs + drift;
-            int rbx = (int)ceil(Rw / P.bsx), rby = (int)ceil(Rw / P.bsy);
-            int wx = 2 * rbx + 1, wy = 2 * rby + 1;
-            const int cbx = min((int)(xi / P.bsx), P.nbx - 1), cby = min((int)(yi / P.bsy), P.nby - 1);
-            int bx0 = cbx - rbx, by0 = cby - rby;
-            if (wx >= P.nbx) {
-                wx = P.nbx;
-                bx0 = 0;
-            }
-            if (wy >= P.nby) {
-                wy = P.nby;
-                by0 = 0;
-            }
-            const double R2 = Rs * Rs * (1.0 + 1e-12);
-            const int lo = P.cell_off, hi = P.cell_off + P.n;
-            for (int b = lane; b < wx * wy; b += 64) {
-                int bx = bx0 + b % wx, by = by0 + b / wx;
-                bx = ((bx % P.nbx) + P.nbx) % P.nbx;
-                by = ((by % P.nby) + P.nby) % P.nby;
-                const int key = w.bin_key[P.bin_off + by * P.nbx + bx];
-                const int c1 = min(w.bin_start[key + 1], hi);
-                for (int q = max(w.bin_start[key], lo); q < c1; q++) {
-                    if (q == i) continue;
-                    const double dx = mimg(c.x[q] - xi, P.Lx, P.hLx), dy = mimg(c.y[q] - yi, P.Ly, P.hLy);
-                    if (dx * dx + dy * dy <= R2) {
-                        const int slot = atomicAdd(&s_n, 1);
-                        if (slot < RP_CAP) {
-                            sx[slot] = dx;
-                            sy[slot] = dy;
-                            sid[slot] = q;
-                            stg[slot] = c.tag[q];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            const int n = s_n;
-            last_n = n;
-            if (n > RP_CAP) {
-                if (lane == 0) atomicOr(&st->err, ERR_CAPACITY);
-                break;
-            }
-            // nearest candidate: exact squared distance in grid units, ties by tag
-            unsigned long long bh = ~0ull, bl = ~0ull;
-            int best = -1;
-            for (int q = lane; q < n; q += 64) {
-                const __int128 X = to_units(sx[q], P.scale), Y = to_units(sy[q], P.scale);
-                const unsigned __int128 d2 = (unsigned __int128)(X * X + Y * Y);
-                const unsigned long long h = (unsigned long long)(d2 >> 64), lw = (unsigned long long)d2;
-                if (best < 0 || h < bh || (h == bh && (lw < bl || (lw == bl && stg[q] < stg[best])))) {
-                    bh = h;
-                    bl = lw;
-                    best = q;
-                }
-            }
-            for (int off = 32; off >= 1; off >>= 1) {
-                const unsigned long long oh = __shfl_xor(bh, off), ol = __shfl_xor(bl, off);
-                const int ob = __shfl_xor(best, off);
-                if (ob >= 0 && (best < 0 || oh < bh ||
-                                (oh == bh && (ol < bl || (ol == bl && stg[ob] < stg[best]))))) {
-                    bh = oh;
-                    bl = ol;
-                    best = ob;
-                }
-            }
-            if (best < 0) {  // no candidate at all
-                if (at_max) break;
-                Rs = fmin(2.0 * Rs, Rmax);
-                at_max = (Rs >= Rmax);
-                continue;
-            }
-            const int start = best;
-            if (lane == 0) s_ring[0] = start;
-            k = 1;
-            int cur = start;
-            bool closed = false;
-            while (k <= KMAX) {
-                const double cx = sx[cur], cy = sy[cur];
-                const int gc = sid[cur];
-                // Next neighbour after c: the left-side candidate whose circle
-                // through (i, c, p) is first met when the circle centre
-                // c/2 + t perp(c) moves left; t_p = (|p|^2 - c.p) / (2 c x p).
-                // p strictly inside circle(i, c, q)  <=>  t_p < t_q.  The keys
-                // are double estimates with a per-key error bound; the exact
-                // in-circle order decides whenever the two best keys overlap.
-                double t1 = INFINITY, e1 = 0.0, t2 = INFINITY, e2 = 0.0;
-                int nb = -1;
-                for (int q = lane; q < n; q += 64) {
-                    if (q == cur) continue;
-                    const double px = sx[q], py = sy[q];
-                    const double cr = cx * py - cy * px;
-                    if (cross_sign(cx, cy, px, py, cr, P.scale) <= 0) continue;
-                    const double num = px * px + py * py - (cx * px + cy * py);
-                    const double t = num / (2.0 * cr);
-                    // rounding bounds: |d num| <= 4e-15 (|p|^2 + |c.p|), |d cr| <= ecr
-                    const double ecr = 1e-15 * (fabs(cx * py) + fabs(cy * px));
-                    const double bnd =
-                        (ecr > 0.25 * fabs(cr))
-                            ? INFINITY
-                            : 4e-15 * (px * px + py * py + fabs(cx * px) + fabs(cy * py)) / (2.0 * fabs(cr)) +
-                                  fabs(t) * (2.0 * ecr / fabs(cr) + 4e-15);
-                    if (t < t1) {
-                        t2 = t1; e2 = e1;
-                        t1 = t; e1 = bnd; nb = q;
-                    } else if (t < t2) {
-                        t2 = t; e2 = bnd;
-                    }
-                }
-                // wave arg-min of (t1, nb) keeping the runner-up key
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const double ot1 = __shfl_xor(t1, off), oe1 = __shfl_xor(e1, off);
-                    const double ot2 = __shfl_xor(t2, off), oe2 = __shfl_xor(e2, off);
-                    const int onb = __shfl_xor(nb, off);
-                    if (ot1 < t1 || (ot1 == t1 && onb >= 0 && (nb < 0 || onb < nb))) {
-                        // other side wins: my best becomes a runner-up candidate
-                        if (t1 < ot2) { t2 = t1; e2 = e1; } else { t2 = ot2; e2 = oe2; }
-                        t1 = ot1; e1 = oe1; nb = onb;
-                    } else {
-                        if (ot1 < t2) { t2 = ot1; e2 = oe1; }
-                    }
-                }
-                if (nb >= 0 && t2 - e2 <= t1 + e1) {
-                    // the keys cannot separate the best from the runner-up:
-                    // exact arg-min under the in-circle order (rare)
-                    nb = -1;
-                    for (int q = lane; q < n; q += 64) {
-                        if (q == cur) continue;
-                        const double px = sx[q], py = sy[q];
-                        if (cross_sign(cx, cy, px, py, cx * py - cy * px, P.scale) <= 0) continue;
-                        if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, c.tag, i, gc, sid[nb], sid[q],
-                                                    P.scale, &exact) > 0)
-                            nb = q;
-                    }
-                    for (int off = 32; off >= 1; off >>= 1) {
-                        const int ob = __shfl_xor(nb, off);
-                        if (ob >= 0 && ob != nb &&
-                            (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], c.tag, i, gc, sid[nb],
-                                                     sid[ob], P.scale, &exact) > 0))
-                            nb = ob;
-                    }
-                }
-                if (nb < 0) break;  // star open: search disk too small
-                if (nb == start) {
-                    closed = true;
-                    break;
-                }
-                if (lane == 0) s_ring[k] = nb;
-                k++;
-                cur = nb;
-            }
-            __syncthreads();
-            double umax = 0.0;
-            if (closed && k >= 3) {
-                for (int m = lane; m < k; m += 64) {
-                    const int p = s_ring[m], q = s_ring[(m + 1 == k) ? 0 : m + 1];
-                    double ux, uy;
-                    circumcentre(sx[p], sy[p], sx[q], sy[q], ux, uy);
-                    umax = fmax(umax, sqrt(ux * ux + uy * uy));
-                }
-                for (int off = 32; off >= 1; off >>= 1) umax = fmax(umax, __shfl_xor(umax, off));
-                if (2.0 * umax * (1.0 + 1e-9) <= Rs) ok = true;
-            }
-            last_closed = closed ? 1 : 0;
-            last_umax = umax;
-            if (!ok) {
-                if (at_max) break;
-                // an uncertified star may be wrong (outer triangles clipped by
-                // the search disk), so its circumradii say nothing: double R
-                Rs = fmin(2.0 * Rs, Rmax);
-                at_max = (Rs >= Rmax);
-                if (lane == 0) atomicAdd(&st->retries, 1ull);
-            }
-        }
-        if (!ok || k > KC) {
-            if (lane == 0) {
-                atomicOr(&st->err, !ok ? (at_max ? ERR_PRECOND : ERR_REPAIR) : ERR_CAPACITY);
-                if (atomicCAS(&st->fail_set, 0, 1) == 0) {
-                    st->fail_cell = c.tag[i];
-                    st->fail_n = last_n;
-                    st->fail_k = k;
-                    st->fail_closed = last_closed;
-                    st->fail_attempts = attempts;
-                    st->fail_R = Rs;
-                    st->fail_umax = last_umax;
-                }
-            }
-            __syncthreads();
-            continue;
-        }
-        // canonical rotation: start at the smallest tag
-        int mt = 0x7fffffff, mi = 0;
-        for (int m = lane; m < k; m += 64) {
-            const int t = stg[s_ring[m]];
-            if (t < mt) {
-                mt = t;
-                mi = m;
-            }
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const int ot = __shfl_xor(mt, off), oi = __shfl_xor(mi, off);
-            if (ot < mt) {
-                mt = ot;
-                mi = oi;
-            }
-        }
-        // touch the old neighbourhood (lanes 0..31), the new one (lanes
-        // 32..63) and the cell itself in one wave-wide append (k, kold <= 32)
-        {
-            const int qnew = (lane >= 32 && lane - 32 < k) ? sid[s_ring[(mi + lane - 32) % k]] : -1;
-            const int qold = lane < kold ? c.ring[i * KC + lane] : -1;
-            __syncthreads();  // every lane has read the old ring
-            if (qnew >= 0) c.ring[i * KC + (lane - 32)] = qnew;
-            int t = lane < 32 ? qold : qnew;
-            const bool self_lane = (lane == 31 && kold < 32) || (lane == 63 && k < 32);
-            if (self_lane && t < 0) t = i;
-            push_touch(w, st, round, t);
-            if (kold >= 32 && k >= 32) push_touch(w, st, round, lane == 0 ? i : -1);
-        }
-        if (lane == 0) c.deg[i] = (uint8_t)k;
-        nrep++;
-        __syncthreads();
-    }
-    if (lane == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
+    bool deferred = false;
+    for (int wi = blockIdx.x; wi < nw; wi += gridDim.x)
+        nrep += repair_one<R, MULTI, KC>(c, w, sp, st, round, wl[wi], drift, L, false, deferred, exact) ? 1 : 0;
+    if (threadIdx.x == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
 }
 
-// ---------------------------------------------------------------- step bookkeeping
-// After the last device repair round: count the step, accumulate the drift,
-// halt if rounds remain (the host finishes them) or an error was raised, and
-// clear the per-step counters otherwise (one 256-thread block).
-__global__ __launch_bounds__(256) void k_finalize(DevState* st, int rounds, const double* blockmax, int nblk)
+// ---------------------------------------------------------------- step tail
+// Repair rounds 1 .. rounds-1 of a step and its close, in one block: after
+// round 0 a step usually has no or a handful of flagged cells, which a few
+// wavefronts repair (one cell each) and a block-wide geometry pass re-tests,
+// with block barriers between the phases instead of kernel boundaries.  A
+// round with more than max_items cells, a cell with more than RP_TAIL
+// candidates, rounds left at the end or an error halt the step; the host
+// then finishes it with full-grid rounds.  Otherwise the per-step counters
+// are cleared for the next step.
+constexpr int TAIL_WAVES = 8;
+constexpr int TAIL_THREADS = 64 * TAIL_WAVES;
+constexpr int TAIL_CPB = TAIL_THREADS / GL;
+constexpr int RP_TAIL = 512;
+
+// counters written by atomics of other wavefronts of this block: read at
+// device scope (past the compute unit's L1)
+__device__ __forceinline__ int load_count(const int* p)
 {
-    __shared__ double smax[256];
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename R, bool MULTI, int KC>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const SysParam* __restrict__ sp,
+                                                       DevState* st, int rounds, int max_items)
+{
+    constexpr size_t kRepBytes =
+        (size_t)TAIL_WAVES * (RP_TAIL * (2 * sizeof(double) + 2 * sizeof(int)) + (KMAX + 1) * sizeof(int));
+    constexpr size_t kGeoBytes = (size_t)TAIL_CPB * KC * (2 * sizeof(double) + 2 * sizeof(R) + sizeof(int));
+    __shared__ __align__(16) unsigned char raw[kRepBytes > kGeoBytes ? kRepBytes : kGeoBytes];
+    __shared__ int s_n[TAIL_WAVES];
+    __shared__ int s_defer;
     if (st->halt) return;
-    double m = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) m = fmax(m, blockmax[b]);
-    smax[threadIdx.x] = m;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + h]);
+    const int wave = threadIdx.x >> 6;
+    // repair views (one slice per wavefront)
+    unsigned char* q = raw;
+    double* sx = reinterpret_cast<double*>(q) + wave * RP_TAIL;
+    q += (size_t)TAIL_WAVES * RP_TAIL * sizeof(double);
+    double* sy = reinterpret_cast<double*>(q) + wave * RP_TAIL;
+    q += (size_t)TAIL_WAVES * RP_TAIL * sizeof(double);
+    int* sid = reinterpret_cast<int*>(q) + wave * RP_TAIL;
+    q += (size_t)TAIL_WAVES * RP_TAIL * sizeof(int);
+    int* stg = reinterpret_cast<int*>(q) + wave * RP_TAIL;
+    q += (size_t)TAIL_WAVES * RP_TAIL * sizeof(int);
+    int* sring = reinterpret_cast<int*>(q) + wave * (KMAX + 1);
+    const RepairLds L{sx, sy, sid, stg, &s_n[wave], sring, RP_TAIL};
+    // geometry views (the same memory, used between block barriers)
+    unsigned char* g = raw;
+    const GeomLds<R, KC> S{reinterpret_cast<double(*)[KC][2]>(g),
+                           reinterpret_cast<R(*)[KC][2]>(g + (size_t)TAIL_CPB * KC * 2 * sizeof(double)),
+                           reinterpret_cast<int(*)[KC]>(g + (size_t)TAIL_CPB * KC * 2 * (sizeof(double) + sizeof(R)))};
+
+    const double drift = st->drift;
+    int exact = 0, nrep = 0, used = st->wl_count[0] > 0 ? 1 : 0;
+    int r = 1, halt_at = -1;
+    for (; r < rounds; r++) {
+        const int nw = load_count(&st->wl_count[r]);
+        if (nw == 0) break;
+        if (nw > max_items) {
+            halt_at = r;
+            break;
+        }
+        used++;
+        if (threadIdx.x == 0) s_defer = 0;
+        __syncthreads();
+        const int* __restrict__ wl = w.wl[r & 1];
+        for (int wi = wave; wi < nw; wi += TAIL_WAVES) {
+            bool deferred = false;
+            nrep += repair_one<R, MULTI, KC>(c, w, sp, st, r, wl[wi], drift, L, true, deferred, exact) ? 1 : 0;
+            if (deferred && (threadIdx.x & 63) == 0) s_defer = 1;
+        }
+        __syncthreads();
+        if (s_defer) {
+            halt_at = r;
+            break;
+        }
+        const int nt = load_count(&st->tl_count[r]);
+        const int* __restrict__ tl = w.tl[r & 1];
+        for (int base = 0; base < nt; base += TAIL_CPB)
+            geom_pass<R, MULTI, KC, true, true>(c, w, sp, st, base, nt, tl, r + 1, S, exact);
         __syncthreads();
     }
+    if (halt_at < 0 && r == rounds && load_count(&st->wl_count[rounds]) > 0) halt_at = rounds;
+    if ((threadIdx.x & 63) == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
+    if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    st->step += 1ull;
-    st->drift += smax[0];
-    st->disp_bits = __double_as_longlong(smax[0]);
-    int used = 0;
-    for (int r = 0; r < rounds; r++) used += st->wl_count[r] > 0;
     st->rounds += (unsigned long long)used;
-    if (st->err || st->wl_count[rounds] > 0) {
+    if (halt_at >= 0 || __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
         st->halt = 1;
-        st->halt_round = rounds;
+        st->halt_round = halt_at >= 0 ? halt_at : rounds;
         return;
     }
-    for (int r = 0; r <= rounds; r++) st->wl_count[r] = 0;
-    for (int r = 0; r < rounds; r++) st->tl_count[r] = 0;
+    for (int v = 0; v <= rounds; v++) st->wl_count[v] = 0;
+    for (int v = 0; v < rounds; v++) st->tl_count[v] = 0;
 }
 
 // host recovery finished: clear the per-step counters and resume
@@ -840,12 +1003,17 @@ __global__ void k_bin_scatter(const int* key, const int* start, int* fill, int* 
 }
 
 // order the few cells of each bin by tag so the permutation is deterministic
-__global__ void k_bin_sort(const int* start, int* perm, const int* tag, int nb, const DevState* st)
+// order the cells of each bin by tag (deterministic memory order) and record
+// the bin's cell range under its spatial index (one load for the repair)
+__global__ void k_bin_sort(const int* start, const int* bin_key, int2* range, int* perm, const int* tag, int nb,
+                           const DevState* st)
 {
     if (st->halt) return;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nb) return;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int r = bin_key[b];
     const int s = start[r], e = start[r + 1];
+    range[b] = make_int2(s, e);
     for (int a = s + 1; a < e; a++) {
         const int cc = perm[a];
         const int tc = tag[cc];
@@ -903,15 +1071,21 @@ __global__ void k_to_tag_order(const T* in, const int* tag, const int* sys, cons
     if (i < n) out[sp[sys[i]].cell_off + tag[i]] = (double)in[i];
 }
 
-// one block per system; fixed in-block tree (deterministic)
+// Observables (Eq. 1 energy, sum of P/sqrt(A), sum of A) in two fixed-order
+// stages: block (s, chunk) sums cells [chunk * OBS_CHUNK, ...) of system s,
+// then one block per system adds its chunks in order (deterministic).
+constexpr int OBS_CHUNK = 8192;
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_observables(const R* A, const R* P, const double* A0, const double* P0,
-                                                     const SysParam* sp, double* out)
+                                                     const SysParam* sp, int chunks, double* part)
 {
     __shared__ double s[3][256];
-    const SysParam& S = sp[blockIdx.x];
+    const int sys = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+    const SysParam& S = sp[sys];
     double e = 0.0, q = 0.0, a = 0.0;
-    for (int i = S.cell_off + threadIdx.x; i < S.cell_off + S.n; i += 256) {
+    const int first = S.cell_off + ch * OBS_CHUNK, last = S.cell_off + min(S.n, (ch + 1) * OBS_CHUNK);
+    for (int i = first + threadIdx.x; i < last; i += 256) {
         const double Ai = (double)A[i], Pi = (double)P[i];
         const double dA = Ai - A0[i], dP = Pi - P0[i];
         e += S.KA * dA * dA + S.KP * dP * dP;
@@ -928,7 +1102,15 @@ __global__ __launch_bounds__(256) void k_observables(const R* A, const R* P, con
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 3; k++) out[3 * blockIdx.x + k] = s[k][0];
+        for (int k = 0; k < 3; k++) part[3 * blockIdx.x + k] = s[k][0];
+}
+
+__global__ void k_observables_sum(const double* part, int chunks, double* out)
+{
+    if (threadIdx.x >= 3) return;
+    double v = 0.0;
+    for (int ch = 0; ch < chunks; ch++) v += part[3 * (blockIdx.x * chunks + ch) + threadIdx.x];
+    out[3 * blockIdx.x + threadIdx.x] = v;
 }
 
 __global__ void k_theta0(double* th, const int* tag, const int* sys, const SysParam* sp, int n)
