@@ -66,6 +66,7 @@ def parse():
                     help="run with the default scheduling knobs instead of the library's tuned ones")
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--big-steps", type=int, default=400)
+    ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -104,14 +105,20 @@ def timed_run(spv, make, steps, warmup, timing=True):
         spv.spv_set_timing(sysm.h, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysm.step(steps)
+    half = steps // 2
+    sysm.step(steps - half)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sysm.step(half)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    second = time.perf_counter() - t1
     E, qbar, sumA, c1 = sysm.observables()
     kt = {name: spv.spv_kernel_time(sysm.h, k) for name, k in
           (("force_update", spv.K_FORCE), ("geometry_test", spv.K_GEOM), ("repair", spv.K_REPAIR))}
     sysm.close()
     return {"value": ncells * steps / wall, "ms_per_step": wall * 1e3 / steps, "cells": ncells, "steps": steps,
+            "steady_value": ncells * half / second if half else None,
             "kernels": kt, "repairs_per_step": float(c1[1] - c0[1]) / steps,
             "rounds_per_step": float(c1[2] - c0[2]) / steps, "E": E, "qbar": qbar, "sumA": sumA,
             "tuning": tuning}
@@ -120,15 +127,31 @@ def timed_run(spv, make, steps, warmup, timing=True):
 AUTOTUNE = 1
 
 
-def single(spv, inputs, name, precision):
+def single(spv, inputs, name, precision, p0=None, **knobs):
     w = inputs.WORKLOADS[name]
 
     def make():
         x, y = inputs.uniform_positions(w["N"], w["L"], w["L"], w["seed"])
         prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"], precision=precision,
-                         autotune=AUTOTUNE)
-        return spv.System(x, y, w["L"], w["L"], p0=w["p0"], params=prm), w["N"]
+                         autotune=0 if knobs else AUTOTUNE, **knobs)
+        return spv.System(x, y, w["L"], w["L"], p0=w["p0"] if p0 is None else p0, params=prm), w["N"]
     return make
+
+
+def sweeps(spv, inputs, steps, warmup):
+    """The paper's solid-to-fluid sweep (target shape index 3.8 / 3.9 / 4.0
+    at v0 = 0.1, N = 1e5, FP64) and the re-sort interval ablation (Hilbert
+    order; 10 / 32 / 100 / 1000 steps between re-sorts) on spv_n100k."""
+    out = {"p0_sweep": {}, "resort_ablation": {}}
+    for p0 in (3.8, 3.9, 4.0):
+        r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, p0=p0), steps, warmup, timing=False)
+        out["p0_sweep"][str(p0)] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                                    "repairs_per_step": r["repairs_per_step"]}
+    for every in (10, 32, 100, 1000):
+        r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, resort_every=every), steps, warmup,
+                      timing=False)
+        out["resort_ablation"][str(every)] = {"value": r["value"], "ms_per_step": r["ms_per_step"]}
+    return out
 
 
 def batched(spv, inputs, precision):
@@ -244,6 +267,7 @@ def main():
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
         "kernels_ms_total": {k: v[0] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
+        "steady_state_value": head["steady_value"],
         "repairs_per_step": head["repairs_per_step"],
         "repair_rounds_per_step": head["rounds_per_step"],
         "observables": {"E": head["E"], "qbar": head["qbar"], "sumA": head["sumA"]},
@@ -269,6 +293,7 @@ def main():
             print(f"[bench] {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)
         extra["mixed_vs_fp64_speedup_n100k"] = extra["spv_n100k_mixed"]["value"] / head["value"]
         extra["adjoint_n4096"] = adjoint_cost(spv, inputs)
+        extra.update(sweeps(spv, inputs, args.sweep_steps, args.warmup))
         print(f"[bench] adjoint/forward: {extra['adjoint_n4096']['adjoint_over_forward']:.2f}", file=sys.stderr,
               flush=True)
         out["extra"] = extra

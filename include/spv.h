@@ -223,9 +223,10 @@ spv_status spv_get_tuning(spv_sys* s, spv_tuning* out);
 
 /*
  * Kernel timing.  While enabled, steps are launched one by one (not as
- * captured graphs) and every launch of the listed kernel is bracketed by HIP
- * events on the handle's stream; spv_kernel_time returns the summed duration
- * (ms) and number of timed launches since enabling.
+ * captured graphs) and every launch of the listed kernels carries a pair of
+ * HIP events attached to its dispatch (start and end of its execution on the
+ * handle's stream); spv_kernel_time returns the summed duration (ms) and
+ * number of timed launches since enabling.
  *   which: 0 = force+update, 1 = geometry+test (all cells),
  *          2 = repair (first device round)
  */

@@ -11,6 +11,7 @@
 // neighbours read step-start positions).  A period has an even number of
 // steps, so positions are back in set[cfg] when the re-sort gathers
 // everything into set[cfg ^ 1] and the configuration flips.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -260,7 +261,6 @@ inline unsigned grid_for(int n, int block) { return (unsigned)std::max(1, (n + b
 
 // all-cell grid of the 8-lanes-per-cell kernels, padded to a multiple of 8 XCDs
 inline unsigned cell_grid(const spv_sys* s) { return (grid_for(s->N, CPB) + 7u) & ~7u; }
-inline unsigned list_grid(const spv_sys* s) { return std::min(grid_for(s->N, CPB), 512u); }
 inline unsigned repair_grid(const spv_sys* s)
 {
     return (unsigned)std::min(std::max(s->N / s->repair_cells, 256), 4096);
@@ -294,29 +294,34 @@ void collect_eager_timing(spv_sys* s)
 }
 
 // ---------------------------------------------------------------- launch sequences
+// Launch on `st`; with an event pair, the events are attached to the
+// dispatch itself (start and end of the kernel's execution).
+template <typename K, typename... Args>
+void launch(const EvPair* ev, K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    if (ev)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev->a, ev->b, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
+
 // One step on stream `st` from (cfg, parity).  ev: optional event pairs
-// (force, geom, repair round 0) to record around the kernels.
+// (force, geom, repair round 0) timing those kernels.
 template <typename R, bool MULTI, int KC>
 void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair* ev)
 {
     Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
-    const unsigned cg = cell_grid(s), lg = list_grid(s), rg = repair_grid(s);
-    if (ev) (void)hipEventRecord(ev[0].a, st);
-    hipLaunchKernelGGL((k_force<R, MULTI, KC, true>), dim3(cg), dim3(256), 0, st, cur, nxt.x, nxt.y, nxt.th,
-                       (double*)nullptr, (double*)nullptr, s->d_sp, s->d_st, s->N, s->d_blockmax);
-    if (ev) (void)hipEventRecord(ev[0].b, st);
-    if (ev) (void)hipEventRecord(ev[1].a, st);
-    hipLaunchKernelGGL((k_geom<R, MULTI, KC, false, false, true>), dim3(cg), dim3(256), 0, st, nxt, s->work,
-                       s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax, (int)cg);
-    if (ev) (void)hipEventRecord(ev[1].b, st);
-    // round 0 over the whole grid, later rounds and the step's close in one block
-    if (ev) (void)hipEventRecord(ev[2].a, st);
-    hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, 0);
-    if (ev) (void)hipEventRecord(ev[2].b, st);
-    hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(lg), dim3(256), 0, st, nxt, s->work, s->d_sp,
-                       s->d_st, s->N, 0, (const double*)nullptr, 0);
-    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(1), dim3(TAIL_THREADS), 0, st, nxt, s->work, s->d_sp, s->d_st,
-                       s->dev_rounds, s->tail_items);
+    const unsigned cg = cell_grid(s), rg = repair_grid(s);
+    launch(ev ? &ev[0] : nullptr, k_force<R, MULTI, KC, true>, dim3(cg), dim3(256), st, cur, nxt.x, nxt.y, nxt.th,
+           (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
+    launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, s->work,
+           (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax, (int)cg);
+    // round 0 over the whole grid; its re-test, later rounds and the step's
+    // close in the tail
+    launch(ev ? &ev[2] : nullptr, k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, s->work,
+           (const SysParam*)s->d_sp, s->d_st, 0);
+    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(TAIL_BLOCKS), dim3(TAIL_THREADS), 0, st, nxt, s->work, s->d_sp,
+                       s->d_st, s->dev_rounds, s->tail_items);
 }
 
 // Re-sort from (cfg, parity 0) into set[cfg ^ 1] (the caller flips cfg).

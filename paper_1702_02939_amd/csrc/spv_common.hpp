@@ -40,7 +40,7 @@ struct DevState {
     unsigned err;                  // error word
     int halt;                      // a step did not converge on the device: later kernels do nothing
     int halt_round;                // first round whose worklist is still pending
-    int done;                      // blocks finished in the last kernel of a step
+    int done;                      // tail blocks finished with their share of the step
     unsigned long long disp_bits;  // max |displacement| of the current step (bits of a non-negative double)
     double drift;                  // sum of per-step max displacements since the last re-sort
     unsigned long long step;       // completed steps (noise counter of the next step)

@@ -69,6 +69,21 @@ __device__ __forceinline__ int incircle_tags(double bx, double by, double cx, do
     return incircle_exact_sos(bx, by, cx, cy, px, py, tag[gi], tag[gb], tag[gc], tag[gp], scale);
 }
 
+// Filter only: 1 when p is certainly strictly inside the circle through
+// (0, b, c) (b, c counter-clockwise), -1 when certainly outside, 0 when the
+// double evaluation cannot tell.
+__device__ __forceinline__ int incircle_filter(double bx, double by, double cx, double cy, double px, double py)
+{
+    const double nb = bx * bx + by * by, nc = cx * cx + cy * cy, np = px * px + py * py;
+    const double t1 = cx * py, t2 = cy * px, t3 = px * by, t4 = py * bx, t5 = bx * cy, t6 = by * cx;
+    const double det = nb * (t1 - t2) + nc * (t3 - t4) + np * (t5 - t6);
+    const double perm = nb * (fabs(t1) + fabs(t2)) + nc * (fabs(t3) + fabs(t4)) + np * (fabs(t5) + fabs(t6));
+    const double bound = 2.0e-15 * perm;
+    if (det > bound) return -1;
+    if (det < -bound) return 1;
+    return 0;
+}
+
 // Wave-aggregated append: the active lanes with `want` write c to list, one
 // counter atomic per wave (same-address atomics from many waves serialise at
 // the device coherence point across the XCDs).
@@ -145,6 +160,20 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     const double xi = c.x[ii], yi = c.y[ii];
     const R* __restrict__ ca = c.ca;
     const R* __restrict__ cb = c.cb;
+    // the update of cell iu (first CPB threads): its state, director
+    // trigonometry and noise are computed up front, under the latency of the
+    // neighbour gathers below
+    const int iu = xcd_block(blockIdx.x, gridDim.x) * CPB + (int)threadIdx.x;
+    const bool upd = UPDATE && threadIdx.x < CPB && iu < N;
+    double xu = 0.0, yu = 0.0, thu = 0.0, nzu = 0.0, snu = 0.0, csu = 1.0;
+    if (upd) {
+        const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
+        xu = c.x[iu];
+        yu = c.y[iu];
+        thu = c.th[iu];
+        nzu = normal_for(Q.seed, st->step, (uint64_t)c.tag[iu]);
+        sincos(thu, &snu, &csu);
+    }
 
     // slot m of this lane: displacements d_m, d_{m+1} (the next slot's ring
     // entry is read again from the same cache line rather than through LDS),
@@ -246,14 +275,10 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     __syncthreads();
     if (threadIdx.x >= 64) return;
     double disp = 0.0;
-    const int iu = xcd_block(blockIdx.x, gridDim.x) * CPB + (int)threadIdx.x;
-    if (threadIdx.x < CPB && iu < N) {
+    if (upd) {
         const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
-        const double xu = c.x[iu], yu = c.y[iu];
         const double Fx = sF[threadIdx.x][0], Fy = sF[threadIdx.x][1];
-        const double th = c.th[iu];
-        double sn, cs;
-        sincos(th, &sn, &cs);
+        const double sn = snu, cs = csu;
         const double xn = xu + Q.dt * (Q.mu * Fx + Q.v0 * cs);
         const double yn = yu + Q.dt * (Q.mu * Fy + Q.v0 * sn);
         double X = rint(xn * Q.scale), Y = rint(yn * Q.scale);
@@ -269,7 +294,7 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
         const double xq = X * Q.inv_scale, yq = Y * Q.inv_scale;
         xo[iu] = xq;
         yo[iu] = yq;
-        tho[iu] = th + Q.amp * normal_for(Q.seed, st->step, (uint64_t)c.tag[iu]);
+        tho[iu] = thu + Q.amp * nzu;
         const double ddx = mimg(xq - xu, Q.Lx, Q.hLx), ddy = mimg(yq - yu, Q.Ly, Q.hLy);
         disp = sqrt(ddx * ddx + ddy * ddy);
     }
@@ -300,7 +325,10 @@ struct GeomLds {
 
 // One pass over cells t = base + g (g = threadIdx.x / GL) of a list (LIST)
 // or of all cells; every thread of the block takes part (block barriers).
-template <typename R, bool MULTI, int KC, bool LIST, bool OPP>
+// EXACT = false (the all-cells pass): a predicate that the double filter
+// cannot decide flags the cell instead of being evaluated exactly; the
+// repair and the exact re-test of the touched cells then settle it.
+template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool EXACT = true>
 __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, const SysParam* __restrict__ sp,
                                           DevState* st, int base, int n, const int* __restrict__ list, int rnext,
                                           const GeomLds<R, KC>& S, int& exact)
@@ -356,7 +384,13 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
                 o = c.opp[i * KC + m];
             }
             const double bx = sD[g][m][0], by = sD[g][m][1], cx = sD[g][mn][0], cy = sD[g][mn][1];
-            bool fail = cross_sign(bx, by, cx, cy, bx * cy - by * cx, P.scale) <= 0;
+            bool fail;
+            if (EXACT) {
+                fail = cross_sign(bx, by, cx, cy, bx * cy - by * cx, P.scale) <= 0;
+            } else {
+                const double cr = bx * cy - by * cx;
+                fail = !(cr > 1.5e-15 * (fabs(bx * cy) + fabs(by * cx)));
+            }
             R ux, uy;
             circumcentre((R)bx, (R)by, (R)cx, (R)cy, ux, uy);
             if (!fail) {
@@ -364,7 +398,10 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
                     fail = true;
                 } else {
                     const double px = mimg(c.x[o] - xi, P.Lx, P.hLx), py = mimg(c.y[o] - yi, P.Ly, P.hLy);
-                    fail = incircle_tags(bx, by, cx, cy, px, py, c.tag, i, jm, jn, o, P.scale, &exact) > 0;
+                    if (EXACT)
+                        fail = incircle_tags(bx, by, cx, cy, px, py, c.tag, i, jm, jn, o, P.scale, &exact) > 0;
+                    else
+                        fail = incircle_filter(bx, by, cx, cy, px, py) >= 0;
                 }
                 // a circumradius >= min(L)/4 is either a non-Delaunay triangle
                 // or a true violation of the box precondition; the repair
@@ -429,7 +466,7 @@ __global__ __launch_bounds__(256) void k_geom(Cells<R> c, Work w, const SysParam
     const GeomLds<R, KC> S{sD, sU, sJ};
     int exact = 0;
     for (int base = bstart * CPB; base < n; base += gridDim.x * CPB)
-        geom_pass<R, MULTI, KC, LIST, OPP>(c, w, sp, st, base, n, list, rnext, S, exact);
+        geom_pass<R, MULTI, KC, LIST, OPP, !STEP>(c, w, sp, st, base, n, list, rnext, S, exact);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
     if (STEP && blockIdx.x == 0) {
         __shared__ double swm[256 / 64];
@@ -466,7 +503,8 @@ struct RepairLds {
     int* sid;     // candidate cell
     int* stg;     // candidate tag
     int* s_n;     // candidate count
-    int* s_ring;  // ring under construction (candidate slots), 65 entries
+    int* s_ring;  // ring under construction (candidate slots), KMAX + 1 entries
+    int* s_tmp;   // KMAX + 1 entries of scratch
     int cap;      // capacity of sx .. stg
 };
 
@@ -479,6 +517,106 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Delaunay neighbours of the cell at the origin among the n candidates
+// (sx, sy), decided all at once, one candidate p per lane.  The circles
+// through 0 and p have centres p/2 + t perp(p); a candidate q left of the
+// line 0 -> p lies outside the circle iff t <= t_q, one on the right iff
+// t >= t_q, with t_q = (|q|^2 - p.q) / (2 p x q), and a candidate strictly
+// inside the segment (0, p) lies inside every such circle.  So (0, p) has an
+// empty circle iff max over right-side t_q < min over left-side t_q.  Each
+// key carries a rounding bound; the members are then ordered
+// counter-clockwise by exact angle comparisons into s_ring.  Returns the
+// number of members with closed = (at least 3 and every consecutive pair
+// turns counter-clockwise), or -1 when some decision is within rounding
+// (near-ties such as cocircular cells, near-collinear candidates): the
+// caller then uses the exact sequential construction.
+__device__ int star_parallel(const double* __restrict__ sx, const double* __restrict__ sy, int n, int* s_ring,
+                             int* s_tmp, double scale, bool& closed)
+{
+    const int lane = threadIdx.x & 63;
+    int unsure = 0, k = 0;
+    for (int base = 0; base < n; base += 64) {
+        const int pi = base + lane;
+        bool mem = false;
+        if (pi < n) {
+            const double px = sx[pi], py = sy[pi];
+            double ulo = INFINITY, uhi = INFINITY, llo = -INFINITY, lhi = -INFINITY;
+            bool blocked = false;
+            for (int q = 0; q < n; q++) {
+                if (q == pi) continue;
+                const double qx = sx[q], qy = sy[q];
+                const double a = px * qy, b = py * qx;
+                const double cr = a - b;
+                const double ecr = 1e-15 * (fabs(a) + fabs(b));
+                if (!(fabs(cr) > 4.0 * ecr)) {
+                    if (cross_sign_exact(px, py, qx, qy, scale) != 0) {
+                        unsure = 1;  // nearly collinear: t_q is ill-conditioned
+                    } else {
+                        // exactly collinear: q = lambda p excludes p iff 0 < lambda < 1
+                        const __int128 PX = to_units(px, scale), PY = to_units(py, scale);
+                        const __int128 QX = to_units(qx, scale), QY = to_units(qy, scale);
+                        if (PX * QX + PY * QY > 0 && QX * QX + QY * QY < PX * PX + PY * PY) blocked = true;
+                    }
+                    continue;
+                }
+                const double pq = fabs(px * qx) + fabs(py * qy);
+                const double num = qx * qx + qy * qy - (px * qx + py * qy);
+                const double t = num / (2.0 * cr);
+                const double e =
+                    4e-15 * (qx * qx + qy * qy + pq) / (2.0 * fabs(cr)) + fabs(t) * (2.0 * ecr / fabs(cr) + 4e-15);
+                if (cr > 0.0) {
+                    ulo = fmin(ulo, t - e);
+                    uhi = fmin(uhi, t + e);
+                } else {
+                    llo = fmax(llo, t - e);
+                    lhi = fmax(lhi, t + e);
+                }
+            }
+            if (!blocked) {
+                if (ulo > lhi) mem = true;           // certainly a non-empty interval
+                else if (!(llo > uhi)) unsure = 1;  // and not certainly empty either
+            }
+        }
+        const unsigned long long m = __ballot(mem);
+        if (mem) {
+            const int pos = k + __popcll(m & ((1ull << lane) - 1ull));
+            if (pos <= KMAX) s_tmp[pos] = pi;
+        }
+        k += __popcll(m);
+    }
+    closed = false;
+    if (__ballot(unsure)) return -1;
+    if (k > KMAX) return k;
+    wave_sync();
+    // counter-clockwise order from the direction (1, 0): half-plane, then
+    // the exact sign of the cross product (no two members share a ray)
+    int rank = 0, my = -1;
+    if (lane < k) {
+        my = s_tmp[lane];
+        const double ax = sx[my], ay = sy[my];
+        const int ha = (ay < 0.0 || (ay == 0.0 && ax < 0.0)) ? 1 : 0;
+        for (int j = 0; j < k; j++) {
+            if (j == lane) continue;
+            const int o = s_tmp[j];
+            const double bx = sx[o], by = sy[o];
+            const int hb = (by < 0.0 || (by == 0.0 && bx < 0.0)) ? 1 : 0;
+            if (hb != ha) rank += hb < ha;
+            else rank += cross_sign(bx, by, ax, ay, bx * ay - by * ax, scale) > 0;
+        }
+    }
+    wave_sync();
+    if (lane < k) s_ring[rank] = my;
+    wave_sync();
+    bool ccw = true;
+    for (int m = lane; m < k; m += 64) {
+        const int p = s_ring[m], q = s_ring[(m + 1 == k) ? 0 : m + 1];
+        const double ax = sx[p], ay = sy[p], bx = sx[q], by = sy[q];
+        ccw = ccw && cross_sign(ax, ay, bx, by, ax * by - ay * bx, scale) > 0;
+    }
+    closed = k >= 3 && !__ballot(!ccw);
+    return k;
 }
 
 // Rebuild the ring of cell i (all 64 lanes of the calling wavefront).
@@ -559,127 +697,128 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
             if (lane == 0) atomicOr(&st->err, ERR_CAPACITY);
             break;
         }
-        // nearest candidate: exact squared distance in grid units, ties by tag
-        unsigned long long bh = ~0ull, bl = ~0ull;
-        int best = -1;
-        for (int q = lane; q < n; q += 64) {
-            const __int128 X = to_units(sx[q], P.scale), Y = to_units(sy[q], P.scale);
-            const unsigned __int128 d2 = (unsigned __int128)(X * X + Y * Y);
-            const unsigned long long h = (unsigned long long)(d2 >> 64), lw = (unsigned long long)d2;
-            if (best < 0 || h < bh || (h == bh && (lw < bl || (lw == bl && stg[q] < stg[best])))) {
-                bh = h;
-                bl = lw;
-                best = q;
-            }
-        }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const unsigned long long oh = __shfl_xor(bh, off), ol = __shfl_xor(bl, off);
-            const int ob = __shfl_xor(best, off);
-            if (ob >= 0 && (best < 0 || oh < bh || (oh == bh && (ol < bl || (ol == bl && stg[ob] < stg[best]))))) {
-                bh = oh;
-                bl = ol;
-                best = ob;
-            }
-        }
-        if (best < 0) {  // no candidate at all
-            if (at_max) break;
-            Rs = fmin(2.0 * Rs, Rmax);
-            at_max = (Rs >= Rmax);
-            continue;
-        }
-        const int start = best;
-        if (lane == 0) s_ring[0] = start;
-        k = 1;
-        int cur = start;
         bool closed = false;
-        while (k <= KMAX) {
-            const double cx = sx[cur], cy = sy[cur];
-            const int gc = sid[cur];
-            // Next neighbour after c: the left-side candidate whose circle
-            // through (i, c, p) is first met when the circle centre
-            // c/2 + t perp(c) moves left; t_p = (|p|^2 - c.p) / (2 c x p).
-            // p strictly inside circle(i, c, q)  <=>  t_p < t_q.  The keys
-            // are double estimates with a per-key error bound; the exact
-            // in-circle order decides whenever the two best keys overlap.
-            double t1 = INFINITY, e1 = 0.0, t2 = INFINITY, e2 = 0.0;
-            int nb = -1;
+        k = star_parallel(sx, sy, n, s_ring, L.s_tmp, P.scale, closed);
+        if (k < 0) {
+            // exact sequential construction: from the nearest candidate (exact
+            // squared distance in grid units, ties by tag), gift-wrapping
+            k = 0;
+            unsigned long long bh = ~0ull, bl = ~0ull;
+            int best = -1;
             for (int q = lane; q < n; q += 64) {
-                if (q == cur) continue;
-                const double px = sx[q], py = sy[q];
-                const double cr = cx * py - cy * px;
-                if (cross_sign(cx, cy, px, py, cr, P.scale) <= 0) continue;
-                const double num = px * px + py * py - (cx * px + cy * py);
-                const double t = num / (2.0 * cr);
-                // rounding bounds: |d num| <= 4e-15 (|p|^2 + |c.p|), |d cr| <= ecr
-                const double ecr = 1e-15 * (fabs(cx * py) + fabs(cy * px));
-                const double bnd = (ecr > 0.25 * fabs(cr))
-                                       ? INFINITY
-                                       : 4e-15 * (px * px + py * py + fabs(cx * px) + fabs(cy * py)) /
-                                                 (2.0 * fabs(cr)) +
-                                             fabs(t) * (2.0 * ecr / fabs(cr) + 4e-15);
-                if (t < t1) {
-                    t2 = t1;
-                    e2 = e1;
-                    t1 = t;
-                    e1 = bnd;
-                    nb = q;
-                } else if (t < t2) {
-                    t2 = t;
-                    e2 = bnd;
+                const __int128 X = to_units(sx[q], P.scale), Y = to_units(sy[q], P.scale);
+                const unsigned __int128 d2 = (unsigned __int128)(X * X + Y * Y);
+                const unsigned long long h = (unsigned long long)(d2 >> 64), lw = (unsigned long long)d2;
+                if (best < 0 || h < bh || (h == bh && (lw < bl || (lw == bl && stg[q] < stg[best])))) {
+                    bh = h;
+                    bl = lw;
+                    best = q;
                 }
             }
-            // wave arg-min of (t1, nb) keeping the runner-up key
             for (int off = 32; off >= 1; off >>= 1) {
-                const double ot1 = __shfl_xor(t1, off), oe1 = __shfl_xor(e1, off);
-                const double ot2 = __shfl_xor(t2, off), oe2 = __shfl_xor(e2, off);
-                const int onb = __shfl_xor(nb, off);
-                if (ot1 < t1 || (ot1 == t1 && onb >= 0 && (nb < 0 || onb < nb))) {
-                    // other side wins: my best becomes a runner-up candidate
-                    if (t1 < ot2) {
-                        t2 = t1;
-                        e2 = e1;
-                    } else {
-                        t2 = ot2;
-                        e2 = oe2;
+                const unsigned long long oh = __shfl_xor(bh, off), ol = __shfl_xor(bl, off);
+                const int ob = __shfl_xor(best, off);
+                if (ob >= 0 && (best < 0 || oh < bh || (oh == bh && (ol < bl || (ol == bl && stg[ob] < stg[best]))))) {
+                    bh = oh;
+                    bl = ol;
+                    best = ob;
+                }
+            }
+            if (best >= 0) {
+                const int start = best;
+                if (lane == 0) s_ring[0] = start;
+                k = 1;
+                int cur = start;
+                while (k <= KMAX) {
+                    const double cx = sx[cur], cy = sy[cur];
+                    const int gc = sid[cur];
+                    // Next neighbour after c: the left-side candidate whose circle
+                    // through (i, c, p) is first met when the circle centre
+                    // c/2 + t perp(c) moves left; t_p = (|p|^2 - c.p) / (2 c x p).
+                    // p strictly inside circle(i, c, q)  <=>  t_p < t_q.  The keys
+                    // are double estimates with a per-key error bound; the exact
+                    // in-circle order decides whenever the two best keys overlap.
+                    double t1 = INFINITY, e1 = 0.0, t2 = INFINITY, e2 = 0.0;
+                    int nb = -1;
+                    for (int q = lane; q < n; q += 64) {
+                        if (q == cur) continue;
+                        const double px = sx[q], py = sy[q];
+                        const double cr = cx * py - cy * px;
+                        if (cross_sign(cx, cy, px, py, cr, P.scale) <= 0) continue;
+                        const double num = px * px + py * py - (cx * px + cy * py);
+                        const double t = num / (2.0 * cr);
+                        // rounding bounds: |d num| <= 4e-15 (|p|^2 + |c.p|), |d cr| <= ecr
+                        const double ecr = 1e-15 * (fabs(cx * py) + fabs(cy * px));
+                        const double bnd = (ecr > 0.25 * fabs(cr))
+                                               ? INFINITY
+                                               : 4e-15 * (px * px + py * py + fabs(cx * px) + fabs(cy * py)) /
+                                                         (2.0 * fabs(cr)) +
+                                                     fabs(t) * (2.0 * ecr / fabs(cr) + 4e-15);
+                        if (t < t1) {
+                            t2 = t1;
+                            e2 = e1;
+                            t1 = t;
+                            e1 = bnd;
+                            nb = q;
+                        } else if (t < t2) {
+                            t2 = t;
+                            e2 = bnd;
+                        }
                     }
-                    t1 = ot1;
-                    e1 = oe1;
-                    nb = onb;
-                } else {
-                    if (ot1 < t2) {
-                        t2 = ot1;
-                        e2 = oe1;
+                    // wave arg-min of (t1, nb) keeping the runner-up key
+                    for (int off = 32; off >= 1; off >>= 1) {
+                        const double ot1 = __shfl_xor(t1, off), oe1 = __shfl_xor(e1, off);
+                        const double ot2 = __shfl_xor(t2, off), oe2 = __shfl_xor(e2, off);
+                        const int onb = __shfl_xor(nb, off);
+                        if (ot1 < t1 || (ot1 == t1 && onb >= 0 && (nb < 0 || onb < nb))) {
+                            // other side wins: my best becomes a runner-up candidate
+                            if (t1 < ot2) {
+                                t2 = t1;
+                                e2 = e1;
+                            } else {
+                                t2 = ot2;
+                                e2 = oe2;
+                            }
+                            t1 = ot1;
+                            e1 = oe1;
+                            nb = onb;
+                        } else {
+                            if (ot1 < t2) {
+                                t2 = ot1;
+                                e2 = oe1;
+                            }
+                        }
                     }
+                    if (nb >= 0 && t2 - e2 <= t1 + e1) {
+                        // the keys cannot separate the best from the runner-up:
+                        // exact arg-min under the in-circle order (rare)
+                        nb = -1;
+                        for (int q = lane; q < n; q += 64) {
+                            if (q == cur) continue;
+                            const double px = sx[q], py = sy[q];
+                            if (cross_sign(cx, cy, px, py, cx * py - cy * px, P.scale) <= 0) continue;
+                            if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, c.tag, i, gc, sid[nb], sid[q],
+                                                        P.scale, &exact) > 0)
+                                nb = q;
+                        }
+                        for (int off = 32; off >= 1; off >>= 1) {
+                            const int ob = __shfl_xor(nb, off);
+                            if (ob >= 0 && ob != nb &&
+                                (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], c.tag, i, gc, sid[nb],
+                                                         sid[ob], P.scale, &exact) > 0))
+                                nb = ob;
+                        }
+                    }
+                    if (nb < 0) break;  // star open: search disk too small
+                    if (nb == start) {
+                        closed = true;
+                        break;
+                    }
+                    if (lane == 0) s_ring[k] = nb;
+                    k++;
+                    cur = nb;
                 }
             }
-            if (nb >= 0 && t2 - e2 <= t1 + e1) {
-                // the keys cannot separate the best from the runner-up:
-                // exact arg-min under the in-circle order (rare)
-                nb = -1;
-                for (int q = lane; q < n; q += 64) {
-                    if (q == cur) continue;
-                    const double px = sx[q], py = sy[q];
-                    if (cross_sign(cx, cy, px, py, cx * py - cy * px, P.scale) <= 0) continue;
-                    if (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], px, py, c.tag, i, gc, sid[nb], sid[q],
-                                                P.scale, &exact) > 0)
-                        nb = q;
-                }
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const int ob = __shfl_xor(nb, off);
-                    if (ob >= 0 && ob != nb &&
-                        (nb < 0 || incircle_tags(cx, cy, sx[nb], sy[nb], sx[ob], sy[ob], c.tag, i, gc, sid[nb],
-                                                 sid[ob], P.scale, &exact) > 0))
-                        nb = ob;
-                }
-            }
-            if (nb < 0) break;  // star open: search disk too small
-            if (nb == start) {
-                closed = true;
-                break;
-            }
-            if (lane == 0) s_ring[k] = nb;
-            k++;
-            cur = nb;
         }
         wave_sync();
         double umax = 0.0;
@@ -762,12 +901,12 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
     __shared__ double sx[RP_CAP], sy[RP_CAP];
     __shared__ int sid[RP_CAP], stg[RP_CAP];
     __shared__ int s_n;
-    __shared__ int s_ring[KMAX + 1];
+    __shared__ int s_ring[KMAX + 1], s_tmp[KMAX + 1];
     if (st->halt) return;
     const int nw = st->wl_count[round];
     const int* __restrict__ wl = w.wl[round & 1];
     const double drift = st->drift;
-    const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, RP_CAP};
+    const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, s_tmp, RP_CAP};
     int exact = 0, nrep = 0;
     bool deferred = false;
     for (int wi = blockIdx.x; wi < nw; wi += gridDim.x)
@@ -777,15 +916,19 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
 }
 
 // ---------------------------------------------------------------- step tail
-// Repair rounds 1 .. rounds-1 of a step and its close, in one block: after
-// round 0 a step usually has no or a handful of flagged cells, which a few
-// wavefronts repair (one cell each) and a block-wide geometry pass re-tests,
-// with block barriers between the phases instead of kernel boundaries.  A
-// round with more than max_items cells, a cell with more than RP_TAIL
-// candidates, rounds left at the end or an error halt the step; the host
-// then finishes it with full-grid rounds.  Otherwise the per-step counters
-// are cleared for the next step.
+// After the full-grid repair of round 0: every block of the tail grid
+// re-tests a share of the cells that round touched (rebuilding their
+// opposite vertices); the last block to finish then runs rounds
+// 1 .. rounds-1 and closes the step alone.  After round 0 a step usually has
+// no or a handful of flagged cells, which a few wavefronts repair (one cell
+// each) and a block-wide geometry pass re-tests, with block barriers between
+// the phases instead of kernel boundaries.  A round with more than max_items
+// cells, a cell with more than RP_TAIL candidates, rounds left at the end or
+// an error halt the step; the host then finishes it with full-grid rounds.
+// Otherwise the per-step counters are cleared for the next step.  No block
+// ever waits for another (the hand-over is a counter, not a barrier).
 constexpr int TAIL_WAVES = 8;
+constexpr int TAIL_BLOCKS = 32;
 constexpr int TAIL_THREADS = 64 * TAIL_WAVES;
 constexpr int TAIL_CPB = TAIL_THREADS / GL;
 constexpr int RP_TAIL = 512;
@@ -802,7 +945,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
                                                        DevState* st, int rounds, int max_items)
 {
     constexpr size_t kRepBytes =
-        (size_t)TAIL_WAVES * (RP_TAIL * (2 * sizeof(double) + 2 * sizeof(int)) + (KMAX + 1) * sizeof(int));
+        (size_t)TAIL_WAVES * (RP_TAIL * (2 * sizeof(double) + 2 * sizeof(int)) + 2 * (KMAX + 1) * sizeof(int));
     constexpr size_t kGeoBytes = (size_t)TAIL_CPB * KC * (2 * sizeof(double) + 2 * sizeof(R) + sizeof(int));
     __shared__ __align__(16) unsigned char raw[kRepBytes > kGeoBytes ? kRepBytes : kGeoBytes];
     __shared__ int s_n[TAIL_WAVES];
@@ -820,15 +963,39 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
     int* stg = reinterpret_cast<int*>(q) + wave * RP_TAIL;
     q += (size_t)TAIL_WAVES * RP_TAIL * sizeof(int);
     int* sring = reinterpret_cast<int*>(q) + wave * (KMAX + 1);
-    const RepairLds L{sx, sy, sid, stg, &s_n[wave], sring, RP_TAIL};
+    q += (size_t)TAIL_WAVES * (KMAX + 1) * sizeof(int);
+    int* stmp = reinterpret_cast<int*>(q) + wave * (KMAX + 1);
+    const RepairLds L{sx, sy, sid, stg, &s_n[wave], sring, stmp, RP_TAIL};
     // geometry views (the same memory, used between block barriers)
     unsigned char* g = raw;
     const GeomLds<R, KC> S{reinterpret_cast<double(*)[KC][2]>(g),
                            reinterpret_cast<R(*)[KC][2]>(g + (size_t)TAIL_CPB * KC * 2 * sizeof(double)),
                            reinterpret_cast<int(*)[KC]>(g + (size_t)TAIL_CPB * KC * 2 * (sizeof(double) + sizeof(R)))};
 
+    int exact = 0, nrep = 0;
+    {
+        // round 0 re-test, shared by the grid; failures go to round 1
+        const int nt = st->tl_count[0];
+        const int* __restrict__ tl = w.tl[0];
+        for (int base = blockIdx.x * TAIL_CPB; base < nt; base += gridDim.x * TAIL_CPB)
+            geom_pass<R, MULTI, KC, true, true>(c, w, sp, st, base, nt, tl, 1, S, exact);
+    }
+    __shared__ int s_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // this block's writes before its count
+        s_last = atomicAdd(&st->done, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) {
+        if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
+        return;
+    }
+    __threadfence();  // every block's writes are visible from here on
+    if (threadIdx.x == 0) st->done = 0;
+
     const double drift = st->drift;
-    int exact = 0, nrep = 0, used = st->wl_count[0] > 0 ? 1 : 0;
+    int used = st->wl_count[0] > 0 ? 1 : 0;
     int r = 1, halt_at = -1;
     for (; r < rounds; r++) {
         const int nw = load_count(&st->wl_count[r]);
