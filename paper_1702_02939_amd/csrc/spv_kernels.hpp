@@ -544,6 +544,7 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
             const double px = sx[pi], py = sy[pi];
             double ulo = INFINITY, uhi = INFINITY, llo = -INFINITY, lhi = -INFINITY;
             bool blocked = false;
+#pragma unroll 4
             for (int q = 0; q < n; q++) {
                 if (q == pi) continue;
                 const double qx = sx[q], qy = sy[q];
@@ -561,11 +562,16 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
                     }
                     continue;
                 }
+                // one division: ir = 1 / (2 p x q); the bound is that of
+                // num / (2 cr) with |num error| <= 4e-15 (|q|^2 + |p.q|
+                // terms), |cr error| <= ecr <= |cr| / 4, and margin for
+                // the rounding of ir and of the product
                 const double pq = fabs(px * qx) + fabs(py * qy);
                 const double num = qx * qx + qy * qy - (px * qx + py * qy);
-                const double t = num / (2.0 * cr);
-                const double e =
-                    4e-15 * (qx * qx + qy * qy + pq) / (2.0 * fabs(cr)) + fabs(t) * (2.0 * ecr / fabs(cr) + 4e-15);
+                const double ir = 1.0 / (2.0 * cr);
+                const double t = num * ir;
+                const double air = fabs(ir);
+                const double e = air * (4e-15 * (qx * qx + qy * qy + pq)) + fabs(t) * (4.0 * ecr * air + 4e-15);
                 if (cr > 0.0) {
                     ulo = fmin(ulo, t - e);
                     uhi = fmin(uhi, t + e);
@@ -640,9 +646,9 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
     // the old ring row (touched at the end), read while the search runs
     const int qrow = lane < KC ? c.ring[i * KC + lane] : -1;
     const double Rmax = 0.5 * fmin(P.Lx, P.Ly) * (1.0 - 1e-9);
-    // first radius: at least R0, and as large as the 7x7 bin window
-    // around the cell covers after the drift since the last re-sort
-    double Rs = fmin(fmax(P.R0, 3.0 * fmin(P.bsx, P.bsy) - drift), Rmax);
+    // first radius R0 (2.5 mean spacings: a Delaunay star rarely reaches
+    // further than half of it); doubled while the star is not certified
+    double Rs = fmin(P.R0, Rmax);
     int k = 0;
     bool ok = false, at_max = false;
     int last_n = 0, last_closed = 0, attempts = 0;
