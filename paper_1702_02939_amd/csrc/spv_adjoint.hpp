@@ -13,6 +13,7 @@
 // of App. B.  One thread per cell; positions and lambda in FP64.
 #pragma once
 #include "spv_common.hpp"
+#include "spv_kernels.hpp"
 
 namespace spv {
 
@@ -64,133 +65,153 @@ __device__ __forceinline__ void dual_disp(const double* x, const double* y, cons
     dy = {mimg(y[j] - y[i], P.Ly, P.hLy), ly[j] - ly[i]};
 }
 
-// directional derivatives of A_i and P_i along lambda (topology fixed)
+// Both tangent kernels use GL lanes per cell (lane l takes ring slots l,
+// l + GL, ...) and sum the lanes' parts with shuffles; grid: N * GL threads.
+
+// directional derivatives of A_i and P_i along lambda (topology fixed);
+// with aq != nullptr also the coefficients of w qbar = (w/N) sum P_c / sqrt(A_c)
+// at this state: aq = d/dA, bq = d/dP (used by the next backward step)
 template <int KC>
 __global__ __launch_bounds__(256) void k_tangent_geom(Cells<double> c, const double* __restrict__ lx,
                                                       const double* __restrict__ ly, const SysParam* __restrict__ sp,
-                                                      int N, double* __restrict__ dA, double* __restrict__ dP)
+                                                      int N, double* __restrict__ dA, double* __restrict__ dP,
+                                                      double w, double* __restrict__ aq, double* __restrict__ bq)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const SysParam& P = sp[c.sys[i]];
-    const int k = min((int)c.deg[i], KC);
-    if (k < 3) {
-        dA[i] = dP[i] = 0.0;
-        return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / GL, l = gid % GL;
+    const bool valid = i < N;
+    const int ii = valid ? i : 0;
+    if (aq && valid && l == 0) {
+        const double sa = sqrt(c.A[i]);
+        aq[i] = -w * c.P[i] / (2.0 * N * c.A[i] * sa);
+        bq[i] = w / (N * sa);
     }
-    Dual b0x, b0y;
-    dual_disp(c.x, c.y, lx, ly, P, i, c.ring[i * KC], b0x, b0y);
-    Dual bx = b0x, by = b0y;
-    Dual a2 = {0.0, 0.0}, per = {0.0, 0.0}, u0x{}, u0y{}, upx{}, upy{};
-    for (int m = 0; m < k; m++) {
-        Dual cx, cy;
-        if (m + 1 < k) dual_disp(c.x, c.y, lx, ly, P, i, c.ring[i * KC + m + 1], cx, cy);
-        else {
-            cx = b0x;
-            cy = b0y;
+    const SysParam& P = sp[c.sys[ii]];
+    const int k = valid ? min((int)c.deg[ii], KC) : 0;
+    double a2 = 0.0, per = 0.0;  // tangents of 2A and P, this lane's slots
+    if (k >= 3) {
+        for (int m = l; m < k; m += GL) {
+            // u_m = cc(d_m, d_{m+1}), u_{m+1} = cc(d_{m+1}, d_{m+2})
+            Dual bx, by, cx, cy, ex, ey;
+            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + m], bx, by);
+            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + (m + 1) % k], cx, cy);
+            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + (m + 2) % k], ex, ey);
+            Dual ux, uy, vx, vy;
+            dual_cc(bx, by, cx, cy, ux, uy);
+            dual_cc(cx, cy, ex, ey, vx, vy);
+            a2 += (ux * vy - uy * vx).d;
+            per += dsqrt((vx - ux) * (vx - ux) + (vy - uy) * (vy - uy)).d;
         }
-        Dual ux, uy;
-        dual_cc(bx, by, cx, cy, ux, uy);
-        if (m == 0) {
-            u0x = ux;
-            u0y = uy;
-        } else {
-            a2 = a2 + (upx * uy - upy * ux);
-            per = per + dsqrt((ux - upx) * (ux - upx) + (uy - upy) * (uy - upy));
-        }
-        upx = ux;
-        upy = uy;
-        bx = cx;
-        by = cy;
     }
-    a2 = a2 + (upx * u0y - upy * u0x);
-    per = per + dsqrt((u0x - upx) * (u0x - upx) + (u0y - upy) * (u0y - upy));
-    dA[i] = 0.5 * a2.d;
-    dP[i] = per.d;
+#pragma unroll
+    for (int off = GL / 2; off > 0; off >>= 1) {
+        a2 += __shfl_xor(a2, off);
+        per += __shfl_xor(per, off);
+    }
+    if (valid && l == 0) {
+        dA[i] = k >= 3 ? 0.5 * a2 : 0.0;
+        dP[i] = k >= 3 ? per : 0.0;
+    }
 }
 
 // dF_i[lambda]: tangent of F_i = -sum_m J_m^T g_m (see k_force), with the
 // area / perimeter coefficients a_c = 2 K_A (A_c - A0_c), b_c = 2 K_P (P_c - P0_c)
 // carrying tangents 2 K_A dA_c and 2 K_P dP_c.
-template <int KC>
+// STEP: instead of dF, write the adjoint of one step into the other lambda
+// buffer, lo = lambda + dt mu dF[lambda], and add dt mu 2 K_P dP_i to g_i.
+template <int KC, bool STEP = false>
 __global__ __launch_bounds__(256) void k_tangent_force(Cells<double> c, const double* __restrict__ lx,
                                                        const double* __restrict__ ly,
                                                        const double* __restrict__ dA, const double* __restrict__ dP,
                                                        const SysParam* __restrict__ sp, int N,
-                                                       double* __restrict__ fdx, double* __restrict__ fdy)
+                                                       double* __restrict__ fdx, double* __restrict__ fdy,
+                                                       double* __restrict__ g = nullptr)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const SysParam& P = sp[c.sys[i]];
-    const int k = min((int)c.deg[i], KC);
-    if (k < 3) {
-        fdx[i] = fdy[i] = 0.0;
-        return;
-    }
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / GL, l = gid % GL;
+    const bool valid = i < N;
+    const int ii = valid ? i : 0;
+    const SysParam& P = sp[c.sys[ii]];
+    const int k = valid ? min((int)c.deg[ii], KC) : 0;
     auto coef = [&](int j, Dual& a, Dual& b) {
         a = {c.ca[j], 2.0 * P.KA * dA[j]};
         b = {c.cb[j], 2.0 * P.KP * dP[j]};
     };
     auto vertex = [&](int m, Dual& hx, Dual& hy) {  // h_m in the frame of i
         Dual bx, by, cx, cy;
-        dual_disp(c.x, c.y, lx, ly, P, i, c.ring[i * KC + m], bx, by);
-        dual_disp(c.x, c.y, lx, ly, P, i, c.ring[i * KC + (m + 1) % k], cx, cy);
+        dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + m], bx, by);
+        dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + (m + 1) % k], cx, cy);
         dual_cc(bx, by, cx, cy, hx, hy);
     };
-    Dual ai, bi;
-    coef(i, ai, bi);
-    Dual fx = {0.0, 0.0}, fy = {0.0, 0.0};
-    for (int m = 0; m < k; m++) {
-        const int mn = (m + 1) % k, mp = (m + k - 1) % k;
-        const int jm = c.ring[i * KC + m], jn = c.ring[i * KC + mn];
-        Dual Bx, By, Cx, Cy;
-        dual_disp(c.x, c.y, lx, ly, P, i, jm, Bx, By);
-        dual_disp(c.x, c.y, lx, ly, P, i, jn, Cx, Cy);
-        Dual hpx, hpy, hcx, hcy, hnx, hny;
-        vertex(mp, hpx, hpy);
-        dual_cc(Bx, By, Cx, Cy, hcx, hcy);
-        vertex(mn, hnx, hny);
-        Dual qx = hcx, qy = hcy;
-        const int o = c.opp[i * KC + m];
-        if (o >= 0) {
-            Dual ox, oy;
-            dual_disp(c.x, c.y, lx, ly, P, i, o, ox, oy);
-            Dual ex = ox - Bx, ey = oy - By, gx2 = Cx - Bx, gy2 = Cy - By, tx, ty;
-            dual_cc(ex, ey, gx2, gy2, tx, ty);
-            qx = tx + Bx;
-            qy = ty + By;
+    double fxd = 0.0, fyd = 0.0;
+    if (k >= 3) {
+        Dual ai, bi;
+        coef(ii, ai, bi);
+        for (int m = l; m < k; m += GL) {
+            const int mn = (m + 1) % k, mp = (m + k - 1) % k;
+            const int jm = c.ring[ii * KC + m], jn = c.ring[ii * KC + mn];
+            Dual Bx, By, Cx, Cy;
+            dual_disp(c.x, c.y, lx, ly, P, ii, jm, Bx, By);
+            dual_disp(c.x, c.y, lx, ly, P, ii, jn, Cx, Cy);
+            Dual hpx, hpy, hcx, hcy, hnx, hny;
+            vertex(mp, hpx, hpy);
+            dual_cc(Bx, By, Cx, Cy, hcx, hcy);
+            vertex(mn, hnx, hny);
+            Dual qx = hcx, qy = hcy;
+            const int o = c.opp[ii * KC + m];
+            if (o >= 0) {
+                Dual ox, oy;
+                dual_disp(c.x, c.y, lx, ly, P, ii, o, ox, oy);
+                Dual ex = ox - Bx, ey = oy - By, gx2 = Cx - Bx, gy2 = Cy - By, tx, ty;
+                dual_cc(ex, ey, gx2, gy2, tx, ty);
+                qx = tx + Bx;
+                qy = ty + By;
+            }
+            Dual t1x, t1y, t2x, t2y, t3x, t3y;
+            dual_unit(hcx - hpx, hcy - hpy, t1x, t1y);
+            dual_unit(hnx - hcx, hny - hcy, t2x, t2y);
+            dual_unit(qx - hcx, qy - hcy, t3x, t3y);
+            Dual am, bm, an, bn;
+            coef(jm, am, bm);
+            coef(jn, an, bn);
+            Dual gx = ai * (0.5 * (hny - hpy)) + bi * (t1x - t2x);
+            Dual gy = ai * (0.5 * (hpx - hnx)) + bi * (t1y - t2y);
+            gx = gx + am * (0.5 * (hpy - qy)) + bm * (t1x - t3x);
+            gy = gy + am * (0.5 * (qx - hpx)) + bm * (t1y - t3y);
+            gx = gx + an * (0.5 * (qy - hny)) + bn * (-t2x - t3x);
+            gy = gy + an * (0.5 * (hnx - qx)) + bn * (-t2y - t3y);
+            const Dual ex = Cx - Bx, ey = Cy - By;
+            const Dual s = Bx * Cy - By * Cx;
+            const Dual be = Bx * ex + By * ey, ce = Cx * ex + Cy * ey;
+            const Dual nb = Bx * Bx + By * By, nc = Cx * Cx + Cy * Cy;
+            const Dual betaD = -(nc * be), gammaD = nb * ce;
+            const Dual zx = betaD * Bx + gammaD * Cx, zy = betaD * By + gammaD * Cy;
+            const Dual gbx = 2.0 * (be * Cx) + nc * ex, gby = 2.0 * (be * Cy) + nc * ey;
+            const Dual ggx = -(2.0 * (ce * Bx)) - nb * ex, ggy = -(2.0 * (ce * By)) - nb * ey;
+            const Dual one = {1.0, 0.0};
+            const Dual is = one / s;
+            const Dual gdx = 2.0 * (is * (-ey)), gdy = 2.0 * (is * ex);
+            const Dual invD = 0.5 * (is * is);
+            const Dual gB = gx * Bx + gy * By, gC = gx * Cx + gy * Cy, gZ = gx * zx + gy * zy;
+            fxd -= (gx + invD * (gB * gbx + gC * ggx - (betaD + gammaD) * gx - gZ * gdx)).d;
+            fyd -= (gy + invD * (gB * gby + gC * ggy - (betaD + gammaD) * gy - gZ * gdy)).d;
         }
-        Dual t1x, t1y, t2x, t2y, t3x, t3y;
-        dual_unit(hcx - hpx, hcy - hpy, t1x, t1y);
-        dual_unit(hnx - hcx, hny - hcy, t2x, t2y);
-        dual_unit(qx - hcx, qy - hcy, t3x, t3y);
-        Dual am, bm, an, bn;
-        coef(jm, am, bm);
-        coef(jn, an, bn);
-        Dual gx = ai * (0.5 * (hny - hpy)) + bi * (t1x - t2x);
-        Dual gy = ai * (0.5 * (hpx - hnx)) + bi * (t1y - t2y);
-        gx = gx + am * (0.5 * (hpy - qy)) + bm * (t1x - t3x);
-        gy = gy + am * (0.5 * (qx - hpx)) + bm * (t1y - t3y);
-        gx = gx + an * (0.5 * (qy - hny)) + bn * (-t2x - t3x);
-        gy = gy + an * (0.5 * (hnx - qx)) + bn * (-t2y - t3y);
-        const Dual ex = Cx - Bx, ey = Cy - By;
-        const Dual s = Bx * Cy - By * Cx;
-        const Dual be = Bx * ex + By * ey, ce = Cx * ex + Cy * ey;
-        const Dual nb = Bx * Bx + By * By, nc = Cx * Cx + Cy * Cy;
-        const Dual betaD = -(nc * be), gammaD = nb * ce;
-        const Dual zx = betaD * Bx + gammaD * Cx, zy = betaD * By + gammaD * Cy;
-        const Dual gbx = 2.0 * (be * Cx) + nc * ex, gby = 2.0 * (be * Cy) + nc * ey;
-        const Dual ggx = -(2.0 * (ce * Bx)) - nb * ex, ggy = -(2.0 * (ce * By)) - nb * ey;
-        const Dual one = {1.0, 0.0};
-        const Dual is = one / s;
-        const Dual gdx = 2.0 * (is * (-ey)), gdy = 2.0 * (is * ex);
-        const Dual invD = 0.5 * (is * is);
-        const Dual gB = gx * Bx + gy * By, gC = gx * Cx + gy * Cy, gZ = gx * zx + gy * zy;
-        fx = fx - (gx + invD * (gB * gbx + gC * ggx - (betaD + gammaD) * gx - gZ * gdx));
-        fy = fy - (gy + invD * (gB * gby + gC * ggy - (betaD + gammaD) * gy - gZ * gdy));
     }
-    fdx[i] = fx.d;
-    fdy[i] = fy.d;
+#pragma unroll
+    for (int off = GL / 2; off > 0; off >>= 1) {
+        fxd += __shfl_xor(fxd, off);
+        fyd += __shfl_xor(fyd, off);
+    }
+    if (!valid || l != 0) return;
+    if (STEP) {
+        const double h = P.dt * P.mu;
+        fdx[i] = lx[i] + h * fxd;
+        fdy[i] = ly[i] + h * fyd;
+        g[i] += h * 2.0 * P.KP * dP[i];
+    } else {
+        fdx[i] = fxd;
+        fdy[i] = fyd;
+    }
 }
 
 // coefficients of w * qbar = w/N sum P_c / sqrt(A_c): d/dA and d/dP
@@ -226,10 +247,13 @@ __global__ void k_adj_step(double* lx, double* ly, const double* fdx, const doub
     ly[i] += h * fdy[i];
 }
 
-// deterministic single-block sum of w * qbar (observable accumulation)
-__global__ __launch_bounds__(256) void k_qbar_accum(const double* A, const double* P, int N, double w, double* acc)
+// deterministic single-block sum of w * qbar (observable accumulation); a
+// halted step (host repair pending) adds nothing
+__global__ __launch_bounds__(256) void k_qbar_accum(const double* A, const double* P, int N, double w, double* acc,
+                                                    const DevState* st)
 {
     __shared__ double s[256];
+    if (st->halt) return;
     double q = 0.0;
     for (int i = threadIdx.x; i < N; i += 256) q += P[i] / sqrt(A[i]);
     s[threadIdx.x] = q;
@@ -239,6 +263,33 @@ __global__ __launch_bounds__(256) void k_qbar_accum(const double* A, const doubl
         __syncthreads();
     }
     if (threadIdx.x == 0) *acc += w * s[0] / N;
+}
+
+// Every per-cell array of a state in one launch (snapshots of the trajectory).
+struct StatePtrs {
+    double *x, *y, *th;
+    uint8_t* deg;
+    int *ring, *opp;
+    double *A, *P, *ca, *cb;
+};
+
+__global__ void k_state_copy(StatePtrs dst, StatePtrs src, int N, int K)
+{
+    const size_t nk = (size_t)N * K;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nk; e += (size_t)gridDim.x * blockDim.x) {
+        dst.ring[e] = src.ring[e];
+        dst.opp[e] = src.opp[e];
+        if (e < (size_t)N) {
+            dst.x[e] = src.x[e];
+            dst.y[e] = src.y[e];
+            dst.th[e] = src.th[e];
+            dst.deg[e] = src.deg[e];
+            dst.A[e] = src.A[e];
+            dst.P[e] = src.P[e];
+            dst.ca[e] = src.ca[e];
+            dst.cb[e] = src.cb[e];
+        }
+    }
 }
 
 }  // namespace spv

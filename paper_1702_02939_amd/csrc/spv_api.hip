@@ -112,6 +112,7 @@ struct Snapshot {
 
 struct TrajCheckpoint {
     Snapshot snap;
+    double* acc = nullptr;  // accumulated observable at the checkpoint (device)
     int pos = 0;
     uint64_t step = 0;
 };
@@ -168,6 +169,7 @@ struct spv_sys {
     std::vector<Snapshot> seg;         // per-step states of the segment being differentiated
     double *d_lx = nullptr, *d_ly = nullptr, *d_g = nullptr, *d_dA = nullptr, *d_dP = nullptr;
     double *d_fdx = nullptr, *d_fdy = nullptr, *d_aq = nullptr, *d_bq = nullptr, *d_acc = nullptr;
+    double *d_lx2 = nullptr, *d_ly2 = nullptr;  // the adjoint's second buffer
 };
 
 namespace {
@@ -1128,23 +1130,16 @@ spv_status snap_alloc(spv_sys* s, Snapshot& z)
 // copy between the live state (current configuration and parity) and z
 spv_status snap_copy(spv_sys* s, Snapshot& z, bool take)
 {
-    const size_t N = s->N, K = s->KC;
+    const int N = s->N, K = s->KC;
     const ArraySet& cur = s->set[s->cfg];
     const ArraySet& par = s->set[(s->pos & 1) ? s->cfg ^ 1 : s->cfg];
-    auto cp = [&](void* live, void* snap, size_t bytes) {
-        return take ? hipMemcpyAsync(snap, live, bytes, hipMemcpyDeviceToDevice, s->stream)
-                    : hipMemcpyAsync(live, snap, bytes, hipMemcpyDeviceToDevice, s->stream);
-    };
-    HIP_TRY(cp(par.x, z.x, N * 8));
-    HIP_TRY(cp(par.y, z.y, N * 8));
-    HIP_TRY(cp(par.th, z.th, N * 8));
-    HIP_TRY(cp(cur.deg, z.deg, N));
-    HIP_TRY(cp(cur.ring, z.ring, N * K * 4));
-    HIP_TRY(cp(cur.opp, z.opp, N * K * 4));
-    HIP_TRY(cp(cur.A, z.A, N * 8));
-    HIP_TRY(cp(cur.P, z.P, N * 8));
-    HIP_TRY(cp(cur.ca, z.ca, N * 8));
-    HIP_TRY(cp(cur.cb, z.cb, N * 8));
+    const StatePtrs live{par.x,  par.y,  par.th, cur.deg, cur.ring, cur.opp, static_cast<double*>(cur.A),
+                         static_cast<double*>(cur.P), static_cast<double*>(cur.ca), static_cast<double*>(cur.cb)};
+    const StatePtrs snap{z.x, z.y, z.th, z.deg, z.ring, z.opp, z.A, z.P, z.ca, z.cb};
+    const unsigned grid = std::min(grid_for(N * K, 256), 2048u);
+    hipLaunchKernelGGL(k_state_copy, dim3(grid), dim3(256), 0, s->stream, take ? snap : live, take ? live : snap, N,
+                       K);
+    HIP_TRY(hipGetLastError());
     return SPV_OK;
 }
 
@@ -1168,32 +1163,70 @@ spv_status traj_buffers(spv_sys* s)
 {
     if (s->d_lx) return SPV_OK;
     const size_t N = s->N;
-    for (double** p : {&s->d_lx, &s->d_ly, &s->d_g, &s->d_dA, &s->d_dP, &s->d_fdx, &s->d_fdy, &s->d_aq, &s->d_bq})
+    for (double** p : {&s->d_lx, &s->d_ly, &s->d_lx2, &s->d_ly2, &s->d_g, &s->d_dA, &s->d_dP, &s->d_fdx, &s->d_fdy,
+                       &s->d_aq, &s->d_bq})
         ST_TRY(dalloc(s, p, N));
     ST_TRY(dalloc(s, &s->d_acc, 1));
     return SPV_OK;
 }
 
+// the state (and the observable accumulated so far) at a segment start
 spv_status take_checkpoint(spv_sys* s, TrajCheckpoint& c)
 {
     ST_TRY(snap_alloc(s, c.snap));
+    if (!c.acc) ST_TRY(dalloc(s, &c.acc, 1));
     ST_TRY(snap_copy(s, c.snap, true));
+    HIP_TRY(hipMemcpyAsync(c.acc, s->d_acc, sizeof(double), hipMemcpyDeviceToDevice, s->stream));
     c.pos = s->pos;
     c.step = s->step;
     return SPV_OK;
 }
 
-// restore a checkpoint, including the device noise counter
-spv_status restore_checkpoint(spv_sys* s, const TrajCheckpoint& c)
+// restore a checkpoint, including the device noise counter; clears a
+// halted step's device state (the segment is then redone)
+spv_status restore_checkpoint(spv_sys* s, const TrajCheckpoint& c, bool with_acc)
 {
     s->pos = c.pos;
     s->step = c.step;
     ST_TRY(snap_copy(s, const_cast<Snapshot&>(c.snap), false));
+    if (with_acc) HIP_TRY(hipMemcpyAsync(s->d_acc, c.acc, sizeof(double), hipMemcpyDeviceToDevice, s->stream));
+    // a halted step leaves flagged / touched cells behind: forget them with
+    // their counters (the restored state is a completed step's)
+    const size_t nwords = ((size_t)s->N + 31) / 32;
+    HIP_TRY(hipMemsetAsync(s->work.flagbits, 0, nwords * sizeof(unsigned), s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.touchbits, 0, nwords * sizeof(unsigned), s->stream));
+    hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s->stream, s->d_st);
+    HIP_TRY(hipGetLastError());
     ST_TRY(read_state(s));
     s->h_st->step = c.step;
-    HIP_TRY(hipMemcpyAsync(&s->d_st->step, &s->h_st->step, sizeof(unsigned long long), hipMemcpyHostToDevice,
-                           s->stream));
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(s->d_st) + offsetof(DevState, step), &s->h_st->step,
+                           sizeof(unsigned long long), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    return SPV_OK;
+}
+
+// m steps of a recorded segment, enqueued back to back (no re-sort), each
+// followed by after(j); one read-back.  *ok = false when a step needed host
+// repair rounds (the later kernels did nothing; the caller redoes the
+// segment one step at a time from its checkpoint).
+template <typename After>
+spv_status segment_fast(spv_sys* s, int64_t m, After&& after, bool* ok)
+{
+    const uint64_t before = s->step;
+    const int pos0 = s->pos;
+    for (int64_t j = 0; j < m; j++) {
+        const int cfg = s->cfg, par = (int)((pos0 + j) & 1);
+        dispatch(s,
+                 [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, nullptr); });
+        s->pos = pos0 + (int)j + 1;  // after() sees the state after step j + 1
+        after(j + 1);
+    }
+    HIP_TRY(hipGetLastError());
+    ST_TRY(read_state(s));
+    if (s->h_st->err) return error_from_word(s);
+    *ok = !s->h_st->halt && s->h_st->step - before == (uint64_t)m;
+    if (*ok) s->step += m;
+    else s->pos = pos0;  // the caller restores the segment's checkpoint
     return SPV_OK;
 }
 
@@ -1209,14 +1242,23 @@ spv_status traj_forward(spv_sys* s, int64_t T, int64_t k, double* Q)
     s->no_resort = true;
     HIP_TRY(hipMemsetAsync(s->d_acc, 0, sizeof(double), s->stream));
     const double w = 1.0 / (double)T;
+    auto accum = [&](int64_t) {
+        const ArraySet& cur = s->set[s->cfg];
+        hipLaunchKernelGGL(k_qbar_accum, dim3(1), dim3(256), 0, s->stream, (const double*)cur.A,
+                           (const double*)cur.P, s->N, w, s->d_acc, (const DevState*)s->d_st);
+    };
     spv_status st = SPV_OK;
-    for (int64_t t = 0; t < T && st == SPV_OK; t++) {
-        if (t % k == 0) st = take_checkpoint(s, s->ckpt[t / k]);
-        if (st == SPV_OK) st = run_steps(s, 1);
-        if (st == SPV_OK) {
-            const ArraySet& cur = s->set[s->cfg];
-            hipLaunchKernelGGL(k_qbar_accum, dim3(1), dim3(256), 0, s->stream, (const double*)cur.A,
-                               (const double*)cur.P, s->N, w, s->d_acc);
+    for (int64_t c = 0; c < nck && st == SPV_OK; c++) {
+        const int64_t m = std::min<int64_t>(k, T - c * k);
+        st = take_checkpoint(s, s->ckpt[c]);
+        bool ok = false;
+        if (st == SPV_OK) st = segment_fast(s, m, accum, &ok);
+        if (st == SPV_OK && !ok) {
+            st = restore_checkpoint(s, s->ckpt[c], true);
+            for (int64_t j = 0; j < m && st == SPV_OK; j++) {
+                st = run_steps(s, 1);
+                if (st == SPV_OK) accum(j + 1);
+            }
         }
     }
     if (st == SPV_OK) st = take_checkpoint(s, s->ckpt[nck]);
@@ -1232,34 +1274,33 @@ spv_status traj_forward(spv_sys* s, int64_t T, int64_t k, double* Q)
     return SPV_OK;
 }
 
+// One backward step over r_{t-1} -> r_t with the adjoint lambda in buffer
+// li:  lambda += d(w qbar)/dr at r_t (the force kernel with the qbar
+// coefficients aq, bq of r_t, which the previous backward step computed),
+// then  lambda' = lambda + dt mu dF(r_{t-1})[lambda]  into buffer li ^ 1 and
+// g += dt mu 2 K_P dP(r_{t-1})[lambda];  the tangent-geometry pass at r_{t-1}
+// also leaves the qbar coefficients of r_{t-1} for the next backward step.
 template <int KC>
-void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_prev, bool add_grad)
+void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_prev, int li)
 {
     const int N = s->N;
-    const unsigned g256 = grid_for(N, 256);
     const double w = 1.0 / (double)s->traj_T;
-    if (add_grad) {
-        // lambda += d(w qbar)/dr at r_t: the force kernel with the qbar coefficients
-        Cells<double> ct = snap_cells(s, at_t);
-        hipLaunchKernelGGL(k_qbar_coef, dim3(g256), dim3(256), 0, s->stream, (const double*)ct.A,
-                           (const double*)ct.P, N, w, s->d_aq, s->d_bq);
-        ct.ca = s->d_aq;
-        ct.cb = s->d_bq;
-        hipLaunchKernelGGL((k_force<double, false, KC, false>), dim3(cell_grid(s)), dim3(256), 0, s->stream, ct,
-                           (double*)nullptr, (double*)nullptr, (double*)nullptr, s->d_fdx, s->d_fdy, s->d_sp,
-                           s->d_st, N, s->d_blockmax);
-        hipLaunchKernelGGL(k_adj_add_grad, dim3(g256), dim3(256), 0, s->stream, s->d_lx, s->d_ly,
-                           (const double*)s->d_fdx, (const double*)s->d_fdy, N);
-    }
-    // step r_{t-1} -> r_t: g += dt mu 2 K_P dP[lambda], lambda += dt mu dF[lambda]
+    double* lx = li ? s->d_lx2 : s->d_lx;
+    double* ly = li ? s->d_ly2 : s->d_ly;
+    double* lxo = li ? s->d_lx : s->d_lx2;
+    double* lyo = li ? s->d_ly : s->d_ly2;
+    Cells<double> ct = snap_cells(s, at_t);
+    ct.ca = s->d_aq;
+    ct.cb = s->d_bq;
+    hipLaunchKernelGGL((k_force<double, false, KC, false, true>), dim3(cell_grid(s)), dim3(256), 0, s->stream, ct,
+                       (double*)nullptr, (double*)nullptr, (double*)nullptr, lx, ly, (const SysParam*)s->d_sp,
+                       s->d_st, N, s->d_blockmax);
     Cells<double> cp = snap_cells(s, at_prev);
-    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(g256), dim3(256), 0, s->stream, cp, (const double*)s->d_lx,
-                       (const double*)s->d_ly, s->d_sp, N, s->d_dA, s->d_dP);
-    hipLaunchKernelGGL((k_tangent_force<KC>), dim3(g256), dim3(256), 0, s->stream, cp, (const double*)s->d_lx,
-                       (const double*)s->d_ly, (const double*)s->d_dA, (const double*)s->d_dP, s->d_sp, N, s->d_fdx,
-                       s->d_fdy);
-    hipLaunchKernelGGL(k_adj_step, dim3(g256), dim3(256), 0, s->stream, s->d_lx, s->d_ly, (const double*)s->d_fdx,
-                       (const double*)s->d_fdy, (const double*)s->d_dP, s->d_g, s->d_sp, (const int*)cp.sys, N);
+    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, cp, (const double*)lx,
+                       (const double*)ly, (const SysParam*)s->d_sp, N, s->d_dA, s->d_dP, w, s->d_aq, s->d_bq);
+    hipLaunchKernelGGL((k_tangent_force<KC, true>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, cp, (const double*)lx,
+                       (const double*)ly, (const double*)s->d_dA, (const double*)s->d_dP, (const SysParam*)s->d_sp, N,
+                       lxo, lyo, s->d_g);
 }
 
 __global__ void k_adj_out(const double* g, const double* A0, const int* tag, double scale, double* out, int n)
@@ -1279,24 +1320,37 @@ spv_status traj_backward(spv_sys* s, double dQ, double* dQ_dp0)
     HIP_TRY(hipMemsetAsync(s->d_ly, 0, N * 8, s->stream));
     HIP_TRY(hipMemsetAsync(s->d_g, 0, N * 8, s->stream));
     s->no_resort = true;
+    int li = 0;
+    const double w = 1.0 / (double)T;
     spv_status st = SPV_OK;
     for (int64_t c = nck - 1; c >= 0 && st == SPV_OK; c--) {
         // recompute the segment from its checkpoint, recording every state
-        st = restore_checkpoint(s, s->ckpt[c]);
-        if (st == SPV_OK) st = snap_copy(s, s->seg[0], true);
         const int64_t m = std::min<int64_t>(k, T - c * k);
-        for (int64_t j = 1; j <= m && st == SPV_OK; j++) {
-            st = run_steps(s, 1);
-            if (st == SPV_OK) st = snap_copy(s, s->seg[j], true);
+        st = restore_checkpoint(s, s->ckpt[c], false);
+        if (st == SPV_OK) st = snap_copy(s, s->seg[0], true);
+        bool ok = false;
+        if (st == SPV_OK)
+            st = segment_fast(s, m, [&](int64_t j) { (void)snap_copy(s, s->seg[j], true); }, &ok);
+        if (st == SPV_OK && !ok) {
+            st = restore_checkpoint(s, s->ckpt[c], false);
+            for (int64_t j = 1; j <= m && st == SPV_OK; j++) {
+                st = run_steps(s, 1);
+                if (st == SPV_OK) st = snap_copy(s, s->seg[j], true);
+            }
         }
-        for (int64_t j = m; j >= 1 && st == SPV_OK; j--) {
-            if (s->KC == 16) enqueue_adjoint_step<16>(s, s->seg[j], s->seg[j - 1], true);
-            else enqueue_adjoint_step<32>(s, s->seg[j], s->seg[j - 1], true);
-            if (hipGetLastError() != hipSuccess) st = fail(SPV_EHIP, "adjoint kernel launch failed");
+        if (st != SPV_OK) break;
+        // qbar coefficients of the segment's last state, then the steps backwards
+        hipLaunchKernelGGL(k_qbar_coef, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, (const double*)s->seg[m].A,
+                           (const double*)s->seg[m].P, (int)N, w, s->d_aq, s->d_bq);
+        for (int64_t j = m; j >= 1; j--) {
+            if (s->KC == 16) enqueue_adjoint_step<16>(s, s->seg[j], s->seg[j - 1], li);
+            else enqueue_adjoint_step<32>(s, s->seg[j], s->seg[j - 1], li);
+            li ^= 1;
         }
+        if (hipGetLastError() != hipSuccess) st = fail(SPV_EHIP, "adjoint kernel launch failed");
     }
     // back to the state reached by the forward pass
-    if (st == SPV_OK) st = restore_checkpoint(s, s->ckpt[nck]);
+    if (st == SPV_OK) st = restore_checkpoint(s, s->ckpt[nck], false);
     s->no_resort = false;
     if (st != SPV_OK) return st;
     const ArraySet& cur = s->set[s->cfg];
@@ -1329,12 +1383,12 @@ spv_status hvp_impl(spv_sys* s, const double* vx, const double* vy, double* hx, 
     HIP_TRY(hipMemcpyAsync(s->d_lx, mx.data(), N * 8, hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->d_ly, my.data(), N * 8, hipMemcpyHostToDevice, s->stream));
     Cells<double> c = cells<double>(s, s->cfg, s->pos & 1);
-    const unsigned g256 = grid_for(N, 256);
-    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(g256), dim3(256), 0, s->stream, c, (const double*)s->d_lx,
-                       (const double*)s->d_ly, s->d_sp, N, s->d_dA, s->d_dP);
-    hipLaunchKernelGGL((k_tangent_force<KC>), dim3(g256), dim3(256), 0, s->stream, c, (const double*)s->d_lx,
-                       (const double*)s->d_ly, (const double*)s->d_dA, (const double*)s->d_dP, s->d_sp, N, s->d_fdx,
-                       s->d_fdy);
+    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, c, (const double*)s->d_lx,
+                       (const double*)s->d_ly, (const SysParam*)s->d_sp, N, s->d_dA, s->d_dP, 0.0, (double*)nullptr,
+                       (double*)nullptr);
+    hipLaunchKernelGGL((k_tangent_force<KC, false>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, c, (const double*)s->d_lx,
+                       (const double*)s->d_ly, (const double*)s->d_dA, (const double*)s->d_dP,
+                       (const SysParam*)s->d_sp, N, s->d_fdx, s->d_fdy, (double*)nullptr);
     HIP_TRY(hipGetLastError());
     ST_TRY(out_tag_order(s, s->d_fdx, hx));
     return out_tag_order(s, s->d_fdy, hy);

@@ -141,7 +141,9 @@ __device__ __forceinline__ int xcd_block(int b, int grid)
 // dA_c = 1/2 (h+_y - h-_y, h-_x - h+_x) for the CCW neighbours (h-, h+) of h_m
 // in cell c, and F_i = -sum_m J_m^T g_m with the circumcentre Jacobian of
 // App. B (Eq. B4), read with s = b x c in the denominator and its gradient.
-template <typename R, bool MULTI, int KC, bool UPDATE>
+// ACC (with UPDATE = false): subtract the force from fxo / fyo instead of
+// storing it (adds the gradient of the energy-like functional to them).
+template <typename R, bool MULTI, int KC, bool UPDATE, bool ACC = false>
 __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
                                                double* __restrict__ tho, double* __restrict__ fxo,
                                                double* __restrict__ fyo, const SysParam* __restrict__ sp,
@@ -260,8 +262,13 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     }
     if (!UPDATE) {
         if (valid && l == 0) {
-            fxo[i] = (double)fx;
-            fyo[i] = (double)fy;
+            if (ACC) {
+                fxo[i] -= (double)fx;
+                fyo[i] -= (double)fy;
+            } else {
+                fxo[i] = (double)fx;
+                fyo[i] = (double)fy;
+            }
         }
         return;
     }

@@ -113,3 +113,30 @@ def test_autograd_function(spv):
     g = s.traj_backward(1.0)
     assert np.array_equal(g, p0.grad.numpy())
     s.close()
+
+
+def test_trajectory_gradient_independent_of_scheduling(spv):
+    """From a random start (many topology changes, some steps finished by
+    host repair rounds, which sends segments to the one-step-at-a-time path),
+    Q and dQ/dp0 are bitwise the same whatever the scheduling knobs, and a
+    second backward pass repeats the first."""
+    n, T, k = 1500, 40, 7
+    L = math.sqrt(n)
+    x, y = inputs.uniform_positions(n, L, L, 74)
+    p0 = inputs.per_cell_p0(n, 3.8, 0.05, 74)
+    out = []
+    for kw in (dict(), dict(device_rounds=1), dict(tail_items=1, repair_cells=8)):
+        s = spv.System(x, y, L, L, P0=p0, params=spv.Params(mu=1.0, v0=0.05, Dr=1.0, dt=0.01, seed=3, **kw))
+        s.step(5)
+        Q = s.traj_forward(T, k)
+        g = s.traj_backward(1.0)
+        g2 = s.traj_backward(1.0)
+        assert np.array_equal(g, g2)
+        xe, ye = s.positions()
+        out.append((Q, g, xe, ye))
+        s.close()
+    for Q, g, xe, ye in out[1:]:
+        assert Q == out[0][0]
+        assert np.array_equal(g, out[0][1])
+        assert np.array_equal(xe, out[0][2]) and np.array_equal(ye, out[0][3])
+    assert np.isfinite(out[0][1]).all() and np.abs(out[0][1]).max() > 0
