@@ -543,16 +543,18 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
                              int* s_tmp, double scale, bool& closed)
 {
     const int lane = threadIdx.x & 63;
+    // G lanes per candidate split the loop over the other candidates
+    const int G = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
+    const int per_pass = 64 / G;
     int unsure = 0, k = 0;
-    for (int base = 0; base < n; base += 64) {
-        const int pi = base + lane;
-        bool mem = false;
+    for (int base = 0; base < n; base += per_pass) {
+        const int pi = base + lane / G, r = lane % G;
+        bool mem = false, blocked = false;
+        double ulo = INFINITY, uhi = INFINITY, llo = -INFINITY, lhi = -INFINITY;
         if (pi < n) {
             const double px = sx[pi], py = sy[pi];
-            double ulo = INFINITY, uhi = INFINITY, llo = -INFINITY, lhi = -INFINITY;
-            bool blocked = false;
 #pragma unroll 4
-            for (int q = 0; q < n; q++) {
+            for (int q = r; q < n; q += G) {
                 if (q == pi) continue;
                 const double qx = sx[q], qy = sy[q];
                 const double a = px * qy, b = py * qx;
@@ -587,10 +589,18 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
                     lhi = fmax(lhi, t + e);
                 }
             }
-            if (!blocked) {
-                if (ulo > lhi) mem = true;           // certainly a non-empty interval
-                else if (!(llo > uhi)) unsure = 1;  // and not certainly empty either
-            }
+        }
+        // combine the G lanes of each candidate (aligned groups)
+        for (int off = 1; off < G; off <<= 1) {
+            ulo = fmin(ulo, __shfl_xor(ulo, off));
+            uhi = fmin(uhi, __shfl_xor(uhi, off));
+            llo = fmax(llo, __shfl_xor(llo, off));
+            lhi = fmax(lhi, __shfl_xor(lhi, off));
+            blocked = __shfl_xor((int)blocked, off) != 0 || blocked;
+        }
+        if (pi < n && r == 0 && !blocked) {
+            if (ulo > lhi) mem = true;           // certainly a non-empty interval
+            else if (!(llo > uhi)) unsure = 1;  // and not certainly empty either
         }
         const unsigned long long m = __ballot(mem);
         if (mem) {
