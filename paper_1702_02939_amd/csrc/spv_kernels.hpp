@@ -376,15 +376,34 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
             const int jm = sJ[g][m], jn = sJ[g][mn];
             int o;
             if (OPP) {
+                // jm's whole ring row in one go (16-byte loads), searched in
+                // registers for i and the two entries before it
                 o = -1;
                 const int kj = min((int)c.deg[jm], KC);
-                for (int p = 0; p < kj; p++) {
-                    if (c.ring[jm * KC + p] == i) {
-                        const int pm1 = (p == 0) ? kj - 1 : p - 1;
-                        const int pm2 = (pm1 == 0) ? kj - 1 : pm1 - 1;
-                        if (c.ring[jm * KC + pm1] == jn) o = c.ring[jm * KC + pm2];
-                        break;
+                int row[KC];
+                const int4* __restrict__ rv = reinterpret_cast<const int4*>(c.ring + (size_t)jm * KC);
+#pragma unroll
+                for (int v = 0; v < KC / 4; v++) {
+                    const int4 t4 = rv[v];
+                    row[4 * v] = t4.x;
+                    row[4 * v + 1] = t4.y;
+                    row[4 * v + 2] = t4.z;
+                    row[4 * v + 3] = t4.w;
+                }
+                int p = -1;
+#pragma unroll
+                for (int q = KC - 1; q >= 0; q--)
+                    if (q < kj && row[q] == i) p = q;
+                if (p >= 0) {
+                    const int pm1 = (p == 0) ? kj - 1 : p - 1;
+                    const int pm2 = (pm1 == 0) ? kj - 1 : pm1 - 1;
+                    int v1 = -1, v2 = -1;
+#pragma unroll
+                    for (int q = 0; q < KC; q++) {
+                        if (q == pm1) v1 = row[q];
+                        if (q == pm2) v2 = row[q];
                     }
+                    if (v1 == jn) o = v2;
                 }
                 c.opp[i * KC + m] = o;
             } else {
@@ -1015,14 +1034,22 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
         return;
     }
     __threadfence();  // every block's writes are visible from here on
-    if (threadIdx.x == 0) st->done = 0;
-
-    const double drift = st->drift;
-    int used = st->wl_count[0] > 0 ? 1 : 0;
+    // the step's counters and error word, read together by one thread
+    __shared__ int s_w0, s_w1, s_err;
+    if (threadIdx.x == 0) {
+        st->done = 0;
+        s_w0 = load_count(&st->wl_count[0]);
+        s_w1 = load_count(&st->wl_count[1]);
+        s_err = (int)__hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    int used = s_w0 > 0 ? 1 : 0;
     int r = 1, halt_at = -1;
+    double drift = 0.0;
     for (; r < rounds; r++) {
-        const int nw = load_count(&st->wl_count[r]);
+        const int nw = r == 1 ? s_w1 : load_count(&st->wl_count[r]);
         if (nw == 0) break;
+        if (r == 1) drift = st->drift;
         if (nw > max_items) {
             halt_at = r;
             break;
@@ -1047,13 +1074,16 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
             geom_pass<R, MULTI, KC, true, true>(c, w, sp, st, base, nt, tl, r + 1, S, exact);
         __syncthreads();
     }
-    if (halt_at < 0 && r == rounds && load_count(&st->wl_count[rounds]) > 0) halt_at = rounds;
+    if (halt_at < 0 && r == rounds && (rounds == 1 ? s_w1 : load_count(&st->wl_count[rounds])) > 0)
+        halt_at = rounds;
     if ((threadIdx.x & 63) == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
     __syncthreads();
     if (threadIdx.x != 0) return;
-    st->rounds += (unsigned long long)used;
-    if (halt_at >= 0 || __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    atomicAdd(&st->rounds, (unsigned long long)used);  // statistics: no read-back
+    const bool tail_ran = used > (s_w0 > 0 ? 1 : 0);
+    if (halt_at >= 0 || s_err ||
+        (tail_ran && __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
         st->halt = 1;
         st->halt_round = halt_at >= 0 ? halt_at : rounds;
         return;
