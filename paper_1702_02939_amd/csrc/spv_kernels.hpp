@@ -31,11 +31,31 @@ constexpr int RP_CAP = 1024;   // max candidate neighbours of one repaired cell
 
 // ---------------------------------------------------------------- helpers
 
+// FP64 reciprocal and reciprocal square root: the hardware estimate refined
+// by two Newton steps (about 1 ulp; only non-degenerate arguments are
+// meaningful: a zero denominator belongs to a triangle already flagged)
+__device__ __forceinline__ double fast_rcp(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = r * (2.0 - d * r);
+    r = r * (2.0 - d * r);
+    return r;
+}
+__device__ __forceinline__ float fast_rcp(float d) { return 1.0f / d; }
+__device__ __forceinline__ double fast_rsqrt(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * (1.5 - 0.5 * x * y * y);
+    return y;
+}
+__device__ __forceinline__ float fast_rsqrt(float x) { return 1.0f / sqrtf(x); }
+
 template <typename R>
 __device__ __forceinline__ void circumcentre(R bx, R by, R cx, R cy, R& ux, R& uy)
 {
     const R nb = bx * bx + by * by, nc = cx * cx + cy * cy;
-    const R inv = R(0.5) / (bx * cy - by * cx);
+    const R inv = R(0.5) * fast_rcp(bx * cy - by * cx);
     ux = (cy * nb - by * nc) * inv;
     uy = (bx * nc - cx * nb) * inv;
 }
@@ -45,7 +65,7 @@ __device__ __forceinline__ void unit(R ex, R ey, R& tx, R& ty)
 {
     const R l2 = ex * ex + ey * ey;
     if (l2 > R(0)) {
-        const R r = R(1) / sqrt(l2);
+        const R r = fast_rsqrt(l2);
         tx = ex * r;
         ty = ey * r;
     } else {  // zero-length Voronoi edge (exact T1 configuration)
@@ -247,7 +267,7 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
             const R zx = betaD * Bx + gammaD * Cx, zy = betaD * By + gammaD * Cy;
             const R gbx = R(2) * be * Cx + nc * ex, gby = R(2) * be * Cy + nc * ey;    // grad(beta D)
             const R ggx = R(-2) * ce * Bx - nb * ex, ggy = R(-2) * ce * By - nb * ey;  // grad(gamma D)
-            const R is = R(1) / sc;
+            const R is = fast_rcp(sc);
             const R gdx = R(2) * is * (-ey), gdy = R(2) * is * ex;                     // grad(D) / D
             const R invD = R(0.5) * is * is;                                           // 1 / (2 s^2)
             const R gB = gx * Bx + gy * By, gC = gx * Cx + gy * Cy, gZ = gx * zx + gy * zy;
