@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="run with the default scheduling knobs instead of the library's tuned ones")
     ap.add_argument("--batch-steps", type=int, default=5000)
-    ap.add_argument("--big-steps", type=int, default=400)
+    ap.add_argument("--big-steps", type=int, default=2000)
     ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")

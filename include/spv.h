@@ -75,19 +75,21 @@ typedef struct {
     int32_t repair_cells;   /* flagged cells per repair wavefront: the repair grid is N / repair_cells
                                blocks, clamped to [256, 4096] (0: 64) */
     int32_t autotune;       /* 0: use the scheduling knobs given here (resort_every, device_rounds,
-                               repair_cells, tail_items, bin_factor); 1: take them from the tuning cache for this
+                               repair_cells, tail_items, full_rounds, bin_factor); 1: take them from the tuning cache for this
                                device and size class, else choose them by timed trial runs and cache
                                them; 2: always run the trials and refresh the cache.  The cache is the
                                JSON file named by the environment variable SPV_TUNE_CACHE, else held
                                in this process only.  The knobs never change results. */
     int32_t tail_items;     /* a later round with more flagged cells than this is handed to the host
                                (full-grid rounds) instead of the one-block tail (0: 64) */
+    int32_t full_rounds;    /* repair rounds per step run over the whole grid before the tail takes
+                               the rest (0: 1; at most 4) */
     double bin_factor;      /* cell-list bin side in mean cell spacings sqrt(Lx Ly / N) (0: 1; 0.5..8) */
 } spv_params;
 
 /* Scheduling knobs a handle runs with (see spv_params). */
 typedef struct {
-    int32_t resort_every, device_rounds, repair_cells, tail_items;
+    int32_t resort_every, device_rounds, repair_cells, tail_items, full_rounds;
     int32_t source;      /* 0: given in spv_params, 1: tuning cache, 2: timed trials */
     double bin_factor;
     double ms_per_step;  /* trial time per step of the chosen knobs (0 when source = 0) */

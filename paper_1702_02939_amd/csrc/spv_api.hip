@@ -124,6 +124,14 @@ struct spv_sys {
     int dev_rounds = 2, max_rounds = 16, unit = 16;
     int repair_cells = 64;  // repair grid = N / this (clamped to [256, 4096] blocks)
     int tail_items = 64;    // largest later round the one-block tail takes
+    int full_rounds = 1;    // repair rounds over the whole grid before the tail
+    // adaptive re-sort: while cells move fast (the drift of a period exceeds
+    // drift_limit, one bin side) steps run eagerly and re-sort as soon as
+    // the drift passes the limit; a full quiet period returns to graphs
+    bool hot = true;
+    int quiet = 0;
+    double drift_limit = 1.0;
+    double drift_rate = INFINITY;  // drift added per step over the last eager batch (unknown: one step)
     double bin_factor = 1.0;
     int tune_source = 0;
     double tune_ms = 0.0;
@@ -318,12 +326,18 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
            (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
     launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, s->work,
            (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax, (int)cg);
-    // round 0 over the whole grid; its re-test, later rounds and the step's
-    // close in the tail
+    // rounds 0 .. f-1 over the whole grid; the last one's re-test, later
+    // rounds and the step's close in the tail
+    const int f = std::min(s->full_rounds, s->dev_rounds);
     launch(ev ? &ev[2] : nullptr, k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, s->work,
            (const SysParam*)s->d_sp, s->d_st, 0);
+    for (int r = 1; r < f; r++) {
+        hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(std::min(grid_for(s->N, CPB), 512u)), dim3(256), 0,
+                           st, nxt, s->work, s->d_sp, s->d_st, s->N, r - 1, (const double*)nullptr, 0);
+        hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, r);
+    }
     hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(TAIL_BLOCKS), dim3(TAIL_THREADS), 0, st, nxt, s->work, s->d_sp,
-                       s->d_st, s->dev_rounds, s->tail_items);
+                       s->d_st, s->dev_rounds, s->tail_items, f);
 }
 
 // Re-sort from (cfg, parity 0) into set[cfg ^ 1] (the caller flips cfg).
@@ -463,8 +477,10 @@ spv_status run_steps(spv_sys* s, int64_t n)
 {
     if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
     while (n > 0) {
-        if (s->pos >= s->unit && !(s->pos & 1) && !s->no_resort) ST_TRY(do_resort_eager(s));
-        if (s->pos == 0 && n >= s->unit && s->use_graphs && !s->timing && !s->no_resort) {
+        if (!(s->pos & 1) && !s->no_resort && s->pos > 0 &&
+            (s->pos >= s->unit || (s->hot && s->h_st->drift > s->drift_limit)))
+            ST_TRY(do_resort_eager(s));
+        if (s->pos == 0 && n >= s->unit && s->use_graphs && !s->timing && !s->no_resort && !s->hot) {
             const int g = s->cfg;
             if (!s->gexec[g]) ST_TRY(capture_graph(s, g));
             const uint64_t before = s->step;
@@ -484,24 +500,50 @@ spv_status run_steps(spv_sys* s, int64_t n)
             n -= (int64_t)done;
             s->cfg ^= 1;
             s->resorts++;
-        } else {
-            EvPair ev[T_COUNT];
-            const EvPair* evp = nullptr;
-            if (s->timing) {
-                for (int k = 0; k < T_COUNT; k++) {
-                    ev[k] = take_events(s);
-                    s->pending.push_back({k, ev[k]});
-                }
-                evp = ev;
+            if (s->h_st->last_drift > s->drift_limit) {
+                s->hot = true;
+                s->quiet = 0;
+                s->drift_rate = s->h_st->last_drift / (double)done;
             }
-            const int cfg = s->cfg, par = s->pos & 1;
-            dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, evp); });
+        } else {
+            // eager: a batch of steps (up to kEagerBatch, not past the next
+            // re-sort point; one step at a time while timing), one read-back
+            constexpr int64_t kEagerBatch = 8;
+            int64_t b = std::min<int64_t>(n, s->timing ? 1 : kEagerBatch);
+            if (!s->no_resort) b = std::min<int64_t>(b, std::max(1, s->unit - s->pos));
+            if (s->hot && s->drift_rate > 0.0)  // about the steps left before the drift limit (at least one)
+                b = std::min<int64_t>(
+                    b, std::max<int64_t>(1, (int64_t)((s->drift_limit - s->h_st->drift) / s->drift_rate)));
+            const uint64_t before = s->step;
+            const double drift0 = s->h_st->drift;
+            for (int64_t j = 0; j < b; j++) {
+                EvPair ev[T_COUNT];
+                const EvPair* evp = nullptr;
+                if (s->timing) {
+                    for (int k = 0; k < T_COUNT; k++) {
+                        ev[k] = take_events(s);
+                        s->pending.push_back({k, ev[k]});
+                    }
+                    evp = ev;
+                }
+                const int cfg = s->cfg, par = (int)((s->pos + j) & 1);
+                dispatch(s, [&]<typename R, bool MULTI, int KC>() {
+                    enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, evp);
+                });
+            }
             HIP_TRY(hipGetLastError());
             ST_TRY(read_state(s));
-            s->step += 1;
-            s->pos += 1;
-            n -= 1;
+            // steps after a halted one did nothing (as in a graph period)
+            const uint64_t done = s->h_st->step - before;
+            s->step += done;
+            s->pos += (int)done;
+            n -= (int64_t)done;
             if (s->h_st->halt) ST_TRY(recover(s));
+            if (s->hot) {
+                if (done > 0 && !s->h_st->halt) s->drift_rate = (s->h_st->drift - drift0) / (double)done;
+                if (s->h_st->drift > s->drift_limit) s->quiet = 0;
+                else if ((s->quiet += (int)done) >= s->unit) s->hot = false;
+            }
         }
     }
     return SPV_OK;
@@ -627,6 +669,8 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     }
     s->cell_off[S] = off;
     for (int k = 0; k < S; k++) s->cell_off[k] = s->hsp[k].cell_off;
+    s->drift_limit = INFINITY;
+    for (int k = 0; k < S; k++) s->drift_limit = std::min({s->drift_limit, s->hsp[k].bsx, s->hsp[k].bsy});
     s->total_bins = boff;
 
     // device state
@@ -704,6 +748,9 @@ spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vect
     s->cfg = 0;
     s->pos = 0;
     s->step = step0;
+    s->hot = true;
+    s->quiet = 0;
+    s->drift_rate = INFINITY;
     ST_TRY(do_resort_eager(s));
     s->resorts = 0;
     hipLaunchKernelGGL(k_all_to_worklist, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->work, s->d_st, N);
@@ -747,8 +794,10 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     if (p.repair_cells < 0 || p.resort_every < 0 || p.device_rounds < 0)
         return fail(SPV_EINVAL, "negative scheduling knob");
     s->repair_cells = p.repair_cells > 0 ? p.repair_cells : 64;
-    if (p.tail_items < 0) return fail(SPV_EINVAL, "negative scheduling knob");
+    if (p.tail_items < 0 || p.full_rounds < 0) return fail(SPV_EINVAL, "negative scheduling knob");
     s->tail_items = p.tail_items > 0 ? p.tail_items : 64;
+    s->full_rounds = p.full_rounds > 0 ? p.full_rounds : 1;
+    if (s->full_rounds > 4) return fail(SPV_EINVAL, "full_rounds must be at most 4");
     s->bin_factor = p.bin_factor != 0.0 ? p.bin_factor : 1.0;
     if (!(s->bin_factor >= 0.5 && s->bin_factor <= 8.0)) return fail(SPV_EINVAL, "bin_factor must be in [0.5, 8]");
     if (p.autotune < 0 || p.autotune > 2) return fail(SPV_EINVAL, "autotune must be 0, 1 or 2");
@@ -916,7 +965,10 @@ spv_status build_handle(const CreateArgs& a, const spv_params& p, spv_sys** out)
     return finish_create(s, create_impl(s, a.in, hx, hy, a.A0, a.P0, a.th), out);
 }
 
-Knobs knobs_of(const spv_sys* s) { return {s->unit, s->dev_rounds, s->repair_cells, s->tail_items, s->bin_factor}; }
+Knobs knobs_of(const spv_sys* s)
+{
+    return {s->unit, s->dev_rounds, s->repair_cells, s->tail_items, s->full_rounds, s->bin_factor};
+}
 
 spv_params with_knobs(spv_params p, const Knobs& k)
 {
@@ -924,6 +976,7 @@ spv_params with_knobs(spv_params p, const Knobs& k)
     p.device_rounds = k.device_rounds;
     p.repair_cells = k.repair_cells;
     p.tail_items = k.tail_items;
+    p.full_rounds = k.full_rounds;
     p.bin_factor = k.bin_factor;
     p.autotune = 0;
     return p;
@@ -942,6 +995,7 @@ spv_status set_runtime_knobs(spv_sys* s, const Knobs& k)
     s->dev_rounds = std::min(k.device_rounds, s->max_rounds);
     s->repair_cells = k.repair_cells;
     s->tail_items = k.tail_items;
+    s->full_rounds = k.full_rounds;
     return SPV_OK;
 }
 
@@ -1025,6 +1079,7 @@ spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
     };
     const Axis axes[] = {{&Knobs::repair_cells, {16, 64, 256}},
                          {&Knobs::tail_items, {16, 64, 256}},
+                         {&Knobs::full_rounds, {1, 2, 1}},
                          {&Knobs::device_rounds, {2, 4, 8}},
                          {&Knobs::resort_every, {16, 32, 64}}};
     for (const Axis& ax : axes) {
@@ -1512,6 +1567,7 @@ spv_status spv_get_tuning(spv_sys* s, spv_tuning* out)
     out->device_rounds = s->dev_rounds;
     out->repair_cells = s->repair_cells;
     out->tail_items = s->tail_items;
+    out->full_rounds = s->full_rounds;
     out->source = s->tune_source;
     out->bin_factor = s->bin_factor;
     out->ms_per_step = s->tune_ms;

@@ -43,6 +43,7 @@ struct DevState {
     int done;                      // tail blocks finished with their share of the step
     unsigned long long disp_bits;  // max |displacement| of the current step (bits of a non-negative double)
     double drift;                  // sum of per-step max displacements since the last re-sort
+    double last_drift;             // drift when the last re-sort started
     unsigned long long step;       // completed steps (noise counter of the next step)
     // statistics
     unsigned long long repaired, exact_calls, retries, rounds;

@@ -1002,9 +1002,11 @@ __device__ __forceinline__ int load_count(const int* p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// f: rounds 0 .. f-1 ran over the whole grid; the tail re-tests round f-1's
+// touched cells and runs rounds f .. rounds-1.
 template <typename R, bool MULTI, int KC>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const SysParam* __restrict__ sp,
-                                                       DevState* st, int rounds, int max_items)
+                                                       DevState* st, int rounds, int max_items, int f)
 {
     constexpr size_t kRepBytes =
         (size_t)TAIL_WAVES * (RP_TAIL * (2 * sizeof(double) + 2 * sizeof(int)) + 2 * (KMAX + 1) * sizeof(int));
@@ -1036,11 +1038,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
 
     int exact = 0, nrep = 0;
     {
-        // round 0 re-test, shared by the grid; failures go to round 1
-        const int nt = st->tl_count[0];
-        const int* __restrict__ tl = w.tl[0];
+        // re-test of round f-1, shared by the grid; failures go to round f
+        const int nt = st->tl_count[f - 1];
+        const int* __restrict__ tl = w.tl[(f - 1) & 1];
         for (int base = blockIdx.x * TAIL_CPB; base < nt; base += gridDim.x * TAIL_CPB)
-            geom_pass<R, MULTI, KC, true, true>(c, w, sp, st, base, nt, tl, 1, S, exact);
+            geom_pass<R, MULTI, KC, true, true>(c, w, sp, st, base, nt, tl, f, S, exact);
     }
     __shared__ int s_last;
     __syncthreads();
@@ -1058,18 +1060,20 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
     __shared__ int s_w0, s_w1, s_err;
     if (threadIdx.x == 0) {
         st->done = 0;
-        s_w0 = load_count(&st->wl_count[0]);
-        s_w1 = load_count(&st->wl_count[1]);
+        int u = 0;
+        for (int v = 0; v < f; v++) u += load_count(&st->wl_count[v]) > 0 ? 1 : 0;
+        s_w0 = u;  // full-grid rounds that had work
+        s_w1 = load_count(&st->wl_count[f]);
         s_err = (int)__hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    int used = s_w0 > 0 ? 1 : 0;
-    int r = 1, halt_at = -1;
+    int used = s_w0;
+    int r = f, halt_at = -1;
     double drift = 0.0;
     for (; r < rounds; r++) {
-        const int nw = r == 1 ? s_w1 : load_count(&st->wl_count[r]);
+        const int nw = r == f ? s_w1 : load_count(&st->wl_count[r]);
         if (nw == 0) break;
-        if (r == 1) drift = st->drift;
+        if (r == f) drift = st->drift;
         if (nw > max_items) {
             halt_at = r;
             break;
@@ -1094,14 +1098,14 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
             geom_pass<R, MULTI, KC, true, true>(c, w, sp, st, base, nt, tl, r + 1, S, exact);
         __syncthreads();
     }
-    if (halt_at < 0 && r == rounds && (rounds == 1 ? s_w1 : load_count(&st->wl_count[rounds])) > 0)
+    if (halt_at < 0 && r == rounds && (rounds == f ? s_w1 : load_count(&st->wl_count[rounds])) > 0)
         halt_at = rounds;
     if ((threadIdx.x & 63) == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
     __syncthreads();
     if (threadIdx.x != 0) return;
     atomicAdd(&st->rounds, (unsigned long long)used);  // statistics: no read-back
-    const bool tail_ran = used > (s_w0 > 0 ? 1 : 0);
+    const bool tail_ran = used > s_w0;
     if (halt_at >= 0 || s_err ||
         (tail_ran && __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
         st->halt = 1;
@@ -1279,7 +1283,10 @@ __global__ void k_gather(Cells<R> src, Cells<R> dst, const int* perm, const int*
 {
     if (st->halt) return;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) st->drift = 0.0;
+    if (p == 0) {
+        st->last_drift = st->drift;
+        st->drift = 0.0;
+    }
     if (p >= N) return;
     const int i = perm[p];
     dst.x[p] = src.x[i];

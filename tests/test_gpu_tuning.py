@@ -43,6 +43,8 @@ KNOB_CASES = [
     dict(device_rounds=1),                    # every later round on the host
     dict(tail_items=1),                       # the tail hands most rounds to the host
     dict(device_rounds=16, tail_items=4096),  # the tail takes everything
+    dict(full_rounds=2),                      # two full-grid rounds before the tail
+    dict(full_rounds=4, device_rounds=3),     # full-grid rounds capped by the device rounds
 ]
 
 
@@ -71,7 +73,7 @@ def test_autotune_trials_cache_and_results(spv, tmp_path, monkeypatch):
     assert t2["source"] == 2 and t2["ms_per_step"] > 0.0
     assert t2["bin_factor"] in (1.0, 1.5, 2.0)
     assert t2["repair_cells"] in (16, 64, 256) and t2["device_rounds"] in (2, 4, 8)
-    assert t2["tail_items"] in (16, 64, 256)
+    assert t2["tail_items"] in (16, 64, 256) and t2["full_rounds"] in (1, 2)
     assert t2["resort_every"] in (16, 32, 64)
     for u, v in zip(ref, tuned):
         assert np.array_equal(u, v)
@@ -83,7 +85,7 @@ def test_autotune_trials_cache_and_results(spv, tmp_path, monkeypatch):
     # a second handle of the same size class reads the cache, runs no trial
     cached, t1 = _run(spv, x, y, L, 50, autotune=1)
     assert t1["source"] == 1
-    knobs = ("resort_every", "device_rounds", "repair_cells", "tail_items", "bin_factor")
+    knobs = ("resort_every", "device_rounds", "repair_cells", "tail_items", "full_rounds", "bin_factor")
     assert {k: t1[k] for k in knobs} == {k: t2[k] for k in knobs}
     for u, v in zip(ref, cached):
         assert np.array_equal(u, v)
