@@ -185,16 +185,21 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     // the update of cell iu (first CPB threads): its state, director
     // trigonometry and noise are computed up front, under the latency of the
     // neighbour gathers below
+    // (parked in LDS, not registers: the body keeps its occupancy)
     const int iu = xcd_block(blockIdx.x, gridDim.x) * CPB + (int)threadIdx.x;
     const bool upd = UPDATE && threadIdx.x < CPB && iu < N;
-    double xu = 0.0, yu = 0.0, thu = 0.0, nzu = 0.0, snu = 0.0, csu = 1.0;
+    __shared__ double sU0[UPDATE ? CPB : 1][6];  // x, y, theta, noise, sin, cos of the update cell
     if (upd) {
         const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
-        xu = c.x[iu];
-        yu = c.y[iu];
-        thu = c.th[iu];
-        nzu = normal_for(Q.seed, st->step, (uint64_t)c.tag[iu]);
-        sincos(thu, &snu, &csu);
+        const double th0 = c.th[iu];
+        double sn0, cs0;
+        sincos(th0, &sn0, &cs0);
+        sU0[threadIdx.x][0] = c.x[iu];
+        sU0[threadIdx.x][1] = c.y[iu];
+        sU0[threadIdx.x][2] = th0;
+        sU0[threadIdx.x][3] = normal_for(Q.seed, st->step, (uint64_t)c.tag[iu]);
+        sU0[threadIdx.x][4] = sn0;
+        sU0[threadIdx.x][5] = cs0;
     }
 
     // slot m of this lane: displacements d_m, d_{m+1} (the next slot's ring
@@ -305,7 +310,8 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     if (upd) {
         const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
         const double Fx = sF[threadIdx.x][0], Fy = sF[threadIdx.x][1];
-        const double sn = snu, cs = csu;
+        const double xu = sU0[threadIdx.x][0], yu = sU0[threadIdx.x][1], thu = sU0[threadIdx.x][2];
+        const double nzu = sU0[threadIdx.x][3], sn = sU0[threadIdx.x][4], cs = sU0[threadIdx.x][5];
         const double xn = xu + Q.dt * (Q.mu * Fx + Q.v0 * cs);
         const double yn = yu + Q.dt * (Q.mu * Fy + Q.v0 * sn);
         double X = rint(xn * Q.scale), Y = rint(yn * Q.scale);
