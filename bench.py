@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 vector
 
 # Algorithmic HBM bytes per cell per launch (FP64, mean ring length 6;
 # neighbour gathers served by cache).  See the design doc.
@@ -41,6 +42,13 @@ BYTES_PER_CELL = {
 # geometry section (constants, helpers, the force kernel).
 MEASURED_TRAFFIC = {
     "force_update": {"bytes": 20.66e6, "source_sha256": "0ddeb082e9e143277f6ee7ad4bef0bde7c6bbfa440f47a36b4fc70315e8ace18"},
+}
+
+# FP64 FLOPs per launch of the force kernel at N = 1e5 from the rocprofv3
+# SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters ((2 FMA + ADD + MUL) x 64 lanes;
+# profiles/), valid for the same source digest as the traffic.
+MEASURED_FP64_FLOPS = {
+    "force_update": {"flops": 246.4e6, "source_sha256": "2a94b7f0568fcc4a6b1efbc61c82ef742a508fd637eaf83c5f789452d64a2e64"},
 }
 
 
@@ -208,6 +216,17 @@ def adjoint_cost(spv, inputs):
             "traj_backward_ms": (t2 - t1) * 1e3, "adjoint_over_forward": (t2 - t0) / t_plain}
 
 
+def alu_roofline(dom, avg_s):
+    """The same kernel against the FP64 vector peak, from its counted FP64
+    operations (None when the counters predate the kernel's source)."""
+    mf = MEASURED_FP64_FLOPS.get(dom)
+    if not mf or mf["source_sha256"] != force_source_digest() or avg_s <= 0:
+        return None
+    tf = mf["flops"] / avg_s / 1e12
+    return {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
+            "flops_per_launch": mf["flops"]}
+
+
 def roofline_of(kt, ncells):
     dom = max(("force_update", "geometry_test"), key=lambda k: kt[k][0])
     ms, launches = kt[dom]
@@ -268,6 +287,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
+        "roofline_fp64_alu": alu_roofline(dom, avg_s),
         "kernels_ms_total": {k: v[0] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "steady_state_value": head["steady_value"],
