@@ -41,14 +41,14 @@ BYTES_PER_CELL = {
 # the digest covers the shared device header and the kernel file up to the
 # geometry section (constants, helpers, the force kernel).
 MEASURED_TRAFFIC = {
-    "force_update": {"bytes": 20.66e6, "source_sha256": "0ddeb082e9e143277f6ee7ad4bef0bde7c6bbfa440f47a36b4fc70315e8ace18"},
+    "force_update": {"bytes": 20.66e6, "source_sha256": "2a94b7f0568fcc4a6b1efbc61c82ef742a508fd637eaf83c5f789452d64a2e64"},
 }
 
 # FP64 FLOPs per launch of the force kernel at N = 1e5 from the rocprofv3
 # SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters ((2 FMA + ADD + MUL) x 64 lanes;
 # profiles/), valid for the same source digest as the traffic.
 MEASURED_FP64_FLOPS = {
-    "force_update": {"flops": 246.4e6, "source_sha256": "2a94b7f0568fcc4a6b1efbc61c82ef742a508fd637eaf83c5f789452d64a2e64"},
+    "force_update": {"flops": 246.3e6, "source_sha256": "2a94b7f0568fcc4a6b1efbc61c82ef742a508fd637eaf83c5f789452d64a2e64"},
 }
 
 
