@@ -73,6 +73,24 @@ __device__ __forceinline__ void unit(R ex, R ey, R& tx, R& ty)
     }
 }
 
+// Unit vector of a Voronoi edge from its dual Delaunay edge: the edge runs
+// along the perpendicular (px, py) of the Delaunay edge, so its direction is
+// taken from the exact displacements rather than from the difference (dx, dy)
+// of two nearly equal rounded vertices (which loses all relative accuracy on
+// short edges); a zero-length edge (exact T1 configuration) keeps a zero
+// vector, as the difference-based form gives.
+template <typename R>
+__device__ __forceinline__ void edge_unit(R dx, R dy, R px, R py, R& tx, R& ty)
+{
+    if (dx == R(0) && dy == R(0)) {
+        tx = ty = R(0);
+        return;
+    }
+    const R r = fast_rsqrt(px * px + py * py);
+    tx = px * r;
+    ty = py * r;
+}
+
 // In-circle with lazily loaded tags (the tie-break almost never runs).
 __device__ __forceinline__ int incircle_tags(double bx, double by, double cx, double cy, double px, double py,
                                              const int* tag, int gi, int gb, int gc, int gp, double scale,
@@ -251,9 +269,18 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
             const R hcx = sH[g][m][0], hcy = sH[g][m][1];
             const R hnx = sH[g][mn][0], hny = sH[g][mn][1];
             R t1x, t1y, t2x, t2y, t3x, t3y;
-            unit(hcx - hpx, hcy - hpy, t1x, t1y);
-            unit(hnx - hcx, hny - hcy, t2x, t2y);
-            unit(qxs[s] - hcx, qys[s] - hcy, t3x, t3y);
+            if constexpr (sizeof(R) == 4) {
+                // FP32: directions from the dual Delaunay edges d_m, d_{m+1}
+                // (counter-clockwise perpendiculars) and d_{m+1} - d_m
+                // (clockwise perpendicular: away from the cell)
+                edge_unit(hcx - hpx, hcy - hpy, -bys[s], bxs[s], t1x, t1y);
+                edge_unit(hnx - hcx, hny - hcy, -cys[s], cxs[s], t2x, t2y);
+                edge_unit(qxs[s] - hcx, qys[s] - hcy, cys[s] - bys[s], bxs[s] - cxs[s], t3x, t3y);
+            } else {
+                unit(hcx - hpx, hcy - hpy, t1x, t1y);
+                unit(hnx - hcx, hny - hcy, t2x, t2y);
+                unit(qxs[s] - hcx, qys[s] - hcy, t3x, t3y);
+            }
             const R am = ams[s], bm = bms[s], an = ans[s], bn = bns[s];
             const R qx = qxs[s], qy = qys[s];
             R gx = ai * R(0.5) * (hny - hpy) + bi * (t1x - t2x);

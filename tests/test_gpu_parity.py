@@ -354,7 +354,7 @@ def test_mixed_precision_forces_and_topology(spv):
     l2 = np.sqrt((dF ** 2).sum() / (F ** 2).sum())
     print(f"mixed precision: max|dF|/scale = {rel:.3e}, |dF|_2/|F|_2 = {l2:.3e}, p99.9 = "
           f"{np.quantile(dF, 0.999) / scale:.3e}")
-    assert rel < 1e-4 and l2 < 1e-5
+    assert rel < 2e-5 and l2 < 5e-6
     A, P = oracle.geometry(gx, gy, Lx, Ly, off, ring)
     gA, gP = s.geometry()
     assert np.abs(gA - A).max() < 1e-5 and np.abs(gP - P).max() < 1e-5
