@@ -982,23 +982,6 @@ spv_params with_knobs(spv_params p, const Knobs& k)
     return p;
 }
 
-// knobs that need no new allocation: the captured graphs depend on them
-spv_status set_runtime_knobs(spv_sys* s, const Knobs& k)
-{
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    for (int g = 0; g < 2; g++)
-        if (s->gexec[g]) {
-            (void)hipGraphExecDestroy(s->gexec[g]);
-            s->gexec[g] = nullptr;
-        }
-    s->unit = k.resort_every + (k.resort_every & 1);
-    s->dev_rounds = std::min(k.device_rounds, s->max_rounds);
-    s->repair_cells = k.repair_cells;
-    s->tail_items = k.tail_items;
-    s->full_rounds = k.full_rounds;
-    return SPV_OK;
-}
-
 // Start a period, run one (captures and replays its graph), then time
 // `steps` steps; steps is a multiple of every candidate period.
 spv_status trial_ms(spv_sys* s, int steps, double* ms)
@@ -1033,11 +1016,11 @@ spv_status tune_key_for(const CreateArgs& a, std::string& key)
     return SPV_OK;
 }
 
-// The search: warm a clone for 64 steps from the input, then, from that
-// state, pick the bin side (a clone per candidate), and on the best clone the
-// repair grid, the device repair budget and the re-sort period, one at a
-// time.  Each knob's candidates are timed right after a fresh time of the
-// current choice, and a candidate replaces it only when 3% faster.
+// The search: warm a clone for 64 steps from the input; from that state,
+// time the bin side, then the repair grid, the tail's largest round, the
+// full-grid rounds, the device repair budget and the re-sort period, one
+// knob at a time, each candidate on a fresh clone of the warmed state; a
+// candidate replaces the current choice only when 3% faster.
 spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
 {
     constexpr int kWarm = 64, kTrial = 128;  // kTrial: a multiple of every candidate period
@@ -1055,23 +1038,30 @@ spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
     destroy_all(w);
     ST_TRY(st);
 
-    // bin side: the bins are allocated at creation, so one clone each
-    spv_sys* cur = nullptr;
+    // every candidate is timed on a fresh clone of the same warmed state (the
+    // same dynamics, the same repairs): only the knobs differ between trials
+    const int maxr = a.prm.repair_rounds > 0 ? std::min(a.prm.repair_rounds, MAX_ROUNDS) : 16;
+    auto time_knobs = [&](const Knobs& k, double* ms) {
+        *ms = INFINITY;
+        spv_sys* c = nullptr;
+        if (build_handle(b, with_knobs(b.prm, k), &c) != SPV_OK) return false;
+        const bool ok = trial_ms(c, kTrial, ms) == SPV_OK;
+        destroy_all(c);
+        return ok;
+    };
+    bool any = false;
     best_ms = INFINITY;
     for (double f : {1.0, 1.5, 2.0}) {
         Knobs k = best;
         k.bin_factor = f;
-        spv_sys* c = nullptr;
-        double ms = INFINITY;
-        if (build_handle(b, with_knobs(b.prm, k), &c) != SPV_OK) continue;
-        if (trial_ms(c, kTrial, &ms) == SPV_OK && (!cur || ms < kMargin * best_ms)) {
-            std::swap(c, cur);
+        double ms;
+        if (time_knobs(k, &ms) && (!any || ms < kMargin * best_ms)) {
             best = k;
             best_ms = ms;
+            any = true;
         }
-        if (c) destroy_all(c);
     }
-    if (!cur) return fail(SPV_EHIP, "autotune: no trial ran");
+    if (!any) return fail(SPV_EHIP, "autotune: no trial ran");
 
     struct Axis {
         int Knobs::*field;
@@ -1083,27 +1073,22 @@ spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
                          {&Knobs::device_rounds, {2, 4, 8}},
                          {&Knobs::resort_every, {16, 32, 64}}};
     for (const Axis& ax : axes) {
-        if (set_runtime_knobs(cur, best) != SPV_OK || trial_ms(cur, kTrial, &best_ms) != SPV_OK) break;
         Knobs choice = best;
         double choice_ms = best_ms;
         for (int v : ax.cand) {
             if (v == best.*ax.field) continue;
             Knobs k = best;
             k.*ax.field = v;
-            if (k.device_rounds > cur->max_rounds) continue;
-            double ms = INFINITY;
-            if (set_runtime_knobs(cur, k) != SPV_OK) break;
-            if (trial_ms(cur, kTrial, &ms) != SPV_OK) break;
-            if (ms < kMargin * best_ms && ms < choice_ms) {
+            if (k.device_rounds > maxr || k.full_rounds > k.device_rounds) continue;
+            double ms;
+            if (time_knobs(k, &ms) && ms < kMargin * best_ms && ms < choice_ms) {
                 choice = k;
                 choice_ms = ms;
             }
         }
         best = choice;
         best_ms = choice_ms;
-        if (cur->sticky != SPV_OK) break;
     }
-    destroy_all(cur);
     return SPV_OK;
 }
 
