@@ -212,7 +212,7 @@ spv_status spv_load_state(spv_sys* s, const void* buf, int64_t len);
 
 /*
  * Scheduling knobs of a handle.  With spv_params.autotune set, creation first
- * runs the tuner: a clone of the input is stepped 64 steps from the given
+ * runs the tuner: a clone of the input is stepped 256 steps from the given
  * state, then clones of that state are timed over whole re-sort periods for
  * each candidate bin side, repair grid, device repair budget and re-sort
  * period (one knob at a time, each against a fresh time of the current best).

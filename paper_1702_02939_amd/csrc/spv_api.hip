@@ -1016,14 +1016,14 @@ spv_status tune_key_for(const CreateArgs& a, std::string& key)
     return SPV_OK;
 }
 
-// The search: warm a clone for 64 steps from the input; from that state,
+// The search: warm a clone for 256 steps from the input; from that state,
 // time the bin side, then the repair grid, the tail's largest round, the
 // full-grid rounds, the device repair budget and the re-sort period, one
 // knob at a time, each candidate on a fresh clone of the warmed state; a
 // candidate replaces the current choice only when 3% faster.
 spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
 {
-    constexpr int kWarm = 64, kTrial = 128;  // kTrial: a multiple of every candidate period
+    constexpr int kWarm = 256, kTrial = 128;  // kTrial: a multiple of every candidate period
     const double kMargin = 0.97;
     spv_sys* w = nullptr;
     ST_TRY(build_handle(a, with_knobs(a.prm, best), &w));
