@@ -271,6 +271,8 @@ inline unsigned grid_for(int n, int block) { return (unsigned)std::max(1, (n + b
 
 // all-cell grid of the 8-lanes-per-cell kernels, padded to a multiple of 8 XCDs
 inline unsigned cell_grid(const spv_sys* s) { return (grid_for(s->N, CPB) + 7u) & ~7u; }
+// the force kernel's grid (its own cells per block), also padded
+inline unsigned force_grid(const spv_sys* s) { return (grid_for(s->N, force_cells_per_block(s->KC)) + 7u) & ~7u; }
 inline unsigned repair_grid(const spv_sys* s)
 {
     return (unsigned)std::min(std::max(s->N / s->repair_cells, 256), 4096);
@@ -322,10 +324,11 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
 {
     Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
     const unsigned cg = cell_grid(s), rg = repair_grid(s);
-    launch(ev ? &ev[0] : nullptr, k_force<R, MULTI, KC, true>, dim3(cg), dim3(256), st, cur, nxt.x, nxt.y, nxt.th,
+    launch(ev ? &ev[0] : nullptr, k_force<R, MULTI, KC, true>, dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
+           nxt.y, nxt.th,
            (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
     launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, s->work,
-           (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax, (int)cg);
+           (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax, (int)force_grid(s));
     // rounds 0 .. f-1 over the whole grid; the last one's re-test, later
     // rounds and the step's close in the tail
     const int f = std::min(s->full_rounds, s->dev_rounds);
@@ -1332,7 +1335,7 @@ void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_p
     Cells<double> ct = snap_cells(s, at_t);
     ct.ca = s->d_aq;
     ct.cb = s->d_bq;
-    hipLaunchKernelGGL((k_force<double, false, KC, false, true>), dim3(cell_grid(s)), dim3(256), 0, s->stream, ct,
+    hipLaunchKernelGGL((k_force<double, false, KC, false, true>), dim3(force_grid(s)), dim3(256), 0, s->stream, ct,
                        (double*)nullptr, (double*)nullptr, (double*)nullptr, lx, ly, (const SysParam*)s->d_sp,
                        s->d_st, N, s->d_blockmax);
     Cells<double> cp = snap_cells(s, at_prev);
@@ -1608,7 +1611,7 @@ spv_status spv_get_forces(spv_sys* s, double* fx, double* fy)
     if (!s || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
     dispatch(s, [&]<typename R, bool MULTI, int KC>() {
         Cells<R> c = cells<R>(s, s->cfg, s->pos & 1);
-        hipLaunchKernelGGL((k_force<R, MULTI, KC, false>), dim3(cell_grid(s)), dim3(256), 0, s->stream, c,
+        hipLaunchKernelGGL((k_force<R, MULTI, KC, false>), dim3(force_grid(s)), dim3(256), 0, s->stream, c,
                            (double*)nullptr, (double*)nullptr, (double*)nullptr, s->d_fx, s->d_fy, s->d_sp, s->d_st,
                            s->N, s->d_blockmax);
     });

@@ -12,11 +12,12 @@
 //                  their opposite vertices rebuilt and are re-tested; repeated
 //                  until no flag is raised (cf. the repeat-until-no-change rule
 //                  of Sec. II.D).
-// Streaming passes use GL = 8 lanes per cell: lane l handles ring slots
-// l, l + 8, ...; per-slot values (displacements, Voronoi vertices, unit edge
-// vectors, neighbour coefficients) are staged in LDS so that a slot can read
-// its ring neighbours m +- 1 for any ring length.  Rings are cell-major
-// [N][KC]; a cell's 8 lanes read one contiguous 32-byte row segment.
+// Streaming passes use a group of lanes per cell (8 in the geometry / test
+// passes, KC / 4 in the force pass): lane l handles ring slots l, l + GL,
+// ...; per-slot values (displacements, Voronoi vertices, unit edge vectors,
+// neighbour coefficients) are staged in LDS so that a slot can read its ring
+// neighbours m +- 1 for any ring length.  Rings are cell-major [N][KC]; a
+// cell's lanes read one contiguous row segment.
 // Every kernel first checks the device halt flag, so that a step whose
 // repair did not converge turns the rest of a captured graph into no-ops.
 #pragma once
@@ -25,8 +26,11 @@
 
 namespace spv {
 
-constexpr int GL = 8;          // lanes per cell in the streaming kernels
+constexpr int GL = 8;          // lanes per cell in the geometry / test kernels
 constexpr int CPB = 256 / GL;  // cells per 256-thread block
+// the force kernel: four ring slots per lane (KC / 4 lanes per cell)
+constexpr int force_lanes(int kc) { return kc / 4; }
+constexpr int force_cells_per_block(int kc) { return 256 / force_lanes(kc); }
 constexpr int RP_CAP = 1024;   // max candidate neighbours of one repaired cell
 
 // ---------------------------------------------------------------- helpers
@@ -187,6 +191,7 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
                                                double* __restrict__ fyo, const SysParam* __restrict__ sp,
                                                DevState* st, int N, double* __restrict__ blockmax)
 {
+    constexpr int GL = force_lanes(KC), CPB = force_cells_per_block(KC);  // (this kernel's own)
     constexpr int NS = KC / GL;
     __shared__ R sH[CPB][KC][2];  // Voronoi vertex m (frame of the cell)
     if (st->halt) return;
@@ -324,8 +329,8 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
         }
         return;
     }
-    // the update (noise, trigonometry) runs on the first CPB threads -- one
-    // half-wave per block -- instead of one lane per 8-lane group
+    // the update runs on the first CPB threads (at most one wavefront) --
+    // one thread per cell instead of one lane per lane group
     __shared__ double sF[CPB][2];
     if (l == 0) {
         sF[g][0] = (double)fx;
