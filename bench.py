@@ -41,14 +41,14 @@ BYTES_PER_CELL = {
 # the digest covers the shared device header and the kernel file up to the
 # geometry section (constants, helpers, the force kernel).
 MEASURED_TRAFFIC = {
-    "force_update": {"bytes": 20.66e6, "source_sha256": "2a94b7f0568fcc4a6b1efbc61c82ef742a508fd637eaf83c5f789452d64a2e64"},
+    "force_update": {"bytes": 20.69e6, "source_sha256": "8dc1c6ada509d166c1c82aafb182f344f3613f8c31f95edbdba6ed3321a193bc"},
 }
 
 # FP64 FLOPs per launch of the force kernel at N = 1e5 from the rocprofv3
 # SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters ((2 FMA + ADD + MUL) x 64 lanes;
 # profiles/), valid for the same source digest as the traffic.
 MEASURED_FP64_FLOPS = {
-    "force_update": {"flops": 246.3e6, "source_sha256": "2a94b7f0568fcc4a6b1efbc61c82ef742a508fd637eaf83c5f789452d64a2e64"},
+    "force_update": {"flops": 218.6e6, "source_sha256": "8dc1c6ada509d166c1c82aafb182f344f3613f8c31f95edbdba6ed3321a193bc"},
 }
 
 
@@ -152,7 +152,8 @@ def single(spv, inputs, name, precision, p0=None, **knobs):
 def sweeps(spv, inputs, steps, warmup):
     """The paper's solid-to-fluid sweep (target shape index 3.8 / 3.9 / 4.0
     at v0 = 0.1, N = 1e5, FP64) and the re-sort interval ablation (Hilbert
-    order; 10 / 32 / 100 / 1000 steps between re-sorts) on spv_n100k."""
+    order; 10 / 32 / 100 / 1000 steps between re-sorts, and row-major bins at
+    32) on spv_n100k."""
     out = {"p0_sweep": {}, "resort_ablation": {}}
     for p0 in (3.8, 3.9, 4.0):
         r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, p0=p0), steps, warmup, timing=False)
@@ -162,6 +163,9 @@ def sweeps(spv, inputs, steps, warmup):
         r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, resort_every=every), steps, warmup,
                       timing=False)
         out["resort_ablation"][str(every)] = {"value": r["value"], "ms_per_step": r["ms_per_step"]}
+    r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, resort_every=32, bin_order=1), steps,
+                  warmup, timing=False)
+    out["resort_ablation"]["32_row_major_bins"] = {"value": r["value"], "ms_per_step": r["ms_per_step"]}
     return out
 
 

@@ -84,6 +84,8 @@ typedef struct {
                                (full-grid rounds) instead of the one-block tail (0: 64) */
     int32_t full_rounds;    /* repair rounds per step run over the whole grid before the tail takes
                                the rest (0: 1; at most 4) */
+    int32_t bin_order;      /* memory order of the cell-list bins (Sec. II.B spatial sorting):
+                               0 = Hilbert curve, 1 = row-major (for locality comparisons) */
     double bin_factor;      /* cell-list bin side in mean cell spacings sqrt(Lx Ly / N) (0: 1; 0.5..8) */
 } spv_params;
 

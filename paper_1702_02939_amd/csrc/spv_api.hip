@@ -663,7 +663,9 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
         while (n2 < std::max(P.nbx, P.nby)) n2 *= 2;
         std::vector<std::pair<int64_t, int>> key(nb);
         for (int by = 0; by < P.nby; by++)
-            for (int bx = 0; bx < P.nbx; bx++) key[by * P.nbx + bx] = {hilbert_index(n2, bx, by), by * P.nbx + bx};
+            for (int bx = 0; bx < P.nbx; bx++)
+                key[by * P.nbx + bx] = {s->prm.bin_order == 1 ? (int64_t)(by * P.nbx + bx) : hilbert_index(n2, bx, by),
+                                        by * P.nbx + bx};
         std::sort(key.begin(), key.end());
         hbinkey.resize(boff + nb);
         for (int r = 0; r < nb; r++) hbinkey[boff + key[r].second] = boff + r;
@@ -804,6 +806,7 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     s->bin_factor = p.bin_factor != 0.0 ? p.bin_factor : 1.0;
     if (!(s->bin_factor >= 0.5 && s->bin_factor <= 8.0)) return fail(SPV_EINVAL, "bin_factor must be in [0.5, 8]");
     if (p.autotune < 0 || p.autotune > 2) return fail(SPV_EINVAL, "autotune must be 0, 1 or 2");
+    if (p.bin_order < 0 || p.bin_order > 1) return fail(SPV_EINVAL, "bin_order must be 0 or 1");
     s->stream = (hipStream_t)stream;
     return SPV_OK;
 }
