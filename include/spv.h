@@ -75,7 +75,7 @@ typedef struct {
     int32_t repair_cells;   /* flagged cells per repair wavefront: the repair grid is N / repair_cells
                                blocks, clamped to [256, 4096] (0: 64) */
     int32_t autotune;       /* 0: use the scheduling knobs given here (resort_every, device_rounds,
-                               repair_cells, tail_items, full_rounds, bin_factor); 1: take them from the tuning cache for this
+                               repair_cells, tail_items, full_rounds, force_mode, bin_factor); 1: take them from the tuning cache for this
                                device and size class, else choose them by timed trial runs and cache
                                them; 2: always run the trials and refresh the cache.  The cache is the
                                JSON file named by the environment variable SPV_TUNE_CACHE, else held
@@ -86,12 +86,16 @@ typedef struct {
                                the rest (0: 1; at most 4) */
     int32_t bin_order;      /* memory order of the cell-list bins (Sec. II.B spatial sorting):
                                0 = Hilbert curve, 1 = row-major (for locality comparisons) */
+    int32_t force_mode;     /* force kernel (Eq. 2, App. A-B), bitwise the same result either way:
+                               1 = kcap/4 lanes per cell, 2 = one thread per (cell, ring slot);
+                               0 = 2 from 2^18 cells on, else 1 */
     double bin_factor;      /* cell-list bin side in mean cell spacings sqrt(Lx Ly / N) (0: 1; 0.5..8) */
 } spv_params;
 
 /* Scheduling knobs a handle runs with (see spv_params). */
 typedef struct {
     int32_t resort_every, device_rounds, repair_cells, tail_items, full_rounds;
+    int32_t force_mode;  /* the force kernel in use: 1 or 2 (see spv_params) */
     int32_t source;      /* 0: given in spv_params, 1: tuning cache, 2: timed trials */
     double bin_factor;
     double ms_per_step;  /* trial time per step of the chosen knobs (0 when source = 0) */

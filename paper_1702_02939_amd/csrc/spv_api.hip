@@ -125,6 +125,7 @@ struct spv_sys {
     int repair_cells = 64;  // repair grid = N / this (clamped to [256, 4096] blocks)
     int tail_items = 64;    // largest later round the one-block tail takes
     int full_rounds = 1;    // repair rounds over the whole grid before the tail
+    int force_mode = 0;     // force kernel: 1 lanes per cell, 2 per (cell, slot) item, 0 by size
     // adaptive re-sort: while cells move fast (the drift of a period exceeds
     // drift_limit, one bin side) steps run eagerly and re-sort as soon as
     // the drift passes the limit; a full quiet period returns to graphs
@@ -273,6 +274,17 @@ inline unsigned grid_for(int n, int block) { return (unsigned)std::max(1, (n + b
 inline unsigned cell_grid(const spv_sys* s) { return (grid_for(s->N, CPB) + 7u) & ~7u; }
 // the force kernel's grid (its own cells per block), also padded
 inline unsigned force_grid(const spv_sys* s) { return (grid_for(s->N, force_cells_per_block(s->KC)) + 7u) & ~7u; }
+// the force kernel of the handle (both give bitwise the same forces)
+constexpr int kItemsFromCells = 1 << 18;
+inline bool items_kernel(const spv_sys* s)
+{
+    return s->force_mode == 2 || (s->force_mode == 0 && s->N >= kItemsFromCells);
+}
+template <typename R, bool MULTI, int KC, bool UPDATE, bool ACC = false>
+auto force_kernel(const spv_sys* s)
+{
+    return items_kernel(s) ? k_force_items<R, MULTI, KC, UPDATE, ACC> : k_force_cells<R, MULTI, KC, UPDATE, ACC>;
+}
 inline unsigned repair_grid(const spv_sys* s)
 {
     return (unsigned)std::min(std::max(s->N / s->repair_cells, 256), 4096);
@@ -324,7 +336,7 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
 {
     Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
     const unsigned cg = cell_grid(s), rg = repair_grid(s);
-    launch(ev ? &ev[0] : nullptr, k_force<R, MULTI, KC, true>, dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
+    launch(ev ? &ev[0] : nullptr, force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
            nxt.y, nxt.th,
            (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
     launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, s->work,
@@ -622,6 +634,8 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
         P.Ly = P.LYu / P.scale;
         P.hLx = 0.5 * P.Lx;
         P.hLy = 0.5 * P.Ly;
+        P.iLx = 1.0 / P.Lx;
+        P.iLy = 1.0 / P.Ly;
         P.mu = s->prm.mu;
         P.v0 = v.v0;
         P.dt = s->prm.dt;
@@ -802,11 +816,13 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     if (p.tail_items < 0 || p.full_rounds < 0) return fail(SPV_EINVAL, "negative scheduling knob");
     s->tail_items = p.tail_items > 0 ? p.tail_items : 64;
     s->full_rounds = p.full_rounds > 0 ? p.full_rounds : 1;
-    if (s->full_rounds > 4) return fail(SPV_EINVAL, "full_rounds must be at most 4");
+    if (s->full_rounds > MAX_FULL_ROUNDS) return fail(SPV_EINVAL, "full_rounds must be at most 4");
     s->bin_factor = p.bin_factor != 0.0 ? p.bin_factor : 1.0;
     if (!(s->bin_factor >= 0.5 && s->bin_factor <= 8.0)) return fail(SPV_EINVAL, "bin_factor must be in [0.5, 8]");
     if (p.autotune < 0 || p.autotune > 2) return fail(SPV_EINVAL, "autotune must be 0, 1 or 2");
     if (p.bin_order < 0 || p.bin_order > 1) return fail(SPV_EINVAL, "bin_order must be 0 or 1");
+    if (p.force_mode < 0 || p.force_mode > 2) return fail(SPV_EINVAL, "force_mode must be 0, 1 or 2");
+    s->force_mode = p.force_mode;
     s->stream = (hipStream_t)stream;
     return SPV_OK;
 }
@@ -973,7 +989,7 @@ spv_status build_handle(const CreateArgs& a, const spv_params& p, spv_sys** out)
 
 Knobs knobs_of(const spv_sys* s)
 {
-    return {s->unit, s->dev_rounds, s->repair_cells, s->tail_items, s->full_rounds, s->bin_factor};
+    return {s->unit, s->dev_rounds, s->repair_cells, s->tail_items, s->full_rounds, s->force_mode, s->bin_factor};
 }
 
 spv_params with_knobs(spv_params p, const Knobs& k)
@@ -983,6 +999,7 @@ spv_params with_knobs(spv_params p, const Knobs& k)
     p.repair_cells = k.repair_cells;
     p.tail_items = k.tail_items;
     p.full_rounds = k.full_rounds;
+    p.force_mode = k.force_mode;
     p.bin_factor = k.bin_factor;
     p.autotune = 0;
     return p;
@@ -1076,6 +1093,7 @@ spv_status run_trials(const CreateArgs& a, Knobs& best, double& best_ms)
     const Axis axes[] = {{&Knobs::repair_cells, {16, 64, 256}},
                          {&Knobs::tail_items, {16, 64, 256}},
                          {&Knobs::full_rounds, {1, 2, 1}},
+                         {&Knobs::force_mode, {1, 2, 1}},
                          {&Knobs::device_rounds, {2, 4, 8}},
                          {&Knobs::resort_every, {16, 32, 64}}};
     for (const Axis& ax : axes) {
@@ -1338,7 +1356,7 @@ void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_p
     Cells<double> ct = snap_cells(s, at_t);
     ct.ca = s->d_aq;
     ct.cb = s->d_bq;
-    hipLaunchKernelGGL((k_force<double, false, KC, false, true>), dim3(force_grid(s)), dim3(256), 0, s->stream, ct,
+    hipLaunchKernelGGL((force_kernel<double, false, KC, false, true>(s)), dim3(force_grid(s)), dim3(256), 0, s->stream, ct,
                        (double*)nullptr, (double*)nullptr, (double*)nullptr, lx, ly, (const SysParam*)s->d_sp,
                        s->d_st, N, s->d_blockmax);
     Cells<double> cp = snap_cells(s, at_prev);
@@ -1559,6 +1577,7 @@ spv_status spv_get_tuning(spv_sys* s, spv_tuning* out)
     out->repair_cells = s->repair_cells;
     out->tail_items = s->tail_items;
     out->full_rounds = s->full_rounds;
+    out->force_mode = items_kernel(s) ? 2 : 1;
     out->source = s->tune_source;
     out->bin_factor = s->bin_factor;
     out->ms_per_step = s->tune_ms;
@@ -1614,7 +1633,7 @@ spv_status spv_get_forces(spv_sys* s, double* fx, double* fy)
     if (!s || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
     dispatch(s, [&]<typename R, bool MULTI, int KC>() {
         Cells<R> c = cells<R>(s, s->cfg, s->pos & 1);
-        hipLaunchKernelGGL((k_force<R, MULTI, KC, false>), dim3(force_grid(s)), dim3(256), 0, s->stream, c,
+        hipLaunchKernelGGL((force_kernel<R, MULTI, KC, false>(s)), dim3(force_grid(s)), dim3(256), 0, s->stream, c,
                            (double*)nullptr, (double*)nullptr, (double*)nullptr, s->d_fx, s->d_fy, s->d_sp, s->d_st,
                            s->N, s->d_blockmax);
     });

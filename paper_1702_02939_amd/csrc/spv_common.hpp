@@ -20,6 +20,7 @@ constexpr int MAX_ROUNDS = 32;  // repair rounds per step (device rounds + host 
 // one after the other; a single system is a batch of one).
 struct SysParam {
     double Lx, Ly, hLx, hLy;  // box (on the grid) and half box
+    double iLx, iLy;          // 1 / Lx, 1 / Ly
     double scale, inv_scale;  // 2^q and 2^-q
     double LXu, LYu;          // box in grid units (exact doubles)
     double bsx, bsy;          // bin sides
@@ -88,6 +89,16 @@ struct Work {
 __device__ __forceinline__ double mimg(double d, double L, double hL)
 {
     return d > hL ? d - L : (d < -hL ? d + L : d);
+}
+
+// The same minimum image in three instructions, d - L rint(d / L), for a
+// displacement that is known to be short (a Delaunay neighbour: shorter than
+// L/2 by the periodic-validity precondition) or near +-L.  The product may
+// round, but only within an ulp of +-L/2 could that change the image; the
+// result d - kL (k in {-1, 0, 1}) is exact on the position grid.
+__device__ __forceinline__ double mimg_near(double d, double L, double iL)
+{
+    return fma(-L, rint(d * iL), d);
 }
 
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of

@@ -28,29 +28,37 @@ namespace spv {
 
 constexpr int GL = 8;          // lanes per cell in the geometry / test kernels
 constexpr int CPB = 256 / GL;  // cells per 256-thread block
-// the force kernel: four ring slots per lane (KC / 4 lanes per cell)
+// the force kernels: kcap/4 lanes per cell (four ring slots each), so a
+// 256-thread block holds 1024/kcap cells and at most 1024 (cell, slot) items
 constexpr int force_lanes(int kc) { return kc / 4; }
 constexpr int force_cells_per_block(int kc) { return 256 / force_lanes(kc); }
 constexpr int RP_CAP = 1024;   // max candidate neighbours of one repaired cell
 
 // ---------------------------------------------------------------- helpers
 
+// The geometry and force arithmetic below fixes its own fused multiply-adds
+// (explicit fma, no automatic contraction): its rounding then does not depend
+// on the code it is inlined into, and the two force kernels agree bitwise.
+
 // FP64 reciprocal and reciprocal square root: the hardware estimate refined
 // by two Newton steps (about 1 ulp; only non-degenerate arguments are
 // meaningful: a zero denominator belongs to a triangle already flagged)
 __device__ __forceinline__ double fast_rcp(double d)
 {
+#pragma clang fp contract(off)
     double r = __builtin_amdgcn_rcp(d);
-    r = r * (2.0 - d * r);
-    r = r * (2.0 - d * r);
+    r = r * fma(-d, r, 2.0);
+    r = r * fma(-d, r, 2.0);
     return r;
 }
 __device__ __forceinline__ float fast_rcp(float d) { return 1.0f / d; }
 __device__ __forceinline__ double fast_rsqrt(double x)
 {
+#pragma clang fp contract(off)
+    const double hx = 0.5 * x;
     double y = __builtin_amdgcn_rsq(x);
-    y = y * (1.5 - 0.5 * x * y * y);
-    y = y * (1.5 - 0.5 * x * y * y);
+    y = y * fma(-hx, y * y, 1.5);
+    y = y * fma(-hx, y * y, 1.5);
     return y;
 }
 __device__ __forceinline__ float fast_rsqrt(float x) { return 1.0f / sqrtf(x); }
@@ -58,16 +66,18 @@ __device__ __forceinline__ float fast_rsqrt(float x) { return 1.0f / sqrtf(x); }
 template <typename R>
 __device__ __forceinline__ void circumcentre(R bx, R by, R cx, R cy, R& ux, R& uy)
 {
-    const R nb = bx * bx + by * by, nc = cx * cx + cy * cy;
-    const R inv = R(0.5) * fast_rcp(bx * cy - by * cx);
-    ux = (cy * nb - by * nc) * inv;
-    uy = (bx * nc - cx * nb) * inv;
+#pragma clang fp contract(off)
+    const R nb = fma(bx, bx, by * by), nc = fma(cx, cx, cy * cy);
+    const R inv = R(0.5) * fast_rcp(fma(bx, cy, -(by * cx)));
+    ux = fma(cy, nb, -(by * nc)) * inv;
+    uy = fma(bx, nc, -(cx * nb)) * inv;
 }
 
 template <typename R>
 __device__ __forceinline__ void unit(R ex, R ey, R& tx, R& ty)
 {
-    const R l2 = ex * ex + ey * ey;
+#pragma clang fp contract(off)
+    const R l2 = fma(ex, ex, ey * ey);
     if (l2 > R(0)) {
         const R r = fast_rsqrt(l2);
         tx = ex * r;
@@ -86,11 +96,12 @@ __device__ __forceinline__ void unit(R ex, R ey, R& tx, R& ty)
 template <typename R>
 __device__ __forceinline__ void edge_unit(R dx, R dy, R px, R py, R& tx, R& ty)
 {
+#pragma clang fp contract(off)
     if (dx == R(0) && dy == R(0)) {
         tx = ty = R(0);
         return;
     }
-    const R r = fast_rsqrt(px * px + py * py);
+    const R r = fast_rsqrt(fma(px, px, py * py));
     tx = px * r;
     ty = py * r;
 }
@@ -183,15 +194,139 @@ __device__ __forceinline__ int xcd_block(int b, int grid)
 // dA_c = 1/2 (h+_y - h-_y, h-_x - h+_x) for the CCW neighbours (h-, h+) of h_m
 // in cell c, and F_i = -sum_m J_m^T g_m with the circumcentre Jacobian of
 // App. B (Eq. B4), read with s = b x c in the denominator and its gradient.
+//
+// Two kernels compute it, with bitwise the same result: k_force_cells gives
+// each cell kcap/4 lanes (four ring slots each), k_force_items gives each
+// thread whole (cell, slot) items from a prefix sum of the ring lengths, so
+// that no lane idles on slots a short ring lacks.  Both evaluate slot m with
+// slot_term and sum a cell's slots in the same order: lane l of the cell
+// subtracts slots l, l + GL, l + 2 GL, ... from zero, and the GL partial sums
+// are added pairwise as a butterfly over the lanes (offsets GL/2 .. 1).
 // ACC (with UPDATE = false): subtract the force from fxo / fyo instead of
 // storing it (adds the gradient of the energy-like functional to them).
-template <typename R, bool MULTI, int KC, bool UPDATE, bool ACC = false>
-__global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
-                                               double* __restrict__ tho, double* __restrict__ fxo,
-                                               double* __restrict__ fyo, const SysParam* __restrict__ sp,
-                                               DevState* st, int N, double* __restrict__ blockmax)
+
+// J_m^T g_m of slot m from b = d_m, c = d_{m+1}, the vertices h_{m-1}, h_m,
+// h_{m+1}, h'_m and the coefficients of i, j_m, j_{m+1}
+template <typename R>
+__device__ __forceinline__ void slot_term(R Bx, R By, R Cx, R Cy, R hpx, R hpy, R hcx, R hcy, R hnx, R hny, R qx,
+                                          R qy, R ai, R bi, R am, R bm, R an, R bn, R& vx, R& vy)
 {
-    constexpr int GL = force_lanes(KC), CPB = force_cells_per_block(KC);  // (this kernel's own)
+#pragma clang fp contract(off)
+    R t1x, t1y, t2x, t2y, t3x, t3y;
+    if constexpr (sizeof(R) == 4) {
+        // FP32: directions from the dual Delaunay edges d_m, d_{m+1}
+        // (counter-clockwise perpendiculars) and d_{m+1} - d_m
+        // (clockwise perpendicular: away from the cell)
+        edge_unit(hcx - hpx, hcy - hpy, -By, Bx, t1x, t1y);
+        edge_unit(hnx - hcx, hny - hcy, -Cy, Cx, t2x, t2y);
+        edge_unit(qx - hcx, qy - hcy, Cy - By, Bx - Cx, t3x, t3y);
+    } else {
+        unit(hcx - hpx, hcy - hpy, t1x, t1y);
+        unit(hnx - hcx, hny - hcy, t2x, t2y);
+        unit(qx - hcx, qy - hcy, t3x, t3y);
+    }
+    const R ai2 = ai * R(0.5), am2 = am * R(0.5), an2 = an * R(0.5);
+    R gx = fma(bi, t1x - t2x, ai2 * (hny - hpy));
+    R gy = fma(bi, t1y - t2y, ai2 * (hpx - hnx));
+    gx = gx + fma(bm, t1x - t3x, am2 * (hpy - qy));
+    gy = gy + fma(bm, t1y - t3y, am2 * (qx - hpx));
+    gx = gx + fma(bn, -t2x - t3x, an2 * (qy - hny));
+    gy = gy + fma(bn, -t2y - t3y, an2 * (hnx - qx));
+    // J_m^T g, b = d_m, c = d_{m+1}, e = c - b
+    const R ex = Cx - Bx, ey = Cy - By;
+    const R sc = fma(Bx, Cy, -(By * Cx));
+    const R be = fma(Bx, ex, By * ey), ce = fma(Cx, ex, Cy * ey);
+    const R nb = fma(Bx, Bx, By * By), nc = fma(Cx, Cx, Cy * Cy);
+    const R betaD = -nc * be, gammaD = nb * ce;
+    const R zx = fma(betaD, Bx, gammaD * Cx), zy = fma(betaD, By, gammaD * Cy);
+    const R be2 = R(2) * be, ce2 = R(-2) * ce;
+    const R gbx = fma(be2, Cx, nc * ex), gby = fma(be2, Cy, nc * ey);        // grad(beta D)
+    const R ggx = fma(ce2, Bx, -(nb * ex)), ggy = fma(ce2, By, -(nb * ey));  // grad(gamma D)
+    const R is = fast_rcp(sc);
+    const R is2 = R(2) * is;
+    const R gdx = is2 * (-ey), gdy = is2 * ex;  // grad(D) / D
+    const R invD = (R(0.5) * is) * is;          // 1 / (2 s^2)
+    const R gB = fma(gx, Bx, gy * By), gC = fma(gx, Cx, gy * Cy), gZ = fma(gx, zx, gy * zy);
+    const R bg = betaD + gammaD;
+    R X = fma(gB, gbx, gC * ggx), Y = fma(gB, gby, gC * ggy);
+    X = fma(-bg, gx, X);
+    Y = fma(-bg, gy, Y);
+    X = fma(-gZ, gdx, X);
+    Y = fma(-gZ, gdy, Y);
+    vx = fma(invD, X, gx);
+    vy = fma(invD, Y, gy);
+}
+
+// h'_m (frame of the cell): circumcentre of (j_m, opp_m, j_{m+1}), or h_m
+// itself when the edge has no opposite cell recorded
+template <typename R>
+__device__ __forceinline__ void opp_vertex(const Cells<R>& c, const SysParam& P, int o, double xi, double yi,
+                                           double dmx, double dmy, double dnx, double dny, R hcx, R hcy, R& qx,
+                                           R& qy)
+{
+    qx = hcx;
+    qy = hcy;
+    if (o >= 0) {
+        const double dox = mimg_near(c.x[o] - xi, P.Lx, P.iLx), doy = mimg_near(c.y[o] - yi, P.Ly, P.iLy);
+        R ux, uy;
+        circumcentre((R)(dox - dmx), (R)(doy - dmy), (R)(dnx - dmx), (R)(dny - dmy), ux, uy);
+        qx = ux + (R)dmx;
+        qy = uy + (R)dmy;
+    }
+}
+
+// Eq. 3 for one cell from its force and the values parked at kernel start
+// (x, y, theta, noise, sin, cos): the quantised, wrapped position, the
+// rotated director, and the displacement length returned
+__device__ __forceinline__ double update_cell(const SysParam& Q, const double* u0, double Fx, double Fy, int iu,
+                                              double* __restrict__ xo, double* __restrict__ yo,
+                                              double* __restrict__ tho, DevState* st)
+{
+    const double xu = u0[0], yu = u0[1], thu = u0[2], nzu = u0[3], sn = u0[4], cs = u0[5];
+    const double xn = xu + Q.dt * (Q.mu * Fx + Q.v0 * cs);
+    const double yn = yu + Q.dt * (Q.mu * Fy + Q.v0 * sn);
+    double X = rint(xn * Q.scale), Y = rint(yn * Q.scale);
+    if (X < 0.0) X += Q.LXu;
+    else if (X >= Q.LXu) X -= Q.LXu;
+    if (Y < 0.0) Y += Q.LYu;
+    else if (Y >= Q.LYu) Y -= Q.LYu;
+    if (!(X >= 0.0 && X < Q.LXu && Y >= 0.0 && Y < Q.LYu)) {
+        atomicOr(&st->err, ERR_NONFINITE);
+        X = rint(xu * Q.scale);  // keep the stored state finite and inside the box
+        Y = rint(yu * Q.scale);
+    }
+    const double xq = X * Q.inv_scale, yq = Y * Q.inv_scale;
+    xo[iu] = xq;
+    yo[iu] = yq;
+    tho[iu] = thu + Q.amp * nzu;
+    const double ddx = mimg(xq - xu, Q.Lx, Q.hLx), ddy = mimg(yq - yu, Q.Ly, Q.hLy);
+    return sqrt(ddx * ddx + ddy * ddy);
+}
+
+// x, y, theta, noise, sin, cos of the update of cell iu
+template <typename R, bool MULTI>
+__device__ __forceinline__ void park_update(const Cells<R>& c, const SysParam* __restrict__ sp, const DevState* st,
+                                            int iu, double* u0)
+{
+    const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
+    const double th0 = c.th[iu];
+    double sn0, cs0;
+    sincos(th0, &sn0, &cs0);
+    u0[0] = c.x[iu];
+    u0[1] = c.y[iu];
+    u0[2] = th0;
+    u0[3] = normal_for(Q.seed, st->step, (uint64_t)c.tag[iu]);
+    u0[4] = sn0;
+    u0[5] = cs0;
+}
+
+template <typename R, bool MULTI, int KC, bool UPDATE, bool ACC = false>
+__global__ __launch_bounds__(256) void k_force_cells(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
+                                                     double* __restrict__ tho, double* __restrict__ fxo,
+                                                     double* __restrict__ fyo, const SysParam* __restrict__ sp,
+                                                     DevState* st, int N, double* __restrict__ blockmax)
+{
+    constexpr int GL = force_lanes(KC), CPB = force_cells_per_block(KC);
     constexpr int NS = KC / GL;
     __shared__ R sH[CPB][KC][2];  // Voronoi vertex m (frame of the cell)
     if (st->halt) return;
@@ -207,27 +342,16 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     const R* __restrict__ cb = c.cb;
     // the update of cell iu (first CPB threads): its state, director
     // trigonometry and noise are computed up front, under the latency of the
-    // neighbour gathers below
-    // (parked in LDS, not registers: the body keeps its occupancy)
+    // neighbour gathers below (parked in LDS, not registers: the body keeps
+    // its occupancy)
     const int iu = xcd_block(blockIdx.x, gridDim.x) * CPB + (int)threadIdx.x;
     const bool upd = UPDATE && threadIdx.x < CPB && iu < N;
-    __shared__ double sU0[UPDATE ? CPB : 1][6];  // x, y, theta, noise, sin, cos of the update cell
-    if (upd) {
-        const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
-        const double th0 = c.th[iu];
-        double sn0, cs0;
-        sincos(th0, &sn0, &cs0);
-        sU0[threadIdx.x][0] = c.x[iu];
-        sU0[threadIdx.x][1] = c.y[iu];
-        sU0[threadIdx.x][2] = th0;
-        sU0[threadIdx.x][3] = normal_for(Q.seed, st->step, (uint64_t)c.tag[iu]);
-        sU0[threadIdx.x][4] = sn0;
-        sU0[threadIdx.x][5] = cs0;
-    }
+    __shared__ double sU0[UPDATE ? CPB : 1][6];
+    if (upd) park_update<R, MULTI>(c, sp, st, iu, sU0[threadIdx.x]);
 
     // slot m of this lane: displacements d_m, d_{m+1} (the next slot's ring
     // entry is read again from the same cache line rather than through LDS),
-    // coefficients of j_m and j_{m+1}, and the opposite cell of edge m
+    // coefficients of j_m and j_{m+1}, and the opposite vertex of edge m
     R bxs[NS], bys[NS], cxs[NS], cys[NS], ams[NS], bms[NS], ans[NS], bns[NS], qxs[NS], qys[NS];
 #pragma unroll
     for (int s = 0; s < NS; s++) {
@@ -236,8 +360,8 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
         if (m < k) {
             const int mn = (m + 1 == k) ? 0 : m + 1;
             const int jm = c.ring[ii * KC + m], jn = c.ring[ii * KC + mn], o = c.opp[ii * KC + m];
-            const double dmx = mimg(c.x[jm] - xi, P.Lx, P.hLx), dmy = mimg(c.y[jm] - yi, P.Ly, P.hLy);
-            const double dnx = mimg(c.x[jn] - xi, P.Lx, P.hLx), dny = mimg(c.y[jn] - yi, P.Ly, P.hLy);
+            const double dmx = mimg_near(c.x[jm] - xi, P.Lx, P.iLx), dmy = mimg_near(c.y[jm] - yi, P.Ly, P.iLy);
+            const double dnx = mimg_near(c.x[jn] - xi, P.Lx, P.iLx), dny = mimg_near(c.y[jn] - yi, P.Ly, P.iLy);
             ams[s] = ca[jm];
             bms[s] = cb[jm];
             ans[s] = ca[jn];
@@ -250,16 +374,7 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
             circumcentre(bxs[s], bys[s], cxs[s], cys[s], hx, hy);
             sH[g][m][0] = hx;
             sH[g][m][1] = hy;
-            qxs[s] = hx;
-            qys[s] = hy;
-            if (o >= 0) {
-                // third vertex of edge (j_m, j_{m+1}): circumcentre of (j_m, opp_m, j_{m+1})
-                const double dox = mimg(c.x[o] - xi, P.Lx, P.hLx), doy = mimg(c.y[o] - yi, P.Ly, P.hLy);
-                R qx, qy;
-                circumcentre((R)(dox - dmx), (R)(doy - dmy), (R)(dnx - dmx), (R)(dny - dmy), qx, qy);
-                qxs[s] = qx + bxs[s];
-                qys[s] = qy + bys[s];
-            }
+            opp_vertex(c, P, o, xi, yi, dmx, dmy, dnx, dny, hx, hy, qxs[s], qys[s]);
         }
     }
     __syncthreads();
@@ -270,46 +385,11 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
         const int m = l + s * GL;
         if (m < k) {
             const int mn = (m + 1 == k) ? 0 : m + 1, mp = (m == 0) ? k - 1 : m - 1;
-            const R hpx = sH[g][mp][0], hpy = sH[g][mp][1];
-            const R hcx = sH[g][m][0], hcy = sH[g][m][1];
-            const R hnx = sH[g][mn][0], hny = sH[g][mn][1];
-            R t1x, t1y, t2x, t2y, t3x, t3y;
-            if constexpr (sizeof(R) == 4) {
-                // FP32: directions from the dual Delaunay edges d_m, d_{m+1}
-                // (counter-clockwise perpendiculars) and d_{m+1} - d_m
-                // (clockwise perpendicular: away from the cell)
-                edge_unit(hcx - hpx, hcy - hpy, -bys[s], bxs[s], t1x, t1y);
-                edge_unit(hnx - hcx, hny - hcy, -cys[s], cxs[s], t2x, t2y);
-                edge_unit(qxs[s] - hcx, qys[s] - hcy, cys[s] - bys[s], bxs[s] - cxs[s], t3x, t3y);
-            } else {
-                unit(hcx - hpx, hcy - hpy, t1x, t1y);
-                unit(hnx - hcx, hny - hcy, t2x, t2y);
-                unit(qxs[s] - hcx, qys[s] - hcy, t3x, t3y);
-            }
-            const R am = ams[s], bm = bms[s], an = ans[s], bn = bns[s];
-            const R qx = qxs[s], qy = qys[s];
-            R gx = ai * R(0.5) * (hny - hpy) + bi * (t1x - t2x);
-            R gy = ai * R(0.5) * (hpx - hnx) + bi * (t1y - t2y);
-            gx += am * R(0.5) * (hpy - qy) + bm * (t1x - t3x);
-            gy += am * R(0.5) * (qx - hpx) + bm * (t1y - t3y);
-            gx += an * R(0.5) * (qy - hny) + bn * (-t2x - t3x);
-            gy += an * R(0.5) * (hnx - qx) + bn * (-t2y - t3y);
-            // J_m^T g, b = d_m, c = d_{m+1}, e = c - b
-            const R Bx = bxs[s], By = bys[s], Cx = cxs[s], Cy = cys[s];
-            const R ex = Cx - Bx, ey = Cy - By;
-            const R sc = Bx * Cy - By * Cx;
-            const R be = Bx * ex + By * ey, ce = Cx * ex + Cy * ey;
-            const R nb = Bx * Bx + By * By, nc = Cx * Cx + Cy * Cy;
-            const R betaD = -nc * be, gammaD = nb * ce;
-            const R zx = betaD * Bx + gammaD * Cx, zy = betaD * By + gammaD * Cy;
-            const R gbx = R(2) * be * Cx + nc * ex, gby = R(2) * be * Cy + nc * ey;    // grad(beta D)
-            const R ggx = R(-2) * ce * Bx - nb * ex, ggy = R(-2) * ce * By - nb * ey;  // grad(gamma D)
-            const R is = fast_rcp(sc);
-            const R gdx = R(2) * is * (-ey), gdy = R(2) * is * ex;                     // grad(D) / D
-            const R invD = R(0.5) * is * is;                                           // 1 / (2 s^2)
-            const R gB = gx * Bx + gy * By, gC = gx * Cx + gy * Cy, gZ = gx * zx + gy * zy;
-            fx -= gx + invD * (gB * gbx + gC * ggx - (betaD + gammaD) * gx - gZ * gdx);
-            fy -= gy + invD * (gB * gby + gC * ggy - (betaD + gammaD) * gy - gZ * gdy);
+            R vx, vy;
+            slot_term(bxs[s], bys[s], cxs[s], cys[s], sH[g][mp][0], sH[g][mp][1], sH[g][m][0], sH[g][m][1],
+                      sH[g][mn][0], sH[g][mn][1], qxs[s], qys[s], ai, bi, ams[s], bms[s], ans[s], bns[s], vx, vy);
+            fx -= vx;
+            fy -= vy;
         }
     }
 #pragma unroll
@@ -339,33 +419,127 @@ __global__ __launch_bounds__(256) void k_force(Cells<R> c, double* __restrict__ 
     __syncthreads();
     if (threadIdx.x >= 64) return;
     double disp = 0.0;
-    if (upd) {
-        const SysParam& Q = sp[MULTI ? c.sys[iu] : 0];
-        const double Fx = sF[threadIdx.x][0], Fy = sF[threadIdx.x][1];
-        const double xu = sU0[threadIdx.x][0], yu = sU0[threadIdx.x][1], thu = sU0[threadIdx.x][2];
-        const double nzu = sU0[threadIdx.x][3], sn = sU0[threadIdx.x][4], cs = sU0[threadIdx.x][5];
-        const double xn = xu + Q.dt * (Q.mu * Fx + Q.v0 * cs);
-        const double yn = yu + Q.dt * (Q.mu * Fy + Q.v0 * sn);
-        double X = rint(xn * Q.scale), Y = rint(yn * Q.scale);
-        if (X < 0.0) X += Q.LXu;
-        else if (X >= Q.LXu) X -= Q.LXu;
-        if (Y < 0.0) Y += Q.LYu;
-        else if (Y >= Q.LYu) Y -= Q.LYu;
-        if (!(X >= 0.0 && X < Q.LXu && Y >= 0.0 && Y < Q.LYu)) {
-            atomicOr(&st->err, ERR_NONFINITE);
-            X = rint(xu * Q.scale);  // keep the stored state finite and inside the box
-            Y = rint(yu * Q.scale);
-        }
-        const double xq = X * Q.inv_scale, yq = Y * Q.inv_scale;
-        xo[iu] = xq;
-        yo[iu] = yq;
-        tho[iu] = thu + Q.amp * nzu;
-        const double ddx = mimg(xq - xu, Q.Lx, Q.hLx), ddy = mimg(yq - yu, Q.Ly, Q.hLy);
-        disp = sqrt(ddx * ddx + ddy * ddy);
-    }
+    if (upd)
+        disp = update_cell(sp[MULTI ? c.sys[iu] : 0], sU0[threadIdx.x], sF[threadIdx.x][0], sF[threadIdx.x][1], iu,
+                           xo, yo, tho, st);
     // block max of the displacement -> blockmax[block] (reduced by the all-cells geometry pass)
     for (int off = 32; off >= 1; off >>= 1) disp = fmax(disp, __shfl_xor(disp, off));
     if (threadIdx.x == 0) blockmax[blockIdx.x] = disp;
+}
+
+template <typename R, bool MULTI, int KC, bool UPDATE, bool ACC = false>
+__global__ __launch_bounds__(256) void k_force_items(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
+                                                     double* __restrict__ tho, double* __restrict__ fxo,
+                                                     double* __restrict__ fyo, const SysParam* __restrict__ sp,
+                                                     DevState* st, int N, double* __restrict__ blockmax)
+{
+    constexpr int GL = force_lanes(KC), CPB = force_cells_per_block(KC);
+    constexpr int ITEMS = CPB * KC;  // most items a block can hold
+    static_assert(CPB <= 64, "the first wavefront owns the cells of a block");
+    __shared__ uint16_t sMap[ITEMS];    // item -> cell | slot << 8
+    __shared__ R sF[ITEMS][2];          // the item's term of its cell's force
+    __shared__ int sOff[CPB], sK[CPB];  // first item and ring length of each cell
+    __shared__ int sItems;
+    __shared__ double sU0[UPDATE ? CPB : 1][6];
+    if (st->halt) return;
+    const int base = xcd_block(blockIdx.x, gridDim.x) * CPB;
+    const int t = threadIdx.x;
+    if (t < 64) {
+        // first wavefront: ring lengths, their prefix sum and the item map
+        const int i = base + t;
+        int k = (t < CPB && i < N) ? (int)c.deg[i] : 0;
+        if (k < 3 || k > KC) k = 0;  // reported by the validity test
+        int incl = k;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (t >= off) incl += v;
+        }
+        if (t < CPB) {
+            sOff[t] = incl - k;
+            sK[t] = k;
+            for (int m = 0; m < k; m++) sMap[incl - k + m] = (uint16_t)(t | m << 8);
+        }
+        if (t == 63) sItems = incl;
+    } else if (UPDATE && t >= 256 - CPB) {
+        // last wavefront (the fewest items): the update values of each cell,
+        // computed while the others gather
+        const int u = t - (256 - CPB);
+        if (base + u < N) park_update<R, MULTI>(c, sp, st, base + u, sU0[u]);
+    }
+    __syncthreads();
+    const int S = sItems;
+    const R* __restrict__ ca = c.ca;
+    const R* __restrict__ cb = c.cb;
+    // item (cell, slot m): the three Voronoi vertices around edge m are
+    // computed here from d_{m-1} .. d_{m+2} (no exchange between items)
+    for (int s = t; s < S; s += 256) {
+        const int e = sMap[s];
+        const int g = e & 0xff, m = e >> 8, k = sK[g];
+        const int i = base + g;
+        const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+        const int mp = (m == 0) ? k - 1 : m - 1, mn = (m + 1 == k) ? 0 : m + 1, mnn = (mn + 1 == k) ? 0 : mn + 1;
+        const int* __restrict__ row = c.ring + (size_t)i * KC;
+        const int jp = row[mp], jm = row[m], jn = row[mn], jq = row[mnn];
+        const int o = c.opp[(size_t)i * KC + m];
+        const double xi = c.x[i], yi = c.y[i];
+        const double dpx = mimg_near(c.x[jp] - xi, P.Lx, P.iLx), dpy = mimg_near(c.y[jp] - yi, P.Ly, P.iLy);
+        const double dmx = mimg_near(c.x[jm] - xi, P.Lx, P.iLx), dmy = mimg_near(c.y[jm] - yi, P.Ly, P.iLy);
+        const double dnx = mimg_near(c.x[jn] - xi, P.Lx, P.iLx), dny = mimg_near(c.y[jn] - yi, P.Ly, P.iLy);
+        const double dqx = mimg_near(c.x[jq] - xi, P.Lx, P.iLx), dqy = mimg_near(c.y[jq] - yi, P.Ly, P.iLy);
+        const R Bx = (R)dmx, By = (R)dmy, Cx = (R)dnx, Cy = (R)dny;
+        R hpx, hpy, hcx, hcy, hnx, hny, qx, qy;
+        circumcentre((R)dpx, (R)dpy, Bx, By, hpx, hpy);
+        circumcentre(Bx, By, Cx, Cy, hcx, hcy);
+        circumcentre(Cx, Cy, (R)dqx, (R)dqy, hnx, hny);
+        opp_vertex(c, P, o, xi, yi, dmx, dmy, dnx, dny, hcx, hcy, qx, qy);
+        slot_term(Bx, By, Cx, Cy, hpx, hpy, hcx, hcy, hnx, hny, qx, qy, ca[i], cb[i], ca[jm], cb[jm], ca[jn], cb[jn],
+                  sF[s][0], sF[s][1]);
+    }
+    __syncthreads();
+    if (t >= 64) return;
+    // first wavefront: each cell's force in the order of k_force_cells
+    const int iu = base + t;
+    const bool own = t < CPB && iu < N;
+    R fx = R(0), fy = R(0);
+    if (own) {
+        const int o0 = sOff[t], k = sK[t];
+        R px[GL], py[GL];
+#pragma unroll
+        for (int l = 0; l < GL; l++) {
+            px[l] = R(0);
+            py[l] = R(0);
+            for (int m = l; m < k; m += GL) {
+                px[l] -= sF[o0 + m][0];
+                py[l] -= sF[o0 + m][1];
+            }
+        }
+#pragma unroll
+        for (int off = GL / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int l = 0; l < off; l++) {
+                px[l] += px[l + off];
+                py[l] += py[l + off];
+            }
+        fx = px[0];
+        fy = py[0];
+    }
+    if (!UPDATE) {
+        if (own) {
+            if (ACC) {
+                fxo[iu] -= (double)fx;
+                fyo[iu] -= (double)fy;
+            } else {
+                fxo[iu] = (double)fx;
+                fyo[iu] = (double)fy;
+            }
+        }
+        return;
+    }
+    double disp = 0.0;
+    if (own) disp = update_cell(sp[MULTI ? c.sys[iu] : 0], sU0[t], (double)fx, (double)fy, iu, xo, yo, tho, st);
+    for (int off = 32; off >= 1; off >>= 1) disp = fmax(disp, __shfl_xor(disp, off));
+    if (t == 0) blockmax[blockIdx.x] = disp;
 }
 
 // ---------------------------------------------------------------- geometry + validity test
@@ -1032,6 +1206,8 @@ constexpr int TAIL_BLOCKS = 32;
 constexpr int TAIL_THREADS = 64 * TAIL_WAVES;
 constexpr int TAIL_CPB = TAIL_THREADS / GL;
 constexpr int RP_TAIL = 512;
+constexpr int MAX_FULL_ROUNDS = 4;  // repair rounds over the whole grid before the tail
+static_assert(MAX_FULL_ROUNDS < MAX_ROUNDS, "the tail reads wl_count[0 .. MAX_FULL_ROUNDS]");
 
 // counters written by atomics of other wavefronts of this block: read at
 // device scope (past the compute unit's L1)
@@ -1094,15 +1270,27 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
         return;
     }
     __threadfence();  // every block's writes are visible from here on
-    // the step's counters and error word, read together by one thread
+    // the step's counters and error word, read by one thread as plain loads:
+    // the fence orders them after every block's writes, and plain loads are
+    // issued back to back (device-scope atomic loads would be serialised,
+    // one round trip past the L2 each)
     __shared__ int s_w0, s_w1, s_err;
     if (threadIdx.x == 0) {
+        const int* wc = st->wl_count;
+        int cnt[MAX_FULL_ROUNDS + 1];
+#pragma unroll
+        for (int v = 0; v <= MAX_FULL_ROUNDS; v++) cnt[v] = wc[v];
+        const unsigned e = st->err;
         st->done = 0;
-        int u = 0;
-        for (int v = 0; v < f; v++) u += load_count(&st->wl_count[v]) > 0 ? 1 : 0;
+        int u = 0, w1 = 0;
+#pragma unroll
+        for (int v = 0; v <= MAX_FULL_ROUNDS; v++) {
+            if (v < f) u += cnt[v] > 0 ? 1 : 0;
+            if (v == f) w1 = cnt[v];
+        }
         s_w0 = u;  // full-grid rounds that had work
-        s_w1 = load_count(&st->wl_count[f]);
-        s_err = (int)__hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_w1 = w1;
+        s_err = (int)e;
     }
     __syncthreads();
     int used = s_w0;

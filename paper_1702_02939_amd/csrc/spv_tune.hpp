@@ -12,7 +12,7 @@
 // systems) to the chosen knobs and the trial time per step, e.g.
 //   {"gfx950/cu256/fp64/kc16/n2^17/s2^0": {"resort_every": 32,
 //     "device_rounds": 8, "repair_cells": 64, "tail_items": 64,
-//     "full_rounds": 1, "bin_factor": 1.5, "ms_per_step": 0.081}}
+//     "full_rounds": 1, "force_mode": 1, "bin_factor": 1.5, "ms_per_step": 0.081}}
 // Reads accept only this shape; an unreadable file counts as empty and is
 // never overwritten.
 #pragma once
@@ -33,6 +33,7 @@ struct Knobs {
     int repair_cells = 64;    // flagged-cell capacity per repair wavefront: grid = N / this
     int tail_items = 64;      // largest late repair round finished on the device
     int full_rounds = 1;      // repair rounds over the whole grid before the tail
+    int force_mode = 0;       // force kernel: 1 lanes per cell, 2 per (cell, slot) item, 0 by size
     double bin_factor = 1.0;  // bin side in mean cell spacings sqrt(L_x L_y / n)
 };
 
@@ -147,6 +148,7 @@ class JsonReader {
             else if (k == "bin_factor") e.k.bin_factor = v, seen |= 8;
             else if (k == "tail_items") e.k.tail_items = (int)v, seen |= 16;
             else if (k == "full_rounds") e.k.full_rounds = (int)v, seen |= 32;
+            else if (k == "force_mode") e.k.force_mode = (int)v, seen |= 64;
             else if (k == "ms_per_step") e.ms_per_step = v;
             else return false;
             ws();
@@ -157,7 +159,7 @@ class JsonReader {
             if (!eat('}')) return false;
             break;
         }
-        return seen == 63 && knobs_valid(e.k);
+        return seen == 127 && knobs_valid(e.k);
     }
 
    public:
@@ -165,7 +167,7 @@ class JsonReader {
     {
         return k.resort_every >= 2 && k.resort_every <= 4096 && k.device_rounds >= 1 && k.device_rounds <= 32 &&
                k.repair_cells >= 1 && k.repair_cells <= 1 << 20 && k.tail_items >= 1 && k.tail_items <= 1 << 20 &&
-               k.full_rounds >= 1 && k.full_rounds <= 4 &&
+               k.full_rounds >= 1 && k.full_rounds <= 4 && k.force_mode >= 0 && k.force_mode <= 2 &&
                k.bin_factor >= 0.5 && k.bin_factor <= 8.0;
     }
 };
@@ -194,7 +196,7 @@ inline std::string cache_dump(const std::map<std::string, TuneEntry>& m)
         o << (first ? "\n" : ",\n") << "  \"" << kv.first << "\": {\"resort_every\": " << kv.second.k.resort_every
           << ", \"device_rounds\": " << kv.second.k.device_rounds << ", \"repair_cells\": " << kv.second.k.repair_cells
           << ", \"tail_items\": " << kv.second.k.tail_items << ", \"full_rounds\": " << kv.second.k.full_rounds
-          << ", \"bin_factor\": " << kv.second.k.bin_factor << ", \"ms_per_step\": " << kv.second.ms_per_step << "}";
+          << ", \"force_mode\": " << kv.second.k.force_mode << ", \"bin_factor\": " << kv.second.k.bin_factor << ", \"ms_per_step\": " << kv.second.ms_per_step << "}";
         first = false;
     }
     o << "\n}\n";

@@ -54,7 +54,8 @@ def test_invalid_arguments_rejected_before_any_gpu_work():
     assert ei.value.status == spv.SPV_EINVAL
     x = np.linspace(0.5, 9.5, 10)
     for kw in (dict(bin_factor=0.25), dict(bin_factor=9.0), dict(autotune=3), dict(repair_cells=-1),
-               dict(device_rounds=-2), dict(full_rounds=5), dict(tail_items=-1), dict(bin_order=2)):
+               dict(device_rounds=-2), dict(full_rounds=5), dict(tail_items=-1), dict(bin_order=2),
+               dict(force_mode=3), dict(force_mode=-1)):
         with pytest.raises(spv.SPVError) as ei:
             spv.spv_create(10, x, x[::-1].copy(), 10.0, 10.0, params=spv.Params(**kw))
         assert ei.value.status == spv.SPV_EINVAL, kw

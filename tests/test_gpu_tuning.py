@@ -46,6 +46,8 @@ KNOB_CASES = [
     dict(full_rounds=2),                      # two full-grid rounds before the tail
     dict(full_rounds=4, device_rounds=3),     # full-grid rounds capped by the device rounds
     dict(bin_order=1),                        # row-major bins instead of the Hilbert order
+    dict(force_mode=1),                       # force kernel with kcap/4 lanes per cell
+    dict(force_mode=2),                       # force kernel with one thread per (cell, slot) item
 ]
 
 
@@ -75,7 +77,7 @@ def test_autotune_trials_cache_and_results(spv, tmp_path, monkeypatch):
     assert t2["source"] == 2 and t2["ms_per_step"] > 0.0
     assert t2["bin_factor"] in (1.0, 1.5, 2.0)
     assert t2["repair_cells"] in (16, 64, 256) and t2["device_rounds"] in (2, 4, 8)
-    assert t2["tail_items"] in (16, 64, 256) and t2["full_rounds"] in (1, 2)
+    assert t2["tail_items"] in (16, 64, 256) and t2["full_rounds"] in (1, 2) and t2["force_mode"] in (1, 2)
     assert t2["resort_every"] in (16, 32, 64)
     for u, v in zip(ref, tuned):
         assert np.array_equal(u, v)
@@ -87,7 +89,7 @@ def test_autotune_trials_cache_and_results(spv, tmp_path, monkeypatch):
     # a second handle of the same size class reads the cache, runs no trial
     cached, t1 = _run(spv, x, y, L, 50, autotune=1)
     assert t1["source"] == 1
-    knobs = ("resort_every", "device_rounds", "repair_cells", "tail_items", "full_rounds", "bin_factor")
+    knobs = ("resort_every", "device_rounds", "repair_cells", "tail_items", "full_rounds", "force_mode", "bin_factor")
     assert {k: t1[k] for k in knobs} == {k: t2[k] for k in knobs}
     for u, v in zip(ref, cached):
         assert np.array_equal(u, v)

@@ -30,15 +30,15 @@ def test_key_buckets(tool):
 def test_missing_file_is_empty_and_round_trip(tool, tmp_path):
     p = tmp_path / "cache.json"
     assert tool("load", p).split() == ["ok", "0"]
-    assert tool("put", p, "a/b", 32, 2, 64, 16, 2, 1.5, 0.0812).strip() == "stored"
-    assert tool("put", p, "c/d", 16, 3, 256, 64, 1, 1.0, 1.25).strip() == "stored"
+    assert tool("put", p, "a/b", 32, 2, 64, 16, 2, 2, 1.5, 0.0812).strip() == "stored"
+    assert tool("put", p, "c/d", 16, 3, 256, 64, 1, 1, 1.0, 1.25).strip() == "stored"
     data = json.loads(p.read_text())  # the file is plain JSON
     assert data["a/b"] == {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 16,
-                           "full_rounds": 2, "bin_factor": 1.5, "ms_per_step": 0.0812}
+                           "full_rounds": 2, "force_mode": 2, "bin_factor": 1.5, "ms_per_step": 0.0812}
     out = tool("load", p).splitlines()
     assert out[0] == "ok 2"
     f = out[1].split()
-    assert f[:6] == ["a/b", "32", "2", "64", "16", "2"] and float(f[6]) == 1.5 and float(f[7]) == 0.0812
+    assert f[:7] == ["a/b", "32", "2", "64", "16", "2", "2"] and float(f[7]) == 1.5 and float(f[8]) == 0.0812
     assert not os.path.exists(str(p) + ".tmp")
 
 
@@ -46,16 +46,18 @@ def test_missing_file_is_empty_and_round_trip(tool, tmp_path):
     "",                                      # empty file
     "[]",                                    # not an object
     '{"k": {"resort_every": 32}}',           # missing knobs
-    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "bin_factor": 1.0, "x": 1}}',
-    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "bin_factor": 99}}',
-    '{"k": {"resort_every": 32, "device_rounds": 0, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "bin_factor": 1}}',
-    '{"k": {"resort_every": "32", "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "bin_factor": 1}}',
-    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "bin_factor": 1}} x',
+    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "force_mode": 1, "bin_factor": 1.0, "x": 1}}',
+    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "force_mode": 1, "bin_factor": 99}}',
+    '{"k": {"resort_every": 32, "device_rounds": 0, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "force_mode": 1, "bin_factor": 1}}',
+    '{"k": {"resort_every": "32", "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "force_mode": 1, "bin_factor": 1}}',
+    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "force_mode": 1, "bin_factor": 1}} x',
+    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "bin_factor": 1}}',
+    '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "tail_items": 8, "full_rounds": 1, "force_mode": 3, "bin_factor": 1}}',
     '{"k": {"resort_every": 32, "device_rounds": 2, "repair_cells": 64, "bin_factor": 1, "ms_per_step": 1}}',
 ])
 def test_malformed_cache_is_rejected_and_kept(tool, tmp_path, text):
     p = tmp_path / "cache.json"
     p.write_text(text)
     assert tool("load", p).strip() == "bad"
-    assert tool("put", p, "a/b", 32, 2, 64, 8, 1, 1.0, 0.1).strip() == "refused"
+    assert tool("put", p, "a/b", 32, 2, 64, 8, 1, 1, 1.0, 0.1).strip() == "refused"
     assert p.read_text() == text

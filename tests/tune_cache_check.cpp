@@ -2,7 +2,7 @@
 // test_tune_cache.py; no GPU code involved).
 //   key ARCH CUS MIXED KC N S         print the cache key
 //   load PATH                         print "ok <n>" and one line per entry, or "bad"
-//   put PATH KEY RE DR RC TI FR BF MS add an entry if the file is readable: "stored" / "refused"
+//   put PATH KEY RE DR RC TI FR FM BF MS  add an entry if the file is readable: "stored" / "refused"
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -27,12 +27,13 @@ int main(int argc, char** argv)
         }
         std::printf("ok %zu\n", m.size());
         for (const auto& kv : m)
-            std::printf("%s %d %d %d %d %d %.17g %.17g\n", kv.first.c_str(), kv.second.k.resort_every,
+            std::printf("%s %d %d %d %d %d %d %.17g %.17g\n", kv.first.c_str(), kv.second.k.resort_every,
                         kv.second.k.device_rounds, kv.second.k.repair_cells, kv.second.k.tail_items,
-                        kv.second.k.full_rounds, kv.second.k.bin_factor, kv.second.ms_per_step);
+                        kv.second.k.full_rounds, kv.second.k.force_mode, kv.second.k.bin_factor,
+                        kv.second.ms_per_step);
         return 0;
     }
-    if (cmd == "put" && argc == 11) {
+    if (cmd == "put" && argc == 12) {
         std::map<std::string, spv::TuneEntry> m;
         if (spv::cache_load(argv[2], m) != 0) {
             std::printf("refused\n");
@@ -44,8 +45,9 @@ int main(int argc, char** argv)
         e.k.repair_cells = std::atoi(argv[6]);
         e.k.tail_items = std::atoi(argv[7]);
         e.k.full_rounds = std::atoi(argv[8]);
-        e.k.bin_factor = std::atof(argv[9]);
-        e.ms_per_step = std::atof(argv[10]);
+        e.k.force_mode = std::atoi(argv[9]);
+        e.k.bin_factor = std::atof(argv[10]);
+        e.ms_per_step = std::atof(argv[11]);
         m[argv[3]] = e;
         std::printf(spv::cache_store(argv[2], m) ? "stored\n" : "failed\n");
         return 0;
