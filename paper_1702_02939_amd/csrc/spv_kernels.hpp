@@ -1261,7 +1261,8 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();  // this block's writes before its count
+        // release: this block's writes before its count (no acquire needed here)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         s_last = atomicAdd(&st->done, 1) == (int)gridDim.x - 1;
     }
     __syncthreads();
@@ -1269,7 +1270,8 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
         if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
         return;
     }
-    __threadfence();  // every block's writes are visible from here on
+    // acquire: every block's writes are visible from here on
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // the step's counters and error word, read by one thread as plain loads:
     // the fence orders them after every block's writes, and plain loads are
     // issued back to back (device-scope atomic loads would be serialised,
