@@ -1270,19 +1270,15 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
         if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
         return;
     }
-    // acquire: every block's writes are visible from here on
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // the step's counters and error word, read by one thread as plain loads:
-    // the fence orders them after every block's writes, and plain loads are
-    // issued back to back (device-scope atomic loads would be serialised,
-    // one round trip past the L2 each)
+    // the step's counters and error word: device-scope atomic loads (they
+    // read past the L2, where the other blocks' atomics were performed before
+    // their counts), issued together into registers, one round trip
     __shared__ int s_w0, s_w1, s_err;
     if (threadIdx.x == 0) {
-        const int* wc = st->wl_count;
         int cnt[MAX_FULL_ROUNDS + 1];
 #pragma unroll
-        for (int v = 0; v <= MAX_FULL_ROUNDS; v++) cnt[v] = wc[v];
-        const unsigned e = st->err;
+        for (int v = 0; v <= MAX_FULL_ROUNDS; v++) cnt[v] = load_count(&st->wl_count[v]);
+        const unsigned e = __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         st->done = 0;
         int u = 0, w1 = 0;
 #pragma unroll
@@ -1295,6 +1291,9 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
         s_err = (int)e;
     }
     __syncthreads();
+    // later rounds read worklist entries that other blocks stored: acquire
+    // (invalidates this XCD's L2) only when there are any
+    if (s_w1 > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     int used = s_w0;
     int r = f, halt_at = -1;
     double drift = 0.0;
