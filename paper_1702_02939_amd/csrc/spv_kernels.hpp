@@ -708,11 +708,12 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
 // STEP (all-cells pass of a step): block 0 also counts the step and adds the
 // step's largest displacement (block maxima of the force kernel) to the drift
 // bound that the repair rounds of this step search with.  The all-cells pass
-// asks for 7 wavefronts per SIMD: it fits in 72 registers without spilling,
-// and its blocks then need fewer rounds; the exact list passes keep their
-// larger register budget.
+// of one system with kcap 16 asks for 7 wavefronts per SIMD: it fits in 72
+// registers without spilling, and its blocks then need fewer rounds (the
+// batched variant would spill; the exact list passes keep their larger
+// register budget).
 template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool STEP = false>
-__global__ __launch_bounds__(256, STEP ? 7 : 1) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
+__global__ __launch_bounds__(256, (STEP && !MULTI && KC == 16) ? 7 : 1) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
                                               int N, int round, const double* __restrict__ blockmax = nullptr,
                                               int nblk = 0)
 {
