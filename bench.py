@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 vector
 
 # Algorithmic HBM bytes per cell per launch (FP64, mean ring length 6;
-# neighbour gathers served by cache).  See the design doc.
+# neighbour gathers served by cache).
 BYTES_PER_CELL = {
     # force+update: read x,y,theta (24), deg (1), ring (24), opp (24), own a,b (16), tag (4);
     # write x,y,theta (24)
@@ -35,20 +35,26 @@ BYTES_PER_CELL = {
 }
 
 
-# HBM bytes per launch of the force kernel at N = 1e5 from the rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy; the summary
-# is in profiles/), valid only for the force kernel's source as it was then:
-# the digest covers the shared device header and the kernel file up to the
-# geometry section (constants, helpers, the force kernel).
+# HBM bytes per launch of the force kernel, per workload, from the rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy; the
+# summaries are in profiles/), valid only for the force kernels' source as it
+# was then: the digest covers the shared device header and the kernel file up
+# to the geometry section (constants, helpers, the force kernels).
 MEASURED_TRAFFIC = {
-    "force_update": {"bytes": 20.66e6, "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
+    ("spv_n100k", "force_update"): {"bytes": 20.66e6,
+                                    "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
+    ("spv_n1m", "force_update"): {"bytes": 200.49e6,
+                                  "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
 }
 
-# FP64 FLOPs per launch of the force kernel at N = 1e5 from the rocprofv3
+# FP64 FLOPs per launch of the force kernel, per workload, from the rocprofv3
 # SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters ((2 FMA + ADD + MUL) x 64 lanes;
 # profiles/), valid for the same source digest as the traffic.
 MEASURED_FP64_FLOPS = {
-    "force_update": {"flops": 222.7e6, "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
+    ("spv_n100k", "force_update"): {"flops": 222.7e6,
+                                    "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
+    ("spv_n1m", "force_update"): {"flops": 2069.8e6,
+                                  "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
 }
 
 
@@ -220,10 +226,11 @@ def adjoint_cost(spv, inputs):
             "traj_backward_ms": (t2 - t1) * 1e3, "adjoint_over_forward": (t2 - t0) / t_plain}
 
 
-def alu_roofline(dom, avg_s):
+def alu_roofline(workload, dom, avg_s):
     """The same kernel against the FP64 vector peak, from its counted FP64
-    operations (None when the counters predate the kernel's source)."""
-    mf = MEASURED_FP64_FLOPS.get(dom)
+    operations (None when there are no counters for this workload or they
+    predate the kernel's source)."""
+    mf = MEASURED_FP64_FLOPS.get((workload, dom))
     if not mf or mf["source_sha256"] != force_source_digest() or avg_s <= 0:
         return None
     tf = mf["flops"] / avg_s / 1e12
@@ -245,8 +252,8 @@ def main():
     args = parse()
     AUTOTUNE = 0 if args.no_autotune else 1
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the SPV step runs on one GPU; sharding across GPUs is not implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
@@ -271,7 +278,7 @@ def main():
         kt = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.timing_steps, args.warmup,
                        timing=True)["kernels"]
     dom, avg_s, bytes_per_launch, achieved = roofline_of(kt, n)
-    mt = MEASURED_TRAFFIC.get(dom)
+    mt = MEASURED_TRAFFIC.get((args.workload, dom))
     traffic = mt["bytes"] if mt and mt["source_sha256"] == force_source_digest() else None
     out = {
         "metric": "cell-steps/s",
@@ -291,7 +298,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
-        "roofline_fp64_alu": alu_roofline(dom, avg_s),
+        "roofline_fp64_alu": alu_roofline(args.workload, dom, avg_s),
         "kernels_ms_total": {k: v[0] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "steady_state_value": head["steady_value"],
