@@ -273,7 +273,12 @@ inline unsigned grid_for(int n, int block) { return (unsigned)std::max(1, (n + b
 // all-cell grid of the 8-lanes-per-cell kernels, padded to a multiple of 8 XCDs
 inline unsigned cell_grid(const spv_sys* s) { return (grid_for(s->N, CPB) + 7u) & ~7u; }
 // the force kernel's grid (its own cells per block), also padded
-inline unsigned force_grid(const spv_sys* s) { return (grid_for(s->N, force_cells_per_block(s->KC)) + 7u) & ~7u; }
+inline bool items_kernel(const spv_sys* s);
+inline unsigned force_grid(const spv_sys* s)
+{
+    const int cpb = items_kernel(s) ? items_cells_per_block(s->KC) : force_cells_per_block(s->KC);
+    return (grid_for(s->N, cpb) + 7u) & ~7u;
+}
 // the force kernel of the handle (both give bitwise the same forces)
 constexpr int kItemsFromCells = 1 << 18;
 inline bool items_kernel(const spv_sys* s)

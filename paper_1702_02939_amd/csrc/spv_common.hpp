@@ -101,6 +101,15 @@ __device__ __forceinline__ double mimg_near(double d, double L, double iL)
     return fma(-L, rint(d * iL), d);
 }
 
+// p[j] through a 32-bit byte offset (j >= 0, j * sizeof(T) < 2^32): the
+// load then adds the offset to the array's scalar base itself, and arrays
+// indexed by the same cell share one offset computation
+template <typename T>
+__device__ __forceinline__ T at(const T* p, int j)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + (uint32_t)j * (uint32_t)sizeof(T));
+}
+
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of
 // (c0, c1, c2, c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)),
 // key bumped by the Weyl constants between rounds.

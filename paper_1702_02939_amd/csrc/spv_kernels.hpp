@@ -32,6 +32,9 @@ constexpr int CPB = 256 / GL;  // cells per 256-thread block
 // 256-thread block holds 1024/kcap cells and at most 1024 (cell, slot) items
 constexpr int force_lanes(int kc) { return kc / 4; }
 constexpr int force_cells_per_block(int kc) { return 256 / force_lanes(kc); }
+// the item kernel: cells per 256-thread block (at most 64: the first
+// wavefront owns them); about 6 items per cell
+constexpr int items_cells_per_block(int kc) { return 1024 / kc; }
 constexpr int RP_CAP = 1024;   // max candidate neighbours of one repaired cell
 
 // ---------------------------------------------------------------- helpers
@@ -267,7 +270,7 @@ __device__ __forceinline__ void opp_vertex(const Cells<R>& c, const SysParam& P,
     qx = hcx;
     qy = hcy;
     if (o >= 0) {
-        const double dox = mimg_near(c.x[o] - xi, P.Lx, P.iLx), doy = mimg_near(c.y[o] - yi, P.Ly, P.iLy);
+        const double dox = mimg_near(at(c.x, o) - xi, P.Lx, P.iLx), doy = mimg_near(at(c.y, o) - yi, P.Ly, P.iLy);
         R ux, uy;
         circumcentre((R)(dox - dmx), (R)(doy - dmy), (R)(dnx - dmx), (R)(dny - dmy), ux, uy);
         qx = ux + (R)dmx;
@@ -359,13 +362,13 @@ __global__ __launch_bounds__(256) void k_force_cells(Cells<R> c, double* __restr
         bxs[s] = bys[s] = cxs[s] = cys[s] = ams[s] = bms[s] = ans[s] = bns[s] = qxs[s] = qys[s] = R(0);
         if (m < k) {
             const int mn = (m + 1 == k) ? 0 : m + 1;
-            const int jm = c.ring[ii * KC + m], jn = c.ring[ii * KC + mn], o = c.opp[ii * KC + m];
-            const double dmx = mimg_near(c.x[jm] - xi, P.Lx, P.iLx), dmy = mimg_near(c.y[jm] - yi, P.Ly, P.iLy);
-            const double dnx = mimg_near(c.x[jn] - xi, P.Lx, P.iLx), dny = mimg_near(c.y[jn] - yi, P.Ly, P.iLy);
-            ams[s] = ca[jm];
-            bms[s] = cb[jm];
-            ans[s] = ca[jn];
-            bns[s] = cb[jn];
+            const int jm = at(c.ring, ii * KC + m), jn = at(c.ring, ii * KC + mn), o = at(c.opp, ii * KC + m);
+            const double dmx = mimg_near(at(c.x, jm) - xi, P.Lx, P.iLx), dmy = mimg_near(at(c.y, jm) - yi, P.Ly, P.iLy);
+            const double dnx = mimg_near(at(c.x, jn) - xi, P.Lx, P.iLx), dny = mimg_near(at(c.y, jn) - yi, P.Ly, P.iLy);
+            ams[s] = at(ca, jm);
+            bms[s] = at(cb, jm);
+            ans[s] = at(ca, jn);
+            bns[s] = at(cb, jn);
             bxs[s] = (R)dmx;
             bys[s] = (R)dmy;
             cxs[s] = (R)dnx;
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(256) void k_force_items(Cells<R> c, double* __restr
                                                      double* __restrict__ fyo, const SysParam* __restrict__ sp,
                                                      DevState* st, int N, double* __restrict__ blockmax)
 {
-    constexpr int GL = force_lanes(KC), CPB = force_cells_per_block(KC);
+    constexpr int GL = force_lanes(KC), CPB = items_cells_per_block(KC);
     constexpr int ITEMS = CPB * KC;  // most items a block can hold
     static_assert(CPB <= 64, "the first wavefront owns the cells of a block");
     __shared__ uint16_t sMap[ITEMS];    // item -> cell | slot << 8
@@ -479,22 +482,23 @@ __global__ __launch_bounds__(256) void k_force_items(Cells<R> c, double* __restr
         const int i = base + g;
         const SysParam& P = sp[MULTI ? c.sys[i] : 0];
         const int mp = (m == 0) ? k - 1 : m - 1, mn = (m + 1 == k) ? 0 : m + 1, mnn = (mn + 1 == k) ? 0 : mn + 1;
-        const int* __restrict__ row = c.ring + (size_t)i * KC;
-        const int jp = row[mp], jm = row[m], jn = row[mn], jq = row[mnn];
-        const int o = c.opp[(size_t)i * KC + m];
-        const double xi = c.x[i], yi = c.y[i];
-        const double dpx = mimg_near(c.x[jp] - xi, P.Lx, P.iLx), dpy = mimg_near(c.y[jp] - yi, P.Ly, P.iLy);
-        const double dmx = mimg_near(c.x[jm] - xi, P.Lx, P.iLx), dmy = mimg_near(c.y[jm] - yi, P.Ly, P.iLy);
-        const double dnx = mimg_near(c.x[jn] - xi, P.Lx, P.iLx), dny = mimg_near(c.y[jn] - yi, P.Ly, P.iLy);
-        const double dqx = mimg_near(c.x[jq] - xi, P.Lx, P.iLx), dqy = mimg_near(c.y[jq] - yi, P.Ly, P.iLy);
+        const int rb = i * KC;
+        const int jp = at(c.ring, rb + mp), jm = at(c.ring, rb + m), jn = at(c.ring, rb + mn),
+                  jq = at(c.ring, rb + mnn);
+        const int o = at(c.opp, rb + m);
+        const double xi = at(c.x, i), yi = at(c.y, i);
+        const double dpx = mimg_near(at(c.x, jp) - xi, P.Lx, P.iLx), dpy = mimg_near(at(c.y, jp) - yi, P.Ly, P.iLy);
+        const double dmx = mimg_near(at(c.x, jm) - xi, P.Lx, P.iLx), dmy = mimg_near(at(c.y, jm) - yi, P.Ly, P.iLy);
+        const double dnx = mimg_near(at(c.x, jn) - xi, P.Lx, P.iLx), dny = mimg_near(at(c.y, jn) - yi, P.Ly, P.iLy);
+        const double dqx = mimg_near(at(c.x, jq) - xi, P.Lx, P.iLx), dqy = mimg_near(at(c.y, jq) - yi, P.Ly, P.iLy);
         const R Bx = (R)dmx, By = (R)dmy, Cx = (R)dnx, Cy = (R)dny;
         R hpx, hpy, hcx, hcy, hnx, hny, qx, qy;
         circumcentre((R)dpx, (R)dpy, Bx, By, hpx, hpy);
         circumcentre(Bx, By, Cx, Cy, hcx, hcy);
         circumcentre(Cx, Cy, (R)dqx, (R)dqy, hnx, hny);
         opp_vertex(c, P, o, xi, yi, dmx, dmy, dnx, dny, hcx, hcy, qx, qy);
-        slot_term(Bx, By, Cx, Cy, hpx, hpy, hcx, hcy, hnx, hny, qx, qy, ca[i], cb[i], ca[jm], cb[jm], ca[jn], cb[jn],
-                  sF[s][0], sF[s][1]);
+        slot_term(Bx, By, Cx, Cy, hpx, hpy, hcx, hcy, hnx, hny, qx, qy, at(ca, i), at(cb, i), at(ca, jm), at(cb, jm),
+                  at(ca, jn), at(cb, jn), sF[s][0], sF[s][1]);
     }
     __syncthreads();
     if (t >= 64) return;
