@@ -41,10 +41,10 @@ BYTES_PER_CELL = {
 # was then: the digest covers the shared device header and the kernel file up
 # to the geometry section (constants, helpers, the force kernels).
 MEASURED_TRAFFIC = {
-    ("spv_n100k", "force_update"): {"bytes": 20.66e6,
-                                    "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
-    ("spv_n1m", "force_update"): {"bytes": 200.49e6,
-                                  "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
+    ("spv_n100k", "force_update"): {"bytes": 20.64e6,
+                                    "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
+    ("spv_n1m", "force_update"): {"bytes": 200.50e6,
+                                  "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
 }
 
 # FP64 FLOPs per launch of the force kernel, per workload, from the rocprofv3
@@ -52,9 +52,9 @@ MEASURED_TRAFFIC = {
 # profiles/), valid for the same source digest as the traffic.
 MEASURED_FP64_FLOPS = {
     ("spv_n100k", "force_update"): {"flops": 222.7e6,
-                                    "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
+                                    "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
     ("spv_n1m", "force_update"): {"flops": 2069.8e6,
-                                  "source_sha256": "8e5b154c7b05eeee5b3f9ccb64039bb84f9d9824409d4d55379bc4df201ffc72"},
+                                  "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
 }
 
 
