@@ -86,9 +86,10 @@ typedef struct {
                                the rest (0: 1; at most 4) */
     int32_t bin_order;      /* memory order of the cell-list bins (Sec. II.B spatial sorting):
                                0 = Hilbert curve, 1 = row-major (for locality comparisons) */
-    int32_t force_mode;     /* force kernel (Eq. 2, App. A-B), bitwise the same result either way:
-                               1 = kcap/4 lanes per cell, 2 = one thread per (cell, ring slot);
-                               0 = 2 from 2^18 cells on, else 1 */
+    int32_t force_mode;     /* layout of the force kernel (Eq. 2, App. A-B) and of the all-cells
+                               geometry and validity pass (Sec. II.C), bitwise the same results
+                               either way: 1 = lanes per cell, 2 = one thread per (cell, ring
+                               slot); 0 = 2 from 2^18 cells on, else 1 */
     double bin_factor;      /* cell-list bin side in mean cell spacings sqrt(Lx Ly / N) (0: 1; 0.5..8) */
 } spv_params;
 

@@ -344,8 +344,14 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
     launch(ev ? &ev[0] : nullptr, force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
            nxt.y, nxt.th,
            (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
-    launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, s->work,
-           (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax, (int)force_grid(s));
+    if (items_kernel(s))
+        launch(ev ? &ev[1] : nullptr, k_geom_items<R, MULTI, KC>,
+               dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, s->work,
+               (const SysParam*)s->d_sp, s->d_st, s->N, (const double*)s->d_blockmax, (int)force_grid(s));
+    else
+        launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt,
+               s->work, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
+               (int)force_grid(s));
     // rounds 0 .. f-1 over the whole grid; the last one's re-test, later
     // rounds and the step's close in the tail
     const int f = std::min(s->full_rounds, s->dev_rounds);

@@ -566,6 +566,36 @@ struct GeomLds {
     int (*sJ)[KC];        // ring members
 };
 
+// Terms of Voronoi edge (u_m, u_{m+1}) in A_i = 1/2 sum u_m x u_{m+1} and
+// P_i = sum |u_{m+1} - u_m| (explicit fused multiply-adds: both geometry
+// kernels round them alike)
+template <typename R>
+__device__ __forceinline__ void edge_terms(R ux, R uy, R vx, R vy, R& a2, R& per)
+{
+#pragma clang fp contract(off)
+    const R dx = vx - ux, dy = vy - uy;
+    a2 = fma(ux, vy, -(uy * vx));
+    per = sqrt(fma(dx, dx, dy * dy));
+}
+
+// the step's largest displacement (block maxima of the force kernel) added
+// to the drift bound, and the step counted (block 0 of the all-cells pass)
+__device__ __forceinline__ void close_drift(DevState* st, const double* __restrict__ blockmax, int nblk)
+{
+    __shared__ double swm[256 / 64];
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = fmax(m, blockmax[b]);
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) swm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x >> 6); v++) m = fmax(m, swm[v]);
+        st->step += 1ull;
+        st->drift += m;
+        st->disp_bits = __double_as_longlong(m);
+    }
+}
+
 // One pass over cells t = base + g (g = threadIdx.x / GL) of a list (LIST)
 // or of all cells; every thread of the block takes part (block barriers).
 // EXACT = false (the all-cells pass): a predicate that the double filter
@@ -687,9 +717,10 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
         const int m = l + s * GL;
         if (m < k) {
             const int mn = (m + 1 == k) ? 0 : m + 1;
-            const R ux = sU[g][m][0], uy = sU[g][m][1], vx = sU[g][mn][0], vy = sU[g][mn][1];
-            a2 += ux * vy - uy * vx;
-            per += sqrt((vx - ux) * (vx - ux) + (vy - uy) * (vy - uy));
+            R ta, tp;
+            edge_terms(sU[g][m][0], sU[g][m][1], sU[g][mn][0], sU[g][mn][1], ta, tp);
+            a2 += ta;
+            per += tp;
         }
     }
 #pragma unroll
@@ -734,20 +765,117 @@ __global__ __launch_bounds__(256, (STEP && !MULTI && KC == 16) ? 7 : 1) void k_g
     for (int base = bstart * CPB; base < n; base += gridDim.x * CPB)
         geom_pass<R, MULTI, KC, LIST, OPP, !STEP>(c, w, sp, st, base, n, list, rnext, S, exact);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
-    if (STEP && blockIdx.x == 0) {
-        __shared__ double swm[256 / 64];
-        double m = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += blockDim.x) m = fmax(m, blockmax[b]);
-        for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off));
-        if ((threadIdx.x & 63) == 0) swm[threadIdx.x >> 6] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int v = 1; v < (int)(blockDim.x >> 6); v++) m = fmax(m, swm[v]);
-            st->step += 1ull;
-            st->drift += m;
-            st->disp_bits = __double_as_longlong(m);
+    if (STEP && blockIdx.x == 0) close_drift(st, blockmax, nblk);
+}
+
+// The all-cells geometry + validity pass of a step with one thread per (cell,
+// ring slot) item (the layout of k_force_items; same results as k_geom with
+// STEP: the same filters, and the area and perimeter summed in its order).
+// An item computes u_m and u_{m+1} itself, tests triangle (i, j_m, j_{m+1})
+// against opp_m and writes its edge's area and perimeter terms.
+template <typename R, bool MULTI, int KC>
+__global__ __launch_bounds__(256) void k_geom_items(Cells<R> c, Work w, const SysParam* __restrict__ sp,
+                                                    DevState* st, int N, const double* __restrict__ blockmax, int nblk)
+{
+    constexpr int CPB_I = items_cells_per_block(KC);
+    constexpr int ITEMS = CPB_I * KC;
+    static_assert(CPB_I <= 64, "the first wavefront owns the cells of a block");
+    __shared__ uint16_t sMap[ITEMS];      // item -> cell | slot << 8
+    __shared__ R sT[ITEMS][2];            // the item's area and perimeter terms
+    __shared__ int sOff[CPB_I], sK[CPB_I];  // first item and ring length of each cell
+    __shared__ int sItems;
+    if (st->halt) return;
+    const int base = xcd_block(blockIdx.x, gridDim.x) * CPB_I;
+    const int t = threadIdx.x;
+    if (t < 64) {
+        const int i = base + t;
+        const bool valid = t < CPB_I && i < N;
+        int k = valid ? (int)c.deg[i] : 0;
+        if (valid && (k < 3 || k > KC)) {
+            atomicOr(&st->err, ERR_DEGREE);
+            k = 0;
         }
+        int incl = k;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off);
+            if (t >= off) incl += v;
+        }
+        if (t < CPB_I) {
+            sOff[t] = incl - k;
+            sK[t] = k;
+            for (int m = 0; m < k; m++) sMap[incl - k + m] = (uint16_t)(t | m << 8);
+        }
+        if (t == 63) sItems = incl;
     }
+    __syncthreads();
+    const int S = sItems;
+    for (int s = t; s < S; s += 256) {
+        const int e = sMap[s];
+        const int g = e & 0xff, m = e >> 8, k = sK[g];
+        const int i = base + g;
+        const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+        const int mn = (m + 1 == k) ? 0 : m + 1, mnn = (mn + 1 == k) ? 0 : mn + 1;
+        const int rb = i * KC;
+        const int jm = at(c.ring, rb + m), jn = at(c.ring, rb + mn), jq = at(c.ring, rb + mnn);
+        const int o = at(c.opp, rb + m);
+        const double xi = at(c.x, i), yi = at(c.y, i);
+        const double bx = mimg(at(c.x, jm) - xi, P.Lx, P.hLx), by = mimg(at(c.y, jm) - yi, P.Ly, P.hLy);
+        const double cx = mimg(at(c.x, jn) - xi, P.Lx, P.hLx), cy = mimg(at(c.y, jn) - yi, P.Ly, P.hLy);
+        const double qx = mimg(at(c.x, jq) - xi, P.Lx, P.hLx), qy = mimg(at(c.y, jq) - yi, P.Ly, P.hLy);
+        const double cr = bx * cy - by * cx;
+        bool fail = !(cr > 1.5e-15 * (fabs(bx * cy) + fabs(by * cx)));
+        R ux, uy, vx, vy;
+        circumcentre((R)bx, (R)by, (R)cx, (R)cy, ux, uy);
+        circumcentre((R)cx, (R)cy, (R)qx, (R)qy, vx, vy);
+        if (!fail) {
+            if (o < 0) {
+                fail = true;
+            } else {
+                const double px = mimg(at(c.x, o) - xi, P.Lx, P.hLx), py = mimg(at(c.y, o) - yi, P.Ly, P.hLy);
+                fail = incircle_filter(bx, by, cx, cy, px, py) >= 0;
+            }
+            const double rlim2 = 0.0625 * fmin(P.Lx, P.Ly) * fmin(P.Lx, P.Ly);
+            if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
+        }
+        if (fail) {
+            push_flag(w, st, 0, i);
+            push_flag(w, st, 0, jm);
+            push_flag(w, st, 0, jn);
+            if (o >= 0) push_flag(w, st, 0, o);
+        }
+        edge_terms(ux, uy, vx, vy, sT[s][0], sT[s][1]);
+    }
+    __syncthreads();
+    if (t < CPB_I && base + t < N && sK[t] >= 3) {
+        // the order of k_geom: lane l of GL sums slots l, l + GL, ..., then
+        // the lane butterfly
+        const int i = base + t, o0 = sOff[t], k = sK[t];
+        const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+        R pa[GL], pp[GL];
+#pragma unroll
+        for (int l = 0; l < GL; l++) {
+            pa[l] = R(0);
+            pp[l] = R(0);
+            for (int m = l; m < k; m += GL) {
+                pa[l] += sT[o0 + m][0];
+                pp[l] += sT[o0 + m][1];
+            }
+        }
+#pragma unroll
+        for (int off = GL / 2; off > 0; off >>= 1)
+#pragma unroll
+            for (int l = 0; l < off; l++) {
+                pa[l] += pa[l + off];
+                pp[l] += pp[l + off];
+            }
+        const R A = R(0.5) * pa[0];
+        c.A[i] = A;
+        c.P[i] = pp[0];
+        c.ca[i] = (R)(2.0 * P.KA * ((double)A - c.A0[i]));
+        c.cb[i] = (R)(2.0 * P.KP * ((double)pp[0] - c.P0[i]));
+    }
+    if (blockIdx.x == 0) close_drift(st, blockmax, nblk);
 }
 
 // ---------------------------------------------------------------- repair
