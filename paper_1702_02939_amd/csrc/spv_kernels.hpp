@@ -278,6 +278,22 @@ __device__ __forceinline__ void opp_vertex(const Cells<R>& c, const SysParam& P,
     }
 }
 
+// X mod LU in grid units for an integral X of any size (the wrap of Eq. 3
+// onto the periodic box): one correction in the common case, an exact
+// integer remainder when a step moved a cell by more than a box length (a
+// stiff random start can); NaN for a non-finite X or one beyond int64 units
+__device__ __forceinline__ double wrap_units(double X, double LU)
+{
+    if (X >= 0.0 && X < LU) return X;
+    if (X < 0.0 && X >= -LU) return X + LU;
+    if (X >= LU && X < 2.0 * LU) return X - LU;
+    if (!(fabs(X) < 4.0e18)) return NAN;
+    const long long L = (long long)LU;
+    long long r = (long long)X % L;
+    if (r < 0) r += L;
+    return (double)r;
+}
+
 // Eq. 3 for one cell from its force and the values parked at kernel start
 // (x, y, theta, noise, sin, cos): the quantised, wrapped position, the
 // rotated director, and the displacement length returned
@@ -288,11 +304,7 @@ __device__ __forceinline__ double update_cell(const SysParam& Q, const double* u
     const double xu = u0[0], yu = u0[1], thu = u0[2], nzu = u0[3], sn = u0[4], cs = u0[5];
     const double xn = xu + Q.dt * (Q.mu * Fx + Q.v0 * cs);
     const double yn = yu + Q.dt * (Q.mu * Fy + Q.v0 * sn);
-    double X = rint(xn * Q.scale), Y = rint(yn * Q.scale);
-    if (X < 0.0) X += Q.LXu;
-    else if (X >= Q.LXu) X -= Q.LXu;
-    if (Y < 0.0) Y += Q.LYu;
-    else if (Y >= Q.LYu) Y -= Q.LYu;
+    double X = wrap_units(rint(xn * Q.scale), Q.LXu), Y = wrap_units(rint(yn * Q.scale), Q.LYu);
     if (!(X >= 0.0 && X < Q.LXu && Y >= 0.0 && Y < Q.LYu)) {
         atomicOr(&st->err, ERR_NONFINITE);
         X = rint(xu * Q.scale);  // keep the stored state finite and inside the box
@@ -302,8 +314,10 @@ __device__ __forceinline__ double update_cell(const SysParam& Q, const double* u
     xo[iu] = xq;
     yo[iu] = yq;
     tho[iu] = thu + Q.amp * nzu;
-    const double ddx = mimg(xq - xu, Q.Lx, Q.hLx), ddy = mimg(yq - yu, Q.Ly, Q.hLy);
-    return sqrt(ddx * ddx + ddy * ddy);
+    // the unwrapped move (a jump across the box counts in full: it bounds the
+    // drift from the binned position) plus a grid unit for the quantisation
+    const double ddx = xn - xu, ddy = yn - yu;
+    return sqrt(ddx * ddx + ddy * ddy) + Q.inv_scale;
 }
 
 // x, y, theta, noise, sin, cos of the update of cell iu

@@ -359,3 +359,29 @@ def test_mixed_precision_forces_and_topology(spv):
     gA, gP = s.geometry()
     assert np.abs(gA - A).max() < 1e-5 and np.abs(gP - P).max() < 1e-5
     s.close()
+
+
+def test_stiff_start_wraps_jumps_longer_than_the_box(spv):
+    """A random start whose first step moves a cell by more than a box length
+    (largest force about 7e3 after step 1 at dt = 0.01, N = 1200): positions
+    wrap modulo the box in grid units, as the oracle's integer wrap does, the
+    drift bound counts the whole jump, and the run goes on; E and qbar follow
+    the oracle step by step."""
+    n = 1200
+    L = math.sqrt(n)
+    x, y = inputs.uniform_positions(n, L, L, 92)
+    th0 = oracle.theta0(7, n)
+    sysm = spv.System(x, y, L, L, p0=3.9, theta0=th0, params=spv.Params(v0=0.15, Dr=1.0, dt=0.01, seed=7))
+    Lxq, Lyq, q = sysm.box()
+    xq, yq, _, _, _ = oracle.prepare(x, y, L, L)
+    T = 4
+    out = oracle.run(xq, yq, th0, Lxq, Lyq, q, 1.0, 3.9, v0=0.15, Dr=1.0, dt=0.01, seed=7, nsteps=T)
+    for t in range(T + 1):
+        E, qbar, _, _ = sysm.observables()
+        assert abs(E - out["E"][t]) <= 1e-6 * abs(out["E"][t]), (t, E, out["E"][t])
+        assert abs(qbar - out["qbar"][t]) <= 1e-6 * abs(out["qbar"][t]), (t, qbar, out["qbar"][t])
+        if t < T:
+            sysm.step(1)
+    gx, gy = sysm.positions()
+    assert gx.min() >= 0 and gx.max() < Lxq and gy.min() >= 0 and gy.max() < Lyq
+    sysm.close()

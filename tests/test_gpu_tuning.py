@@ -114,3 +114,40 @@ def test_autotune_batch(spv, monkeypatch):
     for u, v in zip(*outs):
         assert np.array_equal(u, v)
 
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_force_layouts_agree_batched_and_kcap32(spv, precision):
+    """Both kernel layouts (lanes per cell, one thread per (cell, slot) item)
+    give bitwise the same trajectories for a batch of uneven systems and for
+    a single system with ring capacity 32, in both precisions."""
+    prec = spv.SPV_FP64 if precision == "fp64" else spv.SPV_MIXED
+    N_s = [64, 500, 1200, 300, 2000]
+    L_s = [math.sqrt(v) for v in N_s]
+    xs, ys = zip(*[inputs.uniform_positions(v, L_s[k], L_s[k], 90 + k) for k, v in enumerate(N_s)])
+    p0_s = np.array([3.7, 3.8, 3.9, 4.0, 3.85])
+    v0_s = np.array([0.05, 0.1, 0.15, 0.2, 0.1])
+    seed_s = np.array([5, 6, 7, 8, 9], dtype=np.uint64)
+    outs = []
+    for mode in (1, 2):
+        b = spv.System.batch(N_s, L_s, np.concatenate(xs), np.concatenate(ys), p0_s, v0_s=v0_s, seed_s=seed_s,
+                             params=spv.Params(precision=prec, force_mode=mode))
+        assert b.tuning()["force_mode"] == mode
+        b.step(60)
+        outs.append((*b.positions(), b.directors(), *b.neighbors(), *b.forces()))
+        b.close()
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
+    n = 3000
+    L = math.sqrt(n)
+    x, y = inputs.uniform_positions(n, L, L, 93)
+    outs = []
+    for mode in (1, 2):
+        s = spv.System(x, y, L, L, p0=3.9, params=spv.Params(v0=0.1, seed=31, kcap=32, precision=prec,
+                                                               force_mode=mode))
+        assert s.tuning()["force_mode"] == mode
+        s.step(60)
+        outs.append((*s.positions(), s.directors(), *s.neighbors(), *s.forces()))
+        s.close()
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
