@@ -41,20 +41,20 @@ BYTES_PER_CELL = {
 # was then: the digest covers the shared device header and the kernel file up
 # to the geometry section (constants, helpers, the force kernels).
 MEASURED_TRAFFIC = {
-    ("spv_n100k", "force_update"): {"bytes": 20.64e6,
-                                    "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
-    ("spv_n1m", "force_update"): {"bytes": 200.50e6,
-                                  "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
+    ("spv_n100k", "force_update"): {"bytes": 20.69e6,
+                                    "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
+    ("spv_n1m", "force_update"): {"bytes": 200.52e6,
+                                  "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
 }
 
 # FP64 FLOPs per launch of the force kernel, per workload, from the rocprofv3
 # SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters ((2 FMA + ADD + MUL) x 64 lanes;
 # profiles/), valid for the same source digest as the traffic.
 MEASURED_FP64_FLOPS = {
-    ("spv_n100k", "force_update"): {"flops": 222.7e6,
-                                    "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
-    ("spv_n1m", "force_update"): {"flops": 2069.8e6,
-                                  "source_sha256": "ba9b148b1caa88021b917c6b991885e4ef8bf4a8185ea214818ac5a614a33fea"},
+    ("spv_n100k", "force_update"): {"flops": 221.9e6,
+                                    "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
+    ("spv_n1m", "force_update"): {"flops": 2061.8e6,
+                                  "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
 }
 
 
