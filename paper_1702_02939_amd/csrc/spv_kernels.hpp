@@ -927,6 +927,15 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// v of lane l (l uniform across the wavefront)
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Delaunay neighbours of the cell at the origin among the n candidates
 // (sx, sy), decided all at once, one candidate p per lane.  The circles
 // through 0 and p have centres p/2 + t perp(p); a candidate q left of the
@@ -1016,16 +1025,20 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
     if (k > KMAX) return k;
     wave_sync();
     // counter-clockwise order from the direction (1, 0): half-plane, then
-    // the exact sign of the cross product (no two members share a ray)
+    // the exact sign of the cross product (no two members share a ray).
+    // Member j's coordinates come from lane j's registers (the loop index is
+    // uniform), not through LDS.
     int rank = 0, my = -1;
+    double ax = 0.0, ay = 0.0;
     if (lane < k) {
         my = s_tmp[lane];
-        const double ax = sx[my], ay = sy[my];
-        const int ha = (ay < 0.0 || (ay == 0.0 && ax < 0.0)) ? 1 : 0;
-        for (int j = 0; j < k; j++) {
-            if (j == lane) continue;
-            const int o = s_tmp[j];
-            const double bx = sx[o], by = sy[o];
+        ax = sx[my];
+        ay = sy[my];
+    }
+    const int ha = (ay < 0.0 || (ay == 0.0 && ax < 0.0)) ? 1 : 0;
+    for (int j = 0; j < k; j++) {
+        const double bx = readlane_d(ax, j), by = readlane_d(ay, j);
+        if (lane < k && j != lane) {
             const int hb = (by < 0.0 || (by == 0.0 && bx < 0.0)) ? 1 : 0;
             if (hb != ha) rank += hb < ha;
             else rank += cross_sign(bx, by, ax, ay, bx * ay - by * ax, scale) > 0;
