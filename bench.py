@@ -35,25 +35,27 @@ BYTES_PER_CELL = {
 }
 
 
-# HBM bytes per launch of the force kernel, per workload, from the rocprofv3
+# HBM bytes per launch of the force kernel, per workload and kernel layout
+# (force_mode 1: lanes per cell, 2: per item), from the rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy; the
 # summaries are in profiles/), valid only for the force kernels' source as it
 # was then: the digest covers the shared device header and the kernel file up
 # to the geometry section (constants, helpers, the force kernels).
 MEASURED_TRAFFIC = {
-    ("spv_n100k", "force_update"): {"bytes": 20.69e6,
+    ("spv_n100k", "force_update", 1): {"bytes": 20.69e6,
                                     "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
-    ("spv_n1m", "force_update"): {"bytes": 200.52e6,
+    ("spv_n1m", "force_update", 2): {"bytes": 200.52e6,
                                   "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
 }
 
-# FP64 FLOPs per launch of the force kernel, per workload, from the rocprofv3
-# SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters ((2 FMA + ADD + MUL) x 64 lanes;
-# profiles/), valid for the same source digest as the traffic.
+# FP64 FLOPs per launch of the force kernel, per workload and kernel layout,
+# from the rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters
+# ((2 FMA + ADD + MUL) x 64 lanes; profiles/), valid for the same source
+# digest as the traffic.
 MEASURED_FP64_FLOPS = {
-    ("spv_n100k", "force_update"): {"flops": 221.9e6,
+    ("spv_n100k", "force_update", 1): {"flops": 221.9e6,
                                     "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
-    ("spv_n1m", "force_update"): {"flops": 2061.8e6,
+    ("spv_n1m", "force_update", 2): {"flops": 2061.8e6,
                                   "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
 }
 
@@ -226,11 +228,11 @@ def adjoint_cost(spv, inputs):
             "traj_backward_ms": (t2 - t1) * 1e3, "adjoint_over_forward": (t2 - t0) / t_plain}
 
 
-def alu_roofline(workload, dom, avg_s):
+def alu_roofline(workload, dom, mode, avg_s):
     """The same kernel against the FP64 vector peak, from its counted FP64
     operations (None when there are no counters for this workload or they
     predate the kernel's source)."""
-    mf = MEASURED_FP64_FLOPS.get((workload, dom))
+    mf = MEASURED_FP64_FLOPS.get((workload, dom, mode))
     if not mf or mf["source_sha256"] != force_source_digest() or avg_s <= 0:
         return None
     tf = mf["flops"] / avg_s / 1e12
@@ -278,7 +280,8 @@ def main():
         kt = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.timing_steps, args.warmup,
                        timing=True)["kernels"]
     dom, avg_s, bytes_per_launch, achieved = roofline_of(kt, n)
-    mt = MEASURED_TRAFFIC.get((args.workload, dom))
+    mode = head["tuning"].get("force_mode")
+    mt = MEASURED_TRAFFIC.get((args.workload, dom, mode))
     traffic = mt["bytes"] if mt and mt["source_sha256"] == force_source_digest() else None
     out = {
         "metric": "cell-steps/s",
@@ -298,7 +301,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
-        "roofline_fp64_alu": alu_roofline(args.workload, dom, avg_s),
+        "roofline_fp64_alu": alu_roofline(args.workload, dom, mode, avg_s),
         "kernels_ms_total": {k: v[0] for k, v in kt.items()},
         "kernel_launches": {k: v[1] for k, v in kt.items()},
         "steady_state_value": head["steady_value"],
