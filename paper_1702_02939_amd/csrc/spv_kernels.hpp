@@ -1366,7 +1366,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
 // Otherwise the per-step counters are cleared for the next step.  No block
 // ever waits for another (the hand-over is a counter, not a barrier).
 constexpr int TAIL_WAVES = 8;
-constexpr int TAIL_BLOCKS = 32;
+constexpr int TAIL_BLOCKS = 32;  // the smallest tail grid
 constexpr int TAIL_THREADS = 64 * TAIL_WAVES;
 constexpr int TAIL_CPB = TAIL_THREADS / GL;
 constexpr int RP_TAIL = 512;
