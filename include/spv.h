@@ -114,6 +114,9 @@ typedef struct spv_sys spv_sys; /* opaque handle: all device state of one system
  *   stream   hipStream_t to order all work on (NULL: the default stream)
  * Ownership: *out receives a new handle (free with spv_destroy).  All input
  * arrays are read during the call only.
+ * Size limit: N * kcap < 2^30 (N < 2^26 cells at kcap 16, 2^25 at kcap 32;
+ * ring rows are addressed with 32-bit offsets); larger N is SPV_EINVAL,
+ * decided before any input is read or any memory allocated.
  * Errors: SPV_EINVAL (arguments), SPV_EPRECOND (box too small), SPV_ENOMEM,
  * SPV_EHIP; *out is then NULL.
  */
@@ -132,6 +135,7 @@ spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y
  *   p0_s, v0_s, seed_s          per-system target shape index, speed, noise seed
  *                               (v0_s / seed_s NULL: params->v0 / params->seed)
  * Other model parameters (K_A, K_P, mu, Dr, dt, precision, ...) are shared.
+ * Size limit: (sum of N_s) * kcap < 2^30, as spv_create.
  * Errors as spv_create.
  */
 spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const double* Lx_s, const double* Ly_s,

@@ -500,6 +500,10 @@ spv_status do_resort_eager(spv_sys* s)
 {
     dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->stream, s->cfg); });
     HIP_TRY(hipGetLastError());
+    // the host mirror follows what k_gather does on the device, so that the
+    // next batch is sized from a zero drift
+    s->h_st->last_drift = s->h_st->drift;
+    s->h_st->drift = 0.0;
     s->cfg ^= 1;
     s->pos = 0;
     s->resorts++;
@@ -842,6 +846,18 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     if (p.force_mode < 0 || p.force_mode > 2) return fail(SPV_EINVAL, "force_mode must be 0, 1 or 2");
     s->force_mode = p.force_mode;
     s->stream = (hipStream_t)stream;
+    return SPV_OK;
+}
+
+// The kernels address ring and opposite-vertex rows (int32, N x kcap) with
+// 32-bit byte offsets and form row indices i * kcap + m in int: both need
+// N * kcap < 2^30 (N < 2^26 cells at kcap 16, 2^25 at kcap 32).  Checked on
+// the host before any copy or allocation.
+constexpr int64_t kMaxRingEntries = (int64_t)1 << 30;
+spv_status check_ring_extent(int64_t N, int kcap)
+{
+    if (N * (int64_t)kcap >= kMaxRingEntries)
+        return fail(SPV_EINVAL, "N * kcap must be below 2^30 (ring rows are addressed with 32-bit offsets)");
     return SPV_OK;
 }
 
@@ -1497,6 +1513,7 @@ spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y
     {
         spv_sys probe;  // parameters are checked before any copy
         ST_TRY(setup_params(&probe, params, stream));
+        ST_TRY(check_ring_extent(N, probe.KC));
     }
     CreateArgs a;
     a.prm = *params;
@@ -1547,6 +1564,7 @@ spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const 
     {
         spv_sys probe;
         ST_TRY(setup_params(&probe, params, stream));
+        ST_TRY(check_ring_extent(Ntot, probe.KC));
     }
     CreateArgs a;
     a.prm = *params;

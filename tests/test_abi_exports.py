@@ -59,3 +59,23 @@ def test_invalid_arguments_rejected_before_any_gpu_work():
         with pytest.raises(spv.SPVError) as ei:
             spv.spv_create(10, x, x[::-1].copy(), 10.0, 10.0, params=spv.Params(**kw))
         assert ei.value.status == spv.SPV_EINVAL, kw
+
+
+def test_ring_extent_limit_rejected_before_reading_inputs():
+    """N * kcap must stay below 2^30 (ring rows use 32-bit byte offsets); a
+    larger system is refused on the host before any input is read or any
+    device memory allocated -- here with 4-entry arrays standing in for
+    tens of millions of cells, so reading them would be out of bounds."""
+    from paper_1702_02939_amd import spv
+    import numpy as np
+    tiny = np.zeros(4)
+    for N, kcap in ((1 << 26, 16), (1 << 25, 32), ((1 << 26) + 5, 0), (1 << 29, 16)):
+        with pytest.raises(spv.SPVError) as ei:
+            spv.spv_create(N, tiny, tiny, 8192.0, 8192.0, params=spv.Params(kcap=kcap))
+        assert ei.value.status == spv.SPV_EINVAL
+        assert "2^30" in str(ei.value)
+    # batches: the total over the systems counts
+    with pytest.raises(spv.SPVError) as ei:
+        spv.spv_batch_create([1 << 25, 1 << 25], [5793.0, 5793.0], tiny, tiny, [3.8, 3.8],
+                             params=spv.Params(kcap=16))
+    assert ei.value.status == spv.SPV_EINVAL and "2^30" in str(ei.value)

@@ -180,3 +180,85 @@ def test_run_update_rule(orc):
     np.testing.assert_allclose(out["theta"], th + math.sqrt(2 * Dr * dt) * xi, rtol=0, atol=1e-15)
     # grid: every coordinate is an exact multiple of 2^-q
     assert np.all(np.ldexp(out["x"], q) == np.rint(np.ldexp(out["x"], q)))
+
+
+# ---------------------------------------------------------------- observables
+def test_observables_qbar_hex_and_square(orc):
+    """q-bar (the mean of the per-cell shape index P/sqrt(A)) from the
+    oracle's observables: the regular hexagon gives 2 sqrt 2 3^(1/4) and the
+    square 4 for any spacing (the index is scale-free), a rectangle of sides
+    a, b gives 2 (a + b) / sqrt(a b); E (Eq. 1, no factor 1/2) has the closed
+    form N [K_A (A - A0)^2 + K_P (P - P0)^2]; sum A = Lx Ly."""
+    a = 1.7  # a != 1: P/A or a mean over the total area would differ
+    x, y, Lx, Ly = inputs.hex_lattice(8, 10, a, offset=(0.29, 0.13))
+    xq, yq, Lx, Ly, q = orc.prepare(x, y, Lx, Ly)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    A, P = orc.geometry(xq, yq, Lx, Ly, off, ring)
+    n = len(xq)
+    KA, KP, A0, P0 = 1.3, 0.6, 2.0, 4.4
+    E, qbar, sumA = orc.energy(A, P, A0, P0, KA, KP)
+    A_hex, P_hex = math.sqrt(3) / 2 * a * a, 2 * math.sqrt(3) * a
+    assert abs(qbar - 2 * math.sqrt(2) * 3 ** 0.25) <= 1e-12 * 3.73
+    E_hex = n * (KA * (A_hex - A0) ** 2 + KP * (P_hex - P0) ** 2)
+    assert abs(E - E_hex) <= 1e-11 * E_hex
+    assert abs(sumA - Lx * Ly) <= 1e-11 * Lx * Ly
+
+    x, y, Lx, Ly = inputs.square_lattice(6, 2.5)
+    xq, yq, Lx, Ly, q = orc.prepare(x, y, Lx, Ly)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    A, P = orc.geometry(xq, yq, Lx, Ly, off, ring)
+    E, qbar, sumA = orc.energy(A, P, 1.0, 3.8)
+    assert abs(qbar - 4.0) <= 1e-13
+    assert abs(E - 36 * ((6.25 - 1.0) ** 2 + (10.0 - 3.8) ** 2)) <= 1e-10
+
+    # rectangular lattice 1 x 2: rectangles with P = 6, A = 2
+    xs, ys = np.meshgrid(np.arange(6) * 1.0 + 0.25, np.arange(5) * 2.0 + 0.5)
+    xq, yq, Lx, Ly, q = orc.prepare(xs.ravel().copy(), ys.ravel().copy(), 6.0, 10.0)
+    off, ring, _, _ = orc.triangulate(xq, yq, Lx, Ly, q)
+    A, P = orc.geometry(xq, yq, Lx, Ly, off, ring)
+    np.testing.assert_allclose(A, 2.0, rtol=1e-13)
+    np.testing.assert_allclose(P, 6.0, rtol=1e-13)
+    _, qbar, _ = orc.energy(A, P, 1.0, 3.8)
+    assert abs(qbar - 6.0 / math.sqrt(2.0)) <= 1e-13
+
+
+def test_observables_qbar_is_a_mean_of_ratios(orc):
+    """Two cells with (A, P) = (1, 4) and (4, 4): their shape indices are 4
+    and 2, so q-bar = 3 (the ratio of the totals, 8 / sqrt(5), or a mean
+    over the total area would not give 3); E = (1-1)^2 + (4-4)^2 +
+    (4-1)^2 + (4-4)^2 = 9 with A0 = 1, P0 = 4, unit moduli."""
+    E, qbar, sumA = orc.energy(np.array([1.0, 4.0]), np.array([4.0, 4.0]), 1.0, 4.0)
+    assert qbar == 3.0
+    assert E == 9.0
+    assert sumA == 5.0
+    # moduli enter linearly, each with its own term
+    E2, _, _ = orc.energy(np.array([1.0, 4.0]), np.array([4.0, 5.0]), 1.0, 4.0, KA=2.0, KP=3.0)
+    assert E2 == 2.0 * 9.0 + 3.0 * 1.0
+
+
+def test_theta0_counter_rule_and_uniformity(orc):
+    """Initial directors: theta0 = 2 pi u with u from Philox4x64-10 at counter
+    (2^64 - 1, tag, 0, 0), key (seed, 0): checked against numpy's own Philox
+    (which advances its counter before a block), then uniform on [0, 2 pi):
+    Kolmogorov-Smirnov over 1e5 tags, first two moments, and independent of
+    the step-0 noise stream."""
+    from scipy import stats
+    seed, n = 20170211, 100_000
+    th = orc.theta0(seed, n)
+    for tag in (0, 1, 7, 12345, n - 1):
+        g = np.random.Philox(counter=np.array([2 ** 64 - 2, tag, 0, 0], dtype=np.uint64),
+                             key=np.array([seed, 0], dtype=np.uint64))
+        r0 = int(g.random_raw(1)[0])
+        u = (r0 >> 11) * 2.0 ** -53 + 2.0 ** -54
+        assert th[tag] == 2 * math.pi * u
+    assert th.min() > 0.0 and th.max() < 2 * math.pi
+    ks = stats.kstest(th, "uniform", args=(0.0, 2 * math.pi))
+    assert ks.pvalue > 1e-3, ks
+    assert abs(th.mean() - math.pi) < 5 * (2 * math.pi / math.sqrt(12)) / math.sqrt(n)
+    assert abs(th.var() - (2 * math.pi) ** 2 / 12) < 0.02 * (2 * math.pi) ** 2 / 12
+    # a different seed gives an unrelated sequence
+    th2 = orc.theta0(seed + 1, 2000)
+    assert abs(np.corrcoef(th[:2000], th2)[0, 1]) < 0.1
+    # and the step-0 normals use another counter: uncorrelated with theta0
+    xi = np.array([orc.normal(seed, 0, t) for t in range(2000)])
+    assert abs(np.corrcoef(th[:2000], xi)[0, 1]) < 0.1
