@@ -361,7 +361,9 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
                (int)force_grid(s));
     // rounds 0 .. f-1 over the whole grid; the last one's re-test, later
     // rounds and the step's close in the tail
-    const int f = std::min(s->full_rounds, s->dev_rounds);
+    // while cells move fast (hot), rounds 1 .. 3 are big too: all of them over
+    // the whole grid, so that a step rarely stops for host rounds
+    const int f = std::min(s->hot ? MAX_FULL_ROUNDS : s->full_rounds, s->dev_rounds);
     launch(ev ? &ev[2] : nullptr, k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, s->work,
            (const SysParam*)s->d_sp, s->d_st, 0);
     for (int r = 1; r < f; r++) {

@@ -155,15 +155,39 @@ __device__ __forceinline__ void wave_append(int* list, int* count, int c, bool w
     if (want) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = c;
 }
 
-// append c (if >= 0) to the repair worklist of round r, once per round
-__device__ __forceinline__ void push_flag(const Work& w, DevState* st, int r, int c)
+// append the cells of a failed triangle and its opposite cell (entries < 0
+// skipped) to the repair worklist of round r, each once per round: the four
+// bitmap atomics are in flight together and the wave appends every new entry
+// with one counter atomic (two round trips instead of eight)
+__device__ __forceinline__ void push_flags4(const Work& w, DevState* st, int r, int c0, int c1, int c2, int c3)
 {
-    bool want = false;
-    if (c >= 0) {
-        const unsigned bit = 1u << (c & 31);
-        want = !(atomicOr(&w.flagbits[c >> 5], bit) & bit);
+    const int cs[4] = {c0, c1, c2, c3};
+    unsigned old[4];
+#pragma unroll
+    for (int v = 0; v < 4; v++)
+        old[v] = cs[v] >= 0 ? atomicOr(&w.flagbits[cs[v] >> 5], 1u << (cs[v] & 31)) : ~0u;
+    bool want[4];
+    unsigned long long m[4];
+    int total = 0;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        want[v] = cs[v] >= 0 && !(old[v] & (1u << (cs[v] & 31)));
+        m[v] = __ballot(want[v]);
+        total += __popcll(m[v]);
     }
-    wave_append(w.wl[r & 1], &st->wl_count[r], c, want);
+    if (!total) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&st->wl_count[r], total);
+    base = __shfl(base, leader);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int* list = w.wl[r & 1];
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        if (want[v]) list[base + __popcll(m[v] & below)] = cs[v];
+        base += __popcll(m[v]);
+    }
 }
 
 // append c (if >= 0) to the touched list of round r, once per round
@@ -714,12 +738,7 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
                 // tells them apart (it cannot certify a disk wider than L/2)
                 if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
             }
-            if (fail) {
-                push_flag(w, st, rnext, i);
-                push_flag(w, st, rnext, jm);
-                push_flag(w, st, rnext, jn);
-                if (o >= 0) push_flag(w, st, rnext, o);
-            }
+            if (fail) push_flags4(w, st, rnext, i, jm, jn, o);
             sU[g][m][0] = ux;
             sU[g][m][1] = uy;
         }
@@ -852,12 +871,7 @@ __global__ __launch_bounds__(256) void k_geom_items(Cells<R> c, Work w, const Sy
             const double rlim2 = 0.0625 * fmin(P.Lx, P.Ly) * fmin(P.Lx, P.Ly);
             if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
         }
-        if (fail) {
-            push_flag(w, st, 0, i);
-            push_flag(w, st, 0, jm);
-            push_flag(w, st, 0, jn);
-            if (o >= 0) push_flag(w, st, 0, o);
-        }
+        if (fail) push_flags4(w, st, 0, i, jm, jn, o);
         edge_terms(ux, uy, vx, vy, sT[s][0], sT[s][1]);
     }
     __syncthreads();
