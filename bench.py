@@ -140,6 +140,9 @@ def timed_run(spv, make, steps, warmup, timing=True):
             "steady_value": ncells * half / second if half else None,
             "kernels": kt, "repairs_per_step": float(c1[1] - c0[1]) / steps,
             "rounds_per_step": float(c1[2] - c0[2]) / steps, "E": E, "qbar": qbar, "sumA": sumA,
+            "path": {"graph_periods": int(c1[8] - c0[8]), "dense_steps": int(c1[9] - c0[9]),
+                     "host_rounds": int(c1[10] - c0[10]), "host_recovered_steps": int(c1[11] - c0[11]),
+                     "resorts": int(c1[5] - c0[5])},
             "tuning": tuning}
 
 
@@ -307,6 +310,7 @@ def main():
         "steady_state_value": head["steady_value"],
         "repairs_per_step": head["repairs_per_step"],
         "repair_rounds_per_step": head["rounds_per_step"],
+        "path": head["path"],
         "observables": {"E": head["E"], "qbar": head["qbar"], "sumA": head["sumA"]},
     }
     if not args.headline_only:
@@ -324,7 +328,7 @@ def main():
             d, a_s, bpl, ach = roofline_of(r["kernels"], r["cells"])
             extra[name] = {"value": r["value"], "unit": "cell-steps/s", "ms_per_step": r["ms_per_step"],
                            "cells": r["cells"], "steps": steps, "warmup": warm,
-                           "repairs_per_step": r["repairs_per_step"], "tuning": r["tuning"],
+                           "repairs_per_step": r["repairs_per_step"], "tuning": r["tuning"], "path": r["path"],
                            "kernel_avg_us": {k: (v[0] * 1e3 / max(v[1], 1)) for k, v in r["kernels"].items()},
                            "roofline_frac_hbm": ach / HBM_PEAK_GBS, "dominant_kernel": d}
             print(f"[bench] {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)

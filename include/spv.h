@@ -91,6 +91,11 @@ typedef struct {
                                either way: 1 = lanes per cell, 2 = one thread per (cell, ring
                                slot); 0 = 2 from 2^18 cells on, else 1 */
     double bin_factor;      /* cell-list bin side in mean cell spacings sqrt(Lx Ly / N) (0: 1; 0.5..8) */
+    int32_t dense;          /* first repair rounds of a step (Sec. II.C.4) as dense rounds, which mark
+                               flagged and touched cells in one byte per cell and scan them, instead of
+                               appending them to worklists (suits steps in which a large share of the
+                               cells fails): 0 = while cells move fast (after a random start), 1 =
+                               never, 2 = every step.  Never changes results. */
 } spv_params;
 
 /* Scheduling knobs a handle runs with (see spv_params). */
@@ -186,10 +191,13 @@ spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t
 
 /*
  * Observables of the current state summed over all systems: E (Eq. 1),
- * qbar = mean of P_i/sqrt(A_i), sumA = sum of A_i; counters[8] (host
+ * qbar = mean of P_i/sqrt(A_i), sumA = sum of A_i; counters[12] (host
  * pointer, may be NULL):
  *   [0] steps taken  [1] cells repaired  [2] repair rounds used  [3] exact-arithmetic fallbacks
  *   [4] max ring length written  [5] spatial re-sorts  [6] repair radius retries  [7] error word
+ *   [8] re-sort periods replayed as captured graphs  [9] steps with dense first rounds
+ *   [10] repair rounds run by host recovery  [11] steps finished by host recovery
+ * (statistics since creation or the last load)
  */
 spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA, int64_t* counters);
 

@@ -126,6 +126,7 @@ struct spv_sys {
     int tail_items = 64;    // largest later round the one-block tail takes
     int full_rounds = 1;    // repair rounds over the whole grid before the tail
     int force_mode = 0;     // force kernel: 1 lanes per cell, 2 per (cell, slot) item, 0 by size
+    int dense = 0;          // dense first rounds: 0 while hot, 1 never, 2 always
     // adaptive re-sort: while cells move fast (the drift of a period exceeds
     // drift_limit, one bin side) steps run eagerly and re-sort as soon as
     // the drift passes the limit; a full quiet period returns to graphs
@@ -157,11 +158,16 @@ struct spv_sys {
     int obs_chunks = 1;
     std::vector<void*> allocs;
     // graphs of one period starting in configuration 0 / 1
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // graphs of one period starting in configuration 0 / 1, by period length
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
 
     // bookkeeping
     uint64_t step = 0;
     int64_t resorts = 0;
+    int64_t graph_periods = 0;  // re-sort periods replayed as a captured graph
+    int64_t dense_steps = 0;    // steps whose first repair rounds ran dense
+    int64_t host_rounds = 0;    // repair rounds run by host recovery
+    int64_t recoveries = 0;     // steps finished by host recovery
     spv_status sticky = SPV_OK;
     std::string sticky_msg;
     // timing
@@ -343,6 +349,36 @@ void launch(const EvPair* ev, K kernel, dim3 grid, dim3 block, hipStream_t st, A
 
 // One step on stream `st` from (cfg, parity).  ev: optional event pairs
 // (force, geom, repair round 0) timing those kernels.
+inline bool dense_step(const spv_sys* s) { return s->dense == 2 || (s->dense == 0 && s->hot); }
+// wavefronts of a dense repair round: about one per four cells, at most
+// what the chip holds at once (256 CUs x 4 SIMDs x 4 wavefronts of
+// k_repair_dense's register budget)
+inline unsigned dense_repair_grid(const spv_sys* s) { return (unsigned)std::min(std::max(s->N / 4, 64), 4096); }
+
+// The repair rounds of a dense step: rounds 0 .. nd-1 scan flag and touched
+// bytes over the whole grid, the tail takes the rest from the worklist of
+// round nd.
+template <typename R, bool MULTI, int KC>
+void enqueue_dense_rounds(spv_sys* s, hipStream_t st, const Cells<R>& nxt, const EvPair* ev)
+{
+    const int nd = std::min(DENSE_ROUNDS, s->dev_rounds);
+    const unsigned tg = (grid_for(s->N, DENSE_TCHUNK) + 7u) & ~7u;
+    for (int r = 0; r < nd; r++) {
+        hipLaunchKernelGGL(k_compact_flags, dim3(grid_for(s->N, COMPACT_CELLS)), dim3(256), 0, st, s->work, s->d_st,
+                           r);
+        launch(r == 0 && ev ? &ev[2] : nullptr, k_repair_dense<R, MULTI, KC>, dim3(dense_repair_grid(s)), dim3(64),
+               st, nxt, s->work, (const SysParam*)s->d_sp, s->d_st, r, nd);
+        if (r + 1 < nd)
+            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, false>), dim3(tg), dim3(256), 0, st, nxt, s->work,
+                               (const SysParam*)s->d_sp, s->d_st, s->N, r);
+        else
+            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, true>), dim3(tg), dim3(256), 0, st, nxt, s->work,
+                               (const SysParam*)s->d_sp, s->d_st, s->N, r);
+    }
+    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(tail_grid(s)), dim3(TAIL_THREADS), 0, st, nxt, s->work, s->d_sp,
+                       s->d_st, s->dev_rounds, s->tail_items, nd);
+}
+
 template <typename R, bool MULTI, int KC>
 void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair* ev)
 {
@@ -351,6 +387,18 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair*
     launch(ev ? &ev[0] : nullptr, force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
            nxt.y, nxt.th,
            (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
+    if (dense_step(s)) {
+        if (items_kernel(s))
+            launch(ev ? &ev[1] : nullptr, k_geom_items<R, MULTI, KC, true>,
+                   dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, s->work,
+                   (const SysParam*)s->d_sp, s->d_st, s->N, (const double*)s->d_blockmax, (int)force_grid(s));
+        else
+            launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true, true>, dim3(cg), dim3(256), st,
+                   nxt, s->work, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
+                   (int)force_grid(s));
+        enqueue_dense_rounds<R, MULTI, KC>(s, st, nxt, ev);
+        return;
+    }
     if (items_kernel(s))
         launch(ev ? &ev[1] : nullptr, k_geom_items<R, MULTI, KC>,
                dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, s->work,
@@ -455,6 +503,7 @@ spv_status recover(spv_sys* s)
 {
     if (s->h_st->err) return error_from_word(s);
     int r = s->h_st->halt_round;
+    s->recoveries++;
     hipLaunchKernelGGL(k_set_halt, dim3(1), dim3(64), 0, s->stream, s->d_st, 0);
     while (true) {
         if (r >= s->max_rounds || r >= MAX_ROUNDS) {
@@ -466,6 +515,7 @@ spv_status recover(spv_sys* s)
         dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_round<R, MULTI, KC>(s, s->stream, r, rg); });
         HIP_TRY(hipGetLastError());
         ST_TRY(read_state(s));
+        s->host_rounds++;
         if (s->h_st->err) return error_from_word(s);
         if (s->h_st->wl_count[r + 1] == 0) break;
         r++;
@@ -475,15 +525,18 @@ spv_status recover(spv_sys* s)
     return SPV_OK;
 }
 
-spv_status capture_graph(spv_sys* s, int g)
+// The graph of a period of gu steps (then the re-sort) from configuration g,
+// captured on first use.
+spv_status period_graph(spv_sys* s, int g, int gu, hipGraphExec_t* out)
 {
-    if (s->gexec[g]) {
-        (void)hipGraphExecDestroy(s->gexec[g]);
-        s->gexec[g] = nullptr;
+    auto it = s->graphs.find({g, gu});
+    if (it != s->graphs.end()) {
+        *out = it->second;
+        return SPV_OK;
     }
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-    for (int k = 0; k < s->unit; k++)
+    for (int k = 0; k < gu; k++)
         dispatch(s, [&]<typename R, bool MULTI, int KC>() {
             enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, nullptr);
         });
@@ -492,10 +545,27 @@ spv_status capture_graph(spv_sys* s, int g)
     hipError_t e1 = hipStreamEndCapture(s->cap_stream, &graph);
     if (e1 == hipSuccess && e0 != hipSuccess) e1 = e0;
     if (e1 != hipSuccess) return fail(SPV_EHIP, std::string("graph capture: ") + hipGetErrorString(e1));
-    hipError_t e2 = hipGraphInstantiate(&s->gexec[g], graph, nullptr, nullptr, 0);
+    hipGraphExec_t ex = nullptr;
+    hipError_t e2 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e2 != hipSuccess) return fail(SPV_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    s->graphs[{g, gu}] = ex;
+    *out = ex;
     return SPV_OK;
+}
+
+// Steps per captured period: the re-sort period, or else the longest multiple
+// of 8 steps below it over which the drift bound stays within the limit at
+// the measured drift rate (so that the repair searches stay about as wide as
+// the bins); 0 when not even 8 steps do (the steps then run eagerly, with
+// re-sorts as soon as the drift passes the limit).
+int graph_unit(const spv_sys* s)
+{
+    const double r = s->drift_rate;
+    if (!(r * s->unit > s->drift_limit)) return s->unit;
+    for (int u = (s->unit - 1) / 8 * 8; u >= 8; u -= 8)
+        if (r * u <= s->drift_limit) return u;
+    return 0;
 }
 
 spv_status do_resort_eager(spv_sys* s)
@@ -516,16 +586,24 @@ spv_status run_steps(spv_sys* s, int64_t n)
 {
     if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
     while (n > 0) {
-        if (!(s->pos & 1) && !s->no_resort && s->pos > 0 &&
-            (s->pos >= s->unit || (s->hot && s->h_st->drift > s->drift_limit)))
-            ST_TRY(do_resort_eager(s));
-        if (s->pos == 0 && n >= s->unit && s->use_graphs && !s->timing && !s->no_resort && !s->hot) {
-            const int g = s->cfg;
-            if (!s->gexec[g]) ST_TRY(capture_graph(s, g));
+        if (!(s->pos & 1) && !s->no_resort && s->pos > 0) {
+            // the period's end; while hot, as soon as the drift passes the
+            // limit; after the hot phase, at the end of a period of the length
+            // graphs will take, so that they start from a fresh re-sort
+            const int gq = s->hot ? 0 : graph_unit(s);
+            if (s->pos >= s->unit || (s->hot && s->h_st->drift > s->drift_limit) || (gq > 0 && s->pos >= gq))
+                ST_TRY(do_resort_eager(s));
+        }
+        const int gu = s->hot ? 0 : graph_unit(s);
+        if (s->pos == 0 && gu > 0 && n >= gu && s->use_graphs && !s->timing && !s->no_resort) {
+            hipGraphExec_t ex = nullptr;
+            ST_TRY(period_graph(s, s->cfg, gu, &ex));
             const uint64_t before = s->step;
-            HIP_TRY(hipGraphLaunch(s->gexec[g], s->stream));
+            HIP_TRY(hipGraphLaunch(ex, s->stream));
             ST_TRY(read_state(s));
+            s->graph_periods++;
             const uint64_t done = s->h_st->step - before;
+            if (dense_step(s)) s->dense_steps += (int64_t)done;
             if (s->h_st->halt) {
                 // the period stopped after `done` steps (the last one unfinished);
                 // later kernels, including its re-sort, did nothing
@@ -539,10 +617,12 @@ spv_status run_steps(spv_sys* s, int64_t n)
             n -= (int64_t)done;
             s->cfg ^= 1;
             s->resorts++;
-            if (s->h_st->last_drift > s->drift_limit) {
+            // the drift rate of the period sets the next period's length; too
+            // fast for 8 steps: back to eager steps
+            s->drift_rate = s->h_st->last_drift / (double)done;
+            if (graph_unit(s) == 0) {
                 s->hot = true;
                 s->quiet = 0;
-                s->drift_rate = s->h_st->last_drift / (double)done;
             }
         } else {
             // eager: a batch of steps (up to kEagerBatch, not past the next
@@ -555,6 +635,7 @@ spv_status run_steps(spv_sys* s, int64_t n)
                     b, std::max<int64_t>(1, (int64_t)((s->drift_limit - s->h_st->drift) / s->drift_rate)));
             const uint64_t before = s->step;
             const double drift0 = s->h_st->drift;
+            const bool dense = dense_step(s);
             for (int64_t j = 0; j < b; j++) {
                 EvPair ev[T_COUNT];
                 const EvPair* evp = nullptr;
@@ -577,11 +658,18 @@ spv_status run_steps(spv_sys* s, int64_t n)
             s->step += done;
             s->pos += (int)done;
             n -= (int64_t)done;
+            if (dense) s->dense_steps += (int64_t)done;
             if (s->h_st->halt) ST_TRY(recover(s));
             if (s->hot) {
                 if (done > 0 && !s->h_st->halt) s->drift_rate = (s->h_st->drift - drift0) / (double)done;
-                if (s->h_st->drift > s->drift_limit) s->quiet = 0;
-                else if ((s->quiet += (int)done) >= s->unit) s->hot = false;
+                if (s->h_st->drift > s->drift_limit) {
+                    s->quiet = 0;
+                } else {
+                    // quiet for a whole period of the length the drift rate allows
+                    s->quiet += (int)done;
+                    const int g = graph_unit(s);
+                    if (g > 0 && s->quiet >= g) s->hot = false;
+                }
             }
         }
     }
@@ -599,8 +687,7 @@ void destroy_all(spv_sys* s)
 {
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
-    for (int g = 0; g < 2; g++)
-        if (s->gexec[g]) (void)hipGraphExecDestroy(s->gexec[g]);
+    for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& e : s->pool) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -722,6 +809,13 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     const size_t nwords = (N + 31) / 32;
     ST_TRY(dalloc(s, &s->work.flagbits, nwords));
     ST_TRY(dalloc(s, &s->work.touchbits, nwords));
+    {
+        // flag bytes padded to whole compaction blocks (the padding stays 0)
+        const size_t nf = (size_t)grid_for(N, COMPACT_CELLS) * COMPACT_CELLS;
+        ST_TRY(dalloc(s, &s->work.flag8, nf));
+        HIP_TRY(hipMemsetAsync(s->work.flag8, 0, nf, s->stream));
+    }
+    ST_TRY(dalloc(s, &s->work.touch8, N));
     for (int k = 0; k < 2; k++) {
         ST_TRY(dalloc(s, &s->work.wl[k], N));
         ST_TRY(dalloc(s, &s->work.tl[k], N));
@@ -773,6 +867,8 @@ spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vect
                            hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemsetAsync(s->work.flagbits, 0, nwords * sizeof(unsigned), s->stream));
     HIP_TRY(hipMemsetAsync(s->work.touchbits, 0, nwords * sizeof(unsigned), s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.flag8, 0, N, s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.touch8, 0, N, s->stream));
     ArraySet& A = s->set[0];
     HIP_TRY(hipMemcpyAsync(A.x, hx.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(A.y, hy.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
@@ -796,6 +892,7 @@ spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vect
     s->drift_rate = INFINITY;
     ST_TRY(do_resort_eager(s));
     s->resorts = 0;
+    s->graph_periods = s->dense_steps = s->host_rounds = s->recoveries = 0;
     hipLaunchKernelGGL(k_all_to_worklist, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->work, s->d_st, N);
     int r = 0;
     while (true) {
@@ -847,6 +944,8 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     if (p.bin_order < 0 || p.bin_order > 1) return fail(SPV_EINVAL, "bin_order must be 0 or 1");
     if (p.force_mode < 0 || p.force_mode > 2) return fail(SPV_EINVAL, "force_mode must be 0, 1 or 2");
     s->force_mode = p.force_mode;
+    if (p.dense < 0 || p.dense > 2) return fail(SPV_EINVAL, "dense must be 0, 1 or 2");
+    s->dense = p.dense;
     s->stream = (hipStream_t)stream;
     return SPV_OK;
 }
@@ -1295,6 +1394,8 @@ spv_status restore_checkpoint(spv_sys* s, const TrajCheckpoint& c, bool with_acc
     const size_t nwords = ((size_t)s->N + 31) / 32;
     HIP_TRY(hipMemsetAsync(s->work.flagbits, 0, nwords * sizeof(unsigned), s->stream));
     HIP_TRY(hipMemsetAsync(s->work.touchbits, 0, nwords * sizeof(unsigned), s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.flag8, 0, (size_t)s->N, s->stream));
+    HIP_TRY(hipMemsetAsync(s->work.touch8, 0, (size_t)s->N, s->stream));
     hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s->stream, s->d_st);
     HIP_TRY(hipGetLastError());
     ST_TRY(read_state(s));
@@ -1770,6 +1871,10 @@ spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA
         counters[5] = s->resorts;
         counters[6] = (int64_t)d.retries;
         counters[7] = (int64_t)d.err;
+        counters[8] = s->graph_periods;
+        counters[9] = s->dense_steps;
+        counters[10] = s->host_rounds;
+        counters[11] = s->recoveries;
     }
     return SPV_OK;
 }

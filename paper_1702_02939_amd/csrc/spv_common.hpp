@@ -15,6 +15,7 @@ enum : unsigned {
 };
 
 constexpr int MAX_ROUNDS = 32;  // repair rounds per step (device rounds + host recovery rounds)
+constexpr int DENSE_ROUNDS = 3; // rounds of a dense step (flag bytes scanned by the whole grid)
 
 // Per-system constants (a batch holds several independent systems laid out
 // one after the other; a single system is a batch of one).
@@ -52,6 +53,11 @@ struct DevState {
     // first repair failure (diagnostics for the error message)
     int fail_set, fail_cell, fail_n, fail_k, fail_closed, fail_attempts;
     double fail_R, fail_umax;
+    // dense rounds: some cell was flagged for round r / touched in round r
+    // (plain stores of 1; read by later kernels; cleared when the step closes)
+    int dany[DENSE_ROUNDS + 1];
+    int tany[DENSE_ROUNDS];
+    int dcount[DENSE_ROUNDS];  // cells listed for dense round r
 };
 
 // Per-cell arrays of one configuration (the library keeps two and swaps them
@@ -80,6 +86,9 @@ struct Work {
     unsigned* touchbits;  // cell is in the pending touched list
     int* wl[2];
     int* tl[2];
+    // dense rounds: one byte per cell instead of lists (no append counters)
+    uint8_t* flag8;   // flagged for the current dense round
+    uint8_t* touch8;  // touched by the current dense round's repairs
     // bins (cells are stored in the order of their global bin at the last re-sort)
     const int* bin_key;     // [sum of bins] spatial bin of a system -> global key
     const int* bin_start;   // [total bins + 1], by key

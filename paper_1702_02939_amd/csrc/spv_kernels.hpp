@@ -190,6 +190,25 @@ __device__ __forceinline__ void push_flags4(const Work& w, DevState* st, int r, 
     }
 }
 
+// Where a validity pass sends the cells of a failed triangle (c0 .. c2 >= 0;
+// c3, the opposite cell, may be -1): the worklist of round r (BYTES false),
+// or the flag bytes of dense round r (plain stores of 1, no counter: every
+// writer stores the same value, and the round's repair kernel runs after
+// this kernel has ended)
+template <bool BYTES>
+__device__ __forceinline__ void flag_cells(const Work& w, DevState* st, int r, int c0, int c1, int c2, int c3)
+{
+    if (BYTES) {
+        w.flag8[c0] = 1;
+        w.flag8[c1] = 1;
+        w.flag8[c2] = 1;
+        if (c3 >= 0) w.flag8[c3] = 1;
+        st->dany[r] = 1;
+    } else {
+        push_flags4(w, st, r, c0, c1, c2, c3);
+    }
+}
+
 // append c (if >= 0) to the touched list of round r, once per round
 __device__ __forceinline__ void push_touch(const Work& w, DevState* st, int r, int c)
 {
@@ -639,7 +658,11 @@ __device__ __forceinline__ void close_drift(DevState* st, const double* __restri
 // EXACT = false (the all-cells pass): a predicate that the double filter
 // cannot decide flags the cell instead of being evaluated exactly; the
 // repair and the exact re-test of the touched cells then settle it.
-template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool EXACT = true>
+// DM_TBYTES: the list holds cells whose touched byte the caller cleared (no
+// touched bit to clear); DM_FBYTES: failures go to the flag bytes of dense
+// round rnext instead of its worklist.
+enum : int { DM_TBYTES = 1, DM_FBYTES = 2 };
+template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool EXACT = true, int DM = 0>
 __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, const SysParam* __restrict__ sp,
                                           DevState* st, int base, int n, const int* __restrict__ list, int rnext,
                                           const GeomLds<R, KC>& S, int& exact)
@@ -652,7 +675,7 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
     const int t = base + g;
     const bool valid = t < n;
     const int i = valid ? (LIST ? list[t] : t) : 0;
-    if (LIST && valid && l == 0) atomicAnd(&w.touchbits[i >> 5], ~(1u << (i & 31)));
+    if (LIST && !(DM & DM_TBYTES) && valid && l == 0) atomicAnd(&w.touchbits[i >> 5], ~(1u << (i & 31)));
     const SysParam& P = sp[MULTI ? c.sys[i] : 0];
     int k = valid ? c.deg[i] : 0;
     if (valid && (k < 3 || k > KC)) {
@@ -738,7 +761,7 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
                 // tells them apart (it cannot certify a disk wider than L/2)
                 if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
             }
-            if (fail) push_flags4(w, st, rnext, i, jm, jn, o);
+            if (fail) flag_cells<(DM & DM_FBYTES) != 0>(w, st, rnext, i, jm, jn, o);
             sU[g][m][0] = ux;
             sU[g][m][1] = uy;
         }
@@ -780,7 +803,7 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
 // registers without spilling, and its blocks then need fewer rounds (the
 // batched variant would spill; the exact list passes keep their larger
 // register budget).
-template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool STEP = false>
+template <typename R, bool MULTI, int KC, bool LIST, bool OPP, bool STEP = false, bool DENSE = false>
 __global__ __launch_bounds__(256, (STEP && !MULTI && KC == 16) ? 7 : 1) void k_geom(Cells<R> c, Work w, const SysParam* __restrict__ sp, DevState* st,
                                               int N, int round, const double* __restrict__ blockmax = nullptr,
                                               int nblk = 0)
@@ -796,7 +819,8 @@ __global__ __launch_bounds__(256, (STEP && !MULTI && KC == 16) ? 7 : 1) void k_g
     const GeomLds<R, KC> S{sD, sU, sJ};
     int exact = 0;
     for (int base = bstart * CPB; base < n; base += gridDim.x * CPB)
-        geom_pass<R, MULTI, KC, LIST, OPP, !STEP>(c, w, sp, st, base, n, list, rnext, S, exact);
+        geom_pass<R, MULTI, KC, LIST, OPP, !STEP, DENSE ? DM_FBYTES : 0>(c, w, sp, st, base, n, list, rnext, S,
+                                                                         exact);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
     if (STEP && blockIdx.x == 0) close_drift(st, blockmax, nblk);
 }
@@ -806,7 +830,7 @@ __global__ __launch_bounds__(256, (STEP && !MULTI && KC == 16) ? 7 : 1) void k_g
 // STEP: the same filters, and the area and perimeter summed in its order).
 // An item computes u_m and u_{m+1} itself, tests triangle (i, j_m, j_{m+1})
 // against opp_m and writes its edge's area and perimeter terms.
-template <typename R, bool MULTI, int KC>
+template <typename R, bool MULTI, int KC, bool DENSE = false>
 __global__ __launch_bounds__(256) void k_geom_items(Cells<R> c, Work w, const SysParam* __restrict__ sp,
                                                     DevState* st, int N, const double* __restrict__ blockmax, int nblk)
 {
@@ -871,7 +895,7 @@ __global__ __launch_bounds__(256) void k_geom_items(Cells<R> c, Work w, const Sy
             const double rlim2 = 0.0625 * fmin(P.Lx, P.Ly) * fmin(P.Lx, P.Ly);
             if (!fail && (double)(ux * ux + uy * uy) >= rlim2) fail = true;
         }
-        if (fail) push_flags4(w, st, 0, i, jm, jn, o);
+        if (fail) flag_cells<DENSE>(w, st, 0, i, jm, jn, o);
         edge_terms(ux, uy, vx, vy, sT[s][0], sT[s][1]);
     }
     __syncthreads();
@@ -930,7 +954,8 @@ struct RepairLds {
     int cap;      // capacity of sx .. stg
 };
 
-constexpr int KMAX = 64;  // longest ring a repair may trace
+constexpr int KMAX = 64;      // longest ring a repair may trace
+constexpr int STAR_MAX = 48;  // most candidates the parallel star takes
 
 // Wave-level barrier: the lanes of one wavefront exchange LDS data with no
 // workgroup barrier (several wavefronts of a block repair different cells).
@@ -1075,7 +1100,9 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
 // defer_on_cap: more candidates than L.cap leave the cell untouched and
 // return false (the caller hands the round to a larger kernel); otherwise
 // that is a capacity error.  Returns true when the ring was rewritten.
-template <typename R, bool MULTI, int KC>
+// DENSE: the cell's flag byte was cleared by the caller, and the touched
+// cells are marked in the touched bytes of dense round `round`.
+template <typename R, bool MULTI, int KC, bool DENSE = false>
 __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __restrict__ sp, DevState* st, int round,
                            int i, double drift, const RepairLds& L, bool defer_on_cap, bool& deferred, int& exact)
 {
@@ -1085,7 +1112,7 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
     int* __restrict__ sid = L.sid;
     int* __restrict__ stg = L.stg;
     int* __restrict__ s_ring = L.s_ring;
-    if (lane == 0) atomicAnd(&w.flagbits[i >> 5], ~(1u << (i & 31)));
+    if (!DENSE && lane == 0) atomicAnd(&w.flagbits[i >> 5], ~(1u << (i & 31)));
     const SysParam& P = sp[MULTI ? c.sys[i] : 0];
     const double xi = c.x[i], yi = c.y[i];
     const int kold = min((int)c.deg[i], KC);
@@ -1150,7 +1177,10 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
             break;
         }
         bool closed = false;
-        k = star_parallel(sx, sy, n, s_ring, L.s_tmp, P.scale, closed);
+        // the parallel star costs n^2 / 64 key evaluations per lane, the
+        // sequential wrap about 7 n / 64 plus a wave reduction per member:
+        // past STAR_MAX candidates the wrap is cheaper
+        k = n <= STAR_MAX ? star_parallel(sx, sy, n, s_ring, L.s_tmp, P.scale, closed) : -1;
         if (k < 0) {
             // exact sequential construction: from the nearest candidate (exact
             // squared distance in grid units, ties by tag), gift-wrapping
@@ -1288,9 +1318,14 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
         last_umax = umax;
         if (!ok) {
             if (at_max) break;
-            // an uncertified star may be wrong (outer triangles clipped by
-            // the search disk), so its circumradii say nothing: double R
-            Rs = fmin(2.0 * Rs, Rmax);
+            // a closed star that is not certified is usually right with a
+            // circumdisk reaching just past the search disk: the next radius
+            // is the one that would certify it, between 1.25 R and 2 R.  An
+            // uncertified star may also be wrong (outer triangles clipped by
+            // the disk; its circumradii then say little, and may be huge): R
+            // never more than doubles, and from the fourth attempt on, or for
+            // an open star, it doubles.
+            Rs = fmin((closed && attempt < 3) ? fmin(fmax(2.02 * umax, 1.25 * Rs), 2.0 * Rs) : 2.0 * Rs, Rmax);
             at_max = (Rs >= Rmax);
             if (lane == 0) atomicAdd(&st->retries, 1ull);
         }
@@ -1336,8 +1371,14 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
     int t = lane < 32 ? qold : qnew;
     const bool self_lane = (lane == 31 && kold < 32) || (lane == 63 && k < 32);
     if (self_lane && t < 0) t = i;
-    push_touch(w, st, round, t);
-    if (kold >= 32 && k >= 32) push_touch(w, st, round, lane == 0 ? i : -1);
+    if (DENSE) {
+        if (t >= 0) w.touch8[t] = 1;
+        if (kold >= 32 && k >= 32 && lane == 0) w.touch8[i] = 1;
+        if (lane == 0) st->tany[round] = 1;
+    } else {
+        push_touch(w, st, round, t);
+        if (kold >= 32 && k >= 32) push_touch(w, st, round, lane == 0 ? i : -1);
+    }
     wave_sync();
     if (qnew >= 0) c.ring[i * KC + (lane - 32)] = qnew;
     if (lane == 0) c.deg[i] = (uint8_t)k;
@@ -1364,6 +1405,131 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
     for (int wi = blockIdx.x; wi < nw; wi += gridDim.x)
         nrep += repair_one<R, MULTI, KC>(c, w, sp, st, round, wl[wi], drift, L, false, deferred, exact) ? 1 : 0;
     if (threadIdx.x == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
+    if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
+}
+
+// ---------------------------------------------------------------- dense rounds
+// While many cells fail per step (the transient after a random start: about
+// a fifth of all cells in the first steps), appending each flagged or
+// touched cell to a list through one counter serialises the grid on that
+// counter.  A dense step instead marks cells in one byte per cell (plain
+// stores, no counter).  Round r then compacts the flag bytes into a list
+// (one counter atomic per block of 1024 cells), repairs the list with a
+// fixed grid of wavefronts, one cell at a time each (balanced to within one
+// cell per wavefront), and re-tests the touched cells, each block compacting
+// its 64 cells' touched bytes in LDS.  A repair wavefront keeps RP_DENSE
+// candidates in LDS (a small footprint, so that many wavefronts share a
+// compute unit); a cell with more candidates is handed to the worklist of
+// round nd (the number of dense rounds), which the tail and the host rounds
+// take with their larger capacities.  The last dense re-test also sends its
+// failures to that worklist; the tail then runs the later rounds.  Dense
+// round r lists its cells in tl[r & 1] (count dcount[r]); the worklists wl
+// and the touched counters are left to the rounds from nd on.
+constexpr int RP_DENSE = 160;      // candidates a dense repair holds
+constexpr int DENSE_TCHUNK = 64;   // cells scanned per re-test block
+constexpr int COMPACT_CELLS = 1024;  // flag bytes per compaction block (4 per thread)
+
+// append cell i to the worklist of round r, once per round (rare: a dense
+// repair with more than RP_DENSE candidates)
+__device__ __forceinline__ void push_one(const Work& w, DevState* st, int r, int i)
+{
+    const unsigned bit = 1u << (i & 31);
+    if (!(atomicOr(&w.flagbits[i >> 5], bit) & bit)) w.wl[r & 1][atomicAdd(&st->wl_count[r], 1)] = i;
+}
+
+// flag bytes of dense round r -> list tl[r & 1] (count dcount[r]); the bytes
+// are cleared.  flag8 is padded with zeros to a multiple of COMPACT_CELLS.
+__global__ __launch_bounds__(256) void k_compact_flags(Work w, DevState* st, int r)
+{
+    __shared__ int s_sum[4];
+    __shared__ int s_base;
+    if (st->halt || !st->dany[r]) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int c0 = blockIdx.x * COMPACT_CELLS + 4 * t;
+    unsigned v = *reinterpret_cast<const unsigned*>(w.flag8 + c0);
+    const int cnt = ((v & 0xffu) != 0) + ((v & 0xff00u) != 0) + ((v & 0xff0000u) != 0) + ((v >> 24) != 0);
+    int incl = cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(incl, off);
+        if (lane >= off) incl += u;
+    }
+    if (lane == 63) s_sum[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        before += k < wv ? s_sum[k] : 0;
+        total += s_sum[k];
+    }
+    if (total == 0) return;
+    if (t == 0) s_base = atomicAdd(&st->dcount[r], total);
+    __syncthreads();
+    if (cnt) {
+        int* __restrict__ list = w.tl[r & 1];
+        int pos = s_base + before + incl - cnt;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if ((v >> (8 * k)) & 0xffu) list[pos++] = c0 + k;
+        *reinterpret_cast<unsigned*>(w.flag8 + c0) = 0u;
+    }
+}
+
+// the repair of dense round r: wavefront g takes list entries g, g + grid, ...
+template <typename R, bool MULTI, int KC>
+__global__ __launch_bounds__(64, 4) void k_repair_dense(Cells<R> c, Work w, const SysParam* __restrict__ sp,
+                                                        DevState* st, int round, int nd)
+{
+    __shared__ double sx[RP_DENSE], sy[RP_DENSE];
+    __shared__ int sid[RP_DENSE], stg[RP_DENSE];
+    __shared__ int s_n;
+    __shared__ int s_ring[KMAX + 1], s_tmp[KMAX + 1];
+    if (st->halt || !st->dany[round]) return;
+    const int nw = st->dcount[round];
+    if ((int)blockIdx.x >= nw) return;
+    const int* __restrict__ list = w.tl[round & 1];
+    const double drift = st->drift;
+    const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, s_tmp, RP_DENSE};
+    int exact = 0, nrep = 0;
+    for (int wi = blockIdx.x; wi < nw; wi += gridDim.x) {
+        const int i = list[wi];
+        bool deferred = false;
+        nrep += repair_one<R, MULTI, KC, true>(c, w, sp, st, round, i, drift, L, true, deferred, exact) ? 1 : 0;
+        if (deferred && threadIdx.x == 0) push_one(w, st, nd, i);
+    }
+    if (threadIdx.x == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
+    if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
+}
+
+// LAST: the re-test of the last dense round (failures to the worklist of
+// round round + 1 = nd)
+template <typename R, bool MULTI, int KC, bool LAST>
+__global__ __launch_bounds__(256) void k_retest_dense(Cells<R> c, Work w, const SysParam* __restrict__ sp,
+                                                      DevState* st, int N, int round)
+{
+    __shared__ double sD[CPB][KC][2];
+    __shared__ R sU[CPB][KC][2];
+    __shared__ int sJ[CPB][KC];
+    __shared__ int s_list[DENSE_TCHUNK];
+    __shared__ int s_n;
+    static_assert(DENSE_TCHUNK == 64, "one wavefront scans the block's cells");
+    if (st->halt || !st->tany[round]) return;
+    if (threadIdx.x < 64) {
+        const int cell = xcd_block(blockIdx.x, gridDim.x) * DENSE_TCHUNK + threadIdx.x;
+        const bool t = cell < N && w.touch8[cell] != 0;
+        if (t) w.touch8[cell] = 0;
+        const unsigned long long m = __ballot(t);
+        if (t) s_list[__popcll(m & ((1ull << threadIdx.x) - 1ull))] = cell;
+        if (threadIdx.x == 0) s_n = __popcll(m);
+    }
+    __syncthreads();
+    const int n = s_n;
+    if (n == 0) return;
+    const GeomLds<R, KC> S{sD, sU, sJ};
+    int exact = 0;
+    for (int b = 0; b < n; b += CPB)
+        geom_pass<R, MULTI, KC, true, true, true, LAST ? DM_TBYTES : (DM_TBYTES | DM_FBYTES)>(
+            c, w, sp, st, b, n, s_list, round + 1, S, exact);
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
 }
 
@@ -1461,7 +1627,8 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
         int u = 0, w1 = 0;
 #pragma unroll
         for (int v = 0; v <= MAX_FULL_ROUNDS; v++) {
-            if (v < f) u += cnt[v] > 0 ? 1 : 0;
+            // a round before f had work: its worklist, or its flag bytes (dense)
+            if (v < f) u += (cnt[v] > 0 || (v < DENSE_ROUNDS && st->dany[v])) ? 1 : 0;
             if (v == f) w1 = cnt[v];
         }
         s_w0 = u;  // full-grid rounds that had work
@@ -1519,6 +1686,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
     }
     for (int v = 0; v <= rounds; v++) st->wl_count[v] = 0;
     for (int v = 0; v < rounds; v++) st->tl_count[v] = 0;
+    for (int v = 0; v <= DENSE_ROUNDS; v++) st->dany[v] = 0;
+    for (int v = 0; v < DENSE_ROUNDS; v++) {
+        st->tany[v] = 0;
+        st->dcount[v] = 0;
+    }
 }
 
 // host recovery finished: clear the per-step counters and resume
@@ -1527,6 +1699,11 @@ __global__ void k_resume(DevState* st)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     for (int r = 0; r <= MAX_ROUNDS; r++) st->wl_count[r] = 0;
     for (int r = 0; r < MAX_ROUNDS; r++) st->tl_count[r] = 0;
+    for (int r = 0; r <= DENSE_ROUNDS; r++) st->dany[r] = 0;
+    for (int r = 0; r < DENSE_ROUNDS; r++) {
+        st->tany[r] = 0;
+        st->dcount[r] = 0;
+    }
     st->halt = 0;
 }
 

@@ -5,9 +5,9 @@ the same positions.  Plus the largest ring capacity.
 
 Tolerances: rings bit-exact; FP64 forces within 1e-10 * max(max|F|, K_P P0)
 per system; mixed precision (FP32 geometry and forces on FP64 predicates and
-positions) within 2e-5 of that scale at the maximum and 5e-6 in the relative
-2-norm (measured: at most 4e-6 and 1.3e-6 over N = 1e6 and the 256 systems of
-the sweep, 20 steps after a random start)."""
+positions) within 2e-5 of that scale at the maximum and 5e-6 of it in the
+root mean square (FP32 rounding follows the size of the summed terms, not
+|F|, which vanishes as a system relaxes)."""
 import math
 
 import numpy as np
@@ -43,10 +43,15 @@ def _forces_ok(gfx, gfy, fx, fy, P0max, mixed):
     dF = np.hypot(gfx - fx, gfy - fy)
     scale = max(F.max(), P0max)
     if mixed:
+        # FP32 rounding scales with the terms summed into a force (the energy
+        # coefficients times geometric derivatives: the force scale), not with
+        # |F|, which goes to zero as the system relaxes: both bounds are
+        # relative to the scale (the 2-norm relative to |F| is printed)
+        rms = np.sqrt((dF ** 2).mean()) / scale
         l2 = np.sqrt((dF ** 2).sum() / (F ** 2).sum())
         print(f"mixed: max|dF|/scale = {dF.max() / scale:.3e}, p99.9 = {np.quantile(dF, 0.999) / scale:.3e}, "
-              f"|dF|_2/|F|_2 = {l2:.3e}")
-        assert dF.max() < 2e-5 * scale and l2 < 5e-6, (dF.max() / scale, l2)
+              f"rms|dF|/scale = {rms:.3e}, |dF|_2/|F|_2 = {l2:.3e}")
+        assert dF.max() < 2e-5 * scale and rms < 5e-6, (dF.max() / scale, rms)
     else:
         assert dF.max() <= 1e-10 * scale, dF.max() / scale
 
@@ -70,7 +75,35 @@ def test_n1m_after_steps(spv, precision):
     s.close()
 
 
-def test_batched_sweep_full(spv):
+@pytest.mark.parametrize("p0,steps", [(3.9, 600), (4.0, 200)], ids=["p0_3.9_600", "p0_4.0_200"])
+def test_n100k_after_transient(spv, p0, steps):
+    """spv_n100k in the benchmark's launch configuration (tuned knobs) run
+    past the random-start transient, so that whole re-sort periods replay as
+    captured graphs (p0 = 3.9; counted), then every ring and force against
+    the oracle; and the fluid end of the sweep (p0 = 4.0, FP64)."""
+    w = inputs.WORKLOADS["spv_n100k"]
+    n, L = w["N"], w["L"]
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    s = spv.System(x, y, L, L, p0=p0, params=spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"],
+                                                          seed=w["seed"], autotune=1))
+    s.step(steps)
+    gx, gy = s.positions()
+    Lx, Ly, q = s.box()
+    off, ring = _check(s, gx, gy, Lx, Ly, q)
+    fx, fy = oracle.forces(gx, gy, Lx, Ly, off, ring, 1.0, p0)
+    gfx, gfy = s.forces()
+    _forces_ok(gfx, gfy, fx, fy, p0, False)
+    E, qbar, sumA, cnt = s.observables()
+    assert cnt[0] == steps and cnt[7] == 0
+    if p0 == 3.9:
+        assert cnt[8] > 0, "no re-sort period replayed as a graph"
+    s.close()
+
+
+@pytest.mark.parametrize("steps", [20, 600])
+def test_batched_sweep_full(spv, steps):
+    """The 256-system sweep (mixed precision, tuned knobs): early in the
+    transient, and after 600 steps, when whole periods replay as graphs."""
     systems = inputs.batch_systems()
     N_s = [v["N"] for v in systems]
     L_s = [v["L"] for v in systems]
@@ -78,7 +111,10 @@ def test_batched_sweep_full(spv):
                          np.concatenate([v["y"] for v in systems]), [v["p0"] for v in systems],
                          v0_s=[v["v0"] for v in systems], seed_s=[v["seed"] for v in systems],
                          params=spv.Params(mu=1.0, Dr=1.0, dt=0.01, precision=spv.SPV_MIXED, autotune=1))
-    b.step(20)
+    b.step(steps)
+    cnt = b.observables()[3]
+    if steps >= 600:
+        assert cnt[8] > 0, "no re-sort period replayed as a graph"
     gx, gy = b.positions()
     gfx, gfy = b.forces()
     goff, gring = b.neighbors()

@@ -259,23 +259,80 @@ def test_device_pointer_inputs_and_outputs(spv):
 
 # ---------------------------------------------------------------- launch paths, batches, precision
 
-def _run(spv, x, y, L, steps_seq, **kw):
+def _run(spv, x, y, L, steps_seq, counters=False, **kw):
     s = spv.System(x, y, L, L, p0=3.9, params=spv.Params(v0=0.1, seed=21, **kw))
     for k in steps_seq:
         s.step(k)
     out = (*s.positions(), s.directors(), *s.neighbors())
+    cnt = s.observables()[3]
     s.close()
-    return out
+    return (out, cnt) if counters else out
 
 
 def test_graph_and_eager_paths_bitwise_equal(spv):
+    """A long enough run leaves the fast-moving start, so whole re-sort
+    periods replay as captured graphs (counted); the trajectory is bitwise
+    that of all-eager launches and of other step-count splits."""
     n = 2000
     x, y, L, _ = _random_case(n, 51)
-    a = _run(spv, x, y, L, [37], resort_every=8)                 # 4 graph periods + 5 eager steps
-    b = _run(spv, x, y, L, [37], resort_every=8, no_graphs=1)    # all eager
-    c = _run(spv, x, y, L, [1, 2, 3, 31], resort_every=8)       # mixed boundaries
+    a, ca = _run(spv, x, y, L, [301], counters=True, resort_every=8)      # graph periods + eager steps
+    b, cb = _run(spv, x, y, L, [301], counters=True, resort_every=8, no_graphs=1)
+    c = _run(spv, x, y, L, [1, 2, 3, 31, 264], resort_every=8)            # mixed boundaries
+    assert ca[8] > 0, "no re-sort period was replayed as a graph"
+    assert cb[8] == 0
     for u, v, w in zip(a, b, c):
         assert np.array_equal(u, v) and np.array_equal(u, w)
+    Lx = Ly = L
+    gx, gy = a[0], a[1]
+    s = spv.System(gx, gy, Lx, Ly, p0=3.9)
+    Lq, _, q = s.box()
+    s.close()
+    off, ring, _, _ = oracle.triangulate(gx, gy, Lq, Lq, q)
+    assert np.array_equal(a[3], off) and np.array_equal(a[4], ring)
+
+
+def test_dense_rounds_bitwise_equal(spv):
+    """Dense first rounds (flag and touched bytes scanned by the whole grid)
+    and worklist rounds give the same trajectory bit for bit: from the random
+    start, where a large share of the cells fails every step, on into the
+    quiet phase; and the topology is the oracle's."""
+    n = 3000
+    x, y, L, _ = _random_case(n, 53)
+    a, ca = _run(spv, x, y, L, [90], counters=True, resort_every=8, dense=1)  # never
+    b, cb = _run(spv, x, y, L, [90], counters=True, resort_every=8, dense=2)  # every step, graphs too
+    c, cc = _run(spv, x, y, L, [90], counters=True, resort_every=8)           # while cells move fast
+    assert ca[9] == 0 and cb[9] == 90 and cc[9] > 0
+    for u, v, w in zip(a, b, c):
+        assert np.array_equal(u, v) and np.array_equal(u, w)
+    s = spv.System(a[0], a[1], L, L, p0=3.9)
+    Lq, _, q = s.box()
+    s.close()
+    off, ring, _, _ = oracle.triangulate(a[0], a[1], Lq, Lq, q)
+    assert np.array_equal(a[3], off) and np.array_equal(a[4], ring)
+
+
+def test_dense_repair_hands_crowded_cells_on(spv):
+    """A crowded start (300 cells in a disk of radius 1.2 inside a uniform
+    system) gives repairs with more candidates than a dense repair holds;
+    those go to the worklist rounds and the host rounds, and the result is
+    still bitwise the worklist path's and the oracle's triangulation."""
+    n = 2000
+    L = math.sqrt(n)
+    x, y = inputs.uniform_positions(n, L, L, 54)
+    rng = np.random.default_rng(55)
+    r = 1.2 * np.sqrt(rng.uniform(0.0, 1.0, 300))
+    t = rng.uniform(0.0, 2.0 * math.pi, 300)
+    x[:300] = 0.5 * L + r * np.cos(t)
+    y[:300] = 0.5 * L + r * np.sin(t)
+    a = _run(spv, x, y, L, [12], resort_every=8, dense=1)
+    b, cb = _run(spv, x, y, L, [12], counters=True, resort_every=8, dense=2)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    s = spv.System(b[0], b[1], L, L, p0=3.9)
+    Lq, _, q = s.box()
+    s.close()
+    off, ring, _, _ = oracle.triangulate(b[0], b[1], Lq, Lq, q)
+    assert np.array_equal(b[3], off) and np.array_equal(b[4], ring)
 
 
 def test_host_recovery_rounds_bitwise_equal(spv):
@@ -351,10 +408,11 @@ def test_mixed_precision_forces_and_topology(spv):
     dF = np.hypot(gfx - fx, gfy - fy)
     scale = max(F.max(), 3.9)
     rel = dF.max() / scale
+    rms = np.sqrt((dF ** 2).mean()) / scale
     l2 = np.sqrt((dF ** 2).sum() / (F ** 2).sum())
-    print(f"mixed precision: max|dF|/scale = {rel:.3e}, |dF|_2/|F|_2 = {l2:.3e}, p99.9 = "
-          f"{np.quantile(dF, 0.999) / scale:.3e}")
-    assert rel < 2e-5 and l2 < 5e-6
+    print(f"mixed precision: max|dF|/scale = {rel:.3e}, rms|dF|/scale = {rms:.3e}, |dF|_2/|F|_2 = {l2:.3e}, "
+          f"p99.9 = {np.quantile(dF, 0.999) / scale:.3e}")
+    assert rel < 2e-5 and rms < 5e-6
     A, P = oracle.geometry(gx, gy, Lx, Ly, off, ring)
     gA, gP = s.geometry()
     assert np.abs(gA - A).max() < 1e-5 and np.abs(gP - P).max() < 1e-5
