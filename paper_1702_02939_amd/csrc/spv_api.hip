@@ -151,6 +151,9 @@ struct spv_sys {
     int *d_bin_key = nullptr, *d_bin_start = nullptr, *d_key = nullptr, *d_hist = nullptr, *d_fill = nullptr;
     int *d_perm = nullptr, *d_inv = nullptr, *d_chunk = nullptr;
     int2* d_bin_range = nullptr;
+    // cell list of a step (while hot)
+    int *d_cbin = nullptr, *d_cslot = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_ccells = nullptr;
+    int* d_cchunk = nullptr;
     DevState* d_st = nullptr;
     DevState* h_st = nullptr;  // pinned copy
     double *d_stage = nullptr, *d_fx = nullptr, *d_fy = nullptr, *d_obs = nullptr, *d_blockmax = nullptr;
@@ -349,7 +352,34 @@ void launch(const EvPair* ev, K kernel, dim3 grid, dim3 block, hipStream_t st, A
 
 // One step on stream `st` from (cfg, parity).  ev: optional event pairs
 // (force, geom, repair round 0) timing those kernels.
-inline bool dense_step(const spv_sys* s) { return s->dense == 2 || (s->dense == 0 && s->hot); }
+inline bool dense_step(const spv_sys* s, bool hot) { return s->dense == 2 || (s->dense == 0 && hot); }
+
+// the work lists, with this step's cell list for the repairs when cur
+Work work_for(const spv_sys* s, bool cur)
+{
+    Work w = s->work;
+    w.cur_start = cur ? s->d_cstart : nullptr;
+    w.cur_cells = cur ? s->d_ccells : nullptr;
+    return w;
+}
+
+// this step's cell list of the positions in c
+template <typename R, bool MULTI>
+void enqueue_cell_list(spv_sys* s, hipStream_t st, const Cells<R>& c)
+{
+    const int N = s->N, nb = s->total_bins;
+    const unsigned nchunk = grid_for(nb, SCAN_CHUNK);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_ccount, nb, 0);
+    hipLaunchKernelGGL((k_cur_bins<R, MULTI>), dim3(grid_for(N, 256)), dim3(256), 0, st, c, (const SysParam*)s->d_sp,
+                       (const DevState*)s->d_st, N, s->d_cbin, s->d_cslot, s->d_ccount);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nchunk), dim3(256), 0, st, (const int*)s->d_ccount, nb, s->d_cchunk,
+                       (const DevState*)s->d_st);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(256), 0, st, s->d_cchunk, (int)nchunk, (const DevState*)s->d_st);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nchunk), dim3(256), 0, st, (const int*)s->d_ccount, s->d_cstart, nb,
+                       (const int*)s->d_cchunk, (const DevState*)s->d_st);
+    hipLaunchKernelGGL(k_cur_place, dim3(grid_for(N, 256)), dim3(256), 0, st, (const int*)s->d_cbin,
+                       (const int*)s->d_cslot, (const int*)s->d_cstart, s->d_ccells, N, (const DevState*)s->d_st);
+}
 // wavefronts of a dense repair round: about one per four cells, at most
 // what the chip holds at once (256 CUs x 4 SIMDs x 4 wavefronts of
 // k_repair_dense's register budget)
@@ -359,67 +389,71 @@ inline unsigned dense_repair_grid(const spv_sys* s) { return (unsigned)std::min(
 // bytes over the whole grid, the tail takes the rest from the worklist of
 // round nd.
 template <typename R, bool MULTI, int KC>
-void enqueue_dense_rounds(spv_sys* s, hipStream_t st, const Cells<R>& nxt, const EvPair* ev)
+void enqueue_dense_rounds(spv_sys* s, hipStream_t st, const Cells<R>& nxt, const Work& wk, const EvPair* ev)
 {
     const int nd = std::min(DENSE_ROUNDS, s->dev_rounds);
     const unsigned tg = (grid_for(s->N, DENSE_TCHUNK) + 7u) & ~7u;
     for (int r = 0; r < nd; r++) {
-        hipLaunchKernelGGL(k_compact_flags, dim3(grid_for(s->N, COMPACT_CELLS)), dim3(256), 0, st, s->work, s->d_st,
+        hipLaunchKernelGGL(k_compact_flags, dim3(grid_for(s->N, COMPACT_CELLS)), dim3(256), 0, st, wk, s->d_st,
                            r);
         launch(r == 0 && ev ? &ev[2] : nullptr, k_repair_dense<R, MULTI, KC>, dim3(dense_repair_grid(s)), dim3(64),
-               st, nxt, s->work, (const SysParam*)s->d_sp, s->d_st, r, nd);
+               st, nxt, wk, (const SysParam*)s->d_sp, s->d_st, r, nd);
         if (r + 1 < nd)
-            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, false>), dim3(tg), dim3(256), 0, st, nxt, s->work,
+            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, false>), dim3(tg), dim3(256), 0, st, nxt, wk,
                                (const SysParam*)s->d_sp, s->d_st, s->N, r);
         else
-            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, true>), dim3(tg), dim3(256), 0, st, nxt, s->work,
+            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, true>), dim3(tg), dim3(256), 0, st, nxt, wk,
                                (const SysParam*)s->d_sp, s->d_st, s->N, r);
     }
-    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(tail_grid(s)), dim3(TAIL_THREADS), 0, st, nxt, s->work, s->d_sp,
+    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(tail_grid(s)), dim3(TAIL_THREADS), 0, st, nxt, wk, s->d_sp,
                        s->d_st, s->dev_rounds, s->tail_items, nd);
 }
 
+// hot: the step of the fast-moving phase (its repairs search a cell list of
+// the step's positions; dense first rounds unless switched off)
 template <typename R, bool MULTI, int KC>
-void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair* ev)
+void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair* ev, bool hot)
 {
     Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
     const unsigned cg = cell_grid(s), rg = repair_grid(s);
     launch(ev ? &ev[0] : nullptr, force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
            nxt.y, nxt.th,
            (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
-    if (dense_step(s)) {
+    if (hot) enqueue_cell_list<R, MULTI>(s, st, nxt);
+    const Work wk = work_for(s, hot);
+    if (dense_step(s, hot)) {
         if (items_kernel(s))
             launch(ev ? &ev[1] : nullptr, k_geom_items<R, MULTI, KC, true>,
-                   dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, s->work,
+                   dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, wk,
                    (const SysParam*)s->d_sp, s->d_st, s->N, (const double*)s->d_blockmax, (int)force_grid(s));
         else
             launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true, true>, dim3(cg), dim3(256), st,
-                   nxt, s->work, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
+                   nxt, wk, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
                    (int)force_grid(s));
-        enqueue_dense_rounds<R, MULTI, KC>(s, st, nxt, ev);
+        enqueue_dense_rounds<R, MULTI, KC>(s, st, nxt, wk, ev);
         return;
     }
     if (items_kernel(s))
         launch(ev ? &ev[1] : nullptr, k_geom_items<R, MULTI, KC>,
-               dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, s->work,
+               dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, wk,
                (const SysParam*)s->d_sp, s->d_st, s->N, (const double*)s->d_blockmax, (int)force_grid(s));
     else
         launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt,
-               s->work, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
+               wk, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
                (int)force_grid(s));
     // rounds 0 .. f-1 over the whole grid; the last one's re-test, later
     // rounds and the step's close in the tail
     // while cells move fast (hot), rounds 1 .. 3 are big too: all of them over
     // the whole grid, so that a step rarely stops for host rounds
-    const int f = std::min(s->hot ? MAX_FULL_ROUNDS : s->full_rounds, s->dev_rounds);
-    launch(ev ? &ev[2] : nullptr, k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, s->work,
+    const int f = std::min(hot ? MAX_FULL_ROUNDS : s->full_rounds, s->dev_rounds);
+    launch(ev ? &ev[2] : nullptr, k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, wk,
            (const SysParam*)s->d_sp, s->d_st, 0);
     for (int r = 1; r < f; r++) {
         hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(std::min(grid_for(s->N, CPB), 512u)), dim3(256), 0,
-                           st, nxt, s->work, s->d_sp, s->d_st, s->N, r - 1, (const double*)nullptr, 0);
-        hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, s->work, s->d_sp, s->d_st, r);
+                           st, nxt, wk, s->d_sp, s->d_st, s->N, r - 1, (const double*)nullptr, 0);
+        hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, wk, s->d_sp, s->d_st, r);
     }
-    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(tail_grid(s)), dim3(TAIL_THREADS), 0, st, nxt, s->work, s->d_sp,
+    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(tail_grid(s)), dim3(TAIL_THREADS), 0, st, nxt, wk, s->d_sp,
                        s->d_st, s->dev_rounds, s->tail_items, f);
 }
 
@@ -447,13 +481,14 @@ void enqueue_resort(spv_sys* s, hipStream_t st, int cfg)
                        N, s->d_st);
 }
 
-// one host-driven repair round (creation and recovery)
+// one host-driven repair round (creation and recovery); cur: the halted
+// step built a cell list of the current positions
 template <typename R, bool MULTI, int KC>
-void enqueue_round(spv_sys* s, hipStream_t st, int round, unsigned rgrid)
+void enqueue_round(spv_sys* s, hipStream_t st, int round, unsigned rgrid, bool curlist)
 {
     Cells<R> cur = cells<R>(s, s->cfg, s->pos & 1);
-    hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rgrid), dim3(64), 0, st, cur, s->work, s->d_sp, s->d_st,
-                       round);
+    hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rgrid), dim3(64), 0, st, cur, work_for(s, curlist), s->d_sp,
+                       s->d_st, round);
     hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(std::min(grid_for(s->N, CPB), 4096u)), dim3(256), 0,
                        st, cur, s->work, s->d_sp, s->d_st, s->N, round, (const double*)nullptr, 0);
 }
@@ -499,7 +534,7 @@ spv_status error_from_word(spv_sys* s)
 
 // Finish the repair of the halted step on the host side: more rounds, each
 // read back, until no flag is left.
-spv_status recover(spv_sys* s)
+spv_status recover(spv_sys* s, bool curlist)
 {
     if (s->h_st->err) return error_from_word(s);
     int r = s->h_st->halt_round;
@@ -512,7 +547,9 @@ spv_status recover(spv_sys* s)
             return fail(SPV_EREPAIR, s->sticky_msg);
         }
         const unsigned rg = (unsigned)std::min(std::max(s->h_st->wl_count[r], 1), 65535);
-        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_round<R, MULTI, KC>(s, s->stream, r, rg); });
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() {
+            enqueue_round<R, MULTI, KC>(s, s->stream, r, rg, curlist);
+        });
         HIP_TRY(hipGetLastError());
         ST_TRY(read_state(s));
         s->host_rounds++;
@@ -538,7 +575,7 @@ spv_status period_graph(spv_sys* s, int g, int gu, hipGraphExec_t* out)
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
     for (int k = 0; k < gu; k++)
         dispatch(s, [&]<typename R, bool MULTI, int KC>() {
-            enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, nullptr);
+            enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, nullptr, false);
         });
     dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->cap_stream, g); });
     hipError_t e0 = hipGetLastError();
@@ -587,11 +624,13 @@ spv_status run_steps(spv_sys* s, int64_t n)
     if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
     while (n > 0) {
         if (!(s->pos & 1) && !s->no_resort && s->pos > 0) {
-            // the period's end; while hot, as soon as the drift passes the
-            // limit; after the hot phase, at the end of a period of the length
-            // graphs will take, so that they start from a fresh re-sort
+            // re-sort at the period's end; once quiet, also as soon as the
+            // drift bound (which widens the repair searches) passes the limit,
+            // and when a period of the graph length is complete, so that the
+            // graphs start from a fresh re-sort.  While hot, the repairs search
+            // each step's own cell list and the drift does not matter.
             const int gq = s->hot ? 0 : graph_unit(s);
-            if (s->pos >= s->unit || (s->hot && s->h_st->drift > s->drift_limit) || (gq > 0 && s->pos >= gq))
+            if (s->pos >= s->unit || (!s->hot && s->h_st->drift > s->drift_limit) || (gq > 0 && s->pos >= gq))
                 ST_TRY(do_resort_eager(s));
         }
         const int gu = s->hot ? 0 : graph_unit(s);
@@ -603,14 +642,14 @@ spv_status run_steps(spv_sys* s, int64_t n)
             ST_TRY(read_state(s));
             s->graph_periods++;
             const uint64_t done = s->h_st->step - before;
-            if (dense_step(s)) s->dense_steps += (int64_t)done;
+            if (dense_step(s, false)) s->dense_steps += (int64_t)done;
             if (s->h_st->halt) {
                 // the period stopped after `done` steps (the last one unfinished);
                 // later kernels, including its re-sort, did nothing
                 s->step += done;
                 n -= (int64_t)done;
                 s->pos = (int)done;
-                ST_TRY(recover(s));
+                ST_TRY(recover(s, false));
                 continue;
             }
             s->step += done;
@@ -618,7 +657,7 @@ spv_status run_steps(spv_sys* s, int64_t n)
             s->cfg ^= 1;
             s->resorts++;
             // the drift rate of the period sets the next period's length; too
-            // fast for 8 steps: back to eager steps
+            // fast for 8 steps: back to the fast-moving mode
             s->drift_rate = s->h_st->last_drift / (double)done;
             if (graph_unit(s) == 0) {
                 s->hot = true;
@@ -630,12 +669,9 @@ spv_status run_steps(spv_sys* s, int64_t n)
             constexpr int64_t kEagerBatch = 8;
             int64_t b = std::min<int64_t>(n, s->timing ? 1 : kEagerBatch);
             if (!s->no_resort) b = std::min<int64_t>(b, std::max(1, s->unit - s->pos));
-            if (s->hot && s->drift_rate > 0.0)  // about the steps left before the drift limit (at least one)
-                b = std::min<int64_t>(
-                    b, std::max<int64_t>(1, (int64_t)((s->drift_limit - s->h_st->drift) / s->drift_rate)));
             const uint64_t before = s->step;
             const double drift0 = s->h_st->drift;
-            const bool dense = dense_step(s);
+            const bool hot = s->hot;
             for (int64_t j = 0; j < b; j++) {
                 EvPair ev[T_COUNT];
                 const EvPair* evp = nullptr;
@@ -648,7 +684,7 @@ spv_status run_steps(spv_sys* s, int64_t n)
                 }
                 const int cfg = s->cfg, par = (int)((s->pos + j) & 1);
                 dispatch(s, [&]<typename R, bool MULTI, int KC>() {
-                    enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, evp);
+                    enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, evp, hot);
                 });
             }
             HIP_TRY(hipGetLastError());
@@ -658,17 +694,18 @@ spv_status run_steps(spv_sys* s, int64_t n)
             s->step += done;
             s->pos += (int)done;
             n -= (int64_t)done;
-            if (dense) s->dense_steps += (int64_t)done;
-            if (s->h_st->halt) ST_TRY(recover(s));
-            if (s->hot) {
+            if (dense_step(s, hot)) s->dense_steps += (int64_t)done;
+            if (s->h_st->halt) ST_TRY(recover(s, hot));
+            if (hot) {
+                // quiet once the measured drift rate has allowed graph periods
+                // (at least 8 steps within the drift limit) for a whole period
                 if (done > 0 && !s->h_st->halt) s->drift_rate = (s->h_st->drift - drift0) / (double)done;
-                if (s->h_st->drift > s->drift_limit) {
+                const int g = graph_unit(s);
+                if (g == 0) {
                     s->quiet = 0;
                 } else {
-                    // quiet for a whole period of the length the drift rate allows
                     s->quiet += (int)done;
-                    const int g = graph_unit(s);
-                    if (g > 0 && s->quiet >= g) s->hot = false;
+                    if (s->quiet >= g) s->hot = false;
                 }
             }
         }
@@ -832,6 +869,12 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     ST_TRY(dalloc(s, &s->d_perm, N));
     ST_TRY(dalloc(s, &s->d_chunk, grid_for(s->total_bins, SCAN_CHUNK) + 1));
     ST_TRY(dalloc(s, &s->d_inv, N));
+    ST_TRY(dalloc(s, &s->d_cbin, N));
+    ST_TRY(dalloc(s, &s->d_cslot, N));
+    ST_TRY(dalloc(s, &s->d_ccells, N));
+    ST_TRY(dalloc(s, &s->d_ccount, s->total_bins));
+    ST_TRY(dalloc(s, &s->d_cstart, s->total_bins + 1));
+    ST_TRY(dalloc(s, &s->d_cchunk, grid_for(s->total_bins, SCAN_CHUNK) + 1));
     ST_TRY(dalloc(s, &s->d_st, 1));
     ST_TRY(dalloc(s, &s->d_sp, S));
     ST_TRY(dalloc(s, &s->d_stage, N));
@@ -898,7 +941,7 @@ spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vect
     while (true) {
         if (r >= MAX_ROUNDS) return fail(SPV_EREPAIR, "initial triangulation did not converge");
         const unsigned rg = (r == 0) ? (unsigned)std::min(N, 65535) : 4096u;
-        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_round<R, MULTI, KC>(s, s->stream, r, rg); });
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_round<R, MULTI, KC>(s, s->stream, r, rg, false); });
         HIP_TRY(hipGetLastError());
         ST_TRY(read_state(s));
         if (s->h_st->err) {
@@ -1415,10 +1458,11 @@ spv_status segment_fast(spv_sys* s, int64_t m, After&& after, bool* ok)
 {
     const uint64_t before = s->step;
     const int pos0 = s->pos;
+    const bool hot = s->hot;
     for (int64_t j = 0; j < m; j++) {
         const int cfg = s->cfg, par = (int)((pos0 + j) & 1);
         dispatch(s,
-                 [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, nullptr); });
+                 [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, nullptr, hot); });
         s->pos = pos0 + (int)j + 1;  // after() sees the state after step j + 1
         after(j + 1);
     }

@@ -93,6 +93,10 @@ struct Work {
     const int* bin_key;     // [sum of bins] spatial bin of a system -> global key
     const int* bin_start;   // [total bins + 1], by key
     const int2* bin_range;  // [sum of bins] cells [x, y) of a spatial bin
+    // this step's cell list (null when the repairs use the re-sort's bins):
+    // cells cur_cells[cur_start[b] .. cur_start[b + 1]) lie in spatial bin b
+    const int* cur_start;   // [sum of bins + 1]
+    const int* cur_cells;   // [N]
 };
 
 __device__ __forceinline__ double mimg(double d, double L, double hL)

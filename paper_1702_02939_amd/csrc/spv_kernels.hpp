@@ -934,7 +934,8 @@ __global__ __launch_bounds__(256) void k_geom_items(Cells<R> c, Work w, const Sy
 // One 64-lane wavefront rebuilds the Delaunay ring of one flagged cell i.
 // Candidates: every cell of i's system within distance R, gathered from the
 // bins of the last re-sort (searched with R + drift, drift bounding the
-// motion since then).  The ring is traced counter-clockwise by gift-wrapping:
+// motion since then), or from this step's cell list when one was built (no
+// drift).  The ring is traced counter-clockwise by gift-wrapping:
 // from the nearest candidate (always a Delaunay neighbour) the next neighbour
 // after c is the left-side candidate p whose circle through (i, c, p)
 // contains no other left-side candidate -- an arg-min under the exact
@@ -1122,6 +1123,9 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
     // first radius R0 (2.5 mean spacings: a Delaunay star rarely reaches
     // further than half of it); doubled while the star is not certified
     double Rs = fmin(P.R0, Rmax);
+    // bins: this step's cell list when there is one (then drift is 0), else
+    // the memory order of the last re-sort
+    const bool cur = w.cur_cells != nullptr;
     int k = 0;
     bool ok = false, at_max = false;
     int last_n = 0, last_closed = 0, attempts = 0;
@@ -1149,9 +1153,11 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
             int bx = bx0 + b % wx, by = by0 + b / wx;
             bx = ((bx % P.nbx) + P.nbx) % P.nbx;
             by = ((by % P.nby) + P.nby) % P.nby;
-            const int2 br = w.bin_range[P.bin_off + by * P.nbx + bx];
+            const int bi = P.bin_off + by * P.nbx + bx;
+            const int2 br = cur ? make_int2(w.cur_start[bi], w.cur_start[bi + 1]) : w.bin_range[bi];
             const int c1 = min(br.y, hi);
-            for (int q = max(br.x, lo); q < c1; q++) {
+            for (int e = max(br.x, lo); e < c1; e++) {
+                const int q = cur ? w.cur_cells[e] : e;
                 if (q == i) continue;
                 const double dx = mimg(c.x[q] - xi, P.Lx, P.hLx), dy = mimg(c.y[q] - yi, P.Ly, P.hLy);
                 if (dx * dx + dy * dy <= R2) {
@@ -1398,7 +1404,7 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
     if (st->halt) return;
     const int nw = st->wl_count[round];
     const int* __restrict__ wl = w.wl[round & 1];
-    const double drift = st->drift;
+    const double drift = w.cur_cells ? 0.0 : st->drift;
     const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, s_tmp, RP_CAP};
     int exact = 0, nrep = 0;
     bool deferred = false;
@@ -1488,7 +1494,7 @@ __global__ __launch_bounds__(64, 4) void k_repair_dense(Cells<R> c, Work w, cons
     const int nw = st->dcount[round];
     if ((int)blockIdx.x >= nw) return;
     const int* __restrict__ list = w.tl[round & 1];
-    const double drift = st->drift;
+    const double drift = w.cur_cells ? 0.0 : st->drift;
     const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, s_tmp, RP_DENSE};
     int exact = 0, nrep = 0;
     for (int wi = blockIdx.x; wi < nw; wi += gridDim.x) {
@@ -1645,7 +1651,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
     for (; r < rounds; r++) {
         const int nw = r == f ? s_w1 : load_count(&st->wl_count[r]);
         if (nw == 0) break;
-        if (r == f) drift = st->drift;
+        if (r == f) drift = w.cur_cells ? 0.0 : st->drift;
         if (nw > max_items) {
             halt_at = r;
             break;
@@ -1889,6 +1895,34 @@ __global__ void k_gather(Cells<R> src, Cells<R> dst, const int* perm, const int*
         const int o = src.opp[i * KC + m];
         dst.opp[p * KC + m] = o >= 0 ? inv[o] : -1;
     }
+}
+
+// ---------------------------------------------------------------- cell list of a step
+// While cells move fast, the repairs of a step search a cell list of the
+// step's own positions (cells of each spatial bin listed together, in no
+// particular order inside a bin) instead of the last re-sort's memory order
+// widened by the drift: bin and slot of every cell (count), an exclusive
+// scan of the counts (the re-sort's scan kernels), then the placement.
+template <typename R, bool MULTI>
+__global__ void k_cur_bins(Cells<R> c, const SysParam* __restrict__ sp, const DevState* st, int N, int* cbin,
+                           int* cslot, int* count)
+{
+    if (st->halt) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const SysParam& P = sp[MULTI ? c.sys[i] : 0];
+    const int bx = min((int)(c.x[i] / P.bsx), P.nbx - 1), by = min((int)(c.y[i] / P.bsy), P.nby - 1);
+    const int b = P.bin_off + by * P.nbx + bx;
+    cbin[i] = b;
+    cslot[i] = atomicAdd(&count[b], 1);
+}
+
+__global__ void k_cur_place(const int* __restrict__ cbin, const int* __restrict__ cslot,
+                            const int* __restrict__ start, int* __restrict__ cells, int N, const DevState* st)
+{
+    if (st->halt) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) cells[start[cbin[i]] + cslot[i]] = i;
 }
 
 // ---------------------------------------------------------------- outputs and observables
