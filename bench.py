@@ -23,50 +23,63 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 vector
 
-# Algorithmic HBM bytes per cell per launch (FP64, mean ring length 6;
-# neighbour gathers served by cache).
-BYTES_PER_CELL = {
-    # force+update: read x,y,theta (24), deg (1), ring (24), opp (24), own a,b (16), tag (4);
-    # write x,y,theta (24)
-    "force_update": 24 + 1 + 24 + 24 + 16 + 4 + 24,
-    # geometry+test: read x,y (16), deg (1), ring (24), opp (24), A0,P0 (16);
-    # write A,P,a,b (32)
-    "geometry_test": 16 + 1 + 24 + 24 + 16 + 32,
-}
+# Algorithmic HBM bytes (FP64, mean ring length 6; neighbour gathers served
+# by cache) per kernel class over a timed window, from the cell count, the
+# steps and launches, and the repair counters of the window:
+#   force_update   per cell and launch: read x,y,theta (24), deg (1), ring (24),
+#                  opp (24), own a,b (16), tag (4); write x,y,theta (24) = 117
+#   geometry_test  per cell and launch: read x,y (16), deg (1), ring (24),
+#                  opp (24), A0,P0 (16); write A,P,a,b (32) = 113
+#   repair         per candidate gathered: its x,y (16) and index (4) = 20;
+#                  per repaired cell: old ring row (64), new ring (24), deg (1) = 89
+#   cell_list      per cell and step: read x,y (16), write bin and slot (8),
+#                  count update (8), read bin, slot, start (12), write the
+#                  entry (4) = 48; per bin: count read and start write, two
+#                  scan passes = 16
+#   resort         per cell: every per-cell array read and written once
+#                  (x,y,theta 24, tag,sys 8, A0,P0 16, A,P,a,b 32, deg 1,
+#                  ring,opp 48, each way) plus ring and opp renumbering reads
+#                  (48), key, permutation and inverse (16) = 322
+# The other classes (re-tests, tail, flag compaction, host rounds) are timed
+# but carry no byte model.
+FORCE_B, GEOM_B = 117, 113
+CAND_B, REPAIRED_B = 20, 89
+LIST_CELL_B, LIST_BIN_B = 48, 16
+RESORT_B = 322
+STEP_B = 244  # algorithmic bytes of a whole step per cell (three streaming passes)
 
 
-# HBM bytes per launch of the force kernel, per workload and kernel layout
-# (force_mode 1: lanes per cell, 2: per item), from the rocprofv3
-# FETCH_SIZE / WRITE_SIZE runs (calibrated against a plain copy; the
-# summaries are in profiles/), valid only for the force kernels' source as it
-# was then: the digest covers the shared device header and the kernel file up
-# to the geometry section (constants, helpers, the force kernels).
-MEASURED_TRAFFIC = {
-    ("spv_n100k", "force_update", 1): {"bytes": 20.69e6,
-                                    "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
-    ("spv_n1m", "force_update", 2): {"bytes": 200.52e6,
-                                  "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
-}
-
-# FP64 FLOPs per launch of the force kernel, per workload and kernel layout,
-# from the rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL}_F64 counters
-# ((2 FMA + ADD + MUL) x 64 lanes; profiles/), valid for the same source
-# digest as the traffic.
-MEASURED_FP64_FLOPS = {
-    ("spv_n100k", "force_update", 1): {"flops": 221.9e6,
-                                    "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
-    ("spv_n1m", "force_update", 2): {"flops": 2061.8e6,
-                                  "source_sha256": "420f9cb40282218c4c831cc4fd68e0cb6d7ccdbda9839b03ae7e4caf14a73af1"},
-}
+def class_bytes(cls, r):
+    """Algorithmic bytes of kernel class cls over the timed window of run r
+    (None without a model)."""
+    n, steps, launches = r["cells"], r["steps"], r["kernels"][cls][1]
+    if cls == "force_update":
+        return FORCE_B * n * launches
+    if cls == "geometry_test":
+        return GEOM_B * n * launches
+    if cls == "repair":
+        return CAND_B * r["candidates"] + REPAIRED_B * r["repaired"]
+    if cls == "cell_list":
+        return (LIST_CELL_B * n + LIST_BIN_B * r["bins"]) * (launches // 6)
+    if cls == "resort":
+        return RESORT_B * n * (launches // 10)
+    return None
 
 
-def force_source_digest():
+# Measured HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE,
+# calibrated against a plain device copy; the summaries are in profiles/) per
+# (workload, kernel class, force-kernel layout), valid only for the kernel
+# source they were taken on (digest of the device headers): any later change
+# of the kernels nulls roofline.traffic.
+MEASURED_TRAFFIC = {}
+
+
+def source_digest():
     import hashlib
     csrc = os.path.join(ROOT, "paper_1702_02939_amd", "csrc")
     h = hashlib.sha256()
-    h.update(open(os.path.join(csrc, "spv_common.hpp"), "rb").read())
-    k = open(os.path.join(csrc, "spv_kernels.hpp"), "rb").read()
-    h.update(k[:k.index(b"// ---------------------------------------------------------------- geometry + validity test")])
+    for f in ("spv_common.hpp", "spv_exact.hpp", "spv_kernels.hpp"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
 
 
@@ -80,7 +93,6 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true", help="skip the mixed / batched / 1e6 runs")
     ap.add_argument("--no-timing", action="store_true", help="skip the kernel-timing pass")
-    ap.add_argument("--timing-steps", type=int, default=2000)
     ap.add_argument("--no-autotune", action="store_true",
                     help="run with the default scheduling knobs instead of the library's tuned ones")
     ap.add_argument("--batch-steps", type=int, default=5000)
@@ -107,14 +119,39 @@ def cpu_baseline(w, nsteps):
                seed=w["seed"], nsteps=nsteps)
     dt = time.perf_counter() - t0
     # run() also triangulates the final state once: nsteps + 1 triangulations
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n * nsteps / dt, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w['N']} cells, {nsteps} steps from the random start (serial, 1 thread), {dt:.1f} s"}
+            "sample": f"{w['N']} cells, {nsteps} steps from the random start (serial, 1 thread), {dt:.1f} s",
+            "host_cpu": cpu, "host_nproc": os.cpu_count(),
+            "host_affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def count_bins(sysm, bin_factor):
+    """Cell-list bins of a handle (the library's rule: per system,
+    floor(L / (bin_factor * mean spacing)) per side)."""
+    S, _ = sysm.size()
+    nb = 0
+    for k in range(S):
+        Lx, Ly, _ = sysm.system_box(k)
+        _, n = sysm.system_range(k)
+        h = bin_factor * math.sqrt(Lx * Ly / n)
+        nb += max(1, math.floor(Lx / h)) * max(1, math.floor(Ly / h))
+    return nb
 
 
 def timed_run(spv, make, steps, warmup, timing=True):
     """Create via make() (outside the timed region: this includes the
     autotuner's trials when it has no cached choice), warm up, time `steps`
-    steps; returns a dict."""
+    steps; returns a dict.  With timing, every kernel launch of the timed
+    steps carries HIP events on the library's stream (the steps run as
+    without timing, except that no captured graph replays)."""
     import torch
     sysm, ncells = make()
     tuning = sysm.tuning()
@@ -133,17 +170,53 @@ def timed_run(spv, make, steps, warmup, timing=True):
     wall = time.perf_counter() - t0
     second = time.perf_counter() - t1
     E, qbar, sumA, c1 = sysm.observables()
-    kt = {name: spv.spv_kernel_time(sysm.h, k) for name, k in
-          (("force_update", spv.K_FORCE), ("geometry_test", spv.K_GEOM), ("repair", spv.K_REPAIR))}
+    kt = {name: spv.spv_kernel_time(sysm.h, k) for name, k in spv.KERNEL_CLASSES.items()} if timing else None
+    bins = count_bins(sysm, tuning["bin_factor"])
     sysm.close()
     return {"value": ncells * steps / wall, "ms_per_step": wall * 1e3 / steps, "cells": ncells, "steps": steps,
             "steady_value": ncells * half / second if half else None,
             "kernels": kt, "repairs_per_step": float(c1[1] - c0[1]) / steps,
+            "repaired": int(c1[1] - c0[1]), "candidates": int(c1[12] - c0[12]), "bins": bins,
             "rounds_per_step": float(c1[2] - c0[2]) / steps, "E": E, "qbar": qbar, "sumA": sumA,
             "path": {"graph_periods": int(c1[8] - c0[8]), "dense_steps": int(c1[9] - c0[9]),
                      "host_rounds": int(c1[10] - c0[10]), "host_recovered_steps": int(c1[11] - c0[11]),
                      "resorts": int(c1[5] - c0[5])},
             "tuning": tuning}
+
+
+def kernel_table(r):
+    """Per kernel class over the timed window: total ms, launches, ms per
+    step, and (with a byte model) algorithmic GB/s and its HBM fraction."""
+    out = {}
+    for cls, (ms, launches) in r["kernels"].items():
+        if launches == 0:
+            continue
+        e = {"ms": ms, "launches": launches, "ms_per_step": ms / r["steps"], "avg_launch_us": ms * 1e3 / launches}
+        b = class_bytes(cls, r)
+        if b is not None and ms > 0:
+            e["bytes"] = b
+            e["GBs"] = b / (ms * 1e-3) / 1e9
+            e["hbm_frac"] = e["GBs"] / HBM_PEAK_GBS
+        out[cls] = e
+    return out
+
+
+def roofline(r, workload, mode):
+    """The roofline object for the dominant kernel class (largest total time
+    in the timed window): achieved = algorithmic bytes / kernel time."""
+    table = kernel_table(r)
+    dom = max(table, key=lambda k: table[k]["ms"])
+    e = table[dom]
+    achieved = e.get("GBs")
+    mt = MEASURED_TRAFFIC.get((workload, dom, mode))
+    traffic = None
+    if mt and mt["source_sha256"] == source_digest():
+        traffic = mt["bytes_per_launch"]
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved is not None else None, "traffic": traffic,
+            "kernel": dom, "avg_launch_us": e["avg_launch_us"], "launches": e["launches"],
+            "share_of_kernel_time": e["ms"] / sum(v["ms"] for v in table.values()),
+            "bytes_per_launch": e["bytes"] / e["launches"] if "bytes" in e else None}, table
 
 
 AUTOTUNE = 1
@@ -231,27 +304,6 @@ def adjoint_cost(spv, inputs):
             "traj_backward_ms": (t2 - t1) * 1e3, "adjoint_over_forward": (t2 - t0) / t_plain}
 
 
-def alu_roofline(workload, dom, mode, avg_s):
-    """The same kernel against the FP64 vector peak, from its counted FP64
-    operations (None when there are no counters for this workload or they
-    predate the kernel's source)."""
-    mf = MEASURED_FP64_FLOPS.get((workload, dom, mode))
-    if not mf or mf["source_sha256"] != force_source_digest() or avg_s <= 0:
-        return None
-    tf = mf["flops"] / avg_s / 1e12
-    return {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFLOPS,
-            "flops_per_launch": mf["flops"]}
-
-
-def roofline_of(kt, ncells):
-    dom = max(("force_update", "geometry_test"), key=lambda k: kt[k][0])
-    ms, launches = kt[dom]
-    avg_s = ms / 1e3 / max(launches, 1)
-    bytes_per_launch = BYTES_PER_CELL[dom] * ncells
-    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
-    return dom, avg_s, bytes_per_launch, achieved
-
-
 def main():
     global AUTOTUNE
     args = parse()
@@ -273,19 +325,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = inputs.WORKLOADS[args.workload]
-    # timed region 1: throughput (steps replayed as captured graphs, no events)
+    # timed region 1: throughput (no events) -> value
     head = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.steps, args.warmup, timing=False)
     n = head["cells"]
-    # timed region 2: kernel durations from HIP events around every launch
-    # (timing mode launches each step's kernels one by one on the same stream)
-    kt = {k: (0.0, 0) for k in ("force_update", "geometry_test", "repair")}
-    if not args.no_timing:
-        kt = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.timing_steps, args.warmup,
-                       timing=True)["kernels"]
-    dom, avg_s, bytes_per_launch, achieved = roofline_of(kt, n)
     mode = head["tuning"].get("force_mode")
-    mt = MEASURED_TRAFFIC.get((args.workload, dom, mode))
-    traffic = mt["bytes"] if mt and mt["source_sha256"] == force_source_digest() else None
+    # timed region 2: the same window of the same trajectory (a fresh handle,
+    # the same warm-up and steps) with HIP events on every kernel launch ->
+    # the time of each kernel class and the roofline of the dominant one
+    rl, table = None, None
+    if not args.no_timing:
+        tr = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.steps, args.warmup, timing=True)
+        rl, table = roofline(tr, args.workload, mode)
+        rl["timed_ms_per_step"] = tr["ms_per_step"]
     out = {
         "metric": "cell-steps/s",
         "value": head["value"],
@@ -301,14 +352,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "L": w["L"], "p0": w["p0"], "v0": w["v0"], "Dr": w["Dr"],
                    "mu": w["mu"], "dt": w["dt"], "precision": "fp64", "tuning": head["tuning"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6},
-        "roofline_fp64_alu": alu_roofline(args.workload, dom, mode, avg_s),
-        "kernels_ms_total": {k: v[0] for k, v in kt.items()},
-        "kernel_launches": {k: v[1] for k, v in kt.items()},
+        "roofline": rl,
+        # the whole step's algorithmic bytes (three streaming passes) at the
+        # measured rate, against HBM peak
+        "roofline_step": {"bytes_per_cell_step": STEP_B, "achieved": STEP_B * head["value"] / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": STEP_B * head["value"] / 1e9 / HBM_PEAK_GBS},
+        "kernels": table,
         "steady_state_value": head["steady_value"],
         "repairs_per_step": head["repairs_per_step"],
+        "candidates_per_repair": head["candidates"] / max(head["repaired"], 1),
         "repair_rounds_per_step": head["rounds_per_step"],
         "path": head["path"],
         "observables": {"E": head["E"], "qbar": head["qbar"], "sumA": head["sumA"]},
@@ -324,13 +377,18 @@ def main():
         ]
         for name, make, steps, warm in runs:
             r = timed_run(spv, make, steps, warm, timing=False)
-            r["kernels"] = timed_run(spv, make, max(steps // 10, 50), warm, timing=True)["kernels"]
-            d, a_s, bpl, ach = roofline_of(r["kernels"], r["cells"])
+            # kernel classes over the first tenth of the same window (events
+            # keep the steps eager)
+            tr = timed_run(spv, make, max(steps // 10, 50), warm, timing=True)
+            rr, tab = roofline(tr, name, r["tuning"].get("force_mode"))
             extra[name] = {"value": r["value"], "unit": "cell-steps/s", "ms_per_step": r["ms_per_step"],
+                           "steady_state_value": r["steady_value"],
                            "cells": r["cells"], "steps": steps, "warmup": warm,
                            "repairs_per_step": r["repairs_per_step"], "tuning": r["tuning"], "path": r["path"],
-                           "kernel_avg_us": {k: (v[0] * 1e3 / max(v[1], 1)) for k, v in r["kernels"].items()},
-                           "roofline_frac_hbm": ach / HBM_PEAK_GBS, "dominant_kernel": d}
+                           "kernels_timed_steps": tr["steps"],
+                           "kernels": {k: {"avg_launch_us": v["avg_launch_us"], "ms_per_step": v["ms_per_step"],
+                                           "hbm_frac": v.get("hbm_frac")} for k, v in tab.items()},
+                           "dominant_kernel": rr["kernel"], "roofline_frac_hbm": rr["frac"]}
             print(f"[bench] {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)
         extra["mixed_vs_fp64_speedup_n100k"] = extra["spv_n100k_mixed"]["value"] / head["value"]
         extra["adjoint_n4096"] = adjoint_cost(spv, inputs)

@@ -191,12 +191,13 @@ spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t
 
 /*
  * Observables of the current state summed over all systems: E (Eq. 1),
- * qbar = mean of P_i/sqrt(A_i), sumA = sum of A_i; counters[12] (host
+ * qbar = mean of P_i/sqrt(A_i), sumA = sum of A_i; counters[13] (host
  * pointer, may be NULL):
  *   [0] steps taken  [1] cells repaired  [2] repair rounds used  [3] exact-arithmetic fallbacks
  *   [4] max ring length written  [5] spatial re-sorts  [6] repair radius retries  [7] error word
  *   [8] re-sort periods replayed as captured graphs  [9] steps with dense first rounds
  *   [10] repair rounds run by host recovery  [11] steps finished by host recovery
+ *   [12] candidate cells gathered by the repairs (summed over their radius attempts)
  * (statistics since creation or the last load)
  */
 spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA, int64_t* counters);
@@ -243,13 +244,17 @@ spv_status spv_load_state(spv_sys* s, const void* buf, int64_t len);
 spv_status spv_get_tuning(spv_sys* s, spv_tuning* out);
 
 /*
- * Kernel timing.  While enabled, steps are launched one by one (not as
- * captured graphs) and every launch of the listed kernels carries a pair of
- * HIP events attached to its dispatch (start and end of its execution on the
- * handle's stream); spv_kernel_time returns the summed duration (ms) and
- * number of timed launches since enabling.
- *   which: 0 = force+update, 1 = geometry+test (all cells),
- *          2 = repair (first device round)
+ * Kernel timing.  While enabled, steps are launched eagerly (not as captured
+ * graphs; eager batches as otherwise) and every kernel launch carries a pair
+ * of HIP events attached to its dispatch (start and end of its execution on
+ * the handle's stream); spv_kernel_time returns the summed duration (ms) and
+ * number of timed launches of one kernel class since enabling.
+ *   which: 0 = force + update (Eq. 3, App. B), 1 = geometry + validity test
+ *          of all cells (Sec. II.C), 2 = repair (Sec. II.C.4; every device
+ *          round), 3 = re-test of the cells a repair touched, 4 = step tail
+ *          (later rounds, step close), 5 = the step's cell list (fast-moving
+ *          phase), 6 = flag compaction (dense rounds), 7 = spatial re-sort
+ *          (Sec. II.B), 8 = host-driven recovery rounds
  */
 spv_status spv_set_timing(spv_sys* s, int32_t enable);
 spv_status spv_kernel_time(spv_sys* s, int32_t which, double* total_ms, int64_t* launches);

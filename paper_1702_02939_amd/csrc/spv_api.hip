@@ -86,7 +86,8 @@ int64_t hilbert_index(int64_t n, int64_t x, int64_t y)
     return d;
 }
 
-enum { T_FORCE = 0, T_GEOM = 1, T_REPAIR = 2, T_COUNT = 3 };
+// kernel classes timed by spv_kernel_time
+enum { T_FORCE, T_GEOM, T_REPAIR, T_RETEST, T_TAIL, T_LIST, T_COMPACT, T_RESORT, T_HOST, T_COUNT };
 
 struct ArraySet {
     double *x = nullptr, *y = nullptr, *th = nullptr;
@@ -175,8 +176,8 @@ struct spv_sys {
     std::string sticky_msg;
     // timing
     bool timing = false;
-    double t_ms[T_COUNT] = {0, 0, 0};
-    int64_t t_n[T_COUNT] = {0, 0, 0};
+    double t_ms[T_COUNT] = {};
+    int64_t t_n[T_COUNT] = {};
     std::vector<std::pair<int, EvPair>> pending;  // eager launches
     std::vector<EvPair> pool;
     // trajectory adjoint
@@ -339,19 +340,27 @@ void collect_eager_timing(spv_sys* s)
 }
 
 // ---------------------------------------------------------------- launch sequences
-// Launch on `st`; with an event pair, the events are attached to the
+// Launch on `st`; with an event pair (timing), the events are attached to the
 // dispatch itself (start and end of the kernel's execution).
 template <typename K, typename... Args>
-void launch(const EvPair* ev, K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
+void launch(EvPair ev, K kernel, dim3 grid, dim3 block, hipStream_t st, Args... args)
 {
-    if (ev)
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev->a, ev->b, 0, args...);
+    if (ev.a)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev.a, ev.b, 0, args...);
     else
         hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
 }
 
-// One step on stream `st` from (cfg, parity).  ev: optional event pairs
-// (force, geom, repair round 0) timing those kernels.
+// the event pair of the next launch of kernel class `cat` while timing
+// (none otherwise; timing never coincides with graph capture)
+EvPair tev(spv_sys* s, int cat)
+{
+    if (!s->timing) return EvPair{};
+    EvPair e = take_events(s);
+    s->pending.push_back({cat, e});
+    return e;
+}
+
 inline bool dense_step(const spv_sys* s, bool hot) { return s->dense == 2 || (s->dense == 0 && hot); }
 
 // the work lists, with this step's cell list for the repairs when cur
@@ -369,17 +378,18 @@ void enqueue_cell_list(spv_sys* s, hipStream_t st, const Cells<R>& c)
 {
     const int N = s->N, nb = s->total_bins;
     const unsigned nchunk = grid_for(nb, SCAN_CHUNK);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_ccount, nb, 0);
-    hipLaunchKernelGGL((k_cur_bins<R, MULTI>), dim3(grid_for(N, 256)), dim3(256), 0, st, c, (const SysParam*)s->d_sp,
-                       (const DevState*)s->d_st, N, s->d_cbin, s->d_cslot, s->d_ccount);
-    hipLaunchKernelGGL(k_scan_sums, dim3(nchunk), dim3(256), 0, st, (const int*)s->d_ccount, nb, s->d_cchunk,
-                       (const DevState*)s->d_st);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(256), 0, st, s->d_cchunk, (int)nchunk, (const DevState*)s->d_st);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nchunk), dim3(256), 0, st, (const int*)s->d_ccount, s->d_cstart, nb,
-                       (const int*)s->d_cchunk, (const DevState*)s->d_st);
-    hipLaunchKernelGGL(k_cur_place, dim3(grid_for(N, 256)), dim3(256), 0, st, (const int*)s->d_cbin,
-                       (const int*)s->d_cslot, (const int*)s->d_cstart, s->d_ccells, N, (const DevState*)s->d_st);
+    const DevState* ds = s->d_st;
+    launch(tev(s, T_LIST), k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), st, s->d_ccount, nb, 0);
+    launch(tev(s, T_LIST), k_cur_bins<R, MULTI>, dim3(grid_for(N, 256)), dim3(256), st, c, (const SysParam*)s->d_sp,
+           ds, N, s->d_cbin, s->d_cslot, s->d_ccount);
+    launch(tev(s, T_LIST), k_scan_sums, dim3(nchunk), dim3(256), st, (const int*)s->d_ccount, nb, s->d_cchunk, ds);
+    launch(tev(s, T_LIST), k_scan_offsets, dim3(1), dim3(256), st, s->d_cchunk, (int)nchunk, ds);
+    launch(tev(s, T_LIST), k_scan_apply, dim3(nchunk), dim3(256), st, (const int*)s->d_ccount, s->d_cstart, nb,
+           (const int*)s->d_cchunk, ds);
+    launch(tev(s, T_LIST), k_cur_place, dim3(grid_for(N, 256)), dim3(256), st, (const int*)s->d_cbin,
+           (const int*)s->d_cslot, (const int*)s->d_cstart, s->d_ccells, N, ds);
 }
+
 // wavefronts of a dense repair round: about one per four cells, at most
 // what the chip holds at once (256 CUs x 4 SIMDs x 4 wavefronts of
 // k_repair_dense's register budget)
@@ -389,72 +399,75 @@ inline unsigned dense_repair_grid(const spv_sys* s) { return (unsigned)std::min(
 // bytes over the whole grid, the tail takes the rest from the worklist of
 // round nd.
 template <typename R, bool MULTI, int KC>
-void enqueue_dense_rounds(spv_sys* s, hipStream_t st, const Cells<R>& nxt, const Work& wk, const EvPair* ev)
+void enqueue_dense_rounds(spv_sys* s, hipStream_t st, const Cells<R>& nxt, const Work& wk)
 {
     const int nd = std::min(DENSE_ROUNDS, s->dev_rounds);
     const unsigned tg = (grid_for(s->N, DENSE_TCHUNK) + 7u) & ~7u;
+    const SysParam* sp = s->d_sp;
     for (int r = 0; r < nd; r++) {
-        hipLaunchKernelGGL(k_compact_flags, dim3(grid_for(s->N, COMPACT_CELLS)), dim3(256), 0, st, wk, s->d_st,
-                           r);
-        launch(r == 0 && ev ? &ev[2] : nullptr, k_repair_dense<R, MULTI, KC>, dim3(dense_repair_grid(s)), dim3(64),
-               st, nxt, wk, (const SysParam*)s->d_sp, s->d_st, r, nd);
+        launch(tev(s, T_COMPACT), k_compact_flags, dim3(grid_for(s->N, COMPACT_CELLS)), dim3(256), st, wk, s->d_st,
+               r);
+        launch(tev(s, T_REPAIR), k_repair_dense<R, MULTI, KC>, dim3(dense_repair_grid(s)), dim3(64), st, nxt, wk, sp,
+               s->d_st, r, nd);
         if (r + 1 < nd)
-            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, false>), dim3(tg), dim3(256), 0, st, nxt, wk,
-                               (const SysParam*)s->d_sp, s->d_st, s->N, r);
+            launch(tev(s, T_RETEST), k_retest_dense<R, MULTI, KC, false>, dim3(tg), dim3(256), st, nxt, wk, sp,
+                   s->d_st, s->N, r);
         else
-            hipLaunchKernelGGL((k_retest_dense<R, MULTI, KC, true>), dim3(tg), dim3(256), 0, st, nxt, wk,
-                               (const SysParam*)s->d_sp, s->d_st, s->N, r);
+            launch(tev(s, T_RETEST), k_retest_dense<R, MULTI, KC, true>, dim3(tg), dim3(256), st, nxt, wk, sp,
+                   s->d_st, s->N, r);
     }
-    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(tail_grid(s)), dim3(TAIL_THREADS), 0, st, nxt, wk, s->d_sp,
-                       s->d_st, s->dev_rounds, s->tail_items, nd);
+    launch(tev(s, T_TAIL), k_tail<R, MULTI, KC>, dim3(tail_grid(s)), dim3(TAIL_THREADS), st, nxt, wk, sp, s->d_st,
+           s->dev_rounds, s->tail_items, nd);
 }
 
-// hot: the step of the fast-moving phase (its repairs search a cell list of
-// the step's positions; dense first rounds unless switched off)
+// One step on stream `st` from (cfg, parity).  hot: the step of the
+// fast-moving phase (its repairs search a cell list of the step's positions;
+// dense first rounds unless switched off).
 template <typename R, bool MULTI, int KC>
-void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, const EvPair* ev, bool hot)
+void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, bool hot)
 {
     Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
     const unsigned cg = cell_grid(s), rg = repair_grid(s);
-    launch(ev ? &ev[0] : nullptr, force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
-           nxt.y, nxt.th,
-           (double*)nullptr, (double*)nullptr, (const SysParam*)s->d_sp, s->d_st, s->N, s->d_blockmax);
+    const SysParam* sp = s->d_sp;
+    launch(tev(s, T_FORCE), force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
+           nxt.y, nxt.th, (double*)nullptr, (double*)nullptr, sp, s->d_st, s->N, s->d_blockmax);
     if (hot) enqueue_cell_list<R, MULTI>(s, st, nxt);
     const Work wk = work_for(s, hot);
-    if (dense_step(s, hot)) {
-        if (items_kernel(s))
-            launch(ev ? &ev[1] : nullptr, k_geom_items<R, MULTI, KC, true>,
-                   dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, wk,
-                   (const SysParam*)s->d_sp, s->d_st, s->N, (const double*)s->d_blockmax, (int)force_grid(s));
+    const bool dense = dense_step(s, hot);
+    const double* bmax = s->d_blockmax;
+    if (items_kernel(s)) {
+        const dim3 g((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u);
+        if (dense)
+            launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC, true>, g, dim3(256), st, nxt, wk, sp, s->d_st, s->N,
+                   bmax, (int)force_grid(s));
         else
-            launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true, true>, dim3(cg), dim3(256), st,
-                   nxt, wk, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
+            launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC>, g, dim3(256), st, nxt, wk, sp, s->d_st, s->N, bmax,
                    (int)force_grid(s));
-        enqueue_dense_rounds<R, MULTI, KC>(s, st, nxt, wk, ev);
+    } else {
+        if (dense)
+            launch(tev(s, T_GEOM), k_geom<R, MULTI, KC, false, false, true, true>, dim3(cg), dim3(256), st, nxt, wk,
+                   sp, s->d_st, s->N, 0, bmax, (int)force_grid(s));
+        else
+            launch(tev(s, T_GEOM), k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, wk, sp,
+                   s->d_st, s->N, 0, bmax, (int)force_grid(s));
+    }
+    if (dense) {
+        enqueue_dense_rounds<R, MULTI, KC>(s, st, nxt, wk);
         return;
     }
-    if (items_kernel(s))
-        launch(ev ? &ev[1] : nullptr, k_geom_items<R, MULTI, KC>,
-               dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, wk,
-               (const SysParam*)s->d_sp, s->d_st, s->N, (const double*)s->d_blockmax, (int)force_grid(s));
-    else
-        launch(ev ? &ev[1] : nullptr, k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt,
-               wk, (const SysParam*)s->d_sp, s->d_st, s->N, 0, (const double*)s->d_blockmax,
-               (int)force_grid(s));
     // rounds 0 .. f-1 over the whole grid; the last one's re-test, later
     // rounds and the step's close in the tail
     // while cells move fast (hot), rounds 1 .. 3 are big too: all of them over
     // the whole grid, so that a step rarely stops for host rounds
     const int f = std::min(hot ? MAX_FULL_ROUNDS : s->full_rounds, s->dev_rounds);
-    launch(ev ? &ev[2] : nullptr, k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, wk,
-           (const SysParam*)s->d_sp, s->d_st, 0);
+    launch(tev(s, T_REPAIR), k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, wk, sp, s->d_st, 0);
     for (int r = 1; r < f; r++) {
-        hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(std::min(grid_for(s->N, CPB), 512u)), dim3(256), 0,
-                           st, nxt, wk, s->d_sp, s->d_st, s->N, r - 1, (const double*)nullptr, 0);
-        hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rg), dim3(64), 0, st, nxt, wk, s->d_sp, s->d_st, r);
+        launch(tev(s, T_RETEST), k_geom<R, MULTI, KC, true, true>, dim3(std::min(grid_for(s->N, CPB), 512u)),
+               dim3(256), st, nxt, wk, sp, s->d_st, s->N, r - 1, (const double*)nullptr, 0);
+        launch(tev(s, T_REPAIR), k_repair<R, MULTI, KC>, dim3(rg), dim3(64), st, nxt, wk, sp, s->d_st, r);
     }
-    hipLaunchKernelGGL((k_tail<R, MULTI, KC>), dim3(tail_grid(s)), dim3(TAIL_THREADS), 0, st, nxt, wk, s->d_sp,
-                       s->d_st, s->dev_rounds, s->tail_items, f);
+    launch(tev(s, T_TAIL), k_tail<R, MULTI, KC>, dim3(tail_grid(s)), dim3(TAIL_THREADS), st, nxt, wk, sp, s->d_st,
+           s->dev_rounds, s->tail_items, f);
 }
 
 // Re-sort from (cfg, parity 0) into set[cfg ^ 1] (the caller flips cfg).
@@ -463,22 +476,25 @@ void enqueue_resort(spv_sys* s, hipStream_t st, int cfg)
 {
     Cells<R> src = cells<R>(s, cfg, 0), dst = cells<R>(s, cfg ^ 1, 0);
     const int N = s->N, nb = s->total_bins;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_hist, nb, 0);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_fill, nb, 0);
-    hipLaunchKernelGGL((k_bin_keys<R, MULTI>), dim3(grid_for(N, 256)), dim3(256), 0, st, src, s->work, s->d_sp,
-                       s->d_st, N, s->d_key, s->d_hist);
     const unsigned nchunk = grid_for(nb, SCAN_CHUNK);
-    hipLaunchKernelGGL(k_scan_sums, dim3(nchunk), dim3(256), 0, st, s->d_hist, nb, s->d_chunk, s->d_st);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(256), 0, st, s->d_chunk, (int)nchunk, s->d_st);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nchunk), dim3(256), 0, st, s->d_hist, s->d_bin_start, nb,
-                       (const int*)s->d_chunk, s->d_st);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(N, 256)), dim3(256), 0, st, s->d_key, s->d_bin_start, s->d_fill,
-                       s->d_perm, N, s->d_st);
-    hipLaunchKernelGGL(k_bin_sort, dim3(grid_for(nb, 256)), dim3(256), 0, st, s->d_bin_start,
-                       (const int*)s->d_bin_key, s->d_bin_range, s->d_perm, src.tag, nb, s->d_st);
-    hipLaunchKernelGGL(k_inv_perm, dim3(grid_for(N, 256)), dim3(256), 0, st, s->d_perm, s->d_inv, N, s->d_st);
-    hipLaunchKernelGGL((k_gather<R, KC>), dim3(grid_for(N, 256)), dim3(256), 0, st, src, dst, s->d_perm, s->d_inv,
-                       N, s->d_st);
+    launch(tev(s, T_RESORT), k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), st, s->d_hist, nb, 0);
+    launch(tev(s, T_RESORT), k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), st, s->d_fill, nb, 0);
+    launch(tev(s, T_RESORT), k_bin_keys<R, MULTI>, dim3(grid_for(N, 256)), dim3(256), st, src, s->work,
+           (const SysParam*)s->d_sp, (const DevState*)s->d_st, N, s->d_key, s->d_hist);
+    launch(tev(s, T_RESORT), k_scan_sums, dim3(nchunk), dim3(256), st, (const int*)s->d_hist, nb, s->d_chunk,
+           (const DevState*)s->d_st);
+    launch(tev(s, T_RESORT), k_scan_offsets, dim3(1), dim3(256), st, s->d_chunk, (int)nchunk,
+           (const DevState*)s->d_st);
+    launch(tev(s, T_RESORT), k_scan_apply, dim3(nchunk), dim3(256), st, (const int*)s->d_hist, s->d_bin_start, nb,
+           (const int*)s->d_chunk, (const DevState*)s->d_st);
+    launch(tev(s, T_RESORT), k_bin_scatter, dim3(grid_for(N, 256)), dim3(256), st, (const int*)s->d_key,
+           (const int*)s->d_bin_start, s->d_fill, s->d_perm, N, (const DevState*)s->d_st);
+    launch(tev(s, T_RESORT), k_bin_sort, dim3(grid_for(nb, 256)), dim3(256), st, (const int*)s->d_bin_start,
+           (const int*)s->d_bin_key, s->d_bin_range, s->d_perm, (const int*)src.tag, nb, (const DevState*)s->d_st);
+    launch(tev(s, T_RESORT), k_inv_perm, dim3(grid_for(N, 256)), dim3(256), st, (const int*)s->d_perm, s->d_inv, N,
+           (const DevState*)s->d_st);
+    launch(tev(s, T_RESORT), k_gather<R, KC>, dim3(grid_for(N, 256)), dim3(256), st, src, dst, (const int*)s->d_perm,
+           (const int*)s->d_inv, N, s->d_st);
 }
 
 // one host-driven repair round (creation and recovery); cur: the halted
@@ -487,10 +503,11 @@ template <typename R, bool MULTI, int KC>
 void enqueue_round(spv_sys* s, hipStream_t st, int round, unsigned rgrid, bool curlist)
 {
     Cells<R> cur = cells<R>(s, s->cfg, s->pos & 1);
-    hipLaunchKernelGGL((k_repair<R, MULTI, KC>), dim3(rgrid), dim3(64), 0, st, cur, work_for(s, curlist), s->d_sp,
-                       s->d_st, round);
-    hipLaunchKernelGGL((k_geom<R, MULTI, KC, true, true>), dim3(std::min(grid_for(s->N, CPB), 4096u)), dim3(256), 0,
-                       st, cur, s->work, s->d_sp, s->d_st, s->N, round, (const double*)nullptr, 0);
+    const SysParam* sp = s->d_sp;
+    launch(tev(s, T_HOST), k_repair<R, MULTI, KC>, dim3(rgrid), dim3(64), st, cur, work_for(s, curlist), sp, s->d_st,
+           round);
+    launch(tev(s, T_HOST), k_geom<R, MULTI, KC, true, true>, dim3(std::min(grid_for(s->N, CPB), 4096u)), dim3(256), st,
+           cur, s->work, sp, s->d_st, s->N, round, (const double*)nullptr, 0);
 }
 
 // ---------------------------------------------------------------- control block
@@ -575,7 +592,7 @@ spv_status period_graph(spv_sys* s, int g, int gu, hipGraphExec_t* out)
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
     for (int k = 0; k < gu; k++)
         dispatch(s, [&]<typename R, bool MULTI, int KC>() {
-            enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, nullptr, false);
+            enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, false);
         });
     dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->cap_stream, g); });
     hipError_t e0 = hipGetLastError();
@@ -665,26 +682,17 @@ spv_status run_steps(spv_sys* s, int64_t n)
             }
         } else {
             // eager: a batch of steps (up to kEagerBatch, not past the next
-            // re-sort point; one step at a time while timing), one read-back
+            // re-sort point), one read-back
             constexpr int64_t kEagerBatch = 8;
-            int64_t b = std::min<int64_t>(n, s->timing ? 1 : kEagerBatch);
+            int64_t b = std::min<int64_t>(n, kEagerBatch);
             if (!s->no_resort) b = std::min<int64_t>(b, std::max(1, s->unit - s->pos));
             const uint64_t before = s->step;
             const double drift0 = s->h_st->drift;
             const bool hot = s->hot;
             for (int64_t j = 0; j < b; j++) {
-                EvPair ev[T_COUNT];
-                const EvPair* evp = nullptr;
-                if (s->timing) {
-                    for (int k = 0; k < T_COUNT; k++) {
-                        ev[k] = take_events(s);
-                        s->pending.push_back({k, ev[k]});
-                    }
-                    evp = ev;
-                }
                 const int cfg = s->cfg, par = (int)((s->pos + j) & 1);
                 dispatch(s, [&]<typename R, bool MULTI, int KC>() {
-                    enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, evp, hot);
+                    enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, hot);
                 });
             }
             HIP_TRY(hipGetLastError());
@@ -1462,7 +1470,7 @@ spv_status segment_fast(spv_sys* s, int64_t m, After&& after, bool* ok)
     for (int64_t j = 0; j < m; j++) {
         const int cfg = s->cfg, par = (int)((pos0 + j) & 1);
         dispatch(s,
-                 [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, nullptr, hot); });
+                 [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, hot); });
         s->pos = pos0 + (int)j + 1;  // after() sees the state after step j + 1
         after(j + 1);
     }
@@ -1919,6 +1927,7 @@ spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA
         counters[9] = s->dense_steps;
         counters[10] = s->host_rounds;
         counters[11] = s->recoveries;
+        counters[12] = (int64_t)d.candidates;
     }
     return SPV_OK;
 }

@@ -49,6 +49,7 @@ struct DevState {
     unsigned long long step;       // completed steps (noise counter of the next step)
     // statistics
     unsigned long long repaired, exact_calls, retries, rounds;
+    unsigned long long candidates;  // candidates gathered by the repairs (all attempts)
     int max_deg;
     // first repair failure (diagnostics for the error message)
     int fail_set, fail_cell, fail_n, fail_k, fail_closed, fail_attempts;

@@ -1105,7 +1105,8 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
 // cells are marked in the touched bytes of dense round `round`.
 template <typename R, bool MULTI, int KC, bool DENSE = false>
 __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __restrict__ sp, DevState* st, int round,
-                           int i, double drift, const RepairLds& L, bool defer_on_cap, bool& deferred, int& exact)
+                           int i, double drift, const RepairLds& L, bool defer_on_cap, bool& deferred, int& exact,
+                           int& cand)
 {
     const int lane = threadIdx.x & 63;
     double* __restrict__ sx = L.sx;
@@ -1174,6 +1175,7 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
         wave_sync();
         const int n = *L.s_n;
         last_n = n;
+        cand += n;
         if (n > L.cap) {
             if (defer_on_cap) {
                 deferred = true;
@@ -1406,11 +1408,14 @@ __global__ __launch_bounds__(64) void k_repair(Cells<R> c, Work w, const SysPara
     const int* __restrict__ wl = w.wl[round & 1];
     const double drift = w.cur_cells ? 0.0 : st->drift;
     const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, s_tmp, RP_CAP};
-    int exact = 0, nrep = 0;
+    int exact = 0, nrep = 0, cand = 0;
     bool deferred = false;
     for (int wi = blockIdx.x; wi < nw; wi += gridDim.x)
-        nrep += repair_one<R, MULTI, KC>(c, w, sp, st, round, wl[wi], drift, L, false, deferred, exact) ? 1 : 0;
-    if (threadIdx.x == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
+        nrep += repair_one<R, MULTI, KC>(c, w, sp, st, round, wl[wi], drift, L, false, deferred, exact, cand) ? 1 : 0;
+    if (threadIdx.x == 0 && nrep) {
+        atomicAdd(&st->repaired, (unsigned long long)nrep);
+        atomicAdd(&st->candidates, (unsigned long long)cand);
+    }
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
 }
 
@@ -1496,14 +1501,17 @@ __global__ __launch_bounds__(64, 4) void k_repair_dense(Cells<R> c, Work w, cons
     const int* __restrict__ list = w.tl[round & 1];
     const double drift = w.cur_cells ? 0.0 : st->drift;
     const RepairLds L{sx, sy, sid, stg, &s_n, s_ring, s_tmp, RP_DENSE};
-    int exact = 0, nrep = 0;
+    int exact = 0, nrep = 0, cand = 0;
     for (int wi = blockIdx.x; wi < nw; wi += gridDim.x) {
         const int i = list[wi];
         bool deferred = false;
-        nrep += repair_one<R, MULTI, KC, true>(c, w, sp, st, round, i, drift, L, true, deferred, exact) ? 1 : 0;
+        nrep += repair_one<R, MULTI, KC, true>(c, w, sp, st, round, i, drift, L, true, deferred, exact, cand) ? 1 : 0;
         if (deferred && threadIdx.x == 0) push_one(w, st, nd, i);
     }
-    if (threadIdx.x == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
+    if (threadIdx.x == 0 && nrep) {
+        atomicAdd(&st->repaired, (unsigned long long)nrep);
+        atomicAdd(&st->candidates, (unsigned long long)cand);
+    }
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
 }
 
@@ -1600,7 +1608,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
                            reinterpret_cast<R(*)[KC][2]>(g + (size_t)TAIL_CPB * KC * 2 * sizeof(double)),
                            reinterpret_cast<int(*)[KC]>(g + (size_t)TAIL_CPB * KC * 2 * (sizeof(double) + sizeof(R)))};
 
-    int exact = 0, nrep = 0;
+    int exact = 0, nrep = 0, cand = 0;
     {
         // re-test of round f-1, shared by the grid; failures go to round f
         const int nt = st->tl_count[f - 1];
@@ -1662,7 +1670,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
         const int* __restrict__ wl = w.wl[r & 1];
         for (int wi = wave; wi < nw; wi += TAIL_WAVES) {
             bool deferred = false;
-            nrep += repair_one<R, MULTI, KC>(c, w, sp, st, r, wl[wi], drift, L, true, deferred, exact) ? 1 : 0;
+            nrep += repair_one<R, MULTI, KC>(c, w, sp, st, r, wl[wi], drift, L, true, deferred, exact, cand) ? 1 : 0;
             if (deferred && (threadIdx.x & 63) == 0) s_defer = 1;
         }
         __syncthreads();
@@ -1678,7 +1686,10 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Cells<R> c, Work w, const
     }
     if (halt_at < 0 && r == rounds && (rounds == f ? s_w1 : load_count(&st->wl_count[rounds])) > 0)
         halt_at = rounds;
-    if ((threadIdx.x & 63) == 0 && nrep) atomicAdd(&st->repaired, (unsigned long long)nrep);
+    if ((threadIdx.x & 63) == 0 && nrep) {
+        atomicAdd(&st->repaired, (unsigned long long)nrep);
+        atomicAdd(&st->candidates, (unsigned long long)cand);
+    }
     if (exact) atomicAdd(&st->exact_calls, (unsigned long long)exact);
     __syncthreads();
     if (threadIdx.x != 0) return;

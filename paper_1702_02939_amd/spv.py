@@ -29,8 +29,11 @@ SPV_FP64, SPV_MIXED = 0, 1
 STATUS_NAMES = {0: "SPV_OK", -1: "SPV_EINVAL", -2: "SPV_ENOMEM", -3: "SPV_EHIP", -4: "SPV_EPRECOND",
                 -5: "SPV_ECAPACITY", -6: "SPV_ENONFINITE", -7: "SPV_EREPAIR"}
 
-# kernel ids for spv_kernel_time
-K_FORCE, K_GEOM, K_REPAIR = 0, 1, 2
+# kernel classes for spv_kernel_time
+K_FORCE, K_GEOM, K_REPAIR, K_RETEST, K_TAIL, K_LIST, K_COMPACT, K_RESORT, K_HOST = range(9)
+KERNEL_CLASSES = {"force_update": K_FORCE, "geometry_test": K_GEOM, "repair": K_REPAIR, "retest": K_RETEST,
+                  "tail": K_TAIL, "cell_list": K_LIST, "compact": K_COMPACT, "resort": K_RESORT,
+                  "host_rounds": K_HOST}
 
 
 class Params(ctypes.Structure):
@@ -236,7 +239,7 @@ def spv_get_neighbors(h, N):
 
 def spv_get_observables(h):
     E, q, a = _d(), _d(), _d()
-    cnt = np.zeros(12, dtype=np.int64)
+    cnt = np.zeros(13, dtype=np.int64)
     _check(_lib.spv_get_observables(h, ctypes.byref(E), ctypes.byref(q), ctypes.byref(a), _ptr(cnt)),
            "spv_get_observables")
     return E.value, q.value, a.value, cnt
