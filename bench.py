@@ -47,6 +47,7 @@ CAND_B, REPAIRED_B = 20, 89
 LIST_CELL_B, LIST_BIN_B = 48, 16
 RESORT_B = 322
 STEP_B = 244  # algorithmic bytes of a whole step per cell (three streaming passes)
+LIST_LAUNCHES, RESORT_LAUNCHES = 4, 9  # launches of one cell list / one re-sort
 
 
 def class_bytes(cls, r):
@@ -60,9 +61,9 @@ def class_bytes(cls, r):
     if cls == "repair":
         return CAND_B * r["candidates"] + REPAIRED_B * r["repaired"]
     if cls == "cell_list":
-        return (LIST_CELL_B * n + LIST_BIN_B * r["bins"]) * (launches // 6)
+        return (LIST_CELL_B * n + LIST_BIN_B * r["bins"]) * (launches // LIST_LAUNCHES)
     if cls == "resort":
-        return RESORT_B * n * (launches // 10)
+        return RESORT_B * n * (launches // RESORT_LAUNCHES)
     return None
 
 

@@ -379,12 +379,12 @@ void enqueue_cell_list(spv_sys* s, hipStream_t st, const Cells<R>& c)
     const int N = s->N, nb = s->total_bins;
     const unsigned nchunk = grid_for(nb, SCAN_CHUNK);
     const DevState* ds = s->d_st;
-    launch(tev(s, T_LIST), k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), st, s->d_ccount, nb, 0);
+    // the counts are zero here: cleared at creation and by every list's scan
     launch(tev(s, T_LIST), k_cur_bins<R, MULTI>, dim3(grid_for(N, 256)), dim3(256), st, c, (const SysParam*)s->d_sp,
            ds, N, s->d_cbin, s->d_cslot, s->d_ccount);
-    launch(tev(s, T_LIST), k_scan_sums, dim3(nchunk), dim3(256), st, (const int*)s->d_ccount, nb, s->d_cchunk, ds);
-    launch(tev(s, T_LIST), k_scan_offsets, dim3(1), dim3(256), st, s->d_cchunk, (int)nchunk, ds);
-    launch(tev(s, T_LIST), k_scan_apply, dim3(nchunk), dim3(256), st, (const int*)s->d_ccount, s->d_cstart, nb,
+    launch(tev(s, T_LIST), k_scan_sums_last, dim3(nchunk), dim3(256), st, (const int*)s->d_ccount, nb, s->d_cchunk,
+           s->d_st);
+    launch(tev(s, T_LIST), k_scan_apply<true>, dim3(nchunk), dim3(256), st, s->d_ccount, s->d_cstart, nb,
            (const int*)s->d_cchunk, ds);
     launch(tev(s, T_LIST), k_cur_place, dim3(grid_for(N, 256)), dim3(256), st, (const int*)s->d_cbin,
            (const int*)s->d_cslot, (const int*)s->d_cstart, s->d_ccells, N, ds);
@@ -481,11 +481,9 @@ void enqueue_resort(spv_sys* s, hipStream_t st, int cfg)
     launch(tev(s, T_RESORT), k_fill_i32, dim3(grid_for(nb, 256)), dim3(256), st, s->d_fill, nb, 0);
     launch(tev(s, T_RESORT), k_bin_keys<R, MULTI>, dim3(grid_for(N, 256)), dim3(256), st, src, s->work,
            (const SysParam*)s->d_sp, (const DevState*)s->d_st, N, s->d_key, s->d_hist);
-    launch(tev(s, T_RESORT), k_scan_sums, dim3(nchunk), dim3(256), st, (const int*)s->d_hist, nb, s->d_chunk,
-           (const DevState*)s->d_st);
-    launch(tev(s, T_RESORT), k_scan_offsets, dim3(1), dim3(256), st, s->d_chunk, (int)nchunk,
-           (const DevState*)s->d_st);
-    launch(tev(s, T_RESORT), k_scan_apply, dim3(nchunk), dim3(256), st, (const int*)s->d_hist, s->d_bin_start, nb,
+    launch(tev(s, T_RESORT), k_scan_sums_last, dim3(nchunk), dim3(256), st, (const int*)s->d_hist, nb, s->d_chunk,
+           s->d_st);
+    launch(tev(s, T_RESORT), k_scan_apply<false>, dim3(nchunk), dim3(256), st, s->d_hist, s->d_bin_start, nb,
            (const int*)s->d_chunk, (const DevState*)s->d_st);
     launch(tev(s, T_RESORT), k_bin_scatter, dim3(grid_for(N, 256)), dim3(256), st, (const int*)s->d_key,
            (const int*)s->d_bin_start, s->d_fill, s->d_perm, N, (const DevState*)s->d_st);
@@ -881,6 +879,7 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     ST_TRY(dalloc(s, &s->d_cslot, N));
     ST_TRY(dalloc(s, &s->d_ccells, N));
     ST_TRY(dalloc(s, &s->d_ccount, s->total_bins));
+    HIP_TRY(hipMemsetAsync(s->d_ccount, 0, (size_t)s->total_bins * sizeof(int), s->stream));
     ST_TRY(dalloc(s, &s->d_cstart, s->total_bins + 1));
     ST_TRY(dalloc(s, &s->d_cchunk, grid_for(s->total_bins, SCAN_CHUNK) + 1));
     ST_TRY(dalloc(s, &s->d_st, 1));

@@ -59,6 +59,7 @@ struct DevState {
     int dany[DENSE_ROUNDS + 1];
     int tany[DENSE_ROUNDS];
     int dcount[DENSE_ROUNDS];  // cells listed for dense round r
+    int scan_done;             // blocks of a scan's first pass finished (reset by the last)
 };
 
 // Per-cell arrays of one configuration (the library keeps two and swaps them

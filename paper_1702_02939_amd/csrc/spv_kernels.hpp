@@ -1761,8 +1761,8 @@ __global__ void k_bin_keys(Cells<R> c, Work w, const SysParam* __restrict__ sp, 
     atomicAdd(&hist[kk], 1);
 }
 
-// exclusive scan of n ints into out[0..n] (out[n] = total) in three passes:
-// per-chunk sums, scan of the chunk sums, chunk scans with their offsets
+// exclusive scan of n ints into out[0..n] (out[n] = total) in two launches:
+// per-chunk sums with their scan (last block), chunk scans with offsets
 constexpr int SCAN_CHUNK = 4096;  // elements per 256-thread block (16 per thread)
 
 __device__ __forceinline__ int block_inclusive_scan256(int v, int* part)
@@ -1780,41 +1780,51 @@ __device__ __forceinline__ int block_inclusive_scan256(int v, int* part)
     return v + add;
 }
 
-__global__ __launch_bounds__(256) void k_scan_sums(const int* __restrict__ in, int n, int* __restrict__ sums,
-                                                   const DevState* st)
+// The chunk sums and, in the last block to finish (a counter, no wait), their
+// exclusive scan in place (sums[nchunk] = total): the first two passes in
+// one launch.
+__global__ __launch_bounds__(256) void k_scan_sums_last(const int* __restrict__ in, int n, int* sums, DevState* st)
 {
     __shared__ int part[4];
+    __shared__ int s_last;
     if (st->halt) return;
     const int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * 16;
     int v = 0;
 #pragma unroll
     for (int k = 0; k < 16; k++) v += (base + k < n) ? in[base + k] : 0;
     const int tot = block_inclusive_scan256(v, part);
-    if (threadIdx.x == 255) sums[blockIdx.x] = tot;
-}
-
-// one block: exclusive scan of nb chunk sums in place (any nb, 256 at a time)
-__global__ __launch_bounds__(256) void k_scan_offsets(int* sums, int nb, const DevState* st)
-{
-    __shared__ int part[4];
-    __shared__ int carry;
-    if (st->halt) return;
-    if (threadIdx.x == 0) carry = 0;
+    if (threadIdx.x == 255) {
+        sums[blockIdx.x] = tot;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        s_last = atomicAdd(&st->scan_done, 1) == (int)gridDim.x - 1;
+    }
     __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __shared__ int carry;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        st->scan_done = 0;
+    }
+    __syncthreads();
+    const int nb = gridDim.x;
     for (int b0 = 0; b0 < nb; b0 += 256) {
         const int b = b0 + threadIdx.x;
-        const int v = b < nb ? sums[b] : 0;
-        const int inc = block_inclusive_scan256(v, part);
+        const int x = b < nb ? __hip_atomic_load(&sums[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        const int inc = block_inclusive_scan256(x, part);
         const int c0 = carry;
-        if (b < nb) sums[b] = c0 + inc - v;
+        if (b < nb) sums[b] = c0 + inc - x;
         __syncthreads();
         if (threadIdx.x == 255) carry = c0 + inc;
         __syncthreads();
     }
-    if (threadIdx.x == 0) sums[nb] = carry;  // grand total
+    if (threadIdx.x == 0) sums[nb] = carry;
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const int* __restrict__ in, int* __restrict__ out, int n,
+// ZERO: the input counts are cleared after they are read (the cell list's
+// counts start the next step at zero without a fill launch)
+template <bool ZERO = false>
+__global__ __launch_bounds__(256) void k_scan_apply(int* __restrict__ in, int* __restrict__ out, int n,
                                                     const int* __restrict__ offs, const DevState* st)
 {
     __shared__ int part[4];
@@ -1826,6 +1836,11 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int* __restrict__ in, 
     for (int k = 0; k < 16; k++) {
         v[k] = (base + k < n) ? in[base + k] : 0;
         sum += v[k];
+    }
+    if (ZERO) {
+#pragma unroll
+        for (int k = 0; k < 16; k++)
+            if (base + k < n && v[k]) in[base + k] = 0;
     }
     int run = offs[blockIdx.x] + block_inclusive_scan256(sum, part) - sum;
 #pragma unroll
