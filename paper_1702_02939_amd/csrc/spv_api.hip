@@ -1980,7 +1980,7 @@ spv_status spv_traj_backward(spv_sys* s, double dQ, double* dQ_dp0)
 spv_status spv_force_tangent(spv_sys* s, const double* vx, const double* vy, double* fx, double* fy)
 {
     if (!s || !vx || !vy || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
-    if (s->mixed) return fail(SPV_EINVAL, "the force tangent needs an FP64 handle");
+    if (s->mixed || s->S != 1) return fail(SPV_EINVAL, "the force tangent needs a single FP64 system");
     return s->KC == 16 ? hvp_impl<16>(s, vx, vy, fx, fy) : hvp_impl<32>(s, vx, vy, fx, fy);
 }
 

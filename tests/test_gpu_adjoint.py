@@ -140,3 +140,50 @@ def test_trajectory_gradient_independent_of_scheduling(spv):
         assert np.array_equal(g, out[0][1])
         assert np.array_equal(xe, out[0][2]) and np.array_equal(ye, out[0][3])
     assert np.isfinite(out[0][1]).all() and np.abs(out[0][1]).max() > 0
+
+
+def _oracle_steps(x, y, th, Lx, Ly, q, P0, T, prm):
+    """Q = mean of qbar(r_t), t = 1..T, by the oracle one step at a time,
+    with the topology after every step."""
+    qs, topo = [], []
+    for t in range(T):
+        out = oracle.run(x, y, th, Lx, Ly, q, 1.0, P0, step0=t, nsteps=1, want_rings=True, **prm)
+        x, y, th = out["x"], out["y"], out["theta"]
+        qs.append(out["qbar"][1])
+        topo.append((out["ring_off"].tobytes(), out["ring"].tobytes()))
+    return float(np.mean(qs)), topo
+
+
+def test_adjoint_c4_configuration(spv):
+    """The spv_n4096_adjoint configuration: N = 4096 in a 64 x 64 box,
+    p0_i ~ N(3.8, 0.05), v0 = 0.05, T = 200 steps with a checkpoint every 20,
+    from a start relaxed by the oracle (v0 = 0).  Q against the oracle, and
+    dQ/dp0 along random directions against central differences of the
+    oracle's Q, in the directions where the +/- runs keep the base run's
+    topology after every step (the recorded-topology reading)."""
+    w = inputs.WORKLOADS["spv_n4096_adjoint"]
+    n, T, k = w["N"], w["steps"], w["ckpt"]
+    assert (n, T, k) == (4096, 200, 20)
+    x0, y0, Lx, Ly, q = _relaxed_state(n, 75, 300)
+    th0 = oracle.theta0(w["seed"], n)
+    p0 = inputs.per_cell_p0(n, w["p0"], w["p0_sigma"], w["seed"])
+    prm = dict(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"])
+    s = spv.System(x0, y0, Lx, Ly, P0=p0, theta0=th0, params=spv.Params(**prm))
+    Q = s.traj_forward(T, k)
+    g = s.traj_backward(1.0)
+    s.close()
+    Qb, topo_b = _oracle_steps(x0, y0, th0, Lx, Ly, q, p0, T, prm)
+    assert abs(Q - Qb) < 1e-8 * abs(Qb), (Q, Qb)
+    rng = np.random.default_rng(12)
+    eps, checked = 2e-6, 0
+    for trial in range(6):
+        d = rng.normal(size=n)
+        Qp, topo_p = _oracle_steps(x0, y0, th0, Lx, Ly, q, p0 + eps * d, T, prm)
+        Qm, topo_m = _oracle_steps(x0, y0, th0, Lx, Ly, q, p0 - eps * d, T, prm)
+        if topo_p != topo_b or topo_m != topo_b:
+            continue
+        fd = (Qp - Qm) / (2 * eps)
+        an = float(np.dot(g, d))
+        assert abs(an - fd) < 1e-5 * max(abs(fd), 1e-3), f"dQ/dp0 . d: adjoint {an:.8e} vs FD {fd:.8e}"
+        checked += 1
+    assert checked >= 3, f"only {checked} of 6 directions kept the topology sequence"

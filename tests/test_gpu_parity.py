@@ -443,3 +443,34 @@ def test_stiff_start_wraps_jumps_longer_than_the_box(spv):
     gx, gy = sysm.positions()
     assert gx.min() >= 0 and gx.max() < Lxq and gy.min() >= 0 and gy.max() < Lyq
     sysm.close()
+
+
+# ---------------------------------------------------------------- error paths
+
+def test_repair_budget_exhausted_is_an_error(spv):
+    """repair_rounds = device_rounds = 1 from a random start: the first step
+    needs more rounds than allowed.  The kernels end normally (the tail halts
+    the step), the host returns SPV_EREPAIR, and the handle keeps returning
+    it."""
+    x, y, L, _ = _random_case(2000, 81)
+    s = spv.System(x, y, L, L, p0=3.9, params=spv.Params(v0=0.1, seed=1, repair_rounds=1, device_rounds=1))
+    with pytest.raises(spv.SPVError) as ei:
+        s.step(5)
+    assert ei.value.status == spv.SPV_EREPAIR
+    with pytest.raises(spv.SPVError) as ei:
+        s.step(1)
+    assert ei.value.status == spv.SPV_EREPAIR
+    s.close()
+
+
+def test_overflowing_update_is_a_nonfinite_error(spv):
+    """A time step so large that the Eq. 3 update overflows: SPV_ENONFINITE
+    from the device error word (the stored positions stay finite)."""
+    x, y, L, _ = _random_case(500, 82)
+    s = spv.System(x, y, L, L, p0=3.9, params=spv.Params(v0=1.0, seed=1, dt=1e300))
+    with pytest.raises(spv.SPVError) as ei:
+        s.step(1)
+    assert ei.value.status == spv.SPV_ENONFINITE
+    gx, gy = s.positions()
+    assert np.isfinite(gx).all() and np.isfinite(gy).all()
+    s.close()
