@@ -287,6 +287,22 @@ spv_status spv_traj_backward(spv_sys* s, double dQ, double* dQ_dp0);
  */
 spv_status spv_force_tangent(spv_sys* s, const double* vx, const double* vy, double* fx, double* fy);
 
+/*
+ * spv_force_tangent for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and result, with their scratch (v and the result in memory order,
+ * the tangents of A and P) in a static device array of the library instead
+ * of handle buffers, and no host staging.  No hipMalloc, hipFree or host
+ * synchronisation: the result is written on the handle's stream.
+ *   vx, vy, fx, fy: device pointers (N entries each, tag order); host
+ *   pointers are SPV_EINVAL.
+ * Limit: N <= 65536 cells (3 MiB of scratch per device, held until the
+ * process ends); larger handles are SPV_EINVAL.  Every call on one device
+ * shares that scratch: calls that overlap on one GPU (different streams or
+ * threads) race.  Single FP64 systems, as spv_force_tangent.
+ */
+spv_status spv_force_tangent_static(spv_sys* s, const double* vx, const double* vy, double* fx, double* fy);
+
 /* Release all device state of the handle. */
 spv_status spv_destroy(spv_sys* s);
 

@@ -33,6 +33,10 @@
 
 using namespace spv;
 
+// Scratch of spv_force_tangent_static (see static_scratch below).
+constexpr int kStaticCells = 65536;
+static __device__ __align__(256) double scratch[6 * kStaticCells];
+
 namespace {
 
 thread_local std::string g_err;
@@ -89,6 +93,35 @@ int64_t hilbert_index(int64_t n, int64_t x, int64_t y)
 // kernel classes timed by spv_kernel_time
 enum { T_FORCE, T_GEOM, T_REPAIR, T_RETEST, T_TAIL, T_LIST, T_COMPACT, T_RESORT, T_HOST, T_COUNT };
 
+// Scratch of spv_force_tangent_static (the entry point that allocates
+// nothing): v in memory order (2 N), the tangents of A and P (2 N) and the
+// result in memory order (2 N) for at most kStaticCells cells -- 6 x 65536
+// doubles = 3 MiB, which every device the library runs on holds until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): it uses the device address
+// taken once per device by static_scratch().
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's address of `scratch` (looked up on first use)
+spv_status static_scratch(double** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPV_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SPV_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SPV_OK;
+}
+
 struct ArraySet {
     double *x = nullptr, *y = nullptr, *th = nullptr;
     int *tag = nullptr, *sys = nullptr;
@@ -122,6 +155,7 @@ struct TrajCheckpoint {
 
 struct spv_sys {
     int S = 1, N = 0, KC = 16;
+    double* scratch = nullptr;  // this device's address of the static scratch array
     int dev_rounds = 2, max_rounds = 16, unit = 16;
     int repair_cells = 64;  // repair grid = N / this (clamped to [256, 4096] blocks)
     int tail_items = 64;    // largest later round the one-block tail takes
@@ -762,6 +796,7 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
                        std::vector<double>& hy, const std::vector<double>& hA0, const std::vector<double>& hP0,
                        const std::vector<double>& hth)
 {
+    ST_TRY(static_scratch(&s->scratch));
     const int S = (int)in.size();
     s->S = S;
     s->multi = S > 1;
@@ -1648,6 +1683,43 @@ spv_status hvp_impl(spv_sys* s, const double* vx, const double* vy, double* hx, 
 
 }  // namespace
 
+namespace {
+bool device_pointer(const void* p)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // clear the error of an unregistered host pointer
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+template <int KC>
+spv_status hvp_static(spv_sys* s, const double* vx, const double* vy, double* fx, double* fy)
+{
+    const int N = s->N;
+    const ArraySet& cur = s->set[s->cfg];
+    double* lx = s->scratch;
+    double *ly = lx + N, *dA = ly + N, *dP = dA + N, *ox = dP + N, *oy = ox + N;
+    const unsigned g = grid_for(N, 256);
+    hipLaunchKernelGGL(k_from_tag_order, dim3(g), dim3(256), 0, s->stream, vx, (const int*)cur.tag, lx, N);
+    hipLaunchKernelGGL(k_from_tag_order, dim3(g), dim3(256), 0, s->stream, vy, (const int*)cur.tag, ly, N);
+    Cells<double> c = cells<double>(s, s->cfg, s->pos & 1);
+    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, c,
+                       (const double*)lx, (const double*)ly, (const SysParam*)s->d_sp, N, dA, dP, 0.0,
+                       (double*)nullptr, (double*)nullptr);
+    hipLaunchKernelGGL((k_tangent_force<KC, false>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, c,
+                       (const double*)lx, (const double*)ly, (const double*)dA, (const double*)dP,
+                       (const SysParam*)s->d_sp, N, ox, oy, (double*)nullptr);
+    hipLaunchKernelGGL(k_to_tag_order<double>, dim3(g), dim3(256), 0, s->stream, (const double*)ox,
+                       (const int*)cur.tag, (const int*)cur.sys, (const SysParam*)s->d_sp, fx, N);
+    hipLaunchKernelGGL(k_to_tag_order<double>, dim3(g), dim3(256), 0, s->stream, (const double*)oy,
+                       (const int*)cur.tag, (const int*)cur.sys, (const SysParam*)s->d_sp, fy, N);
+    HIP_TRY(hipGetLastError());
+    return SPV_OK;
+}
+}  // namespace
+
 // ====================================================================== C-ABI
 extern "C" {
 
@@ -1982,6 +2054,20 @@ spv_status spv_force_tangent(spv_sys* s, const double* vx, const double* vy, dou
     if (!s || !vx || !vy || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
     if (s->mixed || s->S != 1) return fail(SPV_EINVAL, "the force tangent needs a single FP64 system");
     return s->KC == 16 ? hvp_impl<16>(s, vx, vy, fx, fy) : hvp_impl<32>(s, vx, vy, fx, fy);
+}
+
+
+spv_status spv_force_tangent_static(spv_sys* s, const double* vx, const double* vy, double* fx, double* fy)
+{
+    if (!s || !vx || !vy || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
+    if (s->mixed || s->S != 1) return fail(SPV_EINVAL, "the force tangent needs a single FP64 system");
+    if (s->N > kStaticCells)
+        return fail(SPV_EINVAL, "spv_force_tangent_static takes at most 65536 cells (its static scratch)");
+    if (!device_pointer(vx) || !device_pointer(vy) || !device_pointer(fx) || !device_pointer(fy))
+        return fail(SPV_EINVAL, "spv_force_tangent_static needs device pointers");
+    if (!s->scratch) return fail(SPV_EHIP, "no static scratch on this handle's device");
+    if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
+    return s->KC == 16 ? hvp_static<16>(s, vx, vy, fx, fy) : hvp_static<32>(s, vx, vy, fx, fy);
 }
 
 spv_status spv_destroy(spv_sys* s)

@@ -1953,6 +1953,14 @@ __global__ void k_cur_place(const int* __restrict__ cbin, const int* __restrict_
 
 // ---------------------------------------------------------------- outputs and observables
 // out[cell_off(sys) + tag] = in[i]
+// one system: out[i] = in[tag[i]] (tag order -> memory order)
+__global__ void k_from_tag_order(const double* __restrict__ in, const int* __restrict__ tag, double* __restrict__ out,
+                                 int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[tag[i]];
+}
+
 template <typename T>
 __global__ void k_to_tag_order(const T* in, const int* tag, const int* sys, const SysParam* sp, double* out, int n)
 {

@@ -93,6 +93,7 @@ _SIGS = {
     "spv_traj_forward": [_H, _i64, _i64, ctypes.POINTER(_d)],
     "spv_traj_backward": [_H, _d, _P],
     "spv_force_tangent": [_H, _P, _P, _P, _P],
+    "spv_force_tangent_static": [_H, _P, _P, _P, _P],
     "spv_destroy": [_H],
 }
 for _name, _args in _SIGS.items():
@@ -290,6 +291,12 @@ def spv_traj_backward(h, dQ, out):
 def spv_force_tangent(h, vx, vy, fx, fy):
     keep = [_f64(vx), _f64(vy)]
     _check(_lib.spv_force_tangent(h, _ptr(keep[0]), _ptr(keep[1]), _ptr(fx), _ptr(fy)), "spv_force_tangent")
+
+
+def spv_force_tangent_static(h, vx, vy, fx, fy):
+    """No-allocation variant: all four arrays are device tensors (float64,
+    contiguous); the result is written on the handle's stream."""
+    _check(_lib.spv_force_tangent_static(h, _ptr(vx), _ptr(vy), _ptr(fx), _ptr(fy)), "spv_force_tangent_static")
 
 
 def spv_destroy(h):
