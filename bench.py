@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--big-steps", type=int, default=2000)
     ap.add_argument("--sweep-steps", type=int, default=2000)
+    ap.add_argument("--hybrid-steps", type=int, default=200)
+    ap.add_argument("--ablation-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -234,23 +236,53 @@ def single(spv, inputs, name, precision, p0=None, **knobs):
     return make
 
 
-def sweeps(spv, inputs, steps, warmup):
+def sweeps(spv, inputs, steps, warmup, hybrid_steps, ablation_steps):
     """The paper's solid-to-fluid sweep (target shape index 3.8 / 3.9 / 4.0
-    at v0 = 0.1, N = 1e5, FP64) and the re-sort interval ablation (Hilbert
-    order; 10 / 32 / 100 / 1000 steps between re-sorts, and row-major bins at
-    32) on spv_n100k."""
-    out = {"p0_sweep": {}, "resort_ablation": {}}
+    at v0 = 0.1, N = 1e5, FP64), the hybrid comparison mode at the same
+    points, and the spatial-sort ablation at N = 1e6 (state beyond the 256 MB
+    Infinity Cache)."""
+    out = {"p0_sweep": {}, "hybrid": {}, "resort_ablation_n1m": {}}
+    w = inputs.WORKLOADS["spv_n100k"]
     for p0 in (3.8, 3.9, 4.0):
         r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, p0=p0), steps, warmup, timing=False)
         out["p0_sweep"][str(p0)] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
-                                    "repairs_per_step": r["repairs_per_step"]}
-    for every in (10, 32, 100, 1000):
-        r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, resort_every=every), steps, warmup,
-                      timing=False)
-        out["resort_ablation"][str(every)] = {"value": r["value"], "ms_per_step": r["ms_per_step"]}
-    r = timed_run(spv, single(spv, inputs, "spv_n100k", spv.SPV_FP64, resort_every=32, bin_order=1), steps,
-                  warmup, timing=False)
-    out["resort_ablation"]["32_row_major_bins"] = {"value": r["value"], "ms_per_step": r["ms_per_step"]}
+                                    "repairs_per_step": r["repairs_per_step"], "path": r["path"]}
+        # hybrid comparison mode (device test, host repair with the worklist
+        # and positions copied to the host every step with failures) against
+        # the device repair over the same steps: both from the state after
+        # the warm-up (saved from a device handle, loaded into each)
+        dev = single(spv, inputs, "spv_n100k", spv.SPV_FP64, p0=p0)()[0]
+        dev.step(warmup)
+        state = dev.save_state()
+        dev.close()
+        res = {}
+        for mode in (0, 1):
+            def make(p0=p0, state=state, mode=mode):
+                x, y = inputs.uniform_positions(w["N"], w["L"], w["L"], w["seed"])
+                prm = spv.Params(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"], repair_mode=mode)
+                h = spv.System(x, y, w["L"], w["L"], p0=p0, params=prm)
+                h.load_state(state)
+                return h, w["N"]
+            res[mode] = timed_run(spv, make, hybrid_steps, 0, timing=False)
+        out["hybrid"][str(p0)] = {"steps": hybrid_steps, "after_warmup": warmup,
+                                  "hybrid_value": res[1]["value"], "hybrid_ms_per_step": res[1]["ms_per_step"],
+                                  "device_value": res[0]["value"], "device_ms_per_step": res[0]["ms_per_step"],
+                                  "repairs_per_step": res[1]["repairs_per_step"],
+                                  "device_over_hybrid": res[0]["value"] / res[1]["value"]}
+        print(f"[bench] p0={p0}: device {res[0]['value']:.3e}, hybrid {res[1]['value']:.3e} cell-steps/s",
+              file=sys.stderr, flush=True)
+    # spatial-sort ablation (Sec. II.B): re-sort every 10 / 100 / 1000 steps
+    # (periods are shortened while the drift bound would pass a bin side) and
+    # never (-1: the memory order of creation, repairs on a per-step cell
+    # list), with Hilbert-ordered or row-major bins
+    for every in (10, 100, 1000, -1):
+        for order, name in ((0, "hilbert"), (1, "row_major")):
+            r = timed_run(spv, single(spv, inputs, "spv_n1m", spv.SPV_FP64, resort_every=every, bin_order=order),
+                          ablation_steps, 100, timing=False)
+            out["resort_ablation_n1m"][f"{every}_{name}"] = {
+                "value": r["value"], "ms_per_step": r["ms_per_step"], "steady_state_value": r["steady_value"],
+                "resorts": r["path"]["resorts"], "steps": ablation_steps, "warmup": 100}
+            print(f"[bench] re-sort {every} {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)
     return out
 
 
@@ -393,7 +425,7 @@ def main():
             print(f"[bench] {name}: {r['value']:.3e} cell-steps/s", file=sys.stderr, flush=True)
         extra["mixed_vs_fp64_speedup_n100k"] = extra["spv_n100k_mixed"]["value"] / head["value"]
         extra["adjoint_n4096"] = adjoint_cost(spv, inputs)
-        extra.update(sweeps(spv, inputs, args.sweep_steps, args.warmup))
+        extra.update(sweeps(spv, inputs, args.sweep_steps, args.warmup, args.hybrid_steps, args.ablation_steps))
         print(f"[bench] adjoint/forward: {extra['adjoint_n4096']['adjoint_over_forward']:.2f}", file=sys.stderr,
               flush=True)
         out["extra"] = extra

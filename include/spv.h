@@ -66,7 +66,10 @@ typedef struct {
     double dt;              /* time step */
     uint64_t seed;          /* noise: Philox4x64-10, key (seed, 0), counter (step, tag, 0, 0) */
     int32_t precision;      /* SPV_FP64 or SPV_MIXED */
-    int32_t resort_every;   /* steps between spatial re-sorts, rounded up to even (0: 32) */
+    int32_t resort_every;   /* steps between spatial re-sorts (Sec. II.B), rounded up to even (0: 32;
+                               shortened while the cells' drift bound would pass a bin side within
+                               it); -1: never re-sort -- the memory order stays that of creation and
+                               every step's repairs search a cell list of the step's positions */
     int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16) */
     int32_t repair_rounds;  /* max test/repair rounds per step, device and host together (0: 16, max 32) */
     int32_t device_rounds;  /* repair rounds run on the device inside each step: round 0 over the whole
@@ -96,6 +99,13 @@ typedef struct {
                                appending them to worklists (suits steps in which a large share of the
                                cells fails): 0 = while cells move fast (after a random start), 1 =
                                never, 2 = every step.  Never changes results. */
+    int32_t repair_mode;    /* where failed rings are rebuilt (Sec. II.C.3-4): 0 = on the device, inside
+                               the step; 1 = hybrid comparison mode, the paper's own split: the device
+                               tests every ring, the worklist and the positions go to the host each
+                               step, the library's host code rebuilds the rings (exact gift-wrapping,
+                               the device's tie-break) and uploads them, the device re-tests the touched
+                               cells, round after round.  Same results; steps run eagerly, with no
+                               graphs and no autotuning.  Single systems and batches. */
 } spv_params;
 
 /* Scheduling knobs a handle runs with (see spv_params). */

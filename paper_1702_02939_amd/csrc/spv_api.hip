@@ -28,6 +28,7 @@
 
 #include "../../include/spv.h"
 #include "spv_adjoint.hpp"
+#include "spv_host_repair.hpp"
 #include "spv_kernels.hpp"
 #include "spv_tune.hpp"
 
@@ -162,6 +163,8 @@ struct spv_sys {
     int full_rounds = 1;    // repair rounds over the whole grid before the tail
     int force_mode = 0;     // force kernel: 1 lanes per cell, 2 per (cell, slot) item, 0 by size
     int dense = 0;          // dense first rounds: 0 while hot, 1 never, 2 always
+    int repair_mode = 0;    // 0 device repair, 1 hybrid (device test, host repair)
+    bool never_resort = false;  // no spatial re-sort: repairs always search the step's cell list
     // adaptive re-sort: while cells move fast (the drift of a period exceeds
     // drift_limit, one bin side) steps run eagerly and re-sort as soon as
     // the drift passes the limit; a full quiet period returns to graphs
@@ -206,6 +209,14 @@ struct spv_sys {
     int64_t dense_steps = 0;    // steps whose first repair rounds ran dense
     int64_t host_rounds = 0;    // repair rounds run by host recovery
     int64_t recoveries = 0;     // steps finished by host recovery
+    // hybrid mode: host repair, pinned staging and the device row buffers
+    HostRepair hr;
+    int64_t hyb_repaired = 0, hyb_rounds = 0;
+    double *h_x = nullptr, *h_y = nullptr;
+    int *h_tag = nullptr, *h_sys = nullptr, *h_list = nullptr, *h_rows = nullptr, *h_new = nullptr,
+        *h_touch = nullptr;
+    int *d_rows = nullptr, *d_new = nullptr;
+    std::vector<uint8_t> h_mark;
     spv_status sticky = SPV_OK;
     std::string sticky_msg;
     // timing
@@ -465,8 +476,11 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, bool hot)
     const SysParam* sp = s->d_sp;
     launch(tev(s, T_FORCE), force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
            nxt.y, nxt.th, (double*)nullptr, (double*)nullptr, sp, s->d_st, s->N, s->d_blockmax);
-    if (hot) enqueue_cell_list<R, MULTI>(s, st, nxt);
-    const Work wk = work_for(s, hot);
+    // the repairs search this step's cell list while cells move fast, and
+    // always when the memory order is never re-sorted
+    const bool curl = hot || s->never_resort;
+    if (curl) enqueue_cell_list<R, MULTI>(s, st, nxt);
+    const Work wk = work_for(s, curl);
     const bool dense = dense_step(s, hot);
     const double* bmax = s->d_blockmax;
     if (items_kernel(s)) {
@@ -626,7 +640,8 @@ spv_status period_graph(spv_sys* s, int g, int gu, hipGraphExec_t* out)
         dispatch(s, [&]<typename R, bool MULTI, int KC>() {
             enqueue_step<R, MULTI, KC>(s, s->cap_stream, g, k & 1, false);
         });
-    dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->cap_stream, g); });
+    if (!s->never_resort)
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_resort<R, MULTI, KC>(s, s->cap_stream, g); });
     hipError_t e0 = hipGetLastError();
     hipError_t e1 = hipStreamEndCapture(s->cap_stream, &graph);
     if (e1 == hipSuccess && e0 != hipSuccess) e1 = e0;
@@ -668,11 +683,126 @@ spv_status do_resort_eager(spv_sys* s)
     return SPV_OK;
 }
 
+// ---------------------------------------------------------------- hybrid comparison mode
+// A step: forces and update, then the validity test of every ring (failures
+// to the worklist of round 0), on the device.
+template <typename R, bool MULTI, int KC>
+void enqueue_test(spv_sys* s, hipStream_t st, int cfg, int parity)
+{
+    Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
+    const SysParam* sp = s->d_sp;
+    const double* bmax = s->d_blockmax;
+    launch(tev(s, T_FORCE), force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
+           nxt.y, nxt.th, (double*)nullptr, (double*)nullptr, sp, s->d_st, s->N, s->d_blockmax);
+    if (items_kernel(s))
+        launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC>,
+               dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, s->work, sp,
+               s->d_st, s->N, bmax, (int)force_grid(s));
+    else
+        launch(tev(s, T_GEOM), k_geom<R, MULTI, KC, false, false, true>, dim3(cell_grid(s)), dim3(256), st, nxt,
+               s->work, sp, s->d_st, s->N, 0, bmax, (int)force_grid(s));
+}
+
+// Round r of a hybrid step: the worklist, the listed cells' old rows and (in
+// the first round) the positions, tags and systems go to the host; the host
+// rebuilds the rings; the new rows and the touched cells come back, and the
+// device re-tests the touched cells (failures to the worklist of round r + 1).
+template <typename R, bool MULTI, int KC>
+spv_status hybrid_round(spv_sys* s, int r, bool first)
+{
+    const int n = s->h_st->wl_count[r], N = s->N;
+    hipStream_t st = s->stream;
+    Cells<R> c = cells<R>(s, s->cfg, s->pos & 1);
+    const int* wl = s->work.wl[r & 1];
+    HIP_TRY(hipMemcpyAsync(s->h_list, wl, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
+    launch(tev(s, T_HOST), k_pack_rows<KC>, dim3(grid_for(n, 256)), dim3(256), st, wl, n, (const uint8_t*)c.deg,
+           (const int*)c.ring, s->d_rows);
+    HIP_TRY(hipMemcpyAsync(s->h_rows, s->d_rows, (size_t)n * (KC + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    if (first) {
+        HIP_TRY(hipMemcpyAsync(s->h_x, c.x, (size_t)N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(s->h_y, c.y, (size_t)N * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(s->h_tag, c.tag, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(s->h_sys, c.sys, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (first) s->hr.build(s->h_x, s->h_y, s->h_sys, N, s->hsp, s->total_bins);
+    int nt = 0;
+    auto touch = [&](int q) {
+        if (q >= 0 && !s->h_mark[q]) {
+            s->h_mark[q] = 1;
+            s->h_touch[nt++] = q;
+        }
+    };
+    for (int t = 0; t < n; t++) {
+        const int i = s->h_list[t];
+        const unsigned e = s->hr.repair(i, s->h_x, s->h_y, s->h_tag, s->h_sys, s->hsp, KC);
+        if (e) {
+            for (int q = 0; q < nt; q++) s->h_mark[s->h_touch[q]] = 0;
+            s->sticky = (e & ERR_PRECOND) ? SPV_EPRECOND : (e & ERR_CAPACITY) ? SPV_ECAPACITY : SPV_EREPAIR;
+            s->sticky_msg = "host repair (hybrid mode) failed at step " + std::to_string(s->step) + " for tag " +
+                            std::to_string(s->h_tag[i]);
+            return fail(s->sticky, s->sticky_msg);
+        }
+        const int* old = s->h_rows + (size_t)t * (KC + 1);
+        for (int m = 0; m < old[0]; m++) touch(old[1 + m]);
+        int* row = s->h_new + (size_t)t * (KC + 2);
+        const int k = (int)s->hr.ring.size();
+        row[0] = i;
+        row[1] = k;
+        for (int m = 0; m < k; m++) {
+            row[2 + m] = s->hr.ring[m];
+            touch(s->hr.ring[m]);
+        }
+        touch(i);
+    }
+    for (int q = 0; q < nt; q++) s->h_mark[s->h_touch[q]] = 0;
+    HIP_TRY(hipMemcpyAsync(s->d_new, s->h_new, (size_t)n * (KC + 2) * sizeof(int), hipMemcpyHostToDevice, st));
+    launch(tev(s, T_HOST), k_unpack_rows<KC>, dim3(grid_for(n, 256)), dim3(256), st, (const int*)s->d_new, n, c.deg,
+           c.ring, s->work.flagbits);
+    HIP_TRY(hipMemcpyAsync(s->work.tl[r & 1], s->h_touch, (size_t)nt * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(s->d_st) + offsetof(DevState, tl_count) + r * sizeof(int), &nt,
+                           sizeof(int), hipMemcpyHostToDevice, st));
+    launch(tev(s, T_HOST), k_geom<R, MULTI, KC, true, true>, dim3(std::min(grid_for(N, CPB), 4096u)), dim3(256), st,
+           c, s->work, (const SysParam*)s->d_sp, s->d_st, N, r, (const double*)nullptr, 0);
+    s->hyb_repaired += n;
+    s->hyb_rounds++;
+    return read_state(s);
+}
+
+spv_status run_steps_hybrid(spv_sys* s, int64_t n)
+{
+    for (; n > 0; n--) {
+        if (!(s->pos & 1) && s->pos > 0 && s->pos >= s->unit && !s->never_resort) ST_TRY(do_resort_eager(s));
+        const int cfg = s->cfg, par = s->pos & 1;
+        dispatch(s, [&]<typename R, bool MULTI, int KC>() { enqueue_test<R, MULTI, KC>(s, s->stream, cfg, par); });
+        HIP_TRY(hipGetLastError());
+        ST_TRY(read_state(s));  // the worklist size: the per-step device-to-host round trip
+        if (s->h_st->err) return error_from_word(s);
+        s->step += 1;
+        s->pos += 1;
+        for (int r = 0; s->h_st->wl_count[r] > 0; r++) {
+            if (r >= s->max_rounds || r + 1 >= MAX_ROUNDS) {
+                s->sticky = SPV_EREPAIR;
+                s->sticky_msg = "topology repair did not converge within repair_rounds";
+                return fail(SPV_EREPAIR, s->sticky_msg);
+            }
+            spv_status st = SPV_OK;
+            dispatch(s, [&]<typename R, bool MULTI, int KC>() { st = hybrid_round<R, MULTI, KC>(s, r, r == 0); });
+            ST_TRY(st);
+            if (s->h_st->err) return error_from_word(s);
+        }
+        hipLaunchKernelGGL(k_resume, dim3(1), dim3(64), 0, s->stream, s->d_st);
+        HIP_TRY(hipGetLastError());
+    }
+    return read_state(s);
+}
+
 spv_status run_steps(spv_sys* s, int64_t n)
 {
     if (s->sticky != SPV_OK) return fail(s->sticky, s->sticky_msg);
+    if (s->repair_mode == 1) return run_steps_hybrid(s, n);
     while (n > 0) {
-        if (!(s->pos & 1) && !s->no_resort && s->pos > 0) {
+        if (!(s->pos & 1) && !s->no_resort && !s->never_resort && s->pos > 0) {
             // re-sort at the period's end; once quiet, also as soon as the
             // drift bound (which widens the repair searches) passes the limit,
             // and when a period of the graph length is complete, so that the
@@ -682,11 +812,15 @@ spv_status run_steps(spv_sys* s, int64_t n)
             if (s->pos >= s->unit || (!s->hot && s->h_st->drift > s->drift_limit) || (gq > 0 && s->pos >= gq))
                 ST_TRY(do_resort_eager(s));
         }
-        const int gu = s->hot ? 0 : graph_unit(s);
-        if (s->pos == 0 && gu > 0 && n >= gu && s->use_graphs && !s->timing && !s->no_resort) {
+        // (never re-sorting: periods of the re-sort period's length, from any
+        // even position, without the re-sort)
+        const int gu = s->hot ? 0 : s->never_resort ? s->unit : graph_unit(s);
+        const bool at_start = s->never_resort ? !(s->pos & 1) : s->pos == 0;
+        if (at_start && gu > 0 && n >= gu && s->use_graphs && !s->timing && !s->no_resort) {
             hipGraphExec_t ex = nullptr;
             ST_TRY(period_graph(s, s->cfg, gu, &ex));
             const uint64_t before = s->step;
+            const double drift0 = s->h_st->drift;
             HIP_TRY(hipGraphLaunch(ex, s->stream));
             ST_TRY(read_state(s));
             s->graph_periods++;
@@ -697,17 +831,19 @@ spv_status run_steps(spv_sys* s, int64_t n)
                 // later kernels, including its re-sort, did nothing
                 s->step += done;
                 n -= (int64_t)done;
-                s->pos = (int)done;
-                ST_TRY(recover(s, false));
+                s->pos += (int)done;
+                ST_TRY(recover(s, s->never_resort));
                 continue;
             }
             s->step += done;
             n -= (int64_t)done;
-            s->cfg ^= 1;
-            s->resorts++;
+            if (!s->never_resort) {
+                s->cfg ^= 1;
+                s->resorts++;
+            }
             // the drift rate of the period sets the next period's length; too
             // fast for 8 steps: back to the fast-moving mode
-            s->drift_rate = s->h_st->last_drift / (double)done;
+            s->drift_rate = ((s->never_resort ? s->h_st->drift : s->h_st->last_drift) - drift0) / (double)done;
             if (graph_unit(s) == 0) {
                 s->hot = true;
                 s->quiet = 0;
@@ -717,7 +853,9 @@ spv_status run_steps(spv_sys* s, int64_t n)
             // re-sort point), one read-back
             constexpr int64_t kEagerBatch = 8;
             int64_t b = std::min<int64_t>(n, kEagerBatch);
-            if (!s->no_resort) b = std::min<int64_t>(b, std::max(1, s->unit - s->pos));
+            if (!s->no_resort && !s->never_resort) b = std::min<int64_t>(b, std::max(1, s->unit - s->pos));
+            // never re-sorting, graphs start at even positions: one step to get there
+            if (s->never_resort && !s->hot && (s->pos & 1)) b = 1;
             const uint64_t before = s->step;
             const double drift0 = s->h_st->drift;
             const bool hot = s->hot;
@@ -735,7 +873,7 @@ spv_status run_steps(spv_sys* s, int64_t n)
             s->pos += (int)done;
             n -= (int64_t)done;
             if (dense_step(s, hot)) s->dense_steps += (int64_t)done;
-            if (s->h_st->halt) ST_TRY(recover(s, hot));
+            if (s->h_st->halt) ST_TRY(recover(s, hot || s->never_resort));
             if (hot) {
                 // quiet once the measured drift rate has allowed graph periods
                 // (at least 8 steps within the drift limit) for a whole period
@@ -776,6 +914,9 @@ void destroy_all(spv_sys* s)
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     for (void* p : s->allocs) (void)hipFree(p);
     if (s->h_st) (void)hipHostFree(s->h_st);
+    for (void* p : {(void*)s->h_x, (void*)s->h_y, (void*)s->h_tag, (void*)s->h_sys, (void*)s->h_list,
+                    (void*)s->h_touch, (void*)s->h_rows, (void*)s->h_new})
+        if (p) (void)hipHostFree(p);
     delete s;
 }
 
@@ -929,6 +1070,20 @@ spv_status create_impl(spv_sys* s, const std::vector<SysInput>& in, std::vector<
     ST_TRY(dalloc(s, &s->d_obs_part, (size_t)3 * S * s->obs_chunks));
     ST_TRY(dalloc(s, &s->d_blockmax, cell_grid(s)));
     HIP_TRY(hipHostMalloc((void**)&s->h_st, sizeof(DevState), hipHostMallocDefault));
+    if (s->repair_mode == 1) {
+        const size_t K = (size_t)s->KC;
+        HIP_TRY(hipHostMalloc((void**)&s->h_x, N * sizeof(double), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&s->h_y, N * sizeof(double), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&s->h_tag, N * sizeof(int), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&s->h_sys, N * sizeof(int), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&s->h_list, N * sizeof(int), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&s->h_touch, N * sizeof(int), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&s->h_rows, N * (K + 1) * sizeof(int), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&s->h_new, N * (K + 2) * sizeof(int), hipHostMallocDefault));
+        ST_TRY(dalloc(s, &s->d_rows, N * (K + 1)));
+        ST_TRY(dalloc(s, &s->d_new, N * (K + 2)));
+        s->h_mark.assign(N, 0);
+    }
     HIP_TRY(hipMemcpyAsync(s->d_sp, s->hsp.data(), S * sizeof(SysParam), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->d_bin_key, hbinkey.data(), s->total_bins * sizeof(int), hipMemcpyHostToDevice,
                            s->stream));
@@ -978,6 +1133,8 @@ spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vect
     ST_TRY(do_resort_eager(s));
     s->resorts = 0;
     s->graph_periods = s->dense_steps = s->host_rounds = s->recoveries = 0;
+    s->hyb_repaired = s->hyb_rounds = 0;
+    s->hr.candidates = 0;
     hipLaunchKernelGGL(k_all_to_worklist, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, s->work, s->d_st, N);
     int r = 0;
     while (true) {
@@ -1014,9 +1171,10 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     s->dev_rounds = p.device_rounds > 0 ? std::min(p.device_rounds, s->max_rounds) : std::min(8, s->max_rounds);
     if (s->dev_rounds > s->max_rounds) return fail(SPV_EINVAL, "device_rounds exceeds repair_rounds");
     s->unit = p.resort_every > 0 ? p.resort_every : 32;
+    s->never_resort = p.resort_every == -1;
     if (s->unit & 1) s->unit += 1;
     s->use_graphs = p.no_graphs == 0;
-    if (p.repair_cells < 0 || p.resort_every < 0 || p.device_rounds < 0)
+    if (p.repair_cells < 0 || p.resort_every < -1 || p.device_rounds < 0)
         return fail(SPV_EINVAL, "negative scheduling knob");
     s->repair_cells = p.repair_cells > 0 ? p.repair_cells : 64;
     if (p.tail_items < 0 || p.full_rounds < 0) return fail(SPV_EINVAL, "negative scheduling knob");
@@ -1031,6 +1189,8 @@ spv_status setup_params(spv_sys* s, const spv_params* params, void* stream)
     s->force_mode = p.force_mode;
     if (p.dense < 0 || p.dense > 2) return fail(SPV_EINVAL, "dense must be 0, 1 or 2");
     s->dense = p.dense;
+    if (p.repair_mode < 0 || p.repair_mode > 1) return fail(SPV_EINVAL, "repair_mode must be 0 or 1");
+    s->repair_mode = p.repair_mode;
     s->stream = (hipStream_t)stream;
     return SPV_OK;
 }
@@ -1341,7 +1501,12 @@ spv_status create_tuned(const CreateArgs& a, spv_sys** out)
 {
     *out = nullptr;
     spv_params p = a.prm;
-    if (p.autotune == 0) return build_handle(a, p, out);
+    // the hybrid mode's cost is the host round trip, and the re-sort period is
+    // a knob of the trials: no trials for either
+    if (p.autotune == 0 || p.repair_mode == 1 || p.resort_every == -1) {
+        p.autotune = 0;
+        return build_handle(a, p, out);
+    }
     // validate the parameters (and fill in the defaults) before any trial
     spv_sys* probe = new spv_sys();
     spv_status st = setup_params(probe, &p, a.stream);
@@ -1983,8 +2148,8 @@ spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA
     if (counters) {
         const DevState& d = *s->h_st;
         counters[0] = (int64_t)s->step;
-        counters[1] = (int64_t)d.repaired;
-        counters[2] = (int64_t)d.rounds;
+        counters[1] = (int64_t)d.repaired + s->hyb_repaired;
+        counters[2] = (int64_t)d.rounds + s->hyb_rounds;
         counters[3] = (int64_t)d.exact_calls;
         {
             std::vector<uint8_t> deg(s->N);
@@ -1998,7 +2163,7 @@ spv_status spv_get_observables(spv_sys* s, double* E, double* qbar, double* sumA
         counters[9] = s->dense_steps;
         counters[10] = s->host_rounds;
         counters[11] = s->recoveries;
-        counters[12] = (int64_t)d.candidates;
+        counters[12] = (int64_t)d.candidates + s->hr.candidates;
     }
     return SPV_OK;
 }

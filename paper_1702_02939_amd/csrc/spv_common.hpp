@@ -101,7 +101,7 @@ struct Work {
     const int* cur_cells;   // [N]
 };
 
-__device__ __forceinline__ double mimg(double d, double L, double hL)
+__host__ __device__ __forceinline__ double mimg(double d, double L, double hL)
 {
     return d > hL ? d - L : (d < -hL ? d + L : d);
 }

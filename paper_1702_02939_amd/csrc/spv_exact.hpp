@@ -9,6 +9,8 @@
 // orientation, a 256-bit two's-complement accumulator for the in-circle
 // determinant, whose magnitude stays below 2^208).
 //
+// The predicates compile for the host too (the hybrid mode's host repair).
+//
 // The Delaunay validity of a triangle is the empty-circumcircle property
 // (Sussman 2017, Sec. II.C.3).  Four or more cocircular cells are resolved by
 // symbolic perturbation of the lifted coordinate |p|^2, the highest-tag point
@@ -24,9 +26,9 @@ struct I256 {
     uint64_t w[4];  // little-endian words, two's complement
 };
 
-__device__ __forceinline__ I256 i256_zero() { I256 r; r.w[0] = r.w[1] = r.w[2] = r.w[3] = 0; return r; }
+__host__ __device__ __forceinline__ I256 i256_zero() { I256 r; r.w[0] = r.w[1] = r.w[2] = r.w[3] = 0; return r; }
 
-__device__ __forceinline__ I256 i256_add(const I256& a, const I256& b)
+__host__ __device__ __forceinline__ I256 i256_add(const I256& a, const I256& b)
 {
     I256 r;
     uint64_t c = 0;
@@ -42,7 +44,7 @@ __device__ __forceinline__ I256 i256_add(const I256& a, const I256& b)
     return r;
 }
 
-__device__ __forceinline__ I256 i256_neg(const I256& a)
+__host__ __device__ __forceinline__ I256 i256_neg(const I256& a)
 {
     I256 r;
     uint64_t c = 1;
@@ -55,14 +57,14 @@ __device__ __forceinline__ I256 i256_neg(const I256& a)
     return r;
 }
 
-__device__ __forceinline__ int i256_sign(const I256& a)
+__host__ __device__ __forceinline__ int i256_sign(const I256& a)
 {
     if ((int64_t)a.w[3] < 0) return -1;
     return (a.w[0] | a.w[1] | a.w[2] | a.w[3]) ? 1 : 0;
 }
 
 // unsigned 128 x unsigned 128 -> 256
-__device__ __forceinline__ I256 u128_mul(unsigned __int128 a, unsigned __int128 b)
+__host__ __device__ __forceinline__ I256 u128_mul(unsigned __int128 a, unsigned __int128 b)
 {
     uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64), b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
     unsigned __int128 p00 = (unsigned __int128)a0 * b0;
@@ -82,25 +84,25 @@ __device__ __forceinline__ I256 u128_mul(unsigned __int128 a, unsigned __int128 
 }
 
 // non-negative 128 x signed 128 -> signed 256
-__device__ __forceinline__ I256 mul_u_s(unsigned __int128 a, __int128 b)
+__host__ __device__ __forceinline__ I256 mul_u_s(unsigned __int128 a, __int128 b)
 {
     if (b < 0) return i256_neg(u128_mul(a, (unsigned __int128)(-b)));
     return u128_mul(a, (unsigned __int128)b);
 }
 
-__device__ __forceinline__ int64_t to_units(double d, double scale) { return (int64_t)(d * scale); }
+__host__ __device__ __forceinline__ int64_t to_units(double d, double scale) { return (int64_t)(d * scale); }
 
-__device__ __forceinline__ int sgn128(__int128 v) { return (v > 0) - (v < 0); }
+__host__ __device__ __forceinline__ int sgn128(__int128 v) { return (v > 0) - (v < 0); }
 
 // sign of b x c (orientation of (0, b, c)); exact
-__device__ __forceinline__ int cross_sign_exact(double bx, double by, double cx, double cy, double scale)
+__host__ __device__ __forceinline__ int cross_sign_exact(double bx, double by, double cx, double cy, double scale)
 {
     int64_t X1 = to_units(bx, scale), Y1 = to_units(by, scale), X2 = to_units(cx, scale), Y2 = to_units(cy, scale);
     return sgn128((__int128)X1 * Y2 - (__int128)Y1 * X2);
 }
 
 // filtered sign of b x c; s must be the double evaluation bx*cy - by*cx
-__device__ __forceinline__ int cross_sign(double bx, double by, double cx, double cy, double s, double scale)
+__host__ __device__ __forceinline__ int cross_sign(double bx, double by, double cx, double cy, double s, double scale)
 {
     double bound = 1.5e-15 * (fabs(bx * cy) + fabs(by * cx));
     if (s > bound) return 1;
@@ -109,7 +111,7 @@ __device__ __forceinline__ int cross_sign(double bx, double by, double cx, doubl
 }
 
 // orientation of (b, c, p): sign of (c - b) x (p - b); exact in units
-__device__ __forceinline__ int orient3_exact(double bx, double by, double cx, double cy, double px, double py,
+__host__ __device__ __forceinline__ int orient3_exact(double bx, double by, double cx, double cy, double px, double py,
                                              double scale)
 {
     int64_t Bx = to_units(bx, scale), By = to_units(by, scale);
@@ -119,7 +121,7 @@ __device__ __forceinline__ int orient3_exact(double bx, double by, double cx, do
 }
 
 // exact value sign of  -( |b|^2 (c x p) + |c|^2 (p x b) + |p|^2 (b x c) )
-__device__ __noinline__ int incircle_exact(double bx, double by, double cx, double cy, double px, double py,
+__host__ __device__ __noinline__ int incircle_exact(double bx, double by, double cx, double cy, double px, double py,
                                            double scale)
 {
     int64_t Bx = to_units(bx, scale), By = to_units(by, scale);
@@ -140,7 +142,7 @@ __device__ __noinline__ int incircle_exact(double bx, double by, double cx, doub
 // the circle through (0, b, c) for (0, b, c) counter-clockwise (the 4x4
 // lifted determinant with rows (i, b, c, p)); ties broken by the tags
 // (ti, tb, tc, tp).
-__device__ __forceinline__ int incircle_exact_sos(double bx, double by, double cx, double cy, double px, double py,
+__host__ __device__ __forceinline__ int incircle_exact_sos(double bx, double by, double cx, double cy, double px, double py,
                                                int ti, int tb, int tc, int tp, double scale)
 {
     int s = incircle_exact(bx, by, cx, cy, px, py, scale);

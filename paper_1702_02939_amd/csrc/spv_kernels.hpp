@@ -1951,6 +1951,37 @@ __global__ void k_cur_place(const int* __restrict__ cbin, const int* __restrict_
     if (i < N) cells[start[cbin[i]] + cslot[i]] = i;
 }
 
+// ---------------------------------------------------------------- hybrid comparison mode
+// The rows (ring length, then kc entries, -1 past the length) of the listed
+// cells, for the host repair.
+template <int KC>
+__global__ void k_pack_rows(const int* __restrict__ list, int n, const uint8_t* __restrict__ deg,
+                            const int* __restrict__ ring, int* __restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = list[t];
+    const int k = min((int)deg[i], KC);
+    int* o = out + (size_t)t * (KC + 1);
+    o[0] = k;
+    for (int m = 0; m < KC; m++) o[1 + m] = m < k ? ring[i * KC + m] : -1;
+}
+
+// The host's new rows (cell, length, kc entries) into the ring arrays; the
+// cells leave the pending worklist (their flag bits cleared).
+template <int KC>
+__global__ void k_unpack_rows(const int* __restrict__ in, int n, uint8_t* __restrict__ deg, int* __restrict__ ring,
+                              unsigned* flagbits)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int* r = in + (size_t)t * (KC + 2);
+    const int i = r[0], k = r[1];
+    deg[i] = (uint8_t)k;
+    for (int m = 0; m < k; m++) ring[i * KC + m] = r[2 + m];
+    atomicAnd(&flagbits[i >> 5], ~(1u << (i & 31)));
+}
+
 // ---------------------------------------------------------------- outputs and observables
 // out[cell_off(sys) + tag] = in[i]
 // one system: out[i] = in[tag[i]] (tag order -> memory order)

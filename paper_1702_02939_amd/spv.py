@@ -43,14 +43,16 @@ class Params(ctypes.Structure):
                 ("kcap", ctypes.c_int32), ("repair_rounds", ctypes.c_int32), ("device_rounds", ctypes.c_int32),
                 ("no_graphs", ctypes.c_int32), ("repair_cells", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("tail_items", ctypes.c_int32), ("full_rounds", ctypes.c_int32), ("bin_order", ctypes.c_int32),
-                ("force_mode", ctypes.c_int32), ("bin_factor", ctypes.c_double), ("dense", ctypes.c_int32)]
+                ("force_mode", ctypes.c_int32), ("bin_factor", ctypes.c_double), ("dense", ctypes.c_int32),
+                ("repair_mode", ctypes.c_int32)]
 
     def __init__(self, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=1.0, dt=0.01, seed=0, precision=SPV_FP64,
                  resort_every=0, kcap=0, repair_rounds=0, device_rounds=0, no_graphs=0, repair_cells=0,
-                 autotune=0, tail_items=0, full_rounds=0, bin_order=0, force_mode=0, bin_factor=0.0, dense=0):
+                 autotune=0, tail_items=0, full_rounds=0, bin_order=0, force_mode=0, bin_factor=0.0, dense=0,
+                 repair_mode=0):
         super().__init__(KA, KP, mu, v0, Dr, dt, seed, precision, resort_every, kcap, repair_rounds,
                          device_rounds, no_graphs, repair_cells, autotune, tail_items, full_rounds, bin_order,
-                         force_mode, bin_factor, dense)
+                         force_mode, bin_factor, dense, repair_mode)
 
 
 class Tuning(ctypes.Structure):

@@ -474,3 +474,53 @@ def test_overflowing_update_is_a_nonfinite_error(spv):
     gx, gy = s.positions()
     assert np.isfinite(gx).all() and np.isfinite(gy).all()
     s.close()
+
+
+# ---------------------------------------------------------------- hybrid comparison mode
+
+def test_hybrid_mode_bitwise_equal_to_device_repair(spv):
+    """repair_mode = 1 (the paper's split: the device tests, the host
+    rebuilds failed rings each step, the device re-tests) follows bitwise the
+    trajectory of the device repair, from the random start (thousands of
+    host repairs in the first steps) on; rings equal the oracle's."""
+    n = 3000
+    x, y, L, _ = _random_case(n, 57)
+    a, ca = _run(spv, x, y, L, [40], counters=True, resort_every=8)
+    b, cb = _run(spv, x, y, L, [7, 33], counters=True, resort_every=8, repair_mode=1)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    assert cb[1] == ca[1] and cb[8] == 0  # the same repairs, no graphs
+    s = spv.System(b[0], b[1], L, L, p0=3.9)
+    Lq, _, q = s.box()
+    s.close()
+    off, ring, _, _ = oracle.triangulate(b[0], b[1], Lq, Lq, q)
+    assert np.array_equal(b[3], off) and np.array_equal(b[4], ring)
+
+
+def test_hybrid_mode_batch(spv):
+    S = 4
+    N_s, L_s, xs, ys, p0_s, v0_s, seed_s = _batch_inputs(S, 62)
+    out = []
+    for mode in (0, 1):
+        b = spv.System.batch(N_s, L_s, np.concatenate(xs), np.concatenate(ys), p0_s, v0_s=v0_s, seed_s=seed_s,
+                             params=spv.Params(Dr=1.0, dt=0.01, resort_every=8, repair_mode=mode))
+        b.step(30)
+        out.append((*b.positions(), *b.neighbors()))
+        b.close()
+    for u, v in zip(*out):
+        assert np.array_equal(u, v)
+
+
+def test_never_resort_bitwise_equal(spv):
+    """resort_every = -1: the memory order of creation is kept and every
+    step's repairs search a cell list of the step's positions; graph periods
+    still replay (without a re-sort).  The trajectory is bitwise that of the
+    re-sorting default, with the same Hilbert or row-major bins."""
+    n = 3000
+    x, y, L, _ = _random_case(n, 58)
+    for order in (0, 1):
+        a, ca = _run(spv, x, y, L, [600], counters=True, bin_order=order)
+        b, cb = _run(spv, x, y, L, [3, 597], counters=True, resort_every=-1, bin_order=order)
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+        assert cb[5] == 0 and cb[8] > 0 and ca[5] > 0
