@@ -165,6 +165,9 @@ struct spv_sys {
     int dense = 0;          // dense first rounds: 0 while hot, 1 never, 2 always
     int repair_mode = 0;    // 0 device repair, 1 hybrid (device test, host repair)
     bool never_resort = false;  // no spatial re-sort: repairs always search the step's cell list
+    // dense first rounds after the hot phase too, while the measured repairs
+    // per step stay above N / 64 (on) / N / 256 (off again)
+    bool dense_busy = false;
     // adaptive re-sort: while cells move fast (the drift of a period exceeds
     // drift_limit, one bin side) steps run eagerly and re-sort as soon as
     // the drift passes the limit; a full quiet period returns to graphs
@@ -406,7 +409,20 @@ EvPair tev(spv_sys* s, int cat)
     return e;
 }
 
-inline bool dense_step(const spv_sys* s, bool hot) { return s->dense == 2 || (s->dense == 0 && hot); }
+inline bool dense_step(const spv_sys* s, bool hot)
+{
+    return s->dense == 2 || (s->dense == 0 && (hot || s->dense_busy));
+}
+
+// after `done` steps that repaired `rep` cells: dense rounds while repairs
+// are many (a large share of the cells failing, as in the fluid regime)
+void note_repairs(spv_sys* s, uint64_t rep, uint64_t done)
+{
+    if (!done) return;
+    const double per = (double)rep / (double)done;
+    if (per > s->N / 64.0) s->dense_busy = true;
+    else if (per < s->N / 256.0) s->dense_busy = false;
+}
 
 // the work lists, with this step's cell list for the repairs when cur
 Work work_for(const spv_sys* s, bool cur)
@@ -629,7 +645,8 @@ spv_status recover(spv_sys* s, bool curlist)
 // captured on first use.
 spv_status period_graph(spv_sys* s, int g, int gu, hipGraphExec_t* out)
 {
-    auto it = s->graphs.find({g, gu});
+    const int key = 2 * gu + (dense_step(s, false) ? 1 : 0);  // the dense flavour is captured too
+    auto it = s->graphs.find({g, key});
     if (it != s->graphs.end()) {
         *out = it->second;
         return SPV_OK;
@@ -650,7 +667,7 @@ spv_status period_graph(spv_sys* s, int g, int gu, hipGraphExec_t* out)
     hipError_t e2 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e2 != hipSuccess) return fail(SPV_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
-    s->graphs[{g, gu}] = ex;
+    s->graphs[{g, key}] = ex;
     *out = ex;
     return SPV_OK;
 }
@@ -819,13 +836,15 @@ spv_status run_steps(spv_sys* s, int64_t n)
         if (at_start && gu > 0 && n >= gu && s->use_graphs && !s->timing && !s->no_resort) {
             hipGraphExec_t ex = nullptr;
             ST_TRY(period_graph(s, s->cfg, gu, &ex));
-            const uint64_t before = s->step;
+            const uint64_t before = s->step, rep0 = s->h_st->repaired;
             const double drift0 = s->h_st->drift;
+            const bool dense = dense_step(s, false);
             HIP_TRY(hipGraphLaunch(ex, s->stream));
             ST_TRY(read_state(s));
             s->graph_periods++;
             const uint64_t done = s->h_st->step - before;
-            if (dense_step(s, false)) s->dense_steps += (int64_t)done;
+            if (dense) s->dense_steps += (int64_t)done;
+            note_repairs(s, s->h_st->repaired - rep0, done);
             if (s->h_st->halt) {
                 // the period stopped after `done` steps (the last one unfinished);
                 // later kernels, including its re-sort, did nothing
@@ -856,9 +875,9 @@ spv_status run_steps(spv_sys* s, int64_t n)
             if (!s->no_resort && !s->never_resort) b = std::min<int64_t>(b, std::max(1, s->unit - s->pos));
             // never re-sorting, graphs start at even positions: one step to get there
             if (s->never_resort && !s->hot && (s->pos & 1)) b = 1;
-            const uint64_t before = s->step;
+            const uint64_t before = s->step, rep0 = s->h_st->repaired;
             const double drift0 = s->h_st->drift;
-            const bool hot = s->hot;
+            const bool hot = s->hot, dense = dense_step(s, hot);
             for (int64_t j = 0; j < b; j++) {
                 const int cfg = s->cfg, par = (int)((s->pos + j) & 1);
                 dispatch(s, [&]<typename R, bool MULTI, int KC>() {
@@ -872,7 +891,8 @@ spv_status run_steps(spv_sys* s, int64_t n)
             s->step += done;
             s->pos += (int)done;
             n -= (int64_t)done;
-            if (dense_step(s, hot)) s->dense_steps += (int64_t)done;
+            if (dense) s->dense_steps += (int64_t)done;
+            note_repairs(s, s->h_st->repaired - rep0, done);
             if (s->h_st->halt) ST_TRY(recover(s, hot || s->never_resort));
             if (hot) {
                 // quiet once the measured drift rate has allowed graph periods
@@ -1130,6 +1150,7 @@ spv_status seat_cells(spv_sys* s, const std::vector<double>& hx, const std::vect
     s->hot = true;
     s->quiet = 0;
     s->drift_rate = INFINITY;
+    s->dense_busy = false;
     ST_TRY(do_resort_eager(s));
     s->resorts = 0;
     s->graph_periods = s->dense_steps = s->host_rounds = s->recoveries = 0;
