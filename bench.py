@@ -72,7 +72,14 @@ def class_bytes(cls, r):
 # (workload, kernel class, force-kernel layout), valid only for the kernel
 # source they were taken on (digest of the device headers): any later change
 # of the kernels nulls roofline.traffic.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("spv_n100k", "repair", 1): {"bytes_per_launch": 10.601e6, "source_sha256":
+                                 "2bfa1b43fd92ea29602281c839da504b94cbdef78ec59e0341afa0ee5d4e8755"},
+    ("spv_n100k", "force_update", 1): {"bytes_per_launch": 20.659e6, "source_sha256":
+                                       "2bfa1b43fd92ea29602281c839da504b94cbdef78ec59e0341afa0ee5d4e8755"},
+    ("spv_n100k", "geometry_test", 1): {"bytes_per_launch": 19.816e6, "source_sha256":
+                                        "2bfa1b43fd92ea29602281c839da504b94cbdef78ec59e0341afa0ee5d4e8755"},
+}
 
 
 def source_digest():
