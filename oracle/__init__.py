@@ -22,6 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "spv_oracle.c")
+_SRC_AVM = os.path.join(_HERE, "avm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, ENOMEM, EPRECOND, ECAPACITY, EFAIL = 0, -1, -2, -4, -5, -8
@@ -32,7 +33,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, _SRC, _SRC_AVM, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -261,4 +262,140 @@ def run(x, y, theta, Lx, Ly, q, A0, P0, *, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=0.
         out["fx"], out["fy"] = fx, fy
     if want_rings:
         out["ring_off"], out["ring"] = off, ring[: off[-1]].copy()
+    return out
+
+
+# ---------------------------------------------------------------- active vertex model
+class _AvmParams(ctypes.Structure):
+    _fields_ = [("KA", ctypes.c_double), ("KP", ctypes.c_double), ("mu", ctypes.c_double),
+                ("v0", ctypes.c_double), ("Dr", ctypes.c_double), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("l_t1", ctypes.c_double), ("l_new", ctypes.c_double)]
+
+
+def _avm_lib():
+    L = lib()
+    if not getattr(L, "_avm_ready", False):
+        P = ctypes.POINTER
+        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int32
+        L.orc_avm_geometry.restype = ctypes.c_int
+        L.orc_avm_geometry.argtypes = [i64, P(d), P(d), d, d, P(i32), P(i32), P(d), P(d)]
+        L.orc_avm_forces.restype = ctypes.c_int
+        L.orc_avm_forces.argtypes = [i64, i64, P(d), P(d), d, d, P(i32), P(i32), P(d), P(d), d, d, P(d), P(d)]
+        L.orc_avm_run.restype = ctypes.c_int
+        L.orc_avm_run.argtypes = [i64, i64, P(d), P(d), P(d), d, d, ctypes.c_int, P(i32), P(i32), i64, P(d), P(d),
+                                  P(_AvmParams), ctypes.c_uint64, i64, P(d), P(d), P(i64)]
+        L._avm_ready = True
+    return L
+
+
+def voronoi_network(x, y, Lx, Ly, q):
+    """The active vertex model's polygon network of the Voronoi tessellation
+    of cells at (x, y) (grid-exact): one vertex per Delaunay triangle at its
+    circumcentre, cell i's vertex list counter-clockwise in the order of its
+    ring (from its smallest-tag neighbour).  Vertices are numbered by first
+    appearance, cells visited in tag order (so a triangle is first met at its
+    smallest-tag corner, whose frame gives its position), positions wrapped
+    into the box and put on the grid 2^-q.  Returns vx, vy, cell_off, cell_vtx."""
+    x, y = _f64(x), _f64(y)
+    off, ring, ntri, _ = triangulate(x, y, Lx, Ly, q)
+    n = len(x)
+    s = 2.0 ** q
+    ids, vx, vy = {}, [], []
+    cv = np.zeros(off[-1], dtype=np.int32)
+    for i in range(n):
+        js = ring[off[i]:off[i + 1]]
+        k = len(js)
+        for m in range(k):
+            a, b = int(js[m]), int(js[(m + 1) % k])
+            tri = (i, a, b)
+            r = tri.index(min(tri))
+            key = tri[r:] + tri[:r]
+            if key not in ids:
+                bx = x[a] - x[i]
+                bx -= Lx * round(bx / Lx)
+                by = y[a] - y[i]
+                by -= Ly * round(by / Ly)
+                cx = x[b] - x[i]
+                cx -= Lx * round(cx / Lx)
+                cy = y[b] - y[i]
+                cy -= Ly * round(cy / Ly)
+                d = 2.0 * (bx * cy - by * cx)
+                ux = (cy * (bx * bx + by * by) - by * (cx * cx + cy * cy)) / d
+                uy = (bx * (cx * cx + cy * cy) - cx * (bx * bx + by * by)) / d
+                X = np.rint((x[i] + ux) * s) % np.rint(Lx * s)
+                Y = np.rint((y[i] + uy) * s) % np.rint(Ly * s)
+                ids[key] = len(vx)
+                vx.append(X / s)
+                vy.append(Y / s)
+            cv[off[i] + m] = ids[key]
+    return np.array(vx), np.array(vy), off.astype(np.int32), cv
+
+
+def avm_geometry(vx, vy, Lx, Ly, cell_off, cell_vtx):
+    vx, vy = _f64(vx), _f64(vy)
+    off = np.ascontiguousarray(cell_off, dtype=np.int32)
+    cv = np.ascontiguousarray(cell_vtx, dtype=np.int32)
+    nc = len(off) - 1
+    A, P = np.zeros(nc), np.zeros(nc)
+    rc = _avm_lib().orc_avm_geometry(nc, _p(vx, ctypes.c_double), _p(vy, ctypes.c_double), float(Lx), float(Ly),
+                                     _p(off, ctypes.c_int32), _p(cv, ctypes.c_int32), _p(A, ctypes.c_double),
+                                     _p(P, ctypes.c_double))
+    if rc != OK:
+        raise OracleError(rc, "avm_geometry")
+    return A, P
+
+
+def avm_forces(vx, vy, Lx, Ly, cell_off, cell_vtx, A0, P0, KA=1.0, KP=1.0):
+    """F_v = -dE/dh_v of Eq. (1) over the polygon cells (dual numbers)."""
+    vx, vy = _f64(vx), _f64(vy)
+    off = np.ascontiguousarray(cell_off, dtype=np.int32)
+    cv = np.ascontiguousarray(cell_vtx, dtype=np.int32)
+    nc, nv = len(off) - 1, len(vx)
+    A0 = _f64(np.broadcast_to(A0, (nc,)))
+    P0 = _f64(np.broadcast_to(P0, (nc,)))
+    fx, fy = np.zeros(nv), np.zeros(nv)
+    rc = _avm_lib().orc_avm_forces(nc, nv, _p(vx, ctypes.c_double), _p(vy, ctypes.c_double), float(Lx), float(Ly),
+                                   _p(off, ctypes.c_int32), _p(cv, ctypes.c_int32), _p(A0, ctypes.c_double),
+                                   _p(P0, ctypes.c_double), float(KA), float(KP), _p(fx, ctypes.c_double),
+                                   _p(fy, ctypes.c_double))
+    if rc != OK:
+        raise OracleError(rc, "avm_forces")
+    return fx, fy
+
+
+def avm_run(vx, vy, theta, Lx, Ly, q, cell_off, cell_vtx, A0, P0, *, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=0.0,
+            dt=0.01, seed=0, l_t1=0.04, l_new=0.06, step0=0, nsteps=1):
+    """nsteps of the active vertex model (Eq. 4, T1 rounds) on copies of the
+    state; returns vx, vy, theta, cell_off, cell_vtx, E and qbar (nsteps + 1
+    entries) and the T1 transitions and rounds."""
+    vx, vy, th = _f64(vx).copy(), _f64(vy).copy(), _f64(theta).copy()
+    off = np.array(cell_off, dtype=np.int32)
+    nc, nv = len(off) - 1, len(vx)
+    cap = 3 * nv + 64 * 8
+    cv = np.zeros(cap, dtype=np.int32)
+    cv[: off[-1]] = np.asarray(cell_vtx, dtype=np.int32)[: off[-1]]
+    A0 = _f64(np.broadcast_to(A0, (nc,)))
+    P0 = _f64(np.broadcast_to(P0, (nc,)))
+    prm = _AvmParams(KA, KP, mu, v0, Dr, dt, seed, l_t1, l_new)
+    E, Q = np.zeros(nsteps + 1), np.zeros(nsteps + 1)
+    cnt = np.zeros(2, dtype=np.int64)
+    rc = _avm_lib().orc_avm_run(nc, nv, _p(vx, ctypes.c_double), _p(vy, ctypes.c_double), _p(th, ctypes.c_double),
+                                float(Lx), float(Ly), int(q), _p(off, ctypes.c_int32), _p(cv, ctypes.c_int32), cap,
+                                _p(A0, ctypes.c_double), _p(P0, ctypes.c_double), ctypes.byref(prm), int(step0),
+                                int(nsteps), _p(E, ctypes.c_double), _p(Q, ctypes.c_double),
+                                _p(cnt, ctypes.c_int64))
+    if rc != OK:
+        raise OracleError(rc, "avm_run")
+    return {"vx": vx, "vy": vy, "theta": th, "cell_off": off, "cell_vtx": cv[: off[-1]].copy(), "E": E, "qbar": Q,
+            "t1": int(cnt[0]), "t1_rounds": int(cnt[1])}
+
+
+def canonical_cells(cell_off, cell_vtx):
+    """Each cell's vertex list rotated to start at its smallest vertex index
+    (the comparison form of two networks)."""
+    out = []
+    for c in range(len(cell_off) - 1):
+        v = list(cell_vtx[cell_off[c]:cell_off[c + 1]])
+        r = v.index(min(v))
+        out.append(tuple(v[r:] + v[:r]))
     return out
