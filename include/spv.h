@@ -316,6 +316,79 @@ spv_status spv_force_tangent_static(spv_sys* s, const double* vx, const double* 
 /* Release all device state of the handle. */
 spv_status spv_destroy(spv_sys* s);
 
+/* ====================================================================== */
+/*
+ * Active vertex model (AVM; Sec. II.A Eq. 4, Sec. II.D, App. A).  The
+ * degrees of freedom are the vertices h_v of a trivalent polygonal tiling of
+ * the periodic box (every vertex in exactly three cells; Nv = 2 Nc on the
+ * torus); the energy is Eq. 1 over the polygons' areas and perimeters, the
+ * force F_v = -dE/dh_v (App. A, with dP/dh = t_in - t_out: incoming minus
+ * outgoing unit edge vector), and the vertices move by Eq. 4:
+ *   dh_v/dt = mu F_v + (v0 / 3) sum of n_c over the three cells at v,
+ * the cell directors n_c = (cos theta_c, sin theta_c) rotating with white
+ * noise of variance 2 Dr (Philox4x64-10, counter (step, cell index)).  After
+ * every move, T1 transitions (Sec. II.D): an edge shorter than t1_length
+ * is replaced by its perpendicular of length t1_new_length through the same
+ * midpoint, so that the two cells that shared it lose a vertex and the two
+ * cells at its ends become neighbours; an edge qualifies only when both
+ * cells sharing it have more than three vertices and the end cells share no
+ * vertex yet; at most one transition per cell in a round (an edge flips
+ * when its key (smaller vertex index, larger vertex index) is the smallest
+ * among the qualifying edges at its four cells); rounds repeat until no
+ * edge qualifies.  Vertices are kept on the grid 2^-q of the box (as the
+ * Voronoi model's cells) and the T1 test is dx*dx + dy*dy < t1_length^2 on
+ * exact differences, evaluated without fused operations.  FP64.
+ */
+typedef struct {
+    double KA, KP, mu, v0, Dr, dt;  /* as spv_params */
+    uint64_t seed;                  /* noise key */
+    double t1_length;               /* T1 threshold (> 0) */
+    double t1_new_length;           /* length of the edge a T1 creates (0: 1.5 t1_length; must exceed it) */
+} spv_avm_params;
+
+typedef struct spv_avm spv_avm;
+
+/*
+ * Create from a polygon network: Nv vertices at (vx, vy) in [0,Lx) x [0,Ly),
+ * Nc cells whose vertex lists are cell_vtx[cell_off[c] .. cell_off[c+1]),
+ * counter-clockwise (3 to 16 vertices each; cell_off has Nc + 1 entries).
+ * A0, P0, p0, theta0 as spv_create (theta0 NULL: 2 pi u with u from Philox
+ * counter (2^64 - 1, c)).  Host or device pointers, read during the call.
+ * Errors: SPV_EINVAL (not a trivalent, consistently oriented network; Nv !=
+ * 2 Nc; bad parameters or positions), SPV_ENOMEM, SPV_EHIP.
+ */
+spv_status spv_avm_create(spv_avm** out, int64_t Nc, int64_t Nv, const double* vx, const double* vy,
+                          const int32_t* cell_off, const int32_t* cell_vtx, double Lx, double Ly, const double* A0,
+                          const double* P0, double p0, const double* theta0, const spv_avm_params* params,
+                          void* stream);
+/* nsteps steps; errors: SPV_ENONFINITE, SPV_ECAPACITY (a T1 would give a
+ * cell more than 16 vertices), SPV_EREPAIR (T1 rounds did not settle within
+ * 64 rounds of a step); the handle then keeps returning the error. */
+spv_status spv_avm_step(spv_avm* h, int64_t nsteps);
+spv_status spv_avm_get_vertices(spv_avm* h, double* vx, double* vy);       /* Nv each */
+spv_status spv_avm_get_forces(spv_avm* h, double* fx, double* fy);         /* at the current state */
+spv_status spv_avm_get_directors(spv_avm* h, double* theta);               /* Nc */
+spv_status spv_avm_get_geometry(spv_avm* h, double* A, double* P);         /* Nc each */
+/* current topology: cell_off (Nc + 1 entries) and the counter-clockwise
+ * vertex lists (cap entries; *needed = 3 Nv); SPV_ECAPACITY if cap is
+ * smaller (cell_off is still written).  Host pointers. */
+spv_status spv_avm_get_cells(spv_avm* h, int32_t* cell_off, int32_t* cell_vtx, int64_t cap, int64_t* needed);
+/* E (Eq. 1), qbar = mean P/sqrt(A); counters[4] (may be NULL): steps, T1
+ * transitions, T1 rounds with transitions, rounds run from the host */
+spv_status spv_avm_get_observables(spv_avm* h, double* E, double* qbar, int64_t* counters);
+spv_status spv_avm_destroy(spv_avm* h);
+
+/*
+ * The polygon network of a Voronoi system's current tessellation (its
+ * Voronoi cells: one vertex per Delaunay triangle at its circumcentre), the
+ * usual start of an active vertex model (single systems).  Vertices are
+ * numbered by first appearance, cells visited in tag order and each ring
+ * from its smallest-tag neighbour; a vertex's position is its circumcentre
+ * in the frame of its smallest-tag cell, wrapped into the box and put on the
+ * grid 2^-q.  Host arrays: vx, vy (2N), cell_off (N + 1), cell_vtx (6N).
+ */
+spv_status spv_voronoi_network(spv_sys* s, double* vx, double* vy, int32_t* cell_off, int32_t* cell_vtx);
+
 /* Message for the last non-OK status returned on this thread. */
 const char* spv_last_error(void);
 

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -1906,6 +1907,10 @@ spv_status hvp_static(spv_sys* s, const double* vx, const double* vy, double* fx
 }
 }  // namespace
 
+// ====================================================================== active vertex model
+#include "avm_kernels.hpp"
+#include "avm_api.hpp"
+
 // ====================================================================== C-ABI
 extern "C" {
 
@@ -2260,6 +2265,316 @@ spv_status spv_destroy(spv_sys* s)
 {
     if (!s) return fail(SPV_EINVAL, "bad handle");
     destroy_all(s);
+    return SPV_OK;
+}
+
+// ---------------------------------------------------------------- active vertex model
+spv_status spv_avm_create(spv_avm** out, int64_t Nc, int64_t Nv, const double* vx, const double* vy,
+                          const int32_t* cell_off, const int32_t* cell_vtx, double Lx, double Ly, const double* A0,
+                          const double* P0, double p0, const double* theta0, const spv_avm_params* params,
+                          void* stream)
+{
+    if (!out) return fail(SPV_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!vx || !vy || !cell_off || !cell_vtx || !params) return fail(SPV_EINVAL, "missing argument");
+    if (Nc < 3 || Nc > (1 << 28) || Nv != 2 * Nc)
+        return fail(SPV_EINVAL, "a trivalent tiling of the torus has Nv = 2 Nc vertices (Nc >= 3)");
+    if (!(Lx > 0.0) || !(Ly > 0.0) || !std::isfinite(Lx) || !std::isfinite(Ly))
+        return fail(SPV_EINVAL, "box sides must be positive and finite");
+    const spv_avm_params& pr = *params;
+    if (!(pr.dt > 0.0) || !(pr.Dr >= 0.0) || !std::isfinite(pr.mu) || !std::isfinite(pr.v0) ||
+        !std::isfinite(pr.KA) || !std::isfinite(pr.KP) || !std::isfinite(pr.dt) || !std::isfinite(pr.Dr))
+        return fail(SPV_EINVAL, "invalid model parameters");
+    if (!(pr.t1_length > 0.0) || !std::isfinite(pr.t1_length) || pr.t1_new_length < 0.0 ||
+        !std::isfinite(pr.t1_new_length))
+        return fail(SPV_EINVAL, "t1_length must be positive, t1_new_length non-negative");
+    const double lnew = pr.t1_new_length > 0.0 ? pr.t1_new_length : 1.5 * pr.t1_length;
+    if (!(lnew > pr.t1_length)) return fail(SPV_EINVAL, "t1_new_length must exceed t1_length");
+    const int nc = (int)Nc, nv = (int)Nv;
+    std::vector<int32_t> off(nc + 1);
+    HIP_TRY(hipMemcpy(off.data(), cell_off, (nc + 1) * sizeof(int32_t), hipMemcpyDefault));
+    if (off[nc] != 3 * nv) return fail(SPV_EINVAL, "the cells must list 3 Nv vertex entries in all");
+    std::vector<int32_t> cv(off[nc]);
+    HIP_TRY(hipMemcpy(cv.data(), cell_vtx, cv.size() * sizeof(int32_t), hipMemcpyDefault));
+    std::vector<double> hx, hy, ha0(nc, 1.0), hp0(nc), hth;
+    ST_TRY(copy_in(vx, hx, nv));
+    ST_TRY(copy_in(vy, hy, nv));
+    if (A0) ST_TRY(copy_in(A0, ha0, nc));
+    if (P0) {
+        ST_TRY(copy_in(P0, hp0, nc));
+    } else {
+        if (!std::isfinite(p0)) return fail(SPV_EINVAL, "p0 must be finite");
+        for (int c = 0; c < nc; c++) hp0[c] = p0 * std::sqrt(ha0[c]);
+    }
+    for (int c = 0; c < nc; c++)
+        if (!(ha0[c] > 0.0) || !std::isfinite(ha0[c]) || !std::isfinite(hp0[c]))
+            return fail(SPV_EINVAL, "A0 must be positive and finite, P0 finite");
+    if (theta0) ST_TRY(copy_in(theta0, hth, nc));
+    std::vector<int> vv, vc, cvf;
+    std::vector<uint8_t> deg;
+    ST_TRY(avm_topology(nc, nv, off, cv, vv, vc, cvf, deg));
+    spv_avm* h = new spv_avm();
+    h->nc = nc;
+    h->nv = nv;
+    h->stream = (hipStream_t)stream;
+    AvmParam& P = h->hp;
+    const int q = grid_exponent(std::max(Lx, Ly));
+    P.scale = std::ldexp(1.0, q);
+    P.inv_scale = 1.0 / P.scale;
+    P.LXu = std::rint(Lx * P.scale);
+    P.LYu = std::rint(Ly * P.scale);
+    P.Lx = P.LXu / P.scale;
+    P.Ly = P.LYu / P.scale;
+    P.hLx = 0.5 * P.Lx;
+    P.hLy = 0.5 * P.Ly;
+    P.mu = pr.mu;
+    P.v0 = pr.v0;
+    P.dt = pr.dt;
+    P.amp = std::sqrt(2.0 * pr.Dr * pr.dt);
+    P.KA = pr.KA;
+    P.KP = pr.KP;
+    P.lt1sq = pr.t1_length * pr.t1_length;
+    P.lnew = lnew;
+    P.seed = pr.seed;
+    for (int v = 0; v < nv; v++) {
+        if (!std::isfinite(hx[v]) || !std::isfinite(hy[v]) || hx[v] < 0.0 || hx[v] >= Lx || hy[v] < 0.0 ||
+            hy[v] >= Ly) {
+            avm_free(h);
+            return fail(SPV_EINVAL, "vertex positions must be finite and inside [0,Lx) x [0,Ly)");
+        }
+        double X = std::rint(hx[v] * P.scale), Y = std::rint(hy[v] * P.scale);
+        if (X >= P.LXu) X -= P.LXu;
+        if (Y >= P.LYu) Y -= P.LYu;
+        hx[v] = X / P.scale;
+        hy[v] = Y / P.scale;
+    }
+    spv_status st = SPV_OK;
+    auto T = [&](spv_status x) {
+        if (st == SPV_OK) st = x;
+    };
+    AvmDev& d = h->d;
+    for (int b = 0; b < 2; b++) {
+        T(avm_alloc(h, &d.x[b], nv));
+        T(avm_alloc(h, &d.y[b], nv));
+    }
+    T(avm_alloc(h, &d.vv, 3 * (size_t)nv));
+    T(avm_alloc(h, &d.vc, 3 * (size_t)nv));
+    T(avm_alloc(h, &d.cv, (size_t)nc * AVM_KV));
+    T(avm_alloc(h, &d.cdeg, nc));
+    T(avm_alloc(h, &d.cand, nv));
+    for (double** p : {&d.th, &d.A0, &d.P0, &d.A, &d.P, &d.ca, &d.cb}) T(avm_alloc(h, p, nc));
+    T(avm_alloc(h, &d.fx, nv));
+    T(avm_alloc(h, &d.fy, nv));
+    T(avm_alloc(h, &d.lock[0], nc));
+    T(avm_alloc(h, &d.lock[1], nc));
+    T(avm_alloc(h, &h->d_p, 1));
+    T(avm_alloc(h, &h->d_st, 1));
+    T(avm_alloc(h, &h->d_sp, 1));
+    h->obs_chunks = (nc + OBS_CHUNK - 1) / OBS_CHUNK;
+    T(avm_alloc(h, &h->d_obs, 3));
+    T(avm_alloc(h, &h->d_obs_part, 3 * (size_t)h->obs_chunks));
+    if (st != SPV_OK) {
+        std::string keep = spv_last_error();
+        avm_free(h);
+        return fail(st, keep);
+    }
+    if (hipHostMalloc((void**)&h->h_st, sizeof(AvmState), hipHostMallocDefault) != hipSuccess) {
+        avm_free(h);
+        return fail(SPV_ENOMEM, "hipHostMalloc failed");
+    }
+    std::memset(h->h_st, 0, sizeof(AvmState));
+    SysParam sp{};
+    sp.KA = pr.KA;
+    sp.KP = pr.KP;
+    sp.n = nc;
+    hipStream_t s = h->stream;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (st == SPV_OK && hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            st = fail(SPV_EHIP, "upload failed");
+    };
+    up(d.x[0], hx.data(), nv * sizeof(double));
+    up(d.y[0], hy.data(), nv * sizeof(double));
+    up(d.vv, vv.data(), vv.size() * sizeof(int));
+    up(d.vc, vc.data(), vc.size() * sizeof(int));
+    up(d.cv, cvf.data(), cvf.size() * sizeof(int));
+    up(d.cdeg, deg.data(), nc);
+    up(d.A0, ha0.data(), nc * sizeof(double));
+    up(d.P0, hp0.data(), nc * sizeof(double));
+    if (!hth.empty()) up(d.th, hth.data(), nc * sizeof(double));
+    up(h->d_p, &h->hp, sizeof(AvmParam));
+    up(h->d_st, h->h_st, sizeof(AvmState));
+    up(h->d_sp, &sp, sizeof(SysParam));
+    if (st == SPV_OK) {
+        if (hth.empty())
+            hipLaunchKernelGGL(k_avm_theta0, dim3(avm_grid(nc)), dim3(256), 0, s, d.th, (uint64_t)pr.seed, nc);
+        hipLaunchKernelGGL(k_avm_fill_lock, dim3(avm_grid(nc)), dim3(256), 0, s, d.lock[0], d.lock[1], nc);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            st = fail(SPV_EHIP, "initialisation kernels failed");
+    }
+    if (st != SPV_OK) {
+        std::string keep = spv_last_error();
+        avm_free(h);
+        return fail(st, keep);
+    }
+    *out = h;
+    return SPV_OK;
+}
+
+spv_status spv_avm_step(spv_avm* h, int64_t nsteps)
+{
+    if (!h || nsteps < 0) return fail(SPV_EINVAL, "bad argument");
+    return avm_steps(h, nsteps);
+}
+
+spv_status spv_avm_get_vertices(spv_avm* h, double* vx, double* vy)
+{
+    if (!h || !vx || !vy) return fail(SPV_EINVAL, "bad argument");
+    HIP_TRY(hipMemcpyAsync(vx, h->d.x[h->cur], h->nv * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(vy, h->d.y[h->cur], h->nv * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return SPV_OK;
+}
+
+spv_status spv_avm_get_directors(spv_avm* h, double* theta)
+{
+    if (!h || !theta) return fail(SPV_EINVAL, "bad argument");
+    HIP_TRY(hipMemcpyAsync(theta, h->d.th, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return SPV_OK;
+}
+
+// geometry and forces at the current state (the step's own kernels without
+// the move)
+static spv_status avm_eval(spv_avm* h)
+{
+    if (h->sticky != SPV_OK) return fail(h->sticky, h->sticky_msg);
+    const AvmArrays a = avm_arrays(h, h->cur);
+    hipLaunchKernelGGL(k_avm_geom, dim3(avm_grid(h->nc)), dim3(256), 0, h->stream, a, (const AvmParam*)h->d_p,
+                       h->d_st);
+    hipLaunchKernelGGL(k_avm_force<false>, dim3(avm_grid(h->nv)), dim3(256), 0, h->stream, a,
+                       (const AvmParam*)h->d_p, h->d_st);
+    HIP_TRY(hipGetLastError());
+    return SPV_OK;
+}
+
+spv_status spv_avm_get_forces(spv_avm* h, double* fx, double* fy)
+{
+    if (!h || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
+    ST_TRY(avm_eval(h));
+    HIP_TRY(hipMemcpyAsync(fx, h->d.fx, h->nv * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(fy, h->d.fy, h->nv * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return SPV_OK;
+}
+
+spv_status spv_avm_get_geometry(spv_avm* h, double* A, double* P)
+{
+    if (!h || !A || !P) return fail(SPV_EINVAL, "bad argument");
+    ST_TRY(avm_eval(h));
+    HIP_TRY(hipMemcpyAsync(A, h->d.A, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipMemcpyAsync(P, h->d.P, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return SPV_OK;
+}
+
+spv_status spv_avm_get_cells(spv_avm* h, int32_t* cell_off, int32_t* cell_vtx, int64_t cap, int64_t* needed)
+{
+    if (!h || !cell_off) return fail(SPV_EINVAL, "bad argument");
+    std::vector<int> cvf((size_t)h->nc * AVM_KV);
+    std::vector<uint8_t> deg(h->nc);
+    HIP_TRY(hipMemcpyAsync(cvf.data(), h->d.cv, cvf.size() * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(deg.data(), h->d.cdeg, h->nc, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int64_t tot = 0;
+    for (int c = 0; c < h->nc; c++) {
+        cell_off[c] = (int32_t)tot;
+        tot += deg[c];
+    }
+    cell_off[h->nc] = (int32_t)tot;
+    if (needed) *needed = tot;
+    if (!cell_vtx || cap < tot) return fail(SPV_ECAPACITY, "cell_vtx too small");
+    for (int c = 0; c < h->nc; c++)
+        for (int m = 0; m < deg[c]; m++) cell_vtx[cell_off[c] + m] = cvf[(size_t)c * AVM_KV + m];
+    return SPV_OK;
+}
+
+spv_status spv_avm_get_observables(spv_avm* h, double* E, double* qbar, int64_t* counters)
+{
+    if (!h) return fail(SPV_EINVAL, "bad handle");
+    ST_TRY(avm_eval(h));
+    hipLaunchKernelGGL(k_observables<double>, dim3(h->obs_chunks), dim3(256), 0, h->stream, (const double*)h->d.A,
+                       (const double*)h->d.P, (const double*)h->d.A0, (const double*)h->d.P0,
+                       (const SysParam*)h->d_sp, h->obs_chunks, h->d_obs_part);
+    hipLaunchKernelGGL(k_observables_sum, dim3(1), dim3(64), 0, h->stream, (const double*)h->d_obs_part,
+                       h->obs_chunks, h->d_obs);
+    double o[3];
+    HIP_TRY(hipMemcpyAsync(o, h->d_obs, sizeof o, hipMemcpyDeviceToHost, h->stream));
+    ST_TRY(avm_read(h));
+    if (E) *E = o[0];
+    if (qbar) *qbar = o[1] / h->nc;
+    if (counters) {
+        counters[0] = (int64_t)h->h_st->step;
+        counters[1] = (int64_t)h->h_st->t1;
+        counters[2] = (int64_t)h->h_st->rounds;
+        counters[3] = h->host_rounds;
+    }
+    return SPV_OK;
+}
+
+spv_status spv_avm_destroy(spv_avm* h)
+{
+    if (!h) return fail(SPV_EINVAL, "bad handle");
+    avm_free(h);
+    return SPV_OK;
+}
+
+spv_status spv_voronoi_network(spv_sys* s, double* vx, double* vy, int32_t* cell_off, int32_t* cell_vtx)
+{
+    if (!s || !vx || !vy || !cell_off || !cell_vtx) return fail(SPV_EINVAL, "bad argument");
+    if (s->S != 1) return fail(SPV_EINVAL, "single systems only");
+    const int N = s->N;
+    std::vector<double> x(N), y(N);
+    ST_TRY(spv_get_positions(s, x.data(), y.data()));
+    std::vector<int32_t> off(N + 1), nbr(6 * (size_t)N);
+    int64_t need = 0;
+    ST_TRY(spv_get_neighbors(s, off.data(), nbr.data(), (int64_t)nbr.size(), &need));
+    if (need != 6 * (int64_t)N) return fail(SPV_EHIP, "unexpected neighbour count");
+    const SysParam& P = s->hsp[0];
+    std::map<std::array<int, 3>, int> ids;
+    int nv = 0;
+    for (int i = 0; i < N; i++) {
+        const int k = off[i + 1] - off[i];
+        for (int m = 0; m < k; m++) {
+            const int a = nbr[off[i] + m], b = nbr[off[i] + (m + 1) % k];
+            std::array<int, 3> t{i, a, b};
+            const int r = (int)(std::min_element(t.begin(), t.end()) - t.begin());
+            std::rotate(t.begin(), t.begin() + r, t.end());
+            auto it = ids.find(t);
+            int id;
+            if (it == ids.end()) {
+                // the circumcentre in i's frame (i is the triangle's smallest tag)
+                const double bx = mimg(x[a] - x[i], P.Lx, P.hLx), by = mimg(y[a] - y[i], P.Ly, P.hLy);
+                const double cx = mimg(x[b] - x[i], P.Lx, P.hLx), cy = mimg(y[b] - y[i], P.Ly, P.hLy);
+                const double nb = bx * bx + by * by, nc = cx * cx + cy * cy, d = 2.0 * (bx * cy - by * cx);
+                const double ux = (cy * nb - by * nc) / d, uy = (bx * nc - cx * nb) / d;
+                double X = std::fmod(std::rint((x[i] + ux) * P.scale), P.LXu);
+                double Y = std::fmod(std::rint((y[i] + uy) * P.scale), P.LYu);
+                if (X < 0) X += P.LXu;
+                if (Y < 0) Y += P.LYu;
+                id = nv++;
+                if (id >= 2 * N) return fail(SPV_EHIP, "more Voronoi vertices than 2N");
+                ids.emplace(t, id);
+                vx[id] = X / P.scale;
+                vy[id] = Y / P.scale;
+            } else {
+                id = it->second;
+            }
+            cell_vtx[off[i] + m] = id;
+        }
+        cell_off[i] = off[i];
+    }
+    cell_off[N] = off[N];
+    if (nv != 2 * N) return fail(SPV_EHIP, "the tessellation does not have 2N vertices");
     return SPV_OK;
 }
 

@@ -55,6 +55,16 @@ class Params(ctypes.Structure):
                          force_mode, bin_factor, dense, repair_mode)
 
 
+class AvmParams(ctypes.Structure):
+    _fields_ = [("KA", ctypes.c_double), ("KP", ctypes.c_double), ("mu", ctypes.c_double),
+                ("v0", ctypes.c_double), ("Dr", ctypes.c_double), ("dt", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("t1_length", ctypes.c_double), ("t1_new_length", ctypes.c_double)]
+
+    def __init__(self, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=1.0, dt=0.01, seed=0, t1_length=0.04,
+                 t1_new_length=0.0):
+        super().__init__(KA, KP, mu, v0, Dr, dt, seed, t1_length, t1_new_length)
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("resort_every", ctypes.c_int32), ("device_rounds", ctypes.c_int32),
                 ("repair_cells", ctypes.c_int32), ("tail_items", ctypes.c_int32), ("full_rounds", ctypes.c_int32),
@@ -97,6 +107,16 @@ _SIGS = {
     "spv_force_tangent": [_H, _P, _P, _P, _P],
     "spv_force_tangent_static": [_H, _P, _P, _P, _P],
     "spv_destroy": [_H],
+    "spv_avm_create": [ctypes.POINTER(_H), _i64, _i64, _P, _P, _P, _P, _d, _d, _P, _P, _d, _P, _P, _P],
+    "spv_avm_step": [_H, _i64],
+    "spv_avm_get_vertices": [_H, _P, _P],
+    "spv_avm_get_forces": [_H, _P, _P],
+    "spv_avm_get_directors": [_H, _P],
+    "spv_avm_get_geometry": [_H, _P, _P],
+    "spv_avm_get_cells": [_H, _P, _P, _i64, ctypes.POINTER(_i64)],
+    "spv_avm_get_observables": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), _P],
+    "spv_avm_destroy": [_H],
+    "spv_voronoi_network": [_H, _P, _P, _P, _P],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -396,6 +416,121 @@ class System:
     def close(self):
         if self.h:
             spv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ active vertex model
+def spv_avm_create(Nc, Nv, vx, vy, cell_off, cell_vtx, Lx, Ly, A0=None, P0=None, p0=3.8, theta0=None, params=None,
+                   stream=None):
+    params = params if params is not None else AvmParams()
+    keep = [_f64(vx), _f64(vy), np.ascontiguousarray(cell_off, dtype=np.int32),
+            np.ascontiguousarray(cell_vtx, dtype=np.int32), _f64(A0), _f64(P0), _f64(theta0)]
+    h = _H()
+    st = _lib.spv_avm_create(ctypes.byref(h), int(Nc), int(Nv), _ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]),
+                             _ptr(keep[3]), float(Lx), float(Ly), _ptr(keep[4]), _ptr(keep[5]), float(p0),
+                             _ptr(keep[6]), ctypes.byref(params), stream if stream is not None else _current_stream())
+    _check(st, "spv_avm_create")
+    return h
+
+
+def spv_avm_step(h, n):
+    _check(_lib.spv_avm_step(h, int(n)), "spv_avm_step")
+
+
+def spv_avm_get_vertices(h, vx, vy):
+    _check(_lib.spv_avm_get_vertices(h, _ptr(vx), _ptr(vy)), "spv_avm_get_vertices")
+
+
+def spv_avm_get_forces(h, fx, fy):
+    _check(_lib.spv_avm_get_forces(h, _ptr(fx), _ptr(fy)), "spv_avm_get_forces")
+
+
+def spv_avm_get_directors(h, theta):
+    _check(_lib.spv_avm_get_directors(h, _ptr(theta)), "spv_avm_get_directors")
+
+
+def spv_avm_get_geometry(h, A, P):
+    _check(_lib.spv_avm_get_geometry(h, _ptr(A), _ptr(P)), "spv_avm_get_geometry")
+
+
+def spv_avm_get_cells(h, Nc, Nv):
+    off = np.zeros(Nc + 1, dtype=np.int32)
+    cv = np.zeros(3 * Nv, dtype=np.int32)
+    need = _i64()
+    _check(_lib.spv_avm_get_cells(h, _ptr(off), _ptr(cv), len(cv), ctypes.byref(need)), "spv_avm_get_cells")
+    return off, cv[: int(need.value)]
+
+
+def spv_avm_get_observables(h):
+    E, q = _d(), _d()
+    cnt = np.zeros(4, dtype=np.int64)
+    _check(_lib.spv_avm_get_observables(h, ctypes.byref(E), ctypes.byref(q), _ptr(cnt)), "spv_avm_get_observables")
+    return E.value, q.value, cnt
+
+
+def spv_avm_destroy(h):
+    _check(_lib.spv_avm_destroy(h), "spv_avm_destroy")
+
+
+def spv_voronoi_network(h, N):
+    vx, vy = np.zeros(2 * N), np.zeros(2 * N)
+    off = np.zeros(N + 1, dtype=np.int32)
+    cv = np.zeros(6 * N, dtype=np.int32)
+    _check(_lib.spv_voronoi_network(h, _ptr(vx), _ptr(vy), _ptr(off), _ptr(cv)), "spv_voronoi_network")
+    return vx, vy, off, cv
+
+
+class AVM:
+    """An active vertex model on the current HIP device (see include/spv.h)."""
+
+    def __init__(self, vx, vy, cell_off, cell_vtx, Lx, Ly, A0=None, P0=None, p0=3.8, theta0=None, params=None):
+        self.Nc, self.Nv = len(cell_off) - 1, len(vx)
+        self.h = spv_avm_create(self.Nc, self.Nv, vx, vy, cell_off, cell_vtx, Lx, Ly, A0, P0, p0, theta0, params)
+
+    @classmethod
+    def from_voronoi(cls, system, A0=None, P0=None, p0=3.8, theta0=None, params=None):
+        vx, vy, off, cv = spv_voronoi_network(system.h, system.N)
+        Lx, Ly, _ = system.box()
+        return cls(vx, vy, off, cv, Lx, Ly, A0, P0, p0, theta0, params)
+
+    def step(self, n):
+        spv_avm_step(self.h, n)
+
+    def vertices(self):
+        x, y = np.zeros(self.Nv), np.zeros(self.Nv)
+        spv_avm_get_vertices(self.h, x, y)
+        return x, y
+
+    def forces(self):
+        x, y = np.zeros(self.Nv), np.zeros(self.Nv)
+        spv_avm_get_forces(self.h, x, y)
+        return x, y
+
+    def directors(self):
+        t = np.zeros(self.Nc)
+        spv_avm_get_directors(self.h, t)
+        return t
+
+    def geometry(self):
+        A, P = np.zeros(self.Nc), np.zeros(self.Nc)
+        spv_avm_get_geometry(self.h, A, P)
+        return A, P
+
+    def cells(self):
+        return spv_avm_get_cells(self.h, self.Nc, self.Nv)
+
+    def observables(self):
+        return spv_avm_get_observables(self.h)
+
+    def close(self):
+        if self.h:
+            spv_avm_destroy(self.h)
             self.h = None
 
     def __del__(self):
