@@ -326,24 +326,34 @@ spv_status spv_destroy(spv_sys* s);
  * outgoing unit edge vector), and the vertices move by Eq. 4:
  *   dh_v/dt = mu F_v + (v0 / 3) sum of n_c over the three cells at v,
  * the cell directors n_c = (cos theta_c, sin theta_c) rotating with white
- * noise of variance 2 Dr (Philox4x64-10, counter (step, cell index)).  After
+ * noise of variance 2 Dr (Philox4x64-10, counter (step, cell label)).  After
  * every move, T1 transitions (Sec. II.D): an edge shorter than t1_length
  * is replaced by its perpendicular of length t1_new_length through the same
  * midpoint, so that the two cells that shared it lose a vertex and the two
  * cells at its ends become neighbours; an edge qualifies only when both
  * cells sharing it have more than three vertices and the end cells share no
  * vertex yet; at most one transition per cell in a round (an edge flips
- * when its key (smaller vertex index, larger vertex index) is the smallest
+ * when its key (smaller vertex label, larger vertex label) is the smallest
  * among the qualifying edges at its four cells); rounds repeat until no
  * edge qualifies.  Vertices are kept on the grid 2^-q of the box (as the
  * Voronoi model's cells) and the T1 test is dx*dx + dy*dy < t1_length^2 on
  * exact differences, evaluated without fused operations.  FP64.
+ *
+ * Labels are the indices the caller created vertices and cells with; every
+ * read-out is in label order.  The library keeps vertices and cells in its
+ * own memory order (Sec. II.B spatial sorting: bins of about one cell ranked
+ * along a Hilbert curve, re-sorted every resort_every steps) and nothing a
+ * result depends on is taken from that order, so results are bitwise the
+ * same for every resort_every and bin_order.
  */
 typedef struct {
     double KA, KP, mu, v0, Dr, dt;  /* as spv_params */
     uint64_t seed;                  /* noise key */
     double t1_length;               /* T1 threshold (> 0) */
     double t1_new_length;           /* length of the edge a T1 creates (0: 1.5 t1_length; must exceed it) */
+    int32_t resort_every;           /* steps between spatial re-sorts (also one at creation);
+                                       0: 1000; -1: never (memory order stays the caller's) */
+    int32_t bin_order;              /* 0: bins along a Hilbert curve; 1: row by row */
 } spv_avm_params;
 
 typedef struct spv_avm spv_avm;
@@ -355,15 +365,18 @@ typedef struct spv_avm spv_avm;
  * A0, P0, p0, theta0 as spv_create (theta0 NULL: 2 pi u with u from Philox
  * counter (2^64 - 1, c)).  Host or device pointers, read during the call.
  * Errors: SPV_EINVAL (not a trivalent, consistently oriented network; Nv !=
- * 2 Nc; bad parameters or positions), SPV_ENOMEM, SPV_EHIP.
+ * 2 Nc; bad parameters or positions; resort_every < -1; bin_order not 0 or
+ * 1), SPV_ENOMEM, SPV_EHIP.
  */
 spv_status spv_avm_create(spv_avm** out, int64_t Nc, int64_t Nv, const double* vx, const double* vy,
                           const int32_t* cell_off, const int32_t* cell_vtx, double Lx, double Ly, const double* A0,
                           const double* P0, double p0, const double* theta0, const spv_avm_params* params,
                           void* stream);
-/* nsteps steps; errors: SPV_ENONFINITE, SPV_ECAPACITY (a T1 would give a
- * cell more than 16 vertices), SPV_EREPAIR (T1 rounds did not settle within
- * 64 rounds of a step); the handle then keeps returning the error. */
+/* nsteps steps (three T1 rounds per step on the device, more from the host
+ * when needed; batches of 8 steps replay a captured HIP graph); errors:
+ * SPV_ENONFINITE, SPV_ECAPACITY (a T1 would give a cell more than 16
+ * vertices), SPV_EREPAIR (T1 rounds did not settle within 64 rounds of a
+ * step); the handle then keeps returning the error. */
 spv_status spv_avm_step(spv_avm* h, int64_t nsteps);
 spv_status spv_avm_get_vertices(spv_avm* h, double* vx, double* vy);       /* Nv each */
 spv_status spv_avm_get_forces(spv_avm* h, double* fx, double* fy);         /* at the current state */
@@ -373,8 +386,9 @@ spv_status spv_avm_get_geometry(spv_avm* h, double* A, double* P);         /* Nc
  * vertex lists (cap entries; *needed = 3 Nv); SPV_ECAPACITY if cap is
  * smaller (cell_off is still written).  Host pointers. */
 spv_status spv_avm_get_cells(spv_avm* h, int32_t* cell_off, int32_t* cell_vtx, int64_t cap, int64_t* needed);
-/* E (Eq. 1), qbar = mean P/sqrt(A); counters[4] (may be NULL): steps, T1
- * transitions, T1 rounds with transitions, rounds run from the host */
+/* E (Eq. 1), qbar = mean P/sqrt(A); counters[6] (may be NULL): steps, T1
+ * transitions, T1 rounds with transitions, rounds run from the host,
+ * batches replayed from a captured graph, re-sorts */
 spv_status spv_avm_get_observables(spv_avm* h, double* E, double* qbar, int64_t* counters);
 spv_status spv_avm_destroy(spv_avm* h);
 

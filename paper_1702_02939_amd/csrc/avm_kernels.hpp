@@ -13,15 +13,22 @@
 //
 // One step: cell geometry (area, perimeter, a = 2 K_A (A - A0),
 // b = 2 K_P (P - P0)); vertex forces and the Eq. 4 move (the mean director
-// of the three cells); director rotation; then T1 rounds (Sec. II.D): an
-// edge shorter than l_T1 is replaced by its perpendicular of length l_new
-// through the same midpoint and the cells at its ends become neighbours, at
-// most one transition per cell in a round (an edge flips when its key is the
-// smallest key of the qualifying edges at each of its four cells), rounds
-// repeated until none qualifies.  Vertices live on the dyadic grid 2^-q
-// (re-quantised after every move), so edge lengths are exact differences
-// and the T1 test dx*dx + dy*dy < l_T1^2 (no fused operations) decides the
-// same way on any implementation that follows it.
+// of the three cells); then T1 rounds (Sec. II.D), the first one also
+// rotating the directors: an edge shorter than l_T1 is replaced by its
+// perpendicular of length l_new through the same midpoint and the cells at
+// its ends become neighbours, at most one transition per cell in a round (an
+// edge flips when its key is the smallest key of the qualifying edges at
+// each of its four cells), rounds repeated until none qualifies.  Vertices
+// live on the dyadic grid 2^-q (re-quantised after every move), so edge
+// lengths are exact differences and the T1 test dx*dx + dy*dy < l_T1^2 (no
+// fused operations) decides the same way on any implementation that
+// follows it.
+//
+// Memory order is free: vertices and cells carry the labels they were
+// created with (vtag, ctag), and everything a result depends on -- which
+// end of an edge owns it, the T1 keys, the noise counters -- is taken from
+// the labels, never from the slots, so a spatial re-sort (Sec. II.B) moves
+// data without changing any result.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,7 +38,7 @@
 namespace spv {
 
 constexpr int AVM_KV = 16;           // most vertices of a cell
-constexpr int AVM_DEV_ROUNDS = 2;    // T1 rounds per step on the device
+constexpr int AVM_DEV_ROUNDS = 3;    // T1 rounds per step on the device (then a marking pass that halts if needed)
 constexpr int AVM_MAX_ROUNDS = 64;   // T1 rounds per step in all
 
 struct AvmParam {
@@ -47,7 +54,7 @@ struct AvmState {
     unsigned long long step;            // noise counter of the next step
     unsigned long long t1, rounds;      // statistics
     unsigned err;
-    int halt;                           // a step's last device round still flipped: later kernels wait
+    int halt;                           // a step needs more rounds than the device runs: later kernels wait
     int any[AVM_MAX_ROUNDS + 1];        // round r found a qualifying edge
 };
 
@@ -61,7 +68,11 @@ struct AvmArrays {
     double *th, *A0, *P0, *A, *P, *ca, *cb;
     double *fx, *fy;
     long long* lock[2];
-    uint8_t* cand;
+    uint8_t* cand;                      // a vertex's candidate edges of the current round (bit k: edge to vv[v][k])
+    uint8_t* dirty;                     // round in which a vertex is examined next (rounds >= 1)
+    int* lcell;                         // the four cells each candidate edge locked (4 per edge, 3 edges per vertex)
+    int* vtag;                          // creation label of each vertex slot
+    int* ctag;                          // creation label of each cell slot
     int nv, nc;
 };
 
@@ -74,7 +85,10 @@ __device__ __forceinline__ double avm_wrap(double v, double LU)
     return X;
 }
 
-// cell geometry; block 0 also clears the step's round flags
+// cell geometry; block 0 also clears the step's round flags.  The first
+// eight list entries are read as two 16-byte words and their position
+// gathers issued together (entries past the degree re-read the first
+// vertex); sums in list order, closing at the first vertex.
 __global__ __launch_bounds__(256) void k_avm_geom(AvmArrays a, const AvmParam* __restrict__ pp, AvmState* st)
 {
 #pragma clang fp contract(off)
@@ -85,14 +99,38 @@ __global__ __launch_bounds__(256) void k_avm_geom(AvmArrays a, const AvmParam* _
         for (int r = threadIdx.x; r <= AVM_MAX_ROUNDS; r += blockDim.x) st->any[r] = 0;
     if (c >= a.nc) return;
     const int k = a.cdeg[c];
-    const int* v = a.cv + (size_t)c * AVM_KV;
-    const double x0 = a.x[v[0]], y0 = a.y[v[0]];
+    const int* row = a.cv + (size_t)c * AVM_KV;
+    const int4 w0 = reinterpret_cast<const int4*>(row)[0], w1 = reinterpret_cast<const int4*>(row)[1];
+    const int id[8] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y, w1.z, w1.w};
+    double xs[8], ys[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        const int j = m < k ? id[m] : id[0];
+        xs[m] = a.x[j];
+        ys[m] = a.y[j];
+    }
     double px = 0.0, py = 0.0, a2 = 0.0, per = 0.0;
-    for (int m = 1; m <= k; m++) {
+#pragma unroll
+    for (int m = 1; m < 8; m++) {
+        if (m <= k) {
+            double qx = 0.0, qy = 0.0;
+            if (m < k) {
+                qx = mimg(xs[m] - xs[0], P.Lx, P.hLx);
+                qy = mimg(ys[m] - ys[0], P.Ly, P.hLy);
+            }
+            a2 += px * qy - py * qx;
+            const double ex = qx - px, ey = qy - py;
+            per += sqrt(ex * ex + ey * ey);
+            px = qx;
+            py = qy;
+        }
+    }
+    for (int m = 8; m <= k; m++) {  // cells with eight vertices or more
         double qx = 0.0, qy = 0.0;
         if (m < k) {
-            qx = mimg(a.x[v[m]] - x0, P.Lx, P.hLx);
-            qy = mimg(a.y[v[m]] - y0, P.Ly, P.hLy);
+            const int j = row[m];
+            qx = mimg(a.x[j] - xs[0], P.Lx, P.hLx);
+            qy = mimg(a.y[j] - ys[0], P.Ly, P.hLy);
         }
         a2 += px * qy - py * qx;
         const double ex = qx - px, ey = qy - py;
@@ -109,8 +147,8 @@ __global__ __launch_bounds__(256) void k_avm_geom(AvmArrays a, const AvmParam* _
 
 // Vertex forces F_v = -sum over v's cells of (a dA/dh + b dP/dh) (App. A:
 // dA/dh = (h+_y - h-_y, h-_x - h+_x) / 2, dP/dh = t_in - t_out with unit edge
-// vectors, a zero-length edge contributing 0); MOVE: then Eq. 4 into the
-// other buffer, re-quantised and wrapped
+// vectors, a zero-length edge contributing 0): stored (!MOVE), or the Eq. 4
+// move into the other buffer, re-quantised and wrapped (MOVE)
 template <bool MOVE>
 __global__ __launch_bounds__(256) void k_avm_force(AvmArrays a, const AvmParam* __restrict__ pp, AvmState* st)
 {
@@ -150,9 +188,11 @@ __global__ __launch_bounds__(256) void k_avm_force(AvmArrays a, const AvmParam* 
             sy += sn;
         }
     }
-    a.fx[v] = fx;
-    a.fy[v] = fy;
-    if (!MOVE) return;
+    if (!MOVE) {
+        a.fx[v] = fx;
+        a.fy[v] = fy;
+        return;
+    }
     const double nx = hx + P.dt * (P.mu * fx + P.v0 * sx / 3.0);
     const double ny = hy + P.dt * (P.mu * fy + P.v0 * sy / 3.0);
     double X = avm_wrap(rint(nx * P.scale), P.LXu), Y = avm_wrap(rint(ny * P.scale), P.LYu);
@@ -165,34 +205,38 @@ __global__ __launch_bounds__(256) void k_avm_force(AvmArrays a, const AvmParam* 
     a.yo[v] = Y * P.inv_scale;
 }
 
-// directors rotate (after the move; the step is counted by the next kernel)
-__global__ __launch_bounds__(256) void k_avm_theta(AvmArrays a, const AvmParam* __restrict__ pp, AvmState* st)
-{
-    if (st->halt) return;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < a.nc) a.th[c] += pp->amp * normal_for(pp->seed, st->step, (uint64_t)c);
-}
-
-// T1 round r, first pass: the qualifying edges (owned by their smaller
-// vertex) and, per cell, the smallest key among them
-__global__ __launch_bounds__(256) void k_avm_t1_mark(AvmArrays a, const AvmParam* __restrict__ pp, AvmState* st,
-                                                     int r)
+// T1 round r, first pass, for vertex v: its qualifying edges (each handled
+// by its smaller-label end) and, per cell, the smallest key among them.  A
+// vertex with a short edge (qualifying or not) is examined again in round
+// r + 1, and so are the six vertices of every flip (apply), so that rounds
+// >= 1 visit only those: no other edge can qualify there, since positions
+// move only at flips and every other change of eligibility (a cell's vertex
+// count, the end cells' shared vertices) touches edges that were already
+// short.  The locks this vertex's candidate edges took in round r - 1 are
+// released here (in the set round r + 1 uses).
+__device__ __forceinline__ bool avm_mark_vertex(const AvmArrays& a, const AvmParam& P, AvmState* st, int r, int v,
+                                                long long* lock, long long* prev)
 {
 #pragma clang fp contract(off)
-    if (st->halt && r < AVM_DEV_ROUNDS) return;
-    if (r == 0 && blockIdx.x == 0 && threadIdx.x == 0) st->step += 1ull;  // the step's noise is drawn
-    if (r > 0 && !st->any[r - 1]) return;  // nothing flipped in the last round: nothing new qualifies
-    const AvmParam& P = *pp;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= a.nv) return;
+    if (r > 0) {
+        const unsigned old = a.cand[v];
+        for (int k = 0; k < 3; k++)
+            if (old & (1u << k))
+                for (int j = 0; j < 4; j++) prev[a.lcell[12 * v + 4 * k + j]] = 0x7fffffffffffffffll;
+    }
     unsigned mask = 0;
-    long long* lock = a.lock[r & 1];
+    bool shortedge = false;
+    const double xv = a.x[v], yv = a.y[v];
+    int tv = -1;
     for (int k = 0; k < 3; k++) {
         const int u = a.vv[3 * v + k];
-        if (u <= v) continue;
-        const double ex = mimg(a.x[u] - a.x[v], P.Lx, P.hLx), ey = mimg(a.y[u] - a.y[v], P.Ly, P.hLy);
+        const double ex = mimg(a.x[u] - xv, P.Lx, P.hLx), ey = mimg(a.y[u] - yv, P.Ly, P.hLy);
         const double xx = ex * ex, yy = ey * ey;
         if (!(xx + yy < P.lt1sq)) continue;
+        shortedge = true;
+        if (tv < 0) tv = a.vtag[v];
+        const int tu = a.vtag[u];
+        if (tu < tv) continue;  // the other end handles it
         const int X = a.vc[3 * v + k], C1 = a.vc[3 * v + (k + 1) % 3], Y = a.vc[3 * v + (k + 2) % 3];
         int q = 0;
         while (q < 3 && a.vv[3 * u + q] != v) q++;
@@ -209,15 +253,51 @@ __global__ __launch_bounds__(256) void k_avm_t1_mark(AvmArrays a, const AvmParam
             for (int j = 0; j < a.cdeg[D1]; j++)
                 if (l1[i] == l2[j]) share = true;
         if (share) continue;
-        const long long key = ((long long)v << 32) | (long long)u;
+        const long long key = ((long long)tv << 32) | (long long)tu;
         atomicMin(&lock[X], key);
         atomicMin(&lock[Y], key);
         atomicMin(&lock[C1], key);
         atomicMin(&lock[D1], key);
+        int* lc = a.lcell + 12 * v + 4 * k;
+        lc[0] = X;
+        lc[1] = Y;
+        lc[2] = C1;
+        lc[3] = D1;
         mask |= 1u << k;
     }
     a.cand[v] = (uint8_t)mask;
-    if (mask) st->any[r] = 1;
+    a.dirty[v] = shortedge ? (uint8_t)(r + 1) : (uint8_t)0;  // examined: no stale flag stays behind
+    return mask != 0;
+}
+
+// Round 0 visits every vertex (one per thread) and rotates the directors
+// (after the move, with the step's counter).  Rounds >= 1 visit the
+// vertices flagged for them (eight flags per thread).  CHECK: the pass after
+// the device's rounds, which halts the batch when it still finds an edge.
+// HOST: a round run from the host for a halted step.
+__global__ __launch_bounds__(256) void k_avm_t1_mark(AvmArrays a, const AvmParam* __restrict__ pp, AvmState* st,
+                                                     int r, int host, int check)
+{
+    if (!host && st->halt) return;
+    const AvmParam& P = *pp;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    long long* lock = a.lock[r & 1];
+    long long* prev = a.lock[(r + 1) & 1];
+    bool found = false;
+    if (r == 0) {
+        if (t < a.nc) a.th[t] += P.amp * normal_for(P.seed, st->step, (uint64_t)a.ctag[t]);
+        if (t < a.nv) found = avm_mark_vertex(a, P, st, 0, t, lock, prev);
+    } else {
+        if (!st->any[r - 1]) return;  // nothing flipped in the last round: nothing new qualifies
+        if (8 * t >= a.nv) return;
+        const uint64_t f = *reinterpret_cast<const uint64_t*>(a.dirty + 8 * (size_t)t);
+        for (int j = 0; j < 8; j++)
+            if (((f >> (8 * j)) & 0xff) == (uint64_t)r) found |= avm_mark_vertex(a, P, st, r, 8 * t + j, lock, prev);
+    }
+    if (found) {
+        st->any[r] = 1;
+        if (check) st->halt = 1;
+    }
 }
 
 __device__ __forceinline__ void cell_remove(int* l, uint8_t* deg, int w)
@@ -242,33 +322,17 @@ __device__ __forceinline__ bool cell_insert_before(int* l, uint8_t* deg, int v, 
     return true;
 }
 
-// T1 round r, second pass: an edge whose key holds all four of its cells
-// flips (such edges share no cell and no vertex); every thread also clears
-// the next round's locks in its range
-__global__ __launch_bounds__(256) void k_avm_t1_apply(AvmArrays a, const AvmParam* __restrict__ pp, AvmState* st,
-                                                      int r, int last)
+// T1 round r, second pass for vertex v: an edge whose key holds all four of
+// its cells flips (such edges share no cell and no vertex)
+__device__ __forceinline__ void avm_apply_vertex(const AvmArrays& a, const AvmParam& P, AvmState* st, int r, int v,
+                                                 unsigned mask)
 {
 #pragma clang fp contract(off)
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < a.nc) a.lock[(r + 1) & 1][t] = 0x7fffffffffffffffll;
-    if (st->halt && r < AVM_DEV_ROUNDS) return;
-    if (!st->any[r]) return;
-    if (t == 0) {
-        atomicAdd(&st->rounds, 1ull);
-        // the step's last device round flipped: later rounds may be needed
-        // before the next step (the host runs them)
-        if (last) st->halt = 1;
-    }
-    if (t >= a.nv) return;
-    const int v = t;
-    const unsigned mask = a.cand[v];
-    if (!mask) return;
-    const AvmParam& P = *pp;
     const long long* lock = a.lock[r & 1];
     for (int k = 0; k < 3; k++) {
         if (!(mask & (1u << k))) continue;
         const int u = a.vv[3 * v + k];
-        const long long key = ((long long)v << 32) | (long long)u;
+        const long long key = ((long long)a.vtag[v] << 32) | (long long)a.vtag[u];
         const int X = a.vc[3 * v + k], C1 = a.vc[3 * v + (k + 1) % 3], Y = a.vc[3 * v + (k + 2) % 3];
         int q = 0;
         while (q < 3 && a.vv[3 * u + q] != v) q++;
@@ -277,7 +341,8 @@ __global__ __launch_bounds__(256) void k_avm_t1_apply(AvmArrays a, const AvmPara
         // neighbours: around v (v2 = u, a_, b_), around u (v, c_, d_)
         const int an = a.vv[3 * v + (k + 1) % 3], bn = a.vv[3 * v + (k + 2) % 3];
         const int cn = a.vv[3 * u + (q + 1) % 3], dn = a.vv[3 * u + (q + 2) % 3];
-        // geometry: the perpendicular through the midpoint, v on X's side
+        // geometry: the perpendicular through the midpoint, v (the smaller
+        // label) on X's side
         const double ex = mimg(a.x[u] - a.x[v], P.Lx, P.hLx), ey = mimg(a.y[u] - a.y[v], P.Ly, P.hLy);
         const double mx = a.x[v] + 0.5 * ex, my = a.y[v] + 0.5 * ey;
         const double len = sqrt(ex * ex + ey * ey);
@@ -309,9 +374,148 @@ __global__ __launch_bounds__(256) void k_avm_t1_apply(AvmArrays a, const AvmPara
         const bool ok1 = cell_insert_before(a.cv + (size_t)C1 * AVM_KV, a.cdeg + C1, v, u);
         const bool ok2 = cell_insert_before(a.cv + (size_t)D1 * AVM_KV, a.cdeg + D1, u, v);
         if (!ok1 || !ok2) atomicOr(&st->err, ERR_CAPACITY);
+        // every edge at the moved vertices changed: examine them next round
+        const uint8_t nr = (uint8_t)(r + 1);
+        a.dirty[v] = a.dirty[u] = a.dirty[an] = a.dirty[bn] = a.dirty[cn] = a.dirty[dn] = nr;
         atomicAdd(&st->t1, 1ull);
         break;
     }
+}
+
+// T1 round r, second pass: eight candidate masks per thread; round 0 counts
+// the step
+__global__ __launch_bounds__(256) void k_avm_t1_apply(AvmArrays a, const AvmParam* __restrict__ pp, AvmState* st,
+                                                      int r, int host)
+{
+    if (!host && st->halt) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r == 0 && t == 0) st->step += 1ull;  // the step's noise is drawn
+    if (!st->any[r]) return;
+    if (t == 0) atomicAdd(&st->rounds, 1ull);
+    if (8 * t >= a.nv) return;
+    const uint64_t f = *reinterpret_cast<const uint64_t*>(a.cand + 8 * (size_t)t);
+    if (!f) return;
+    const AvmParam& P = *pp;
+    for (int j = 0; j < 8; j++) {
+        const unsigned m = (unsigned)((f >> (8 * j)) & 0xff);
+        if (m) avm_apply_vertex(a, P, st, r, 8 * t + j, m);
+    }
+}
+
+// ---------------------------------------------------------------- spatial re-sort
+// Vertices by their position's bin, cells by their first vertex's bin, the
+// bins ranked along a Hilbert curve (or row by row): a counting sort (keys
+// and counts, a scan of the counts, a scatter, then each bin's few entries
+// ordered by label so the order is deterministic), then every array
+// gathered into its new slot with vertex and cell indices renamed.
+struct AvmBins {
+    double bsx, bsy;                    // bin sides
+    int nbx, nby, nb;
+    const int* rank;                    // rank of bin (by * nbx + bx) along the curve
+};
+
+__device__ __forceinline__ int avm_bin_rank(const AvmBins& b, double x, double y)
+{
+    const int bx = min((int)(x / b.bsx), b.nbx - 1), by = min((int)(y / b.bsy), b.nby - 1);
+    return b.rank[by * b.nbx + bx];
+}
+
+__global__ __launch_bounds__(256) void k_avm_keys(AvmArrays a, AvmBins b, int* vkey, int* vcount, int* ckey,
+                                                  int* ccount)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < a.nv) {
+        const int k = avm_bin_rank(b, a.x[t], a.y[t]);
+        vkey[t] = k;
+        atomicAdd(&vcount[k], 1);
+    }
+    if (t < a.nc) {
+        const int v0 = a.cv[(size_t)t * AVM_KV];
+        const int k = avm_bin_rank(b, a.x[v0], a.y[v0]);
+        ckey[t] = k;
+        atomicAdd(&ccount[k], 1);
+    }
+}
+
+// slot of every entry within its bin's range (start: exclusive scan of the
+// counts; fill: zeroed counts)
+__global__ __launch_bounds__(256) void k_avm_scatter(const int* vkey, const int* vstart, int* vfill, int* vperm,
+                                                     const int* ckey, const int* cstart, int* cfill, int* cperm,
+                                                     int nv, int nc)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nv) {
+        const int k = vkey[t];
+        vperm[vstart[k] + atomicAdd(&vfill[k], 1)] = t;
+    }
+    if (t < nc) {
+        const int k = ckey[t];
+        cperm[cstart[k] + atomicAdd(&cfill[k], 1)] = t;
+    }
+}
+
+// each bin's entries by label, their inverse permutation, and the bin's fill
+// counter back to zero for the next sort
+__global__ __launch_bounds__(256) void k_avm_bin_order(const int* start, int* fill, int* perm, int* inv,
+                                                       const int* tag, int nb)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int s = start[b], e = start[b + 1];
+    for (int i = s + 1; i < e; i++) {
+        const int x = perm[i], tx = tag[x];
+        int j = i - 1;
+        while (j >= s && tag[perm[j]] > tx) {
+            perm[j + 1] = perm[j];
+            j--;
+        }
+        perm[j + 1] = x;
+    }
+    for (int i = s; i < e; i++) inv[perm[i]] = i;
+    fill[b] = 0;
+}
+
+// new slot t holds old vertex vperm[t] / old cell cperm[t]
+__global__ __launch_bounds__(256) void k_avm_gather(AvmArrays src, AvmArrays dst, const int* __restrict__ vperm,
+                                                   const int* __restrict__ vinv, const int* __restrict__ cperm,
+                                                   const int* __restrict__ cinv)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < src.nv) {
+        const int i = vperm[t];
+        dst.x[t] = src.x[i];
+        dst.y[t] = src.y[i];
+        dst.vtag[t] = src.vtag[i];
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            dst.vv[3 * t + k] = vinv[src.vv[3 * i + k]];
+            dst.vc[3 * t + k] = cinv[src.vc[3 * i + k]];
+        }
+    }
+    if (t < src.nc) {
+        const int c = cperm[t];
+        const int k = src.cdeg[c];
+        dst.cdeg[t] = (uint8_t)k;
+        for (int m = 0; m < k; m++) dst.cv[(size_t)t * AVM_KV + m] = vinv[src.cv[(size_t)c * AVM_KV + m]];
+        dst.th[t] = src.th[c];
+        dst.A0[t] = src.A0[c];
+        dst.P0[t] = src.P0[c];
+        dst.ctag[t] = src.ctag[c];
+    }
+}
+
+// per-slot values into label order
+__global__ void k_avm_by_label(const double* __restrict__ in, const int* __restrict__ tag, double* __restrict__ out,
+                               int n)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[tag[t]] = in[t];
+}
+
+__global__ void k_avm_iota(int* a, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = i;
 }
 
 // host rounds finished: the next step may run
@@ -320,7 +524,8 @@ __global__ void k_avm_resume(AvmState* st)
     if (threadIdx.x == 0 && blockIdx.x == 0) st->halt = 0;
 }
 
-// initial directors: 2 pi u, u from Philox counter (2^64 - 1, cell)
+// initial directors: 2 pi u, u from Philox counter (2^64 - 1, cell label);
+// at creation slots and labels coincide
 __global__ void k_avm_theta0(double* th, uint64_t seed, int n)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;

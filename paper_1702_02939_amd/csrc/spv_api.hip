@@ -2290,6 +2290,8 @@ spv_status spv_avm_create(spv_avm** out, int64_t Nc, int64_t Nv, const double* v
         return fail(SPV_EINVAL, "t1_length must be positive, t1_new_length non-negative");
     const double lnew = pr.t1_new_length > 0.0 ? pr.t1_new_length : 1.5 * pr.t1_length;
     if (!(lnew > pr.t1_length)) return fail(SPV_EINVAL, "t1_new_length must exceed t1_length");
+    if (pr.resort_every < -1) return fail(SPV_EINVAL, "resort_every must be -1, 0 or positive");
+    if (pr.bin_order != 0 && pr.bin_order != 1) return fail(SPV_EINVAL, "bin_order must be 0 or 1");
     const int nc = (int)Nc, nv = (int)Nv;
     std::vector<int32_t> off(nc + 1);
     HIP_TRY(hipMemcpy(off.data(), cell_off, (nc + 1) * sizeof(int32_t), hipMemcpyDefault));
@@ -2317,6 +2319,7 @@ spv_status spv_avm_create(spv_avm** out, int64_t Nc, int64_t Nv, const double* v
     h->nc = nc;
     h->nv = nv;
     h->stream = (hipStream_t)stream;
+    h->resort_every = pr.resort_every == 0 ? AVM_DEFAULT_RESORT : pr.resort_every;
     AvmParam& P = h->hp;
     const int q = grid_exponent(std::max(Lx, Ly));
     P.scale = std::ldexp(1.0, q);
@@ -2353,20 +2356,40 @@ spv_status spv_avm_create(spv_avm** out, int64_t Nc, int64_t Nv, const double* v
         if (st == SPV_OK) st = x;
     };
     AvmDev& d = h->d;
+    const std::vector<int> rank = avm_bin_ranks(h->bins, P.Lx, P.Ly, nc, pr.bin_order);
+    const int nb = h->bins.nb;
+    const bool sorting = h->resort_every > 0;
     for (int b = 0; b < 2; b++) {
         T(avm_alloc(h, &d.x[b], nv));
         T(avm_alloc(h, &d.y[b], nv));
+        if (b == 1 && !sorting) break;  // one array set without re-sorts
+        T(avm_alloc(h, &d.vv[b], 3 * (size_t)nv));
+        T(avm_alloc(h, &d.vc[b], 3 * (size_t)nv));
+        T(avm_alloc(h, &d.cv[b], (size_t)nc * AVM_KV));
+        T(avm_alloc(h, &d.vtag[b], nv));
+        T(avm_alloc(h, &d.ctag[b], nc));
+        T(avm_alloc(h, &d.cdeg[b], nc));
+        for (double** p : {&d.th[b], &d.A0[b], &d.P0[b]}) T(avm_alloc(h, p, nc));
     }
-    T(avm_alloc(h, &d.vv, 3 * (size_t)nv));
-    T(avm_alloc(h, &d.vc, 3 * (size_t)nv));
-    T(avm_alloc(h, &d.cv, (size_t)nc * AVM_KV));
-    T(avm_alloc(h, &d.cdeg, nc));
-    T(avm_alloc(h, &d.cand, nv));
-    for (double** p : {&d.th, &d.A0, &d.P0, &d.A, &d.P, &d.ca, &d.cb}) T(avm_alloc(h, p, nc));
+    const size_t nv8 = ((size_t)nv + 7) / 8 * 8;
+    T(avm_alloc(h, &d.cand, nv8));
+    T(avm_alloc(h, &d.dirty, nv8));
+    T(avm_alloc(h, &d.lcell, 12 * (size_t)nv));
+    for (double** p : {&d.A, &d.P, &d.ca, &d.cb}) T(avm_alloc(h, p, nc));
     T(avm_alloc(h, &d.fx, nv));
     T(avm_alloc(h, &d.fy, nv));
+    T(avm_alloc(h, &d.out, nv));
     T(avm_alloc(h, &d.lock[0], nc));
     T(avm_alloc(h, &d.lock[1], nc));
+    if (sorting) {
+        for (int** p : {&d.vkey, &d.vperm, &d.vinv}) T(avm_alloc(h, p, nv));
+        for (int** p : {&d.ckey, &d.cperm, &d.cinv}) T(avm_alloc(h, p, nc));
+        for (int** p : {&d.vcount, &d.ccount, &d.rank}) T(avm_alloc(h, p, nb));
+        for (int** p : {&d.vstart, &d.cstart}) T(avm_alloc(h, p, (size_t)nb + 1));
+        for (int** p : {&d.vchunk, &d.cchunk}) T(avm_alloc(h, p, (size_t)grid_for(nb, SCAN_CHUNK) + 1));
+        T(avm_alloc(h, &h->d_scan, 1));
+    }
+    h->bins.rank = d.rank;
     T(avm_alloc(h, &h->d_p, 1));
     T(avm_alloc(h, &h->d_st, 1));
     T(avm_alloc(h, &h->d_sp, 1));
@@ -2394,23 +2417,34 @@ spv_status spv_avm_create(spv_avm** out, int64_t Nc, int64_t Nv, const double* v
     };
     up(d.x[0], hx.data(), nv * sizeof(double));
     up(d.y[0], hy.data(), nv * sizeof(double));
-    up(d.vv, vv.data(), vv.size() * sizeof(int));
-    up(d.vc, vc.data(), vc.size() * sizeof(int));
-    up(d.cv, cvf.data(), cvf.size() * sizeof(int));
-    up(d.cdeg, deg.data(), nc);
-    up(d.A0, ha0.data(), nc * sizeof(double));
-    up(d.P0, hp0.data(), nc * sizeof(double));
-    if (!hth.empty()) up(d.th, hth.data(), nc * sizeof(double));
+    up(d.vv[0], vv.data(), vv.size() * sizeof(int));
+    up(d.vc[0], vc.data(), vc.size() * sizeof(int));
+    up(d.cv[0], cvf.data(), cvf.size() * sizeof(int));
+    up(d.cdeg[0], deg.data(), nc);
+    up(d.A0[0], ha0.data(), nc * sizeof(double));
+    up(d.P0[0], hp0.data(), nc * sizeof(double));
+    if (!hth.empty()) up(d.th[0], hth.data(), nc * sizeof(double));
+    if (sorting) up(d.rank, rank.data(), nb * sizeof(int));
     up(h->d_p, &h->hp, sizeof(AvmParam));
     up(h->d_st, h->h_st, sizeof(AvmState));
     up(h->d_sp, &sp, sizeof(SysParam));
     if (st == SPV_OK) {
         if (hth.empty())
-            hipLaunchKernelGGL(k_avm_theta0, dim3(avm_grid(nc)), dim3(256), 0, s, d.th, (uint64_t)pr.seed, nc);
+            hipLaunchKernelGGL(k_avm_theta0, dim3(avm_grid(nc)), dim3(256), 0, s, d.th[0], (uint64_t)pr.seed, nc);
         hipLaunchKernelGGL(k_avm_fill_lock, dim3(avm_grid(nc)), dim3(256), 0, s, d.lock[0], d.lock[1], nc);
+        HIP_TRY(hipMemsetAsync(d.cand, 0, nv8, s));
+        HIP_TRY(hipMemsetAsync(d.dirty, 0, nv8, s));
+        hipLaunchKernelGGL(k_avm_iota, dim3(avm_grid(nv)), dim3(256), 0, s, d.vtag[0], nv);
+        hipLaunchKernelGGL(k_avm_iota, dim3(avm_grid(nc)), dim3(256), 0, s, d.ctag[0], nc);
+        if (sorting) {
+            hipLaunchKernelGGL(k_fill_i32, dim3(avm_grid(nb)), dim3(256), 0, s, d.vcount, nb, 0);
+            hipLaunchKernelGGL(k_fill_i32, dim3(avm_grid(nb)), dim3(256), 0, s, d.ccount, nb, 0);
+            HIP_TRY(hipMemsetAsync(h->d_scan, 0, sizeof(DevState), s));
+        }
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             st = fail(SPV_EHIP, "initialisation kernels failed");
     }
+    if (st == SPV_OK && sorting) st = avm_resort(h);
     if (st != SPV_OK) {
         std::string keep = spv_last_error();
         avm_free(h);
@@ -2426,21 +2460,30 @@ spv_status spv_avm_step(spv_avm* h, int64_t nsteps)
     return avm_steps(h, nsteps);
 }
 
+// a per-slot array into label order, then to the caller's memory (host or
+// device)
+static spv_status avm_out(spv_avm* h, const double* src, bool vertices, double* dst)
+{
+    const int n = vertices ? h->nv : h->nc;
+    const int* tag = vertices ? h->d.vtag[h->set] : h->d.ctag[h->set];
+    hipLaunchKernelGGL(k_avm_by_label, dim3(avm_grid(n)), dim3(256), 0, h->stream, src, tag, h->d.out, n);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(dst, h->d.out, n * sizeof(double), hipMemcpyDefault, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return SPV_OK;
+}
+
 spv_status spv_avm_get_vertices(spv_avm* h, double* vx, double* vy)
 {
     if (!h || !vx || !vy) return fail(SPV_EINVAL, "bad argument");
-    HIP_TRY(hipMemcpyAsync(vx, h->d.x[h->cur], h->nv * sizeof(double), hipMemcpyDefault, h->stream));
-    HIP_TRY(hipMemcpyAsync(vy, h->d.y[h->cur], h->nv * sizeof(double), hipMemcpyDefault, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return SPV_OK;
+    ST_TRY(avm_out(h, h->d.x[h->cur], true, vx));
+    return avm_out(h, h->d.y[h->cur], true, vy);
 }
 
 spv_status spv_avm_get_directors(spv_avm* h, double* theta)
 {
     if (!h || !theta) return fail(SPV_EINVAL, "bad argument");
-    HIP_TRY(hipMemcpyAsync(theta, h->d.th, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return SPV_OK;
+    return avm_out(h, h->d.th[h->set], false, theta);
 }
 
 // geometry and forces at the current state (the step's own kernels without
@@ -2461,40 +2504,43 @@ spv_status spv_avm_get_forces(spv_avm* h, double* fx, double* fy)
 {
     if (!h || !fx || !fy) return fail(SPV_EINVAL, "bad argument");
     ST_TRY(avm_eval(h));
-    HIP_TRY(hipMemcpyAsync(fx, h->d.fx, h->nv * sizeof(double), hipMemcpyDefault, h->stream));
-    HIP_TRY(hipMemcpyAsync(fy, h->d.fy, h->nv * sizeof(double), hipMemcpyDefault, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return SPV_OK;
+    ST_TRY(avm_out(h, h->d.fx, true, fx));
+    return avm_out(h, h->d.fy, true, fy);
 }
 
 spv_status spv_avm_get_geometry(spv_avm* h, double* A, double* P)
 {
     if (!h || !A || !P) return fail(SPV_EINVAL, "bad argument");
     ST_TRY(avm_eval(h));
-    HIP_TRY(hipMemcpyAsync(A, h->d.A, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
-    HIP_TRY(hipMemcpyAsync(P, h->d.P, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return SPV_OK;
+    ST_TRY(avm_out(h, h->d.A, false, A));
+    return avm_out(h, h->d.P, false, P);
 }
 
 spv_status spv_avm_get_cells(spv_avm* h, int32_t* cell_off, int32_t* cell_vtx, int64_t cap, int64_t* needed)
 {
     if (!h || !cell_off) return fail(SPV_EINVAL, "bad argument");
-    std::vector<int> cvf((size_t)h->nc * AVM_KV);
-    std::vector<uint8_t> deg(h->nc);
-    HIP_TRY(hipMemcpyAsync(cvf.data(), h->d.cv, cvf.size() * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(deg.data(), h->d.cdeg, h->nc, hipMemcpyDeviceToHost, h->stream));
+    const int nc = h->nc, nv = h->nv, s = h->set;
+    std::vector<int> cvf((size_t)nc * AVM_KV), vtag(nv), ctag(nc);
+    std::vector<uint8_t> deg(nc);
+    HIP_TRY(hipMemcpyAsync(cvf.data(), h->d.cv[s], cvf.size() * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(deg.data(), h->d.cdeg[s], nc, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(vtag.data(), h->d.vtag[s], nv * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(ctag.data(), h->d.ctag[s], nc * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    std::vector<int> slot(nc);  // slot of each cell label
+    for (int c = 0; c < nc; c++) slot[ctag[c]] = c;
     int64_t tot = 0;
-    for (int c = 0; c < h->nc; c++) {
-        cell_off[c] = (int32_t)tot;
-        tot += deg[c];
+    for (int t = 0; t < nc; t++) {
+        cell_off[t] = (int32_t)tot;
+        tot += deg[slot[t]];
     }
-    cell_off[h->nc] = (int32_t)tot;
+    cell_off[nc] = (int32_t)tot;
     if (needed) *needed = tot;
     if (!cell_vtx || cap < tot) return fail(SPV_ECAPACITY, "cell_vtx too small");
-    for (int c = 0; c < h->nc; c++)
-        for (int m = 0; m < deg[c]; m++) cell_vtx[cell_off[c] + m] = cvf[(size_t)c * AVM_KV + m];
+    for (int t = 0; t < nc; t++) {
+        const int c = slot[t];
+        for (int m = 0; m < deg[c]; m++) cell_vtx[cell_off[t] + m] = vtag[cvf[(size_t)c * AVM_KV + m]];
+    }
     return SPV_OK;
 }
 
@@ -2503,7 +2549,7 @@ spv_status spv_avm_get_observables(spv_avm* h, double* E, double* qbar, int64_t*
     if (!h) return fail(SPV_EINVAL, "bad handle");
     ST_TRY(avm_eval(h));
     hipLaunchKernelGGL(k_observables<double>, dim3(h->obs_chunks), dim3(256), 0, h->stream, (const double*)h->d.A,
-                       (const double*)h->d.P, (const double*)h->d.A0, (const double*)h->d.P0,
+                       (const double*)h->d.P, (const double*)h->d.A0[h->set], (const double*)h->d.P0[h->set],
                        (const SysParam*)h->d_sp, h->obs_chunks, h->d_obs_part);
     hipLaunchKernelGGL(k_observables_sum, dim3(1), dim3(64), 0, h->stream, (const double*)h->d_obs_part,
                        h->obs_chunks, h->d_obs);
@@ -2517,6 +2563,8 @@ spv_status spv_avm_get_observables(spv_avm* h, double* E, double* qbar, int64_t*
         counters[1] = (int64_t)h->h_st->t1;
         counters[2] = (int64_t)h->h_st->rounds;
         counters[3] = h->host_rounds;
+        counters[4] = h->graph_batches;
+        counters[5] = h->resorts;
     }
     return SPV_OK;
 }

@@ -58,11 +58,12 @@ class Params(ctypes.Structure):
 class AvmParams(ctypes.Structure):
     _fields_ = [("KA", ctypes.c_double), ("KP", ctypes.c_double), ("mu", ctypes.c_double),
                 ("v0", ctypes.c_double), ("Dr", ctypes.c_double), ("dt", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("t1_length", ctypes.c_double), ("t1_new_length", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("t1_length", ctypes.c_double), ("t1_new_length", ctypes.c_double),
+                ("resort_every", ctypes.c_int32), ("bin_order", ctypes.c_int32)]
 
     def __init__(self, KA=1.0, KP=1.0, mu=1.0, v0=0.0, Dr=1.0, dt=0.01, seed=0, t1_length=0.04,
-                 t1_new_length=0.0):
-        super().__init__(KA, KP, mu, v0, Dr, dt, seed, t1_length, t1_new_length)
+                 t1_new_length=0.0, resort_every=0, bin_order=0):
+        super().__init__(KA, KP, mu, v0, Dr, dt, seed, t1_length, t1_new_length, resort_every, bin_order)
 
 
 class Tuning(ctypes.Structure):
@@ -469,7 +470,7 @@ def spv_avm_get_cells(h, Nc, Nv):
 
 def spv_avm_get_observables(h):
     E, q = _d(), _d()
-    cnt = np.zeros(4, dtype=np.int64)
+    cnt = np.zeros(6, dtype=np.int64)
     _check(_lib.spv_avm_get_observables(h, ctypes.byref(E), ctypes.byref(q), _ptr(cnt)), "spv_avm_get_observables")
     return E.value, q.value, cnt
 

@@ -105,6 +105,7 @@ def test_steps_match_oracle(spv, n, p0, v0):
     a.step(55)
     E, qbar, cnt = a.observables()
     assert cnt[0] == 60 and cnt[1] > 0, cnt  # transitions happened
+    assert cnt[4] > 0 and cnt[5] >= 1, cnt   # captured batches replayed; sorted at creation
     gx, gy = a.vertices()
     goff, gcv = a.cells()
     gth = a.directors()
@@ -163,3 +164,34 @@ def test_invalid_networks_rejected(spv):
     with pytest.raises(spv.SPVError) as ei:
         spv.AVM(vx[:-2], vy[:-2], off, cv, Lx, Ly)
     assert ei.value.status == spv.SPV_EINVAL
+
+
+@pytest.mark.parametrize("resort_every,bin_order", [(16, 0), (8, 1), (1, 0)])
+def test_memory_order_is_invisible(spv, resort_every, bin_order):
+    """Re-sorting vertices and cells (any interval, Hilbert or row-major
+    bins) changes no result: positions, directors and topology after 120
+    steps with transitions are bitwise those of a run that keeps the
+    caller's order; the network comes in randomly relabelled, so that the
+    memory order after the first sort differs from the labels."""
+    vx, vy, off, cv, Lx, Ly, q, _ = _network(1200, 310)
+    rng = np.random.default_rng(5)
+    nc, nv = len(off) - 1, len(vx)
+    cp, vp = rng.permutation(nc), rng.permutation(nv)  # new label of old cell / vertex
+    rows = [cv[off[c]:off[c + 1]] for c in np.argsort(cp)]
+    off2 = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    cv2 = vp[np.concatenate(rows)].astype(np.int32)
+    vx2, vy2 = vx[np.argsort(vp)], vy[np.argsort(vp)]
+    prm = dict(KA=1.0, KP=1.0, mu=1.0, v0=0.3, Dr=1.0, dt=0.01, seed=21, t1_length=0.04, t1_new_length=0.06)
+    out = []
+    for re, bo in ((-1, 0), (resort_every, bin_order)):
+        a = spv.AVM(vx2, vy2, off2, cv2, Lx, Ly, p0=3.95, params=spv.AvmParams(resort_every=re, bin_order=bo, **prm))
+        a.step(120)
+        _, _, cnt = a.observables()
+        out.append((a.vertices(), a.directors(), a.cells(), cnt))
+        a.close()
+    (v1, t1, c1, n1), (v2, t2, c2, n2) = out
+    assert n1[1] > 0 and n1[1] == n2[1] and n1[2] == n2[2], (n1, n2)
+    assert n1[5] == 0 and n2[5] >= 120 // resort_every, (n1, n2)
+    assert np.array_equal(v1[0], v2[0]) and np.array_equal(v1[1], v2[1])
+    assert np.array_equal(t1, t2)
+    assert np.array_equal(c1[0], c2[0]) and np.array_equal(c1[1], c2[1])
