@@ -108,6 +108,9 @@ def parse():
     ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--hybrid-steps", type=int, default=200)
     ap.add_argument("--ablation-steps", type=int, default=1000)
+    ap.add_argument("--avm-steps", type=int, default=2000)
+    ap.add_argument("--avm-cpu-steps", type=int, default=20)
+    ap.add_argument("--avm-only", action="store_true", help="run only the active vertex model runs (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -344,6 +347,79 @@ def adjoint_cost(spv, inputs):
             "traj_backward_ms": (t2 - t1) * 1e3, "adjoint_over_forward": (t2 - t0) / t_plain}
 
 
+# Active vertex model, algorithmic bytes per cell-step (two vertices per
+# cell): geometry 113 (degree, the first eight list entries, two vertex
+# positions, A0 and P0 in; A, P, a, b out), force and move 136 (per vertex
+# position, neighbour and cell rows, a third of three cells' a, b, theta,
+# the new position out), first T1 marking pass with the director rotation
+# 80, the other passes about 8 (flag bytes).
+AVM_STEP_B = 337
+
+
+def avm_runs(spv, inputs, steps):
+    """The active vertex model from the Voronoi network of uniform-random
+    points: cell-steps/s with the memory order kept along a Hilbert curve
+    (every 1000 or 100 steps), by rows of bins, or never sorted (the
+    caller's order, spatially random)."""
+    import torch
+    out = {}
+    for name in ("avm_n100k", "avm_n1m"):
+        w = inputs.WORKLOADS[name]
+        n, L = w["N"], w["L"]
+        nsteps = steps if name == "avm_n100k" else max(steps // 5, 100)
+        x, y = inputs.uniform_positions(n, L, L, w["seed"])
+        s = spv.System(x, y, L, L)
+        vx, vy, off, cv = spv.spv_voronoi_network(s.h, s.N)
+        s.close()
+        res = {}
+        for label, re, bo in (("hilbert_every_1000", 0, 0), ("row_major_every_1000", 0, 1),
+                              ("hilbert_every_100", 100, 0), ("never_sorted", -1, 0)):
+            prm = spv.AvmParams(mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"],
+                                t1_length=w["t1"], t1_new_length=w["t1_new"], resort_every=re, bin_order=bo)
+            a = spv.AVM(vx, vy, off, cv, L, L, p0=w["p0"], params=prm)
+            a.step(104)  # past the first T1 burst of a Voronoi start
+            torch.cuda.synchronize()
+            c0 = a.observables()[2]
+            t0 = time.perf_counter()
+            a.step(nsteps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c1 = a.observables()[2]
+            a.close()
+            d = c1 - c0
+            v = n * nsteps / dt
+            res[label] = {"value": v, "unit": "cell-steps/s", "ms_per_step": dt / nsteps * 1e3, "steps": nsteps,
+                          "t1_per_step": float(d[1]) / nsteps, "t1_rounds_per_step": float(d[2]) / nsteps,
+                          "host_rounds": int(d[3]), "graph_batches": int(d[4]), "resorts": int(d[5]),
+                          "roofline_step": {"bytes_per_cell_step": AVM_STEP_B, "achieved": AVM_STEP_B * v / 1e9,
+                                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                            "frac": AVM_STEP_B * v / 1e9 / HBM_PEAK_GBS}}
+            print(f"[bench] {name} {label}: {v:.3e} cell-steps/s", file=sys.stderr, flush=True)
+        res["hilbert_over_never"] = res["hilbert_every_1000"]["value"] / res["never_sorted"]["value"]
+        out[name] = res
+    return out
+
+
+def avm_cpu_baseline(inputs, nsteps):
+    """The oracle's active vertex model on the host (one thread): nsteps
+    steps of the avm_n100k workload from its Voronoi network, a bounded
+    sample that includes the first burst of T1 transitions (which the device
+    figures skip)."""
+    import oracle
+    w = inputs.WORKLOADS["avm_n100k"]
+    n, L = w["N"], w["L"]
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    xq, yq, Lx, Ly, q = oracle.prepare(x, y, L, L)
+    vx, vy, off, cv = oracle.voronoi_network(xq, yq, Lx, Ly, q)
+    th = oracle.theta0(w["seed"], n)
+    t0 = time.perf_counter()
+    oracle.avm_run(vx, vy, th, Lx, Ly, q, off, cv, 1.0, w["p0"], KA=1.0, KP=1.0, mu=w["mu"], v0=w["v0"], Dr=w["Dr"],
+                   dt=w["dt"], seed=w["seed"], l_t1=w["t1"], l_new=w["t1_new"], nsteps=nsteps)
+    dt = time.perf_counter() - t0
+    return {"value": n * nsteps / dt, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"avm_n100k, {nsteps} steps from the Voronoi network (includes the first T1 burst)"}
+
+
 def main():
     global AUTOTUNE
     args = parse()
@@ -364,6 +440,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.avm_only:
+        print(json.dumps({"avm": avm_runs(spv, inputs, args.avm_steps)}))
+        return
     w = inputs.WORKLOADS[args.workload]
     # timed region 1: throughput (no events) -> value
     head = timed_run(spv, single(spv, inputs, args.workload, spv.SPV_FP64), args.steps, args.warmup, timing=False)
@@ -433,6 +512,9 @@ def main():
         extra["mixed_vs_fp64_speedup_n100k"] = extra["spv_n100k_mixed"]["value"] / head["value"]
         extra["adjoint_n4096"] = adjoint_cost(spv, inputs)
         extra.update(sweeps(spv, inputs, args.sweep_steps, args.warmup, args.hybrid_steps, args.ablation_steps))
+        extra["avm"] = avm_runs(spv, inputs, args.avm_steps)
+        if not args.no_cpu_baseline:
+            extra["avm"]["cpu_baseline"] = avm_cpu_baseline(inputs, args.avm_cpu_steps)
         print(f"[bench] adjoint/forward: {extra['adjoint_n4096']['adjoint_over_forward']:.2f}", file=sys.stderr,
               flush=True)
         out["extra"] = extra

@@ -25,6 +25,13 @@ WORKLOADS = {
                               ckpt=20, seed=BASE_SEED + 4),
     "spv_n1m": dict(N=1_000_000, L=1000.0, p0=3.85, v0=0.1, Dr=1.0, mu=1.0, dt=0.01, steps=2000,
                     seed=BASE_SEED + 5),
+    # active vertex model: the Voronoi network of N uniform-random points
+    # (2N vertices), T1 threshold 0.04 and new edge 0.06 (in units of the
+    # mean cell side sqrt(A0) = 1)
+    "avm_n100k": dict(N=100_000, L=math.sqrt(100_000), p0=3.8, v0=0.1, Dr=1.0, mu=1.0, dt=0.01, t1=0.04,
+                      t1_new=0.06, steps=2000, seed=BASE_SEED + 6),
+    "avm_n1m": dict(N=1_000_000, L=1000.0, p0=3.8, v0=0.1, Dr=1.0, mu=1.0, dt=0.01, t1=0.04, t1_new=0.06,
+                    steps=400, seed=BASE_SEED + 7),
 }
 
 
