@@ -93,9 +93,9 @@ __global__ __launch_bounds__(256) void k_tangent_geom(Cells<double> c, const dou
         for (int m = l; m < k; m += GL) {
             // u_m = cc(d_m, d_{m+1}), u_{m+1} = cc(d_{m+1}, d_{m+2})
             Dual bx, by, cx, cy, ex, ey;
-            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + m], bx, by);
-            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + (m + 1) % k], cx, cy);
-            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + (m + 2) % k], ex, ey);
+            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[rslot<KC>(c.rhi, ii, m)], bx, by);
+            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[rslot<KC>(c.rhi, ii, (m + 1) % k)], cx, cy);
+            dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[rslot<KC>(c.rhi, ii, (m + 2) % k)], ex, ey);
             Dual ux, uy, vx, vy;
             dual_cc(bx, by, cx, cy, ux, uy);
             dual_cc(cx, cy, ex, ey, vx, vy);
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(256) void k_tangent_force(Cells<double> c, const do
     };
     auto vertex = [&](int m, Dual& hx, Dual& hy) {  // h_m in the frame of i
         Dual bx, by, cx, cy;
-        dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + m], bx, by);
-        dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[ii * KC + (m + 1) % k], cx, cy);
+        dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[rslot<KC>(c.rhi, ii, m)], bx, by);
+        dual_disp(c.x, c.y, lx, ly, P, ii, c.ring[rslot<KC>(c.rhi, ii, (m + 1) % k)], cx, cy);
         dual_cc(bx, by, cx, cy, hx, hy);
     };
     double fxd = 0.0, fyd = 0.0;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void k_tangent_force(Cells<double> c, const do
         coef(ii, ai, bi);
         for (int m = l; m < k; m += GL) {
             const int mn = (m + 1) % k, mp = (m + k - 1) % k;
-            const int jm = c.ring[ii * KC + m], jn = c.ring[ii * KC + mn];
+            const int jm = c.ring[rslot<KC>(c.rhi, ii, m)], jn = c.ring[rslot<KC>(c.rhi, ii, mn)];
             Dual Bx, By, Cx, Cy;
             dual_disp(c.x, c.y, lx, ly, P, ii, jm, Bx, By);
             dual_disp(c.x, c.y, lx, ly, P, ii, jn, Cx, Cy);
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_tangent_force(Cells<double> c, const do
             dual_cc(Bx, By, Cx, Cy, hcx, hcy);
             vertex(mn, hnx, hny);
             Dual qx = hcx, qy = hcy;
-            const int o = c.opp[ii * KC + m];
+            const int o = c.opp[rslot<KC>(c.rhi, ii, m)];
             if (o >= 0) {
                 Dual ox, oy;
                 dual_disp(c.x, c.y, lx, ly, P, ii, o, ox, oy);

@@ -297,6 +297,7 @@ Cells<R> cells(const spv_sys* s, int cfg, int parity)
     c.deg = P.deg;
     c.ring = P.ring;
     c.opp = P.opp;
+    c.rhi = RLO * s->N;
     c.A = static_cast<R*>(P.A);
     c.P = static_cast<R*>(P.P);
     c.ca = static_cast<R*>(P.ca);
@@ -734,7 +735,7 @@ spv_status hybrid_round(spv_sys* s, int r, bool first)
     const int* wl = s->work.wl[r & 1];
     HIP_TRY(hipMemcpyAsync(s->h_list, wl, (size_t)n * sizeof(int), hipMemcpyDeviceToHost, st));
     launch(tev(s, T_HOST), k_pack_rows<KC>, dim3(grid_for(n, 256)), dim3(256), st, wl, n, (const uint8_t*)c.deg,
-           (const int*)c.ring, s->d_rows);
+           (const int*)c.ring, c.rhi, s->d_rows);
     HIP_TRY(hipMemcpyAsync(s->h_rows, s->d_rows, (size_t)n * (KC + 1) * sizeof(int), hipMemcpyDeviceToHost, st));
     if (first) {
         HIP_TRY(hipMemcpyAsync(s->h_x, c.x, (size_t)N * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -776,7 +777,7 @@ spv_status hybrid_round(spv_sys* s, int r, bool first)
     for (int q = 0; q < nt; q++) s->h_mark[s->h_touch[q]] = 0;
     HIP_TRY(hipMemcpyAsync(s->d_new, s->h_new, (size_t)n * (KC + 2) * sizeof(int), hipMemcpyHostToDevice, st));
     launch(tev(s, T_HOST), k_unpack_rows<KC>, dim3(grid_for(n, 256)), dim3(256), st, (const int*)s->d_new, n, c.deg,
-           c.ring, s->work.flagbits);
+           c.ring, c.rhi, s->work.flagbits);
     HIP_TRY(hipMemcpyAsync(s->work.tl[r & 1], s->h_touch, (size_t)nt * sizeof(int), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(reinterpret_cast<char*>(s->d_st) + offsetof(DevState, tl_count) + r * sizeof(int), &nt,
                            sizeof(int), hipMemcpyHostToDevice, st));
@@ -2134,7 +2135,7 @@ spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t
     if (!nbr || cap < tot) return fail(SPV_ECAPACITY, "nbr buffer too small");
     for (int t = 0; t < N; t++) {
         const int i = slot_of[t];
-        for (int m = 0; m < deg[i]; m++) nbr[offsets[t] + m] = gid[ring[(size_t)i * K + m]];
+        for (int m = 0; m < deg[i]; m++) nbr[offsets[t] + m] = gid[ring[rslot_host(RLO * N, K, i, m)]];
     }
     return SPV_OK;
 }

@@ -74,13 +74,31 @@ struct Cells {
     double* A0;
     double* P0;
     uint8_t* deg;
-    int* ring;   // [N][kcap], counter-clockwise, starting at the smallest tag
-    int* opp;    // [N][kcap], third vertex across edge (ring[m], ring[m+1])
+    int* ring;   // kcap slots per cell (split rows, rslot), counter-clockwise, starting at the smallest tag
+    int* opp;    // the same layout: third vertex across edge (ring[m], ring[m+1])
+    int rhi;     // first index of the rows' second parts (RLO x cells of the array set)
     R* A;
     R* P;
     R* ca;       // 2 K_A (A - A0)
     R* cb;       // 2 K_P (P - P0)
 };
+
+// Ring and opposite-vertex rows are stored in two parts, so that a cell with
+// at most RLO neighbours (nearly all of them) is read as one 32-byte row:
+// slot m < RLO of cell i at [i RLO + m], slot m >= RLO at
+// [rhi + i (kcap - RLO) + m - RLO], rhi = RLO x the cells of the array set.
+constexpr int RLO = 8;
+
+template <int KC>
+__host__ __device__ __forceinline__ int rslot(int rhi, int i, int m)
+{
+    return m < RLO ? i * RLO + m : rhi + i * (KC - RLO) + (m - RLO);
+}
+
+__host__ __forceinline__ size_t rslot_host(int rhi, int kc, int i, int m)
+{
+    return m < RLO ? (size_t)i * RLO + m : (size_t)rhi + (size_t)i * (kc - RLO) + (m - RLO);
+}
 
 // Work lists and bitmaps shared by both configurations.
 struct Work {

@@ -419,7 +419,8 @@ __global__ __launch_bounds__(256) void k_force_cells(Cells<R> c, double* __restr
         bxs[s] = bys[s] = cxs[s] = cys[s] = ams[s] = bms[s] = ans[s] = bns[s] = qxs[s] = qys[s] = R(0);
         if (m < k) {
             const int mn = (m + 1 == k) ? 0 : m + 1;
-            const int jm = at(c.ring, ii * KC + m), jn = at(c.ring, ii * KC + mn), o = at(c.opp, ii * KC + m);
+            const int jm = at(c.ring, rslot<KC>(c.rhi, ii, m)), jn = at(c.ring, rslot<KC>(c.rhi, ii, mn)),
+                      o = at(c.opp, rslot<KC>(c.rhi, ii, m));
             const double dmx = mimg_near(at(c.x, jm) - xi, P.Lx, P.iLx), dmy = mimg_near(at(c.y, jm) - yi, P.Ly, P.iLy);
             const double dnx = mimg_near(at(c.x, jn) - xi, P.Lx, P.iLx), dny = mimg_near(at(c.y, jn) - yi, P.Ly, P.iLy);
             ams[s] = at(ca, jm);
@@ -539,10 +540,9 @@ __global__ __launch_bounds__(256) void k_force_items(Cells<R> c, double* __restr
         const int i = base + g;
         const SysParam& P = sp[MULTI ? c.sys[i] : 0];
         const int mp = (m == 0) ? k - 1 : m - 1, mn = (m + 1 == k) ? 0 : m + 1, mnn = (mn + 1 == k) ? 0 : mn + 1;
-        const int rb = i * KC;
-        const int jp = at(c.ring, rb + mp), jm = at(c.ring, rb + m), jn = at(c.ring, rb + mn),
-                  jq = at(c.ring, rb + mnn);
-        const int o = at(c.opp, rb + m);
+        const int jp = at(c.ring, rslot<KC>(c.rhi, i, mp)), jm = at(c.ring, rslot<KC>(c.rhi, i, m)),
+                  jn = at(c.ring, rslot<KC>(c.rhi, i, mn)), jq = at(c.ring, rslot<KC>(c.rhi, i, mnn));
+        const int o = at(c.opp, rslot<KC>(c.rhi, i, m));
         const double xi = at(c.x, i), yi = at(c.y, i);
         const double dpx = mimg_near(at(c.x, jp) - xi, P.Lx, P.iLx), dpy = mimg_near(at(c.y, jp) - yi, P.Ly, P.iLy);
         const double dmx = mimg_near(at(c.x, jm) - xi, P.Lx, P.iLx), dmy = mimg_near(at(c.y, jm) - yi, P.Ly, P.iLy);
@@ -687,7 +687,7 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
     for (int s = 0; s < NS; s++) {
         const int m = l + s * GL;
         if (m < k) {
-            const int j = c.ring[i * KC + m];
+            const int j = c.ring[rslot<KC>(c.rhi, i, m)];
             sJ[g][m] = j;
             sD[g][m][0] = mimg(c.x[j] - xi, P.Lx, P.hLx);
             sD[g][m][1] = mimg(c.y[j] - yi, P.Ly, P.hLy);
@@ -703,19 +703,35 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
             const int jm = sJ[g][m], jn = sJ[g][mn];
             int o;
             if (OPP) {
-                // jm's whole ring row in one go (16-byte loads), searched in
-                // registers for i and the two entries before it
+                // jm's ring row in one go (16-byte loads of its first part,
+                // and of its second part only when jm has more than RLO
+                // neighbours), searched in registers for i and the two
+                // entries before it
                 o = -1;
                 const int kj = min((int)c.deg[jm], KC);
                 int row[KC];
-                const int4* __restrict__ rv = reinterpret_cast<const int4*>(c.ring + (size_t)jm * KC);
+                const int4* __restrict__ rv = reinterpret_cast<const int4*>(c.ring + (size_t)jm * RLO);
 #pragma unroll
-                for (int v = 0; v < KC / 4; v++) {
+                for (int v = 0; v < RLO / 4; v++) {
                     const int4 t4 = rv[v];
                     row[4 * v] = t4.x;
                     row[4 * v + 1] = t4.y;
                     row[4 * v + 2] = t4.z;
                     row[4 * v + 3] = t4.w;
+                }
+#pragma unroll
+                for (int q = RLO; q < KC; q++) row[q] = -1;
+                if (kj > RLO) {
+                    const int4* __restrict__ hv =
+                        reinterpret_cast<const int4*>(c.ring + c.rhi + (size_t)jm * (KC - RLO));
+#pragma unroll
+                    for (int v = 0; v < (KC - RLO) / 4; v++) {
+                        const int4 t4 = hv[v];
+                        row[RLO + 4 * v] = t4.x;
+                        row[RLO + 4 * v + 1] = t4.y;
+                        row[RLO + 4 * v + 2] = t4.z;
+                        row[RLO + 4 * v + 3] = t4.w;
+                    }
                 }
                 int p = -1;
 #pragma unroll
@@ -732,9 +748,9 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
                     }
                     if (v1 == jn) o = v2;
                 }
-                c.opp[i * KC + m] = o;
+                c.opp[rslot<KC>(c.rhi, i, m)] = o;
             } else {
-                o = c.opp[i * KC + m];
+                o = c.opp[rslot<KC>(c.rhi, i, m)];
             }
             const double bx = sD[g][m][0], by = sD[g][m][1], cx = sD[g][mn][0], cy = sD[g][mn][1];
             bool fail;
@@ -873,9 +889,9 @@ __global__ __launch_bounds__(256) void k_geom_items(Cells<R> c, Work w, const Sy
         const int i = base + g;
         const SysParam& P = sp[MULTI ? c.sys[i] : 0];
         const int mn = (m + 1 == k) ? 0 : m + 1, mnn = (mn + 1 == k) ? 0 : mn + 1;
-        const int rb = i * KC;
-        const int jm = at(c.ring, rb + m), jn = at(c.ring, rb + mn), jq = at(c.ring, rb + mnn);
-        const int o = at(c.opp, rb + m);
+        const int jm = at(c.ring, rslot<KC>(c.rhi, i, m)), jn = at(c.ring, rslot<KC>(c.rhi, i, mn)),
+                  jq = at(c.ring, rslot<KC>(c.rhi, i, mnn));
+        const int o = at(c.opp, rslot<KC>(c.rhi, i, m));
         const double xi = at(c.x, i), yi = at(c.y, i);
         const double bx = mimg(at(c.x, jm) - xi, P.Lx, P.hLx), by = mimg(at(c.y, jm) - yi, P.Ly, P.hLy);
         const double cx = mimg(at(c.x, jn) - xi, P.Lx, P.hLx), cy = mimg(at(c.y, jn) - yi, P.Ly, P.hLy);
@@ -1119,7 +1135,7 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
     const double xi = c.x[i], yi = c.y[i];
     const int kold = min((int)c.deg[i], KC);
     // the old ring row (touched at the end), read while the search runs
-    const int qrow = lane < KC ? c.ring[i * KC + lane] : -1;
+    const int qrow = lane < KC ? c.ring[rslot<KC>(c.rhi, i, lane)] : -1;
     const double Rmax = 0.5 * fmin(P.Lx, P.Ly) * (1.0 - 1e-9);
     // first radius R0 (2.5 mean spacings: a Delaunay star rarely reaches
     // further than half of it); doubled while the star is not certified
@@ -1388,7 +1404,7 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
         if (kold >= 32 && k >= 32) push_touch(w, st, round, lane == 0 ? i : -1);
     }
     wave_sync();
-    if (qnew >= 0) c.ring[i * KC + (lane - 32)] = qnew;
+    if (qnew >= 0) c.ring[rslot<KC>(c.rhi, i, lane - 32)] = qnew;
     if (lane == 0) c.deg[i] = (uint8_t)k;
     wave_sync();
     return true;
@@ -1917,9 +1933,9 @@ __global__ void k_gather(Cells<R> src, Cells<R> dst, const int* perm, const int*
     const int k = min((int)src.deg[i], KC);
     dst.deg[p] = (uint8_t)k;
     for (int m = 0; m < k; m++) {
-        dst.ring[p * KC + m] = inv[src.ring[i * KC + m]];
-        const int o = src.opp[i * KC + m];
-        dst.opp[p * KC + m] = o >= 0 ? inv[o] : -1;
+        dst.ring[rslot<KC>(dst.rhi, p, m)] = inv[src.ring[rslot<KC>(src.rhi, i, m)]];
+        const int o = src.opp[rslot<KC>(src.rhi, i, m)];
+        dst.opp[rslot<KC>(dst.rhi, p, m)] = o >= 0 ? inv[o] : -1;
     }
 }
 
@@ -1956,7 +1972,7 @@ __global__ void k_cur_place(const int* __restrict__ cbin, const int* __restrict_
 // cells, for the host repair.
 template <int KC>
 __global__ void k_pack_rows(const int* __restrict__ list, int n, const uint8_t* __restrict__ deg,
-                            const int* __restrict__ ring, int* __restrict__ out)
+                            const int* __restrict__ ring, int rhi, int* __restrict__ out)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
@@ -1964,21 +1980,21 @@ __global__ void k_pack_rows(const int* __restrict__ list, int n, const uint8_t* 
     const int k = min((int)deg[i], KC);
     int* o = out + (size_t)t * (KC + 1);
     o[0] = k;
-    for (int m = 0; m < KC; m++) o[1 + m] = m < k ? ring[i * KC + m] : -1;
+    for (int m = 0; m < KC; m++) o[1 + m] = m < k ? ring[rslot<KC>(rhi, i, m)] : -1;
 }
 
 // The host's new rows (cell, length, kc entries) into the ring arrays; the
 // cells leave the pending worklist (their flag bits cleared).
 template <int KC>
 __global__ void k_unpack_rows(const int* __restrict__ in, int n, uint8_t* __restrict__ deg, int* __restrict__ ring,
-                              unsigned* flagbits)
+                              int rhi, unsigned* flagbits)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int* r = in + (size_t)t * (KC + 2);
     const int i = r[0], k = r[1];
     deg[i] = (uint8_t)k;
-    for (int m = 0; m < k; m++) ring[i * KC + m] = r[2 + m];
+    for (int m = 0; m < k; m++) ring[rslot<KC>(rhi, i, m)] = r[2 + m];
     atomicAnd(&flagbits[i >> 5], ~(1u << (i & 31)));
 }
 
