@@ -1166,24 +1166,56 @@ __device__ bool repair_one(const Cells<R>& c, const Work& w, const SysParam* __r
         }
         const double R2 = Rs * Rs * (1.0 + 1e-12);
         const int lo = P.cell_off, hi = P.cell_off + P.n;
-        for (int b = lane; b < wx * wy; b += 64) {
-            int bx = bx0 + b % wx, by = by0 + b / wx;
-            bx = ((bx % P.nbx) + P.nbx) % P.nbx;
-            by = ((by % P.nby) + P.nby) % P.nby;
-            const int bi = P.bin_off + by * P.nbx + bx;
-            const int2 br = cur ? make_int2(w.cur_start[bi], w.cur_start[bi + 1]) : w.bin_range[bi];
-            const int c1 = min(br.y, hi);
-            for (int e = max(br.x, lo); e < c1; e++) {
-                const int q = cur ? w.cur_cells[e] : e;
-                if (q == i) continue;
-                const double dx = mimg(c.x[q] - xi, P.Lx, P.hLx), dy = mimg(c.y[q] - yi, P.Ly, P.hLy);
-                if (dx * dx + dy * dy <= R2) {
-                    const int slot = atomicAdd(L.s_n, 1);
-                    if (slot < L.cap) {
-                        sx[slot] = dx;
-                        sy[slot] = dy;
-                        sid[slot] = q;
-                        stg[slot] = c.tag[q];
+        // the window's bins 64 at a time: each lane reads one bin's range,
+        // a prefix sum over the wave numbers the cells of the group, and the
+        // lanes then take one cell each (the owning bin found by a binary
+        // search over the lanes' offsets): three dependent loads per cell
+        // instead of a walk through each bin
+        const int nbins = wx * wy;
+        for (int b0 = 0; b0 < nbins; b0 += 64) {
+            const int b = b0 + lane;
+            int s0 = 0, cnt = 0;
+            if (b < nbins) {
+                int bx = bx0 + b % wx, by = by0 + b / wx;
+                bx = ((bx % P.nbx) + P.nbx) % P.nbx;
+                by = ((by % P.nby) + P.nby) % P.nby;
+                const int bi = P.bin_off + by * P.nbx + bx;
+                const int2 br = cur ? make_int2(w.cur_start[bi], w.cur_start[bi + 1]) : w.bin_range[bi];
+                s0 = max(br.x, lo);
+                cnt = max(min(br.y, hi) - s0, 0);
+            }
+            int inc = cnt;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(inc, off);
+                if (lane >= off) inc += v;
+            }
+            const int exc = inc - cnt;
+            const int tot = __shfl(inc, 63);
+            for (int base = 0; base < tot; base += 64) {
+                const int idx = base + lane;
+                // the last lane whose offset is <= idx owns cell idx
+                int own = 0;
+#pragma unroll
+                for (int step = 32; step >= 1; step >>= 1) {
+                    const int cl = min(own + step, 63);
+                    if (__shfl(exc, cl) <= idx) own = cl;
+                }
+                const int so = __shfl(s0, own), eo = __shfl(exc, own);
+                if (idx < tot) {
+                    const int e = so + (idx - eo);
+                    const int q = cur ? w.cur_cells[e] : e;
+                    if (q != i) {
+                        const double dx = mimg(c.x[q] - xi, P.Lx, P.hLx), dy = mimg(c.y[q] - yi, P.Ly, P.hLy);
+                        if (dx * dx + dy * dy <= R2) {
+                            const int slot = atomicAdd(L.s_n, 1);
+                            if (slot < L.cap) {
+                                sx[slot] = dx;
+                                sy[slot] = dy;
+                                sid[slot] = q;
+                                stg[slot] = c.tag[q];
+                            }
+                        }
                     }
                 }
             }
