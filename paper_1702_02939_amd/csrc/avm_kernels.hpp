@@ -322,6 +322,57 @@ __device__ __forceinline__ bool cell_insert_before(int* l, uint8_t* deg, int v, 
     return true;
 }
 
+// The same two edits on a list held in registers (all indices constant after
+// unrolling): loaded and stored as four 16-byte words, so that a flip's four
+// cell lists cost one round trip instead of a dependent walk each.
+__device__ __forceinline__ void row_load(const int* p, int (&r)[AVM_KV])
+{
+    const int4* q = reinterpret_cast<const int4*>(p);
+#pragma unroll
+    for (int v = 0; v < AVM_KV / 4; v++) {
+        const int4 w = q[v];
+        r[4 * v] = w.x;
+        r[4 * v + 1] = w.y;
+        r[4 * v + 2] = w.z;
+        r[4 * v + 3] = w.w;
+    }
+}
+
+__device__ __forceinline__ void row_store(int* p, const int (&r)[AVM_KV])
+{
+    int4* q = reinterpret_cast<int4*>(p);
+#pragma unroll
+    for (int v = 0; v < AVM_KV / 4; v++) q[v] = make_int4(r[4 * v], r[4 * v + 1], r[4 * v + 2], r[4 * v + 3]);
+}
+
+// remove the one entry w among the first k; returns the new length
+__device__ __forceinline__ int row_remove(int (&r)[AVM_KV], int k, int w)
+{
+    int pos = AVM_KV;
+#pragma unroll
+    for (int i = AVM_KV - 1; i >= 0; i--)
+        if (i < k && r[i] == w) pos = i;
+#pragma unroll
+    for (int i = 0; i + 1 < AVM_KV; i++)
+        if (i >= pos) r[i] = r[i + 1];
+    return pos < k ? k - 1 : k;
+}
+
+// insert w just before v (at the end when v is absent); k < AVM_KV
+__device__ __forceinline__ void row_insert_before(int (&r)[AVM_KV], int k, int v, int w)
+{
+    int pos = k;
+#pragma unroll
+    for (int i = AVM_KV - 1; i >= 0; i--)
+        if (i < k && r[i] == v) pos = i;
+#pragma unroll
+    for (int i = AVM_KV - 1; i > 0; i--)
+        if (i > pos) r[i] = r[i - 1];
+#pragma unroll
+    for (int i = 0; i < AVM_KV; i++)
+        if (i == pos) r[i] = w;
+}
+
 // T1 round r, second pass for vertex v: an edge whose key holds all four of
 // its cells flips (such edges share no cell and no vertex)
 __device__ __forceinline__ void avm_apply_vertex(const AvmArrays& a, const AvmParam& P, AvmState* st, int r, int v,
@@ -369,11 +420,36 @@ __device__ __forceinline__ void avm_apply_vertex(const AvmArrays& a, const AvmPa
             if (a.vv[3 * bn + j] == v) a.vv[3 * bn + j] = u;
             if (a.vv[3 * dn + j] == u) a.vv[3 * dn + j] = v;
         }
-        cell_remove(a.cv + (size_t)X * AVM_KV, a.cdeg + X, u);
-        cell_remove(a.cv + (size_t)Y * AVM_KV, a.cdeg + Y, v);
-        const bool ok1 = cell_insert_before(a.cv + (size_t)C1 * AVM_KV, a.cdeg + C1, v, u);
-        const bool ok2 = cell_insert_before(a.cv + (size_t)D1 * AVM_KV, a.cdeg + D1, u, v);
-        if (!ok1 || !ok2) atomicOr(&st->err, ERR_CAPACITY);
+        if (X != Y && X != C1 && X != D1 && Y != C1 && Y != D1) {
+            // four distinct lists (always, unless a cell meets itself):
+            // all loaded together, edited in registers, stored
+            int lX[AVM_KV], lY[AVM_KV], lC[AVM_KV], lD[AVM_KV];
+            row_load(a.cv + (size_t)X * AVM_KV, lX);
+            row_load(a.cv + (size_t)Y * AVM_KV, lY);
+            row_load(a.cv + (size_t)C1 * AVM_KV, lC);
+            row_load(a.cv + (size_t)D1 * AVM_KV, lD);
+            const int kX = a.cdeg[X], kY = a.cdeg[Y], kC = a.cdeg[C1], kD = a.cdeg[D1];
+            a.cdeg[X] = (uint8_t)row_remove(lX, kX, u);
+            a.cdeg[Y] = (uint8_t)row_remove(lY, kY, v);
+            row_store(a.cv + (size_t)X * AVM_KV, lX);
+            row_store(a.cv + (size_t)Y * AVM_KV, lY);
+            if (kC < AVM_KV && kD < AVM_KV) {
+                row_insert_before(lC, kC, v, u);
+                row_insert_before(lD, kD, u, v);
+                a.cdeg[C1] = (uint8_t)(kC + 1);
+                a.cdeg[D1] = (uint8_t)(kD + 1);
+                row_store(a.cv + (size_t)C1 * AVM_KV, lC);
+                row_store(a.cv + (size_t)D1 * AVM_KV, lD);
+            } else {
+                atomicOr(&st->err, ERR_CAPACITY);
+            }
+        } else {
+            cell_remove(a.cv + (size_t)X * AVM_KV, a.cdeg + X, u);
+            cell_remove(a.cv + (size_t)Y * AVM_KV, a.cdeg + Y, v);
+            const bool ok1 = cell_insert_before(a.cv + (size_t)C1 * AVM_KV, a.cdeg + C1, v, u);
+            const bool ok2 = cell_insert_before(a.cv + (size_t)D1 * AVM_KV, a.cdeg + D1, u, v);
+            if (!ok1 || !ok2) atomicOr(&st->err, ERR_CAPACITY);
+        }
         // every edge at the moved vertices changed: examine them next round
         const uint8_t nr = (uint8_t)(r + 1);
         a.dirty[v] = a.dirty[u] = a.dirty[an] = a.dirty[bn] = a.dirty[cn] = a.dirty[dn] = nr;
