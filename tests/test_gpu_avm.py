@@ -195,3 +195,25 @@ def test_memory_order_is_invisible(spv, resort_every, bin_order):
     assert np.array_equal(v1[0], v2[0]) and np.array_equal(v1[1], v2[1])
     assert np.array_equal(t1, t2)
     assert np.array_equal(c1[0], c2[0]) and np.array_equal(c1[1], c2[1])
+
+
+def test_error_paths(spv):
+    """Bad parameters are refused at creation; an update that overflows is
+    SPV_ENONFINITE and stays the handle's answer (its stored vertices are
+    the last finite ones)."""
+    vx, vy, off, cv, Lx, Ly, q, _ = _network(300, 306)
+    for bad in (dict(resort_every=-2), dict(bin_order=2), dict(t1_length=0.0), dict(t1_length=0.1, t1_new_length=0.05),
+                dict(dt=0.0)):
+        with pytest.raises(spv.SPVError) as ei:
+            spv.AVM(vx, vy, off, cv, Lx, Ly, params=spv.AvmParams(**bad))
+        assert ei.value.status == spv.SPV_EINVAL, bad
+    a = spv.AVM(vx, vy, off, cv, Lx, Ly, params=spv.AvmParams(v0=1.0, dt=1e300))
+    with pytest.raises(spv.SPVError) as ei:
+        a.step(1)
+    assert ei.value.status == spv.SPV_ENONFINITE
+    with pytest.raises(spv.SPVError) as ei:
+        a.step(1)
+    assert ei.value.status == spv.SPV_ENONFINITE
+    gx, gy = a.vertices()
+    assert np.isfinite(gx).all() and np.isfinite(gy).all()
+    a.close()
