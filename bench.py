@@ -73,12 +73,12 @@ def class_bytes(cls, r):
 # source they were taken on (digest of the device headers): any later change
 # of the kernels nulls roofline.traffic.
 MEASURED_TRAFFIC = {
-    ("spv_n100k", "repair", 1): {"bytes_per_launch": 11.455e6, "source_sha256":
-                                 "ba400b9d2e57b5c8aa9b813d1562072e563fbbb28ca6a47795ad8fe2d2d33095"},
-    ("spv_n100k", "force_update", 1): {"bytes_per_launch": 14.653e6, "source_sha256":
-                                       "ba400b9d2e57b5c8aa9b813d1562072e563fbbb28ca6a47795ad8fe2d2d33095"},
+    ("spv_n100k", "repair", 1): {"bytes_per_launch": 17.201e6, "source_sha256":
+                                 "b9fa107333225a0ff1115900c3f768b6ddaba9946ab2a22390bebb00a7ca6d87"},
+    ("spv_n100k", "force_update", 1): {"bytes_per_launch": 14.650e6, "source_sha256":
+                                       "b9fa107333225a0ff1115900c3f768b6ddaba9946ab2a22390bebb00a7ca6d87"},
     ("spv_n100k", "geometry_test", 1): {"bytes_per_launch": 13.811e6, "source_sha256":
-                                        "ba400b9d2e57b5c8aa9b813d1562072e563fbbb28ca6a47795ad8fe2d2d33095"},
+                                        "b9fa107333225a0ff1115900c3f768b6ddaba9946ab2a22390bebb00a7ca6d87"},
 }
 
 

@@ -15,7 +15,7 @@ enum : unsigned {
 };
 
 constexpr int MAX_ROUNDS = 32;  // repair rounds per step (device rounds + host recovery rounds)
-constexpr int DENSE_ROUNDS = 3; // rounds of a dense step (flag bytes scanned by the whole grid)
+constexpr int DENSE_ROUNDS = 2; // rounds of a dense step (flag bytes scanned by the whole grid)
 
 // Per-system constants (a batch holds several independent systems laid out
 // one after the other; a single system is a batch of one).
