@@ -225,8 +225,12 @@ def roofline(r, workload, mode):
     traffic = None
     if mt and mt["source_sha256"] == source_digest():
         traffic = mt["bytes_per_launch"]
+    # the counter-measured bytes over the same live launch time (wasted
+    # re-reads included), beside the algorithmic figure
+    measured = traffic / (e["avg_launch_us"] * 1e-6) / 1e9 if traffic else None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS if achieved is not None else None, "traffic": traffic,
+            "measured_achieved": measured, "measured_frac": measured / HBM_PEAK_GBS if measured else None,
             "kernel": dom, "avg_launch_us": e["avg_launch_us"], "launches": e["launches"],
             "share_of_kernel_time": e["ms"] / sum(v["ms"] for v in table.values()),
             "bytes_per_launch": e["bytes"] / e["launches"] if "bytes" in e else None}, table
