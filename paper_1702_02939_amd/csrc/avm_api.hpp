@@ -5,12 +5,14 @@
 // A handle owns the vertex positions (two buffers: the move writes the
 // other), the flat topology (vv, vc, cv), the cell directors, targets and
 // geometry, the creation labels of vertices and cells, the T1 locks and a
-// control block.  A step is nine launches: geometry, force + move, three
-// T1 rounds of two passes each (the first marking pass visits every vertex
-// and also rotates the directors; later passes only the vertices the round
-// before flagged), and a last marking pass that halts the later kernels of
-// the batch when a fourth round is needed; the host then runs more rounds
-// (one read-back each) until none qualifies.  Batches of eight steps are
+// control block.  A step is geometry, force + move, one to three T1 rounds
+// of two passes each (the first marking pass visits every vertex and also
+// rotates the directors; later passes only the vertices the round before
+// flagged), and a last marking pass that halts the later kernels of the
+// batch when one more round is needed; the host then runs more rounds (one
+// read-back each) until none qualifies.  The number of device rounds follows
+// the rounds the last batch needed per step: one while flips seldom
+// conflict (five launches a step), up to three when they often do.  Batches of eight steps are
 // captured once as HIP graphs and replayed.  A spatial re-sort (vertices
 // and cells along a Hilbert curve of bins) runs at creation and every
 // resort_every steps; results do not depend on it.
@@ -57,7 +59,8 @@ struct spv_avm {
     int obs_chunks = 1;
     int resort_every = AVM_DEFAULT_RESORT;  // -1: never
     int64_t since_sort = 0;
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (position buffer, array set) -> batch graph
+    int dev_rounds = AVM_DEV_ROUNDS;  // T1 rounds of a step on the device (1 .. AVM_DEV_ROUNDS)
+    std::map<std::array<int, 3>, hipGraphExec_t> graphs;  // (position buffer, array set, rounds) -> batch graph
     std::vector<void*> allocs;
     int64_t host_rounds = 0, graph_batches = 0, resorts = 0;
     spv_status sticky = SPV_OK;
@@ -143,26 +146,28 @@ spv_status avm_error(spv_avm* h)
     return fail(h->sticky, h->sticky_msg);
 }
 
-// one step from position buffer b on stream s
+// one step from position buffer b on stream s (h->dev_rounds rounds)
 void enqueue_avm_step(spv_avm* h, hipStream_t s, int b)
 {
+    const int nr = h->dev_rounds;
     const unsigned gv = avm_grid(h->nv), gc = avm_grid(h->nc), g8 = avm_grid8(h->nv);
     const AvmArrays a = avm_arrays(h, b), n = avm_arrays(h, b ^ 1);
     const AvmParam* p = h->d_p;
     hipLaunchKernelGGL(k_avm_geom, dim3(gc), dim3(256), 0, s, a, p, h->d_st);
     hipLaunchKernelGGL(k_avm_force<true>, dim3(gv), dim3(256), 0, s, a, p, h->d_st);
-    for (int r = 0; r < AVM_DEV_ROUNDS; r++) {
+    for (int r = 0; r < nr; r++) {
         hipLaunchKernelGGL(k_avm_t1_mark, dim3(r == 0 ? gv : g8), dim3(256), 0, s, n, p, h->d_st, r, 0, 0);
         hipLaunchKernelGGL(k_avm_t1_apply, dim3(g8), dim3(256), 0, s, n, p, h->d_st, r, 0);
     }
-    hipLaunchKernelGGL(k_avm_t1_mark, dim3(g8), dim3(256), 0, s, n, p, h->d_st, AVM_DEV_ROUNDS, 0, 1);
+    hipLaunchKernelGGL(k_avm_t1_mark, dim3(g8), dim3(256), 0, s, n, p, h->d_st, nr, 0, 1);
 }
 
 // The graph of a batch of AVM_BATCH steps from position buffer b with the
-// current array set, captured on first use.
+// current array set and round count, captured on first use.
 spv_status avm_batch_graph(spv_avm* h, int b, hipGraphExec_t* out)
 {
-    auto it = h->graphs.find({b, h->set});
+    const std::array<int, 3> key{b, h->set, h->dev_rounds};
+    auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         *out = it->second;
         return SPV_OK;
@@ -179,18 +184,19 @@ spv_status avm_batch_graph(spv_avm* h, int b, hipGraphExec_t* out)
     hipError_t e2 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e2 != hipSuccess) return fail(SPV_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
-    h->graphs[{b, h->set}] = ex;
+    h->graphs[key] = ex;
     *out = ex;
     return SPV_OK;
 }
 
-// more T1 rounds for the halted step (its positions are current; the last
-// marking pass found edges), one read-back each, until one finds none
-spv_status avm_finish_rounds(spv_avm* h)
+// more T1 rounds for the halted step (its positions are current; the
+// marking pass after its `first` device rounds found edges), one read-back
+// each, until one finds none
+spv_status avm_finish_rounds(spv_avm* h, int first)
 {
     const unsigned g8 = avm_grid8(h->nv);
     const AvmArrays a = avm_arrays(h, h->cur);
-    for (int r = AVM_DEV_ROUNDS;; r++) {
+    for (int r = first;; r++) {
         if (r + 1 > AVM_MAX_ROUNDS) {
             h->sticky = SPV_EREPAIR;
             h->sticky_msg = "T1 transitions did not settle within 64 rounds";
@@ -257,8 +263,8 @@ spv_status avm_steps(spv_avm* h, int64_t n)
         if (h->resort_every > 0 && h->since_sort >= h->resort_every) ST_TRY(avm_resort(h));
         int64_t b = std::min<int64_t>(n, AVM_BATCH);
         if (h->resort_every > 0) b = std::min<int64_t>(b, h->resort_every - h->since_sort);
-        const unsigned long long before = h->h_st->step;
-        const int cur0 = h->cur;
+        const unsigned long long before = h->h_st->step, rounds0 = h->h_st->rounds;
+        const int cur0 = h->cur, nr = h->dev_rounds;
         if (b == AVM_BATCH) {
             hipGraphExec_t ex = nullptr;
             ST_TRY(avm_batch_graph(h, cur0, &ex));
@@ -276,7 +282,15 @@ spv_status avm_steps(spv_avm* h, int64_t n)
         h->cur = (int)((cur0 + done) & 1);
         n -= done;
         h->since_sort += done;
-        if (h->h_st->halt) ST_TRY(avm_finish_rounds(h));
+        const bool halted = h->h_st->halt != 0;
+        if (halted) ST_TRY(avm_finish_rounds(h, nr));
+        // rounds with flips per step over this batch (a halted step's host
+        // rounds included; the control block was just read) -> the next
+        // batch's device rounds
+        if (done > 0) {
+            const double rate = (double)(h->h_st->rounds - rounds0) / (double)done;
+            h->dev_rounds = rate <= 1.15 ? 1 : (rate <= 1.6 ? 2 : AVM_DEV_ROUNDS);
+        }
     }
     return SPV_OK;
 }

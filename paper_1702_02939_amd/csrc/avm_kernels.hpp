@@ -38,7 +38,7 @@
 namespace spv {
 
 constexpr int AVM_KV = 16;           // most vertices of a cell
-constexpr int AVM_DEV_ROUNDS = 3;    // T1 rounds per step on the device (then a marking pass that halts if needed)
+constexpr int AVM_DEV_ROUNDS = 3;    // most T1 rounds per step on the device (then a marking pass that halts if needed)
 constexpr int AVM_MAX_ROUNDS = 64;   // T1 rounds per step in all
 
 struct AvmParam {
