@@ -217,3 +217,36 @@ def test_error_paths(spv):
     gx, gy = a.vertices()
     assert np.isfinite(gx).all() and np.isfinite(gy).all()
     a.close()
+
+
+@pytest.mark.parametrize("name", ["avm_n100k", "avm_n1m"])
+def test_benchmark_workloads_one_step_from_device_state(spv, name):
+    """The benchmark's active vertex model workloads in its launch
+    configuration (the Voronoi network of the random points built by the
+    library, Hilbert re-sort, batches replayed from graphs, the adaptive
+    device rounds), 104 steps in as the benchmark times them; then one step
+    from the device's state on both sides: topology exact, vertices within a
+    grid unit, directors within 1e-12, E and q-bar."""
+    w = inputs.WORKLOADS[name]
+    n, L = w["N"], w["L"]
+    x, y = inputs.uniform_positions(n, L, L, w["seed"])
+    s = spv.System(x, y, L, L)
+    Lx, Ly, q = s.box()
+    vx, vy, off, cv = spv.spv_voronoi_network(s.h, s.N)
+    s.close()
+    prm = dict(KA=1.0, KP=1.0, mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"], seed=w["seed"])
+    a = spv.AVM(vx, vy, off, cv, Lx, Ly, p0=w["p0"],
+                params=spv.AvmParams(t1_length=w["t1"], t1_new_length=w["t1_new"], **prm))
+    a.step(104)
+    _, _, cnt = a.observables()
+    assert cnt[0] == 104 and cnt[1] > 0 and cnt[4] > 0 and cnt[5] >= 1, cnt
+    gx, gy = a.vertices()
+    goff, gcv = a.cells()
+    gth = a.directors()
+    ref = oracle.avm_run(gx, gy, gth, Lx, Ly, q, goff, gcv, 1.0, w["p0"], l_t1=w["t1"], l_new=w["t1_new"], step0=104,
+                         nsteps=1, **prm)
+    a.step(1)
+    _compare_state(a, ref, Lx, Ly, q)
+    E, qb, _ = a.observables()
+    assert abs(E - ref["E"][-1]) < 1e-9 * abs(ref["E"][-1]) and abs(qb - ref["qbar"][-1]) < 1e-12 * qb
+    a.close()
