@@ -32,10 +32,11 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 vector
 #                  opp (24), A0,P0 (16); write A,P,a,b (32) = 113
 #   repair         per candidate gathered: its x,y (16) and index (4) = 20;
 #                  per repaired cell: old ring row (64), new ring (24), deg (1) = 89
-#   cell_list      per cell and step: read x,y (16), write bin and slot (8),
-#                  count update (8), read bin, slot, start (12), write the
-#                  entry (4) = 48; per bin: count read and start write, two
-#                  scan passes = 16
+#   cell_list      the scan of the step's bin counts: per bin the count read,
+#                  the start written, the count cleared = 12 (the per-cell
+#                  part -- bin, slot and count update in the force kernel's
+#                  update, the placement in the all-cells pass -- is in those
+#                  kernels' time)
 #   resort         per cell: every per-cell array read and written once
 #                  (x,y,theta 24, tag,sys 8, A0,P0 16, A,P,a,b 32, deg 1,
 #                  ring,opp 48, each way) plus ring and opp renumbering reads
@@ -44,10 +45,10 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X dense FP64 vector
 # but carry no byte model.
 FORCE_B, GEOM_B = 117, 113
 CAND_B, REPAIRED_B = 20, 89
-LIST_CELL_B, LIST_BIN_B = 48, 16
+LIST_CELL_B, LIST_BIN_B = 0, 12
 RESORT_B = 322
 STEP_B = 244  # algorithmic bytes of a whole step per cell (three streaming passes)
-LIST_LAUNCHES, RESORT_LAUNCHES = 4, 9  # launches of one cell list / one re-sort
+LIST_LAUNCHES, RESORT_LAUNCHES = 2, 9  # launches of one cell list (its scan) / one re-sort
 
 
 def class_bytes(cls, r):

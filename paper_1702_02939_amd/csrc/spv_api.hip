@@ -427,30 +427,35 @@ void note_repairs(spv_sys* s, uint64_t rep, uint64_t done)
 }
 
 // the work lists, with this step's cell list for the repairs when cur
-Work work_for(const spv_sys* s, bool cur)
+// place: the step's all-cells pass also places the cells of this step's list
+Work work_for(const spv_sys* s, bool cur, bool place = false)
 {
     Work w = s->work;
     w.cur_start = cur ? s->d_cstart : nullptr;
     w.cur_cells = cur ? s->d_ccells : nullptr;
+    w.cbin = (cur && place) ? s->d_cbin : nullptr;
+    w.cslot = (cur && place) ? s->d_cslot : nullptr;
+    w.cplace = (cur && place) ? s->d_ccells : nullptr;
     return w;
 }
 
-// this step's cell list of the positions in c
-template <typename R, bool MULTI>
-void enqueue_cell_list(spv_sys* s, hipStream_t st, const Cells<R>& c)
+// the counting half of this step's cell list (done by the force kernel's
+// update; the counts are zero here: cleared at creation and by every list's
+// scan)
+CellCount cell_count_for(const spv_sys* s, bool cur)
 {
-    const int N = s->N, nb = s->total_bins;
+    return cur ? CellCount{s->d_cbin, s->d_cslot, s->d_ccount} : CellCount{nullptr, nullptr, nullptr};
+}
+
+// the counts of this step's cell list into bin starts
+void enqueue_cell_scan(spv_sys* s, hipStream_t st)
+{
+    const int nb = s->total_bins;
     const unsigned nchunk = grid_for(nb, SCAN_CHUNK);
-    const DevState* ds = s->d_st;
-    // the counts are zero here: cleared at creation and by every list's scan
-    launch(tev(s, T_LIST), k_cur_bins<R, MULTI>, dim3(grid_for(N, 256)), dim3(256), st, c, (const SysParam*)s->d_sp,
-           ds, N, s->d_cbin, s->d_cslot, s->d_ccount);
     launch(tev(s, T_LIST), k_scan_sums_last, dim3(nchunk), dim3(256), st, (const int*)s->d_ccount, nb, s->d_cchunk,
            s->d_st);
     launch(tev(s, T_LIST), k_scan_apply<true>, dim3(nchunk), dim3(256), st, s->d_ccount, s->d_cstart, nb,
-           (const int*)s->d_cchunk, ds);
-    launch(tev(s, T_LIST), k_cur_place, dim3(grid_for(N, 256)), dim3(256), st, (const int*)s->d_cbin,
-           (const int*)s->d_cslot, (const int*)s->d_cstart, s->d_ccells, N, ds);
+           (const int*)s->d_cchunk, (const DevState*)s->d_st);
 }
 
 // wavefronts of a dense repair round: about one per four cells, at most
@@ -492,29 +497,29 @@ void enqueue_step(spv_sys* s, hipStream_t st, int cfg, int parity, bool hot)
     Cells<R> cur = cells<R>(s, cfg, parity), nxt = cells<R>(s, cfg, parity ^ 1);
     const unsigned cg = cell_grid(s), rg = repair_grid(s);
     const SysParam* sp = s->d_sp;
-    launch(tev(s, T_FORCE), force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
-           nxt.y, nxt.th, (double*)nullptr, (double*)nullptr, sp, s->d_st, s->N, s->d_blockmax);
     // the repairs search this step's cell list while cells move fast, and
     // always when the memory order is never re-sorted
     const bool curl = hot || s->never_resort;
-    if (curl) enqueue_cell_list<R, MULTI>(s, st, nxt);
-    const Work wk = work_for(s, curl);
+    launch(tev(s, T_FORCE), force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
+           nxt.y, nxt.th, (double*)nullptr, (double*)nullptr, sp, s->d_st, s->N, s->d_blockmax, cell_count_for(s, curl));
+    if (curl) enqueue_cell_scan(s, st);
+    const Work wk = work_for(s, curl), wplace = work_for(s, curl, true);
     const bool dense = dense_step(s, hot);
     const double* bmax = s->d_blockmax;
     if (items_kernel(s)) {
         const dim3 g((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u);
         if (dense)
-            launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC, true>, g, dim3(256), st, nxt, wk, sp, s->d_st, s->N,
-                   bmax, (int)force_grid(s));
+            launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC, true>, g, dim3(256), st, nxt, wplace, sp, s->d_st,
+                   s->N, bmax, (int)force_grid(s));
         else
-            launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC>, g, dim3(256), st, nxt, wk, sp, s->d_st, s->N, bmax,
+            launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC>, g, dim3(256), st, nxt, wplace, sp, s->d_st, s->N, bmax,
                    (int)force_grid(s));
     } else {
         if (dense)
-            launch(tev(s, T_GEOM), k_geom<R, MULTI, KC, false, false, true, true>, dim3(cg), dim3(256), st, nxt, wk,
-                   sp, s->d_st, s->N, 0, bmax, (int)force_grid(s));
+            launch(tev(s, T_GEOM), k_geom<R, MULTI, KC, false, false, true, true>, dim3(cg), dim3(256), st, nxt,
+                   wplace, sp, s->d_st, s->N, 0, bmax, (int)force_grid(s));
         else
-            launch(tev(s, T_GEOM), k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, wk, sp,
+            launch(tev(s, T_GEOM), k_geom<R, MULTI, KC, false, false, true>, dim3(cg), dim3(256), st, nxt, wplace, sp,
                    s->d_st, s->N, 0, bmax, (int)force_grid(s));
     }
     if (dense) {
@@ -712,7 +717,7 @@ void enqueue_test(spv_sys* s, hipStream_t st, int cfg, int parity)
     const SysParam* sp = s->d_sp;
     const double* bmax = s->d_blockmax;
     launch(tev(s, T_FORCE), force_kernel<R, MULTI, KC, true>(s), dim3(force_grid(s)), dim3(256), st, cur, nxt.x,
-           nxt.y, nxt.th, (double*)nullptr, (double*)nullptr, sp, s->d_st, s->N, s->d_blockmax);
+           nxt.y, nxt.th, (double*)nullptr, (double*)nullptr, sp, s->d_st, s->N, s->d_blockmax, CellCount{});
     if (items_kernel(s))
         launch(tev(s, T_GEOM), k_geom_items<R, MULTI, KC>,
                dim3((grid_for(s->N, items_cells_per_block(KC)) + 7u) & ~7u), dim3(256), st, nxt, s->work, sp,
@@ -1769,7 +1774,7 @@ void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_p
     ct.cb = s->d_bq;
     hipLaunchKernelGGL((force_kernel<double, false, KC, false, true>(s)), dim3(force_grid(s)), dim3(256), 0, s->stream, ct,
                        (double*)nullptr, (double*)nullptr, (double*)nullptr, lx, ly, (const SysParam*)s->d_sp,
-                       s->d_st, N, s->d_blockmax);
+                       s->d_st, N, s->d_blockmax, CellCount{});
     Cells<double> cp = snap_cells(s, at_prev);
     hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, cp, (const double*)lx,
                        (const double*)ly, (const SysParam*)s->d_sp, N, s->d_dA, s->d_dP, w, s->d_aq, s->d_bq);
@@ -2089,7 +2094,7 @@ spv_status spv_get_forces(spv_sys* s, double* fx, double* fy)
         Cells<R> c = cells<R>(s, s->cfg, s->pos & 1);
         hipLaunchKernelGGL((force_kernel<R, MULTI, KC, false>(s)), dim3(force_grid(s)), dim3(256), 0, s->stream, c,
                            (double*)nullptr, (double*)nullptr, (double*)nullptr, s->d_fx, s->d_fy, s->d_sp, s->d_st,
-                           s->N, s->d_blockmax);
+                           s->N, s->d_blockmax, CellCount{});
     });
     HIP_TRY(hipGetLastError());
     ST_TRY(out_tag_order(s, s->d_fx, fx));

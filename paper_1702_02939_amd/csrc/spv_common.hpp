@@ -117,6 +117,19 @@ struct Work {
     // cells cur_cells[cur_start[b] .. cur_start[b + 1]) lie in spatial bin b
     const int* cur_start;   // [sum of bins + 1]
     const int* cur_cells;   // [N]
+    // the list's placement, done by the step's all-cells pass (null: none):
+    // cell i goes to cplace[cur_start[cbin[i]] + cslot[i]]
+    const int* cbin;
+    const int* cslot;
+    int* cplace;
+};
+
+// Bin and slot of every cell in this step's cell list, counted by the force
+// kernel's update from the new positions (null count: no list this step).
+struct CellCount {
+    int* bin;
+    int* slot;
+    int* count;
 };
 
 __host__ __device__ __forceinline__ double mimg(double d, double L, double hL)

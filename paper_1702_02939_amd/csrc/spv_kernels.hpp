@@ -342,7 +342,7 @@ __device__ __forceinline__ double wrap_units(double X, double LU)
 // rotated director, and the displacement length returned
 __device__ __forceinline__ double update_cell(const SysParam& Q, const double* u0, double Fx, double Fy, int iu,
                                               double* __restrict__ xo, double* __restrict__ yo,
-                                              double* __restrict__ tho, DevState* st)
+                                              double* __restrict__ tho, DevState* st, const CellCount& cc)
 {
     const double xu = u0[0], yu = u0[1], thu = u0[2], nzu = u0[3], sn = u0[4], cs = u0[5];
     const double xn = xu + Q.dt * (Q.mu * Fx + Q.v0 * cs);
@@ -357,6 +357,13 @@ __device__ __forceinline__ double update_cell(const SysParam& Q, const double* u
     xo[iu] = xq;
     yo[iu] = yq;
     tho[iu] = thu + Q.amp * nzu;
+    if (cc.count) {
+        // this step's cell list: the cell's bin and its slot there
+        const int bx = min((int)(xq / Q.bsx), Q.nbx - 1), by = min((int)(yq / Q.bsy), Q.nby - 1);
+        const int b = Q.bin_off + by * Q.nbx + bx;
+        cc.bin[iu] = b;
+        cc.slot[iu] = atomicAdd(&cc.count[b], 1);
+    }
     // the unwrapped move (a jump across the box counts in full: it bounds the
     // drift from the binned position) plus a grid unit for the quantisation
     const double ddx = xn - xu, ddy = yn - yu;
@@ -384,7 +391,7 @@ template <typename R, bool MULTI, int KC, bool UPDATE, bool ACC = false>
 __global__ __launch_bounds__(256) void k_force_cells(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
                                                      double* __restrict__ tho, double* __restrict__ fxo,
                                                      double* __restrict__ fyo, const SysParam* __restrict__ sp,
-                                                     DevState* st, int N, double* __restrict__ blockmax)
+                                                     DevState* st, int N, double* __restrict__ blockmax, CellCount cc)
 {
     constexpr int GL = force_lanes(KC), CPB = force_cells_per_block(KC);
     constexpr int NS = KC / GL;
@@ -482,7 +489,7 @@ __global__ __launch_bounds__(256) void k_force_cells(Cells<R> c, double* __restr
     double disp = 0.0;
     if (upd)
         disp = update_cell(sp[MULTI ? c.sys[iu] : 0], sU0[threadIdx.x], sF[threadIdx.x][0], sF[threadIdx.x][1], iu,
-                           xo, yo, tho, st);
+                           xo, yo, tho, st, cc);
     // block max of the displacement -> blockmax[block] (reduced by the all-cells geometry pass)
     for (int off = 32; off >= 1; off >>= 1) disp = fmax(disp, __shfl_xor(disp, off));
     if (threadIdx.x == 0) blockmax[blockIdx.x] = disp;
@@ -492,7 +499,7 @@ template <typename R, bool MULTI, int KC, bool UPDATE, bool ACC = false>
 __global__ __launch_bounds__(256) void k_force_items(Cells<R> c, double* __restrict__ xo, double* __restrict__ yo,
                                                      double* __restrict__ tho, double* __restrict__ fxo,
                                                      double* __restrict__ fyo, const SysParam* __restrict__ sp,
-                                                     DevState* st, int N, double* __restrict__ blockmax)
+                                                     DevState* st, int N, double* __restrict__ blockmax, CellCount cc)
 {
     constexpr int GL = force_lanes(KC), CPB = items_cells_per_block(KC);
     constexpr int ITEMS = CPB * KC;  // most items a block can hold
@@ -598,7 +605,7 @@ __global__ __launch_bounds__(256) void k_force_items(Cells<R> c, double* __restr
         return;
     }
     double disp = 0.0;
-    if (own) disp = update_cell(sp[MULTI ? c.sys[iu] : 0], sU0[t], (double)fx, (double)fy, iu, xo, yo, tho, st);
+    if (own) disp = update_cell(sp[MULTI ? c.sys[iu] : 0], sU0[t], (double)fx, (double)fy, iu, xo, yo, tho, st, cc);
     for (int off = 32; off >= 1; off >>= 1) disp = fmax(disp, __shfl_xor(disp, off));
     if (t == 0) blockmax[blockIdx.x] = disp;
 }
@@ -676,6 +683,7 @@ __device__ __forceinline__ void geom_pass(const Cells<R>& c, const Work& w, cons
     const bool valid = t < n;
     const int i = valid ? (LIST ? list[t] : t) : 0;
     if (LIST && !(DM & DM_TBYTES) && valid && l == 0) atomicAnd(&w.touchbits[i >> 5], ~(1u << (i & 31)));
+    if (!LIST && w.cplace && valid && l == 0) w.cplace[w.cur_start[w.cbin[i]] + w.cslot[i]] = i;
     const SysParam& P = sp[MULTI ? c.sys[i] : 0];
     int k = valid ? c.deg[i] : 0;
     if (valid && (k < 3 || k > KC)) {
@@ -863,6 +871,7 @@ __global__ __launch_bounds__(256) void k_geom_items(Cells<R> c, Work w, const Sy
     if (t < 64) {
         const int i = base + t;
         const bool valid = t < CPB_I && i < N;
+        if (w.cplace && valid) w.cplace[w.cur_start[w.cbin[i]] + w.cslot[i]] = i;
         int k = valid ? (int)c.deg[i] : 0;
         if (valid && (k < 3 || k > KC)) {
             atomicOr(&st->err, ERR_DEGREE);
@@ -1975,29 +1984,9 @@ __global__ void k_gather(Cells<R> src, Cells<R> dst, const int* perm, const int*
 // While cells move fast, the repairs of a step search a cell list of the
 // step's own positions (cells of each spatial bin listed together, in no
 // particular order inside a bin) instead of the last re-sort's memory order
-// widened by the drift: bin and slot of every cell (count), an exclusive
-// scan of the counts (the re-sort's scan kernels), then the placement.
-template <typename R, bool MULTI>
-__global__ void k_cur_bins(Cells<R> c, const SysParam* __restrict__ sp, const DevState* st, int N, int* cbin,
-                           int* cslot, int* count)
-{
-    if (st->halt) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const SysParam& P = sp[MULTI ? c.sys[i] : 0];
-    const int bx = min((int)(c.x[i] / P.bsx), P.nbx - 1), by = min((int)(c.y[i] / P.bsy), P.nby - 1);
-    const int b = P.bin_off + by * P.nbx + bx;
-    cbin[i] = b;
-    cslot[i] = atomicAdd(&count[b], 1);
-}
-
-__global__ void k_cur_place(const int* __restrict__ cbin, const int* __restrict__ cslot,
-                            const int* __restrict__ start, int* __restrict__ cells, int N, const DevState* st)
-{
-    if (st->halt) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) cells[start[cbin[i]] + cslot[i]] = i;
-}
+// widened by the drift: the force kernel's update counts every cell into its
+// bin (CellCount), the re-sort's scan kernels turn the counts into starts,
+// and the all-cells geometry pass places the cells (Work::cplace).
 
 // ---------------------------------------------------------------- hybrid comparison mode
 // The rows (ring length, then kc entries, -1 past the length) of the listed
