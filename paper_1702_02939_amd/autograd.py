@@ -15,12 +15,19 @@ import torch
 from . import spv
 
 
+def _f64(a):
+    # tensors (host or device) go to the library as they are, anything else
+    # as a float64 numpy array
+    if isinstance(a, torch.Tensor):
+        return a.detach().to(torch.float64).contiguous()
+    return np.asarray(a, dtype=np.float64)
+
+
 class SPVTrajectory(torch.autograd.Function):
     @staticmethod
     def forward(ctx, p0, x0, y0, theta0, L, params, T, ckpt_every):
-        p0n = p0.detach().to(torch.float64).cpu().numpy()
-        s = spv.System(np.asarray(x0, dtype=np.float64), np.asarray(y0, dtype=np.float64), L, L, P0=p0n,
-                       theta0=np.asarray(theta0, dtype=np.float64), params=params)
+        # p0 stays where it is (the library reads host or device memory)
+        s = spv.System(_f64(x0), _f64(y0), L, L, P0=_f64(p0), theta0=_f64(theta0), params=params)
         Q = s.traj_forward(T, ckpt_every)
         ctx.sys = s
         ctx.p0_meta = (p0.dtype, p0.device)
@@ -29,10 +36,11 @@ class SPVTrajectory(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gQ):
         s = ctx.sys
-        g = s.traj_backward(float(gQ))
-        s.close()
         dtype, device = ctx.p0_meta
-        return torch.as_tensor(g, dtype=dtype, device=device), None, None, None, None, None, None, None
+        g = torch.empty(s.N, dtype=torch.float64, device=device)  # written by the library in place
+        s.traj_backward(float(gQ), g)
+        s.close()
+        return g.to(dtype), None, None, None, None, None, None, None
 
 
 def trajectory_q(p0, x0, y0, theta0, L, params, T, ckpt_every):

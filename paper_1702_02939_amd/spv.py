@@ -404,8 +404,10 @@ class System:
     def traj_forward(self, T, ckpt_every):
         return spv_traj_forward(self.h, T, ckpt_every)
 
-    def traj_backward(self, dQ=1.0):
-        g = np.zeros(self.N)
+    def traj_backward(self, dQ=1.0, out=None):
+        """dQ * dQ/dp0 (tag order) into `out` (a float64 numpy array or
+        device tensor of N entries; a new numpy array when None)."""
+        g = np.zeros(self.N) if out is None else out
         spv_traj_backward(self.h, dQ, g)
         return g
 

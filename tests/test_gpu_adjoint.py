@@ -113,6 +113,12 @@ def test_autograd_function(spv):
     g = s.traj_backward(1.0)
     assert np.array_equal(g, p0.grad.numpy())
     s.close()
+    # p0 on the device: read there and the gradient written there, the same numbers
+    p0d = torch.full((n,), 3.75, dtype=torch.float64, device="cuda", requires_grad=True)
+    Qd = trajectory_q(p0d, x0, y0, th0, Lx, prm, T, k)
+    Qd.backward()
+    assert p0d.grad.device.type == "cuda" and Qd.item() == Qt.item()
+    assert np.array_equal(p0d.grad.cpu().numpy(), g)
 
 
 def test_trajectory_gradient_independent_of_scheduling(spv):
