@@ -205,6 +205,7 @@ struct spv_sys {
     // graphs of one period starting in configuration 0 / 1
     // graphs of one period starting in configuration 0 / 1, by period length
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::map<std::vector<int64_t>, hipGraphExec_t> tgraphs;  // trajectory segments (adjoint), by shape
 
     // bookkeeping
     uint64_t step = 0;
@@ -930,6 +931,7 @@ void destroy_all(spv_sys* s)
     if (!s) return;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : s->tgraphs) (void)hipGraphExecDestroy(kv.second);
     for (auto& e : s->pool) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -1605,7 +1607,7 @@ spv_status snap_alloc(spv_sys* s, Snapshot& z)
 }
 
 // copy between the live state (current configuration and parity) and z
-spv_status snap_copy(spv_sys* s, Snapshot& z, bool take)
+spv_status snap_copy(spv_sys* s, Snapshot& z, bool take, hipStream_t stream = nullptr)
 {
     const int N = s->N, K = s->KC;
     const ArraySet& cur = s->set[s->cfg];
@@ -1614,8 +1616,8 @@ spv_status snap_copy(spv_sys* s, Snapshot& z, bool take)
                          static_cast<double*>(cur.P), static_cast<double*>(cur.ca), static_cast<double*>(cur.cb)};
     const StatePtrs snap{z.x, z.y, z.th, z.deg, z.ring, z.opp, z.A, z.P, z.ca, z.cb};
     const unsigned grid = std::min(grid_for(N * K, 256), 2048u);
-    hipLaunchKernelGGL(k_state_copy, dim3(grid), dim3(256), 0, s->stream, take ? snap : live, take ? live : snap, N,
-                       K);
+    hipLaunchKernelGGL(k_state_copy, dim3(grid), dim3(256), 0, stream ? stream : s->stream, take ? snap : live,
+                       take ? live : snap, N, K);
     HIP_TRY(hipGetLastError());
     return SPV_OK;
 }
@@ -1688,19 +1690,57 @@ spv_status restore_checkpoint(spv_sys* s, const TrajCheckpoint& c, bool with_acc
 // followed by after(j); one read-back.  *ok = false when a step needed host
 // repair rounds (the later kernels did nothing; the caller redoes the
 // segment one step at a time from its checkpoint).
+// The launches enq(stream) makes, captured on first use as a graph under key
+// (a trajectory segment of a given shape: the same buffers every time) and
+// replayed on the handle's stream.
+template <typename F>
+spv_status traj_graph(spv_sys* s, const std::vector<int64_t>& key, F&& enq)
+{
+    auto it = s->tgraphs.find(key);
+    if (it == s->tgraphs.end()) {
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+        enq(s->cap_stream);
+        hipError_t e0 = hipGetLastError();
+        hipError_t e1 = hipStreamEndCapture(s->cap_stream, &graph);
+        if (e1 == hipSuccess && e0 != hipSuccess) e1 = e0;
+        if (e1 != hipSuccess) return fail(SPV_EHIP, std::string("graph capture: ") + hipGetErrorString(e1));
+        hipGraphExec_t ex = nullptr;
+        hipError_t e2 = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess) return fail(SPV_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e2));
+        it = s->tgraphs.emplace(key, ex).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, s->stream));
+    return SPV_OK;
+}
+
+// m steps of a trajectory segment with after(j, stream) after step j, then
+// one read-back; *ok when every step finished on the device.  kind >= 0:
+// the segment's launches replay a graph captured for its shape (kind, m,
+// parity, configuration, step flavour, extra) -- what the events of the
+// timing mode cannot be part of.
 template <typename After>
-spv_status segment_fast(spv_sys* s, int64_t m, After&& after, bool* ok)
+spv_status segment_fast(spv_sys* s, int64_t m, After&& after, bool* ok, int64_t kind = -1, int64_t extra = 0)
 {
     const uint64_t before = s->step;
-    const int pos0 = s->pos;
+    const int pos0 = s->pos, cfg = s->cfg;
     const bool hot = s->hot;
-    for (int64_t j = 0; j < m; j++) {
-        const int cfg = s->cfg, par = (int)((pos0 + j) & 1);
-        dispatch(s,
-                 [&]<typename R, bool MULTI, int KC>() { enqueue_step<R, MULTI, KC>(s, s->stream, cfg, par, hot); });
-        s->pos = pos0 + (int)j + 1;  // after() sees the state after step j + 1
-        after(j + 1);
-    }
+    auto enq = [&](hipStream_t stream) {
+        for (int64_t j = 0; j < m; j++) {
+            const int par = (int)((pos0 + j) & 1);
+            dispatch(s, [&]<typename R, bool MULTI, int KC>() {
+                enqueue_step<R, MULTI, KC>(s, stream, cfg, par, hot);
+            });
+            s->pos = pos0 + (int)j + 1;  // after() sees the state after step j + 1
+            after(j + 1, stream);
+        }
+    };
+    if (kind >= 0 && s->use_graphs && !s->timing)
+        ST_TRY(traj_graph(s, {kind, m, pos0 & 1, cfg, hot ? 1 : 0, dense_step(s, hot) ? 1 : 0, extra}, enq));
+    else
+        enq(s->stream);
+    s->pos = pos0 + (int)m;  // a replayed graph did not run enq's bookkeeping
     HIP_TRY(hipGetLastError());
     ST_TRY(read_state(s));
     if (s->h_st->err) return error_from_word(s);
@@ -1722,22 +1762,22 @@ spv_status traj_forward(spv_sys* s, int64_t T, int64_t k, double* Q)
     s->no_resort = true;
     HIP_TRY(hipMemsetAsync(s->d_acc, 0, sizeof(double), s->stream));
     const double w = 1.0 / (double)T;
-    auto accum = [&](int64_t) {
+    auto accum = [&](int64_t, hipStream_t stream) {
         const ArraySet& cur = s->set[s->cfg];
-        hipLaunchKernelGGL(k_qbar_accum, dim3(1), dim3(256), 0, s->stream, (const double*)cur.A,
-                           (const double*)cur.P, s->N, w, s->d_acc, (const DevState*)s->d_st);
+        hipLaunchKernelGGL(k_qbar_accum, dim3(1), dim3(256), 0, stream, (const double*)cur.A, (const double*)cur.P,
+                           s->N, w, s->d_acc, (const DevState*)s->d_st);
     };
     spv_status st = SPV_OK;
     for (int64_t c = 0; c < nck && st == SPV_OK; c++) {
         const int64_t m = std::min<int64_t>(k, T - c * k);
         st = take_checkpoint(s, s->ckpt[c]);
         bool ok = false;
-        if (st == SPV_OK) st = segment_fast(s, m, accum, &ok);
+        if (st == SPV_OK) st = segment_fast(s, m, accum, &ok, 1, T);
         if (st == SPV_OK && !ok) {
             st = restore_checkpoint(s, s->ckpt[c], true);
             for (int64_t j = 0; j < m && st == SPV_OK; j++) {
                 st = run_steps(s, 1);
-                if (st == SPV_OK) accum(j + 1);
+                if (st == SPV_OK) accum(j + 1, s->stream);
             }
         }
     }
@@ -1761,7 +1801,7 @@ spv_status traj_forward(spv_sys* s, int64_t T, int64_t k, double* Q)
 // g += dt mu 2 K_P dP(r_{t-1})[lambda];  the tangent-geometry pass at r_{t-1}
 // also leaves the qbar coefficients of r_{t-1} for the next backward step.
 template <int KC>
-void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_prev, int li)
+void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_prev, int li, hipStream_t stream)
 {
     const int N = s->N;
     const double w = 1.0 / (double)s->traj_T;
@@ -1772,13 +1812,13 @@ void enqueue_adjoint_step(spv_sys* s, const Snapshot& at_t, const Snapshot& at_p
     Cells<double> ct = snap_cells(s, at_t);
     ct.ca = s->d_aq;
     ct.cb = s->d_bq;
-    hipLaunchKernelGGL((force_kernel<double, false, KC, false, true>(s)), dim3(force_grid(s)), dim3(256), 0, s->stream, ct,
+    hipLaunchKernelGGL((force_kernel<double, false, KC, false, true>(s)), dim3(force_grid(s)), dim3(256), 0, stream, ct,
                        (double*)nullptr, (double*)nullptr, (double*)nullptr, lx, ly, (const SysParam*)s->d_sp,
                        s->d_st, N, s->d_blockmax, CellCount{});
     Cells<double> cp = snap_cells(s, at_prev);
-    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, cp, (const double*)lx,
+    hipLaunchKernelGGL((k_tangent_geom<KC>), dim3(grid_for(N * GL, 256)), dim3(256), 0, stream, cp, (const double*)lx,
                        (const double*)ly, (const SysParam*)s->d_sp, N, s->d_dA, s->d_dP, w, s->d_aq, s->d_bq);
-    hipLaunchKernelGGL((k_tangent_force<KC, true>), dim3(grid_for(N * GL, 256)), dim3(256), 0, s->stream, cp, (const double*)lx,
+    hipLaunchKernelGGL((k_tangent_force<KC, true>), dim3(grid_for(N * GL, 256)), dim3(256), 0, stream, cp, (const double*)lx,
                        (const double*)ly, (const double*)s->d_dA, (const double*)s->d_dP, (const SysParam*)s->d_sp, N,
                        lxo, lyo, s->d_g);
 }
@@ -1810,7 +1850,8 @@ spv_status traj_backward(spv_sys* s, double dQ, double* dQ_dp0)
         if (st == SPV_OK) st = snap_copy(s, s->seg[0], true);
         bool ok = false;
         if (st == SPV_OK)
-            st = segment_fast(s, m, [&](int64_t j) { (void)snap_copy(s, s->seg[j], true); }, &ok);
+            st = segment_fast(
+                s, m, [&](int64_t j, hipStream_t stream) { (void)snap_copy(s, s->seg[j], true, stream); }, &ok, 2);
         if (st == SPV_OK && !ok) {
             st = restore_checkpoint(s, s->ckpt[c], false);
             for (int64_t j = 1; j <= m && st == SPV_OK; j++) {
@@ -1819,15 +1860,22 @@ spv_status traj_backward(spv_sys* s, double dQ, double* dQ_dp0)
             }
         }
         if (st != SPV_OK) break;
-        // qbar coefficients of the segment's last state, then the steps backwards
-        hipLaunchKernelGGL(k_qbar_coef, dim3(grid_for(N, 256)), dim3(256), 0, s->stream, (const double*)s->seg[m].A,
-                           (const double*)s->seg[m].P, (int)N, w, s->d_aq, s->d_bq);
-        for (int64_t j = m; j >= 1; j--) {
-            if (s->KC == 16) enqueue_adjoint_step<16>(s, s->seg[j], s->seg[j - 1], li);
-            else enqueue_adjoint_step<32>(s, s->seg[j], s->seg[j - 1], li);
-            li ^= 1;
-        }
-        if (hipGetLastError() != hipSuccess) st = fail(SPV_EHIP, "adjoint kernel launch failed");
+        // qbar coefficients of the segment's last state, then the steps
+        // backwards (a graph per segment shape)
+        auto adj = [&](hipStream_t stream) {
+            hipLaunchKernelGGL(k_qbar_coef, dim3(grid_for(N, 256)), dim3(256), 0, stream, (const double*)s->seg[m].A,
+                               (const double*)s->seg[m].P, (int)N, w, s->d_aq, s->d_bq);
+            int l = li;
+            for (int64_t j = m; j >= 1; j--) {
+                if (s->KC == 16) enqueue_adjoint_step<16>(s, s->seg[j], s->seg[j - 1], l, stream);
+                else enqueue_adjoint_step<32>(s, s->seg[j], s->seg[j - 1], l, stream);
+                l ^= 1;
+            }
+        };
+        if (s->use_graphs && !s->timing) st = traj_graph(s, {3, m, li, s->cfg, T}, adj);
+        else adj(s->stream);
+        li ^= (int)(m & 1);
+        if (st == SPV_OK && hipGetLastError() != hipSuccess) st = fail(SPV_EHIP, "adjoint kernel launch failed");
     }
     // back to the state reached by the forward pass
     if (st == SPV_OK) st = restore_checkpoint(s, s->ckpt[nck], false);
