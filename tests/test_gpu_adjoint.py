@@ -193,3 +193,26 @@ def test_adjoint_c4_configuration(spv):
         assert abs(an - fd) < 1e-5 * max(abs(fd), 1e-3), f"dQ/dp0 . d: adjoint {an:.8e} vs FD {fd:.8e}"
         checked += 1
     assert checked >= 3, f"only {checked} of 6 directions kept the topology sequence"
+
+
+def test_trajectory_graph_replay_equals_eager(spv):
+    """Segments of the same shape replay one captured graph (forward,
+    backward replay and adjoint steps): Q, dQ/dp0 and the final positions
+    are bitwise those of the eager path, over enough segments that every
+    shape is replayed (a replay must also advance the host's step parity)."""
+    n, T, k = 1500, 28, 7
+    L = math.sqrt(n)
+    x, y = inputs.uniform_positions(n, L, L, 74)
+    p0 = inputs.per_cell_p0(n, 3.8, 0.05, 74)
+    out = []
+    for ng in (1, 0):
+        s = spv.System(x, y, L, L, P0=p0, params=spv.Params(mu=1.0, v0=0.05, Dr=1.0, dt=0.01, seed=3, no_graphs=ng))
+        s.step(5)
+        Q = s.traj_forward(T, k)
+        g = s.traj_backward(1.0)
+        xe, ye = s.positions()
+        out.append((Q, g, xe, ye))
+        s.close()
+    (Q0, g0, x0, y0), (Q1, g1, x1, y1) = out
+    assert Q0 == Q1 and np.array_equal(g0, g1)
+    assert np.array_equal(x0, x1) and np.array_equal(y0, y1)
