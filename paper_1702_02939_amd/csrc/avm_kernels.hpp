@@ -289,10 +289,17 @@ __global__ __launch_bounds__(256) void k_avm_t1_mark(AvmArrays a, const AvmParam
         if (t < a.nv) found = avm_mark_vertex(a, P, st, 0, t, lock, prev);
     } else {
         if (!st->any[r - 1]) return;  // nothing flipped in the last round: nothing new qualifies
-        if (8 * t >= a.nv) return;
-        const uint64_t f = *reinterpret_cast<const uint64_t*>(a.dirty + 8 * (size_t)t);
+        // vertices t, t + S, ..., t + 7 S: flagged vertices sit together in
+        // memory (neighbours of the same flips), so that consecutive ones go
+        // to different threads; the eight flags are read before any work
+        const int S = (a.nv + 7) >> 3;
+        if (t >= S) return;
+        uint8_t f[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) f[j] = t + j * S < a.nv ? a.dirty[t + j * S] : (uint8_t)0;
+#pragma unroll
         for (int j = 0; j < 8; j++)
-            if (((f >> (8 * j)) & 0xff) == (uint64_t)r) found |= avm_mark_vertex(a, P, st, r, 8 * t + j, lock, prev);
+            if (f[j] == r) found |= avm_mark_vertex(a, P, st, r, t + j * S, lock, prev);
     }
     if (found) {
         st->any[r] = 1;
@@ -468,14 +475,22 @@ __global__ __launch_bounds__(256) void k_avm_t1_apply(AvmArrays a, const AvmPara
     if (r == 0 && t == 0) st->step += 1ull;  // the step's noise is drawn
     if (!st->any[r]) return;
     if (t == 0) atomicAdd(&st->rounds, 1ull);
-    if (8 * t >= a.nv) return;
-    const uint64_t f = *reinterpret_cast<const uint64_t*>(a.cand + 8 * (size_t)t);
-    if (!f) return;
-    const AvmParam& P = *pp;
+    // vertices t, t + S, ..., t + 7 S (conflicting candidates sit together
+    // in memory: spread over threads), the eight masks read first
+    const int S = (a.nv + 7) >> 3;
+    if (t >= S) return;
+    uint8_t m8[8];
+    unsigned any = 0;
+#pragma unroll
     for (int j = 0; j < 8; j++) {
-        const unsigned m = (unsigned)((f >> (8 * j)) & 0xff);
-        if (m) avm_apply_vertex(a, P, st, r, 8 * t + j, m);
+        m8[j] = t + j * S < a.nv ? a.cand[t + j * S] : (uint8_t)0;
+        any |= m8[j];
     }
+    if (!any) return;
+    const AvmParam& P = *pp;
+#pragma unroll 1
+    for (int j = 0; j < 8; j++)
+        if (m8[j]) avm_apply_vertex(a, P, st, r, t + j * S, m8[j]);
 }
 
 // ---------------------------------------------------------------- spatial re-sort
