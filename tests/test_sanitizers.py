@@ -1,5 +1,5 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU
-only): the oracle's C entry points on small seeded systems, and the
+only): the oracle's C entry points (both models) on small seeded systems, and the
 library's tuning-cache reader and writer on well-formed and malformed
 files.  Any sanitizer report fails the run (no recovery)."""
 import os
@@ -33,6 +33,17 @@ def test_oracle_under_sanitizers(tmp):
     r = subprocess.run([exe], capture_output=True, text=True, env=ENV, timeout=600)
     assert r.returncode == 0, r.stderr[-4000:]
     assert "sanitized oracle ok" in r.stdout
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
+
+
+def test_avm_oracle_under_sanitizers(tmp):
+    exe = str(tmp / "avm_oracle_san")
+    odir = os.path.join(HERE, "..", "oracle")
+    subprocess.run(["gcc", "-std=c11", "-ffp-contract=off", *SAN, "-o", exe, os.path.join(HERE, "sanitize_avm_main.c"),
+                    os.path.join(odir, "spv_oracle.c"), os.path.join(odir, "avm_oracle.c"), "-lm"], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, env=ENV, timeout=600)
+    assert r.returncode == 0, r.stderr[-4000:]
+    assert "sanitized avm oracle ok" in r.stdout
     assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
 
 
