@@ -200,6 +200,20 @@ spv_status spv_get_geometry(spv_sys* s, double* A, double* P);
 spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t cap, int64_t* needed);
 
 /*
+ * Fault injection for tests of the topology test and repair (Sec. II.C: every
+ * ring is tested after each move and the failing ones are rebuilt).  Replaces
+ * the ring of cell `cell` (tag-order index, as in spv_get_neighbors) with
+ * the k entries of nbr (tag-order indices, host pointer), whatever the
+ * geometry says, and records no opposite cell for any of its edges, so that
+ * the next step's test of the cell fails and the repair rebuilds its ring
+ * from the positions.  That step's forces still use the ring as written.
+ * Errors: SPV_EINVAL for a cell out of range, k outside [3, kcap], or an
+ * entry outside the cell's system, equal to the cell or repeated (the
+ * handle unchanged).
+ */
+spv_status spv_debug_set_ring(spv_sys* s, int64_t cell, int32_t k, const int32_t* nbr);
+
+/*
  * Observables of the current state summed over all systems: E (Eq. 1),
  * qbar = mean of P_i/sqrt(A_i), sumA = sum of A_i; counters[13] (host
  * pointer, may be NULL):

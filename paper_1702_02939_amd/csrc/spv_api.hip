@@ -2193,6 +2193,47 @@ spv_status spv_get_neighbors(spv_sys* s, int32_t* offsets, int32_t* nbr, int64_t
     return SPV_OK;
 }
 
+spv_status spv_debug_set_ring(spv_sys* s, int64_t cell, int32_t k, const int32_t* nbr)
+{
+    if (!s || !nbr) return fail(SPV_EINVAL, "bad argument");
+    const int N = s->N, K = s->KC;
+    if (cell < 0 || cell >= N) return fail(SPV_EINVAL, "cell index out of range");
+    if (k < 3 || k > K) return fail(SPV_EINVAL, "ring length outside [3, kcap]");
+    int sysk = 0;
+    while (sysk + 1 < s->S && s->hsp[sysk + 1].cell_off <= cell) sysk++;
+    const int64_t lo = s->hsp[sysk].cell_off, hi = lo + s->hsp[sysk].n;
+    for (int m = 0; m < k; m++) {
+        if (nbr[m] < lo || nbr[m] >= hi || nbr[m] == cell)
+            return fail(SPV_EINVAL, "ring member outside the cell's system or the cell itself");
+        for (int q = 0; q < m; q++)
+            if (nbr[q] == nbr[m]) return fail(SPV_EINVAL, "repeated ring member");
+    }
+    const ArraySet& cur = s->set[s->cfg];
+    std::vector<int> tag(N), sys(N);
+    HIP_TRY(hipMemcpyAsync(tag.data(), cur.tag, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(sys.data(), cur.sys, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::vector<int> slot_of(N);
+    for (int i = 0; i < N; i++) slot_of[s->hsp[sys[i]].cell_off + tag[i]] = i;
+    // the row in its two parts (first RLO slots, then the overflow part),
+    // every slot past k cleared; no opposite cell recorded for any edge
+    const int i = slot_of[cell];
+    std::vector<int> row(K, -1), opp(K, -1);
+    for (int m = 0; m < k; m++) row[m] = slot_of[nbr[m]];
+    const uint8_t d = (uint8_t)k;
+    const size_t lo_off = (size_t)i * RLO, hi_off = (size_t)RLO * N + (size_t)i * (K - RLO);
+    HIP_TRY(hipMemcpyAsync(cur.ring + lo_off, row.data(), RLO * sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(cur.ring + hi_off, row.data() + RLO, (K - RLO) * sizeof(int), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(cur.opp + lo_off, opp.data(), RLO * sizeof(int), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(cur.opp + hi_off, opp.data() + RLO, (K - RLO) * sizeof(int), hipMemcpyHostToDevice,
+                           s->stream));
+    HIP_TRY(hipMemcpyAsync(cur.deg + i, &d, 1, hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->traj_valid = false;
+    return SPV_OK;
+}
+
 static spv_status observables_all(spv_sys* s, std::vector<double>& h)
 {
     const ArraySet& cur = s->set[s->cfg];

@@ -100,6 +100,7 @@ _SIGS = {
     "spv_get_forces": [_H, _P, _P],
     "spv_get_geometry": [_H, _P, _P],
     "spv_get_neighbors": [_H, _P, _P, _i64, ctypes.POINTER(_i64)],
+    "spv_debug_set_ring": [_H, _i64, _i32, _P],
     "spv_get_observables": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d), _P],
     "spv_set_timing": [_H, _i32],
     "spv_kernel_time": [_H, _i32, ctypes.POINTER(_d), ctypes.POINTER(_i64)],
@@ -261,6 +262,11 @@ def spv_get_neighbors(h, N):
     return off, nbr[: int(need.value)]
 
 
+def spv_debug_set_ring(h, cell, nbr):
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    _check(_lib.spv_debug_set_ring(h, int(cell), len(nbr), _ptr(nbr)), "spv_debug_set_ring")
+
+
 def spv_get_observables(h):
     E, q, a = _d(), _d(), _d()
     cnt = np.zeros(13, dtype=np.int64)
@@ -388,6 +394,10 @@ class System:
 
     def neighbors(self):
         return spv_get_neighbors(self.h, self.N)
+
+    def debug_set_ring(self, cell, nbr):
+        """Overwrite one cell's ring (fault injection for tests)."""
+        spv_debug_set_ring(self.h, cell, nbr)
 
     def observables(self):
         return spv_get_observables(self.h)

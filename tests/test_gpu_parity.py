@@ -524,3 +524,59 @@ def test_never_resort_bitwise_equal(spv):
         for u, v in zip(a, b):
             assert np.array_equal(u, v)
         assert cb[5] == 0 and cb[8] > 0 and ca[5] > 0
+
+
+@pytest.mark.parametrize("repair_mode", [0, 1])
+def test_corrupted_ring_is_detected_and_repaired(spv, repair_mode):
+    """A ring overwritten through the fault-injection hook (one neighbour
+    dropped, two swapped, one replaced by a second-shell cell) fails the
+    next step's test and is rebuilt by the repair (device rounds inside
+    replayed graph periods, or the hybrid host repair): the topology equals
+    the oracle's triangulation of the positions again, forces within the
+    bound.  Invalid rings are rejected with the topology unchanged."""
+    n = 2000
+    x, y, L, _ = _random_case(n, 63)
+    s = spv.System(x, y, L, L, p0=3.9, params=spv.Params(v0=0.1, Dr=1.0, seed=5, resort_every=8,
+                                                           repair_mode=repair_mode))
+    s.step(301)
+    off, ring = s.neighbors()
+    rng = np.random.default_rng(9)
+    cells = [int(c) for c in rng.choice(n, 40, replace=False) if off[c + 1] - off[c] >= 5][:3]
+    assert len(cells) == 3
+    a, b, c = cells
+    ra, rb, rc = (list(ring[off[t]:off[t + 1]]) for t in (a, b, c))
+    second = [int(v) for v in ring[off[rc[0]]:off[rc[0] + 1]] if v != c and v not in rc]
+    bad = {a: ra[:2] + ra[3:], b: [rb[1], rb[0]] + rb[2:], c: [second[0]] + rc[1:]}
+    cnt0 = s.observables()[3]
+    for t, r in bad.items():
+        s.debug_set_ring(t, r)
+    goff, gring = s.neighbors()
+    for t, r in bad.items():
+        assert list(gring[goff[t]:goff[t + 1]]) == r
+    s.step(1)  # the next step's test and repair fix all three rings
+    gx, gy = s.positions()
+    _compare_topology(s, gx, gy)
+    cnt = s.observables()[3]
+    assert cnt[1] >= cnt0[1] + 3 and cnt[7] == 0
+    for t, r in bad.items():
+        s.debug_set_ring(t, r)
+    s.step(16)  # corrupted again, now with re-sort periods replayed as graphs
+    gx, gy = s.positions()
+    o2, r2 = _compare_topology(s, gx, gy)
+    _compare_forces(s, gx, gy, o2, r2, 1.0, 3.9)
+    cnt = s.observables()[3]
+    assert cnt[7] == 0
+    if repair_mode == 0:
+        assert cnt[8] > cnt0[8], "no graph period replayed after the corruption"
+    t = int(rng.integers(n))
+    r = list(r2[o2[t]:o2[t + 1]])
+    kcap = 16
+    for wrong in ([r[0], r[1]], (r * 3)[:kcap + 1], [t] + r[1:], [r[0]] + r[:-1], [n] + r[1:], [-1] + r[1:]):
+        with pytest.raises(spv.SPVError) as ei:
+            s.debug_set_ring(t, wrong)
+        assert ei.value.status == spv.SPV_EINVAL
+    with pytest.raises(spv.SPVError):
+        s.debug_set_ring(n, r)
+    o3, r3 = s.neighbors()
+    assert np.array_equal(o3, o2) and np.array_equal(r3, r2)
+    s.close()
