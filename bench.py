@@ -117,11 +117,9 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, nsteps):
-    """The oracle (serial C: full Bowyer-Watson each step, dual-number forces)
-    on the same workload, a bounded number of steps from the same start."""
-    import numpy as np
-
+def _oracle_sample(w, nsteps):
+    """nsteps of the oracle on workload w from its random start; returns the
+    seconds the steps took (setup excluded)."""
     import oracle
     from paper_1702_02939_amd import inputs
     n, L = w["N"], w["L"]
@@ -131,7 +129,30 @@ def cpu_baseline(w, nsteps):
     t0 = time.perf_counter()
     oracle.run(xq, yq, th, Lx, Ly, q, 1.0, w["p0"], mu=w["mu"], v0=w["v0"], Dr=w["Dr"], dt=w["dt"],
                seed=w["seed"], nsteps=nsteps)
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0
+
+
+def _oracle_copies(w, nsteps, procs):
+    """The same oracle sample in `procs` independent processes at once (fresh
+    interpreters that load only the oracle): the host's aggregate rate on
+    independent systems.  Returns (cell-steps/s over the slowest copy, its
+    seconds)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        times = pool.starmap(_oracle_sample, [(w, nsteps)] * procs)
+    slow = max(times)
+    return procs * w["N"] * nsteps / slow, slow
+
+
+def cpu_baseline(w, nsteps, copies_steps=None):
+    """The oracle (serial C: full Bowyer-Watson each step, dual-number forces)
+    on the same workload, a bounded number of steps from the same start; and
+    the same sample run as independent copies, one per available core (up to
+    16), for the host's aggregate rate."""
+    n = w["N"]
+    copies_steps = nsteps if copies_steps is None else copies_steps
+    dt = _oracle_sample(w, nsteps)
     # run() also triangulates the final state once: nsteps + 1 triangulations
     cpu = "unknown"
     try:
@@ -141,10 +162,18 @@ def cpu_baseline(w, nsteps):
                 break
     except OSError:
         pass
-    return {"value": n * nsteps / dt, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{w['N']} cells, {nsteps} steps from the random start (serial, 1 thread), {dt:.1f} s",
-            "host_cpu": cpu, "host_nproc": os.cpu_count(),
-            "host_affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    out = {"value": n * nsteps / dt, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"{w['N']} cells, {nsteps} steps from the random start (serial, 1 thread), {dt:.1f} s",
+           "host_cpu": cpu, "host_nproc": os.cpu_count(), "host_affinity": affinity}
+    procs = max(1, min(16, affinity or 1))
+    if copies_steps > 0 and procs > 1:
+        v, slow = _oracle_copies(w, copies_steps, procs)
+        out["independent_copies"] = {
+            "value": v, "unit": "cell-steps/s", "processes": procs,
+            "sample": f"{procs} copies of {w['N']} cells x {copies_steps} steps, one process each, "
+                      f"slowest {slow:.1f} s"}
+    return out
 
 
 def count_bins(sysm, bin_factor):
