@@ -70,7 +70,8 @@ typedef struct {
                                shortened while the cells' drift bound would pass a bin side within
                                it); -1: never re-sort -- the memory order stays that of creation and
                                every step's repairs search a cell list of the step's positions */
-    int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16) */
+    int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16, or 32
+                               when the starting triangulation has a longer ring) */
     int32_t repair_rounds;  /* max test/repair rounds per step, device and host together (0: 16, max 32) */
     int32_t device_rounds;  /* repair rounds run on the device inside each step: round 0 over the whole
                                grid, later ones in one block (0: 8) */

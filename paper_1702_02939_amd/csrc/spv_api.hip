@@ -1970,6 +1970,19 @@ extern "C" {
 
 const char* spv_last_error(void) { return g_err.c_str(); }
 
+// kcap 0: rings of up to 16 entries, or 32 when the starting triangulation
+// has a longer ring (the creation is repeated once with 32; a ring that
+// outgrows the capacity later in the run is an error, as with kcap given)
+spv_status create_regrow(CreateArgs& a, int64_t Ntot, spv_sys** out)
+{
+    const bool auto_cap = a.prm.kcap == 0;
+    spv_status st = create_tuned(a, out);
+    if (st != SPV_ECAPACITY || !auto_cap) return st;
+    ST_TRY(check_ring_extent(Ntot, 32));
+    a.prm.kcap = 32;
+    return create_tuned(a, out);
+}
+
 spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y, double Lx, double Ly,
                       const double* A0, const double* P0, double p0, const double* theta0,
                       const spv_params* params, void* stream)
@@ -2011,7 +2024,7 @@ spv_status spv_create(spv_sys** out, int64_t N, const double* x, const double* y
             if (!std::isfinite(a.th[i])) return fail(SPV_EINVAL, "theta0 must be finite");
     }
     a.in = {{N, Lx, Ly, params->v0, params->seed}};
-    return create_tuned(a, out);
+    return create_regrow(a, N, out);
 }
 
 spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const double* Lx_s, const double* Ly_s,
@@ -2054,7 +2067,7 @@ spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const 
     }
     for (int64_t i = 0; i < Ntot; i++)
         if (!std::isfinite(a.P0[i])) return fail(SPV_EINVAL, "P0 must be finite");
-    return create_tuned(a, out);
+    return create_regrow(a, Ntot, out);
 }
 
 spv_status spv_step(spv_sys* s, int64_t nsteps)

@@ -145,7 +145,8 @@ def test_batched_sweep_full(spv, steps):
 
 def test_ring_capacity(spv):
     """A cell with 20 Delaunay neighbours (a perturbed 20-gon around it):
-    kcap 16 reports SPV_ECAPACITY, kcap 32 reproduces the oracle's rings."""
+    kcap 16 reports SPV_ECAPACITY, kcap 32 and the default (regrown to 32 at
+    creation) reproduce the oracle's rings, also after a few steps."""
     L = 40.0
     rng = np.random.default_rng(5)
     xs, ys = [20.0], [20.0]
@@ -164,10 +165,16 @@ def test_ring_capacity(spv):
     with pytest.raises(spv.SPVError) as ei:
         spv.System(x, y, L, L, params=spv.Params(kcap=16))
     assert ei.value.status == spv.SPV_ECAPACITY
-    s = spv.System(x, y, L, L, params=spv.Params(kcap=32))
-    goff, gring = s.neighbors()
-    assert np.array_equal(goff, off) and np.array_equal(gring, ring)
-    fx, fy = oracle.forces(xq, yq, Lx, Ly, off, ring, 1.0, 3.8)
-    gfx, gfy = s.forces()
-    _forces_ok(gfx, gfy, fx, fy, 3.8, False)
-    s.close()
+    for kcap in (32, 0):  # 0: the default capacity, regrown to 32 at creation
+        s = spv.System(x, y, L, L, params=spv.Params(kcap=kcap))
+        goff, gring = s.neighbors()
+        assert np.array_equal(goff, off) and np.array_equal(gring, ring)
+        fx, fy = oracle.forces(xq, yq, Lx, Ly, off, ring, 1.0, 3.8)
+        gfx, gfy = s.forces()
+        _forces_ok(gfx, gfy, fx, fy, 3.8, False)
+        s.step(5)
+        gx, gy = s.positions()
+        o2, r2, _, _ = oracle.triangulate(gx, gy, Lx, Ly, q)
+        goff, gring = s.neighbors()
+        assert np.array_equal(goff, o2) and np.array_equal(gring, r2)
+        s.close()
