@@ -70,8 +70,8 @@ typedef struct {
                                shortened while the cells' drift bound would pass a bin side within
                                it); -1: never re-sort -- the memory order stays that of creation and
                                every step's repairs search a cell list of the step's positions */
-    int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16, or 32
-                               when the starting triangulation has a longer ring) */
+    int32_t kcap;           /* ring capacity = max Delaunay degree: 16 or 32 (0: 16, regrown
+                               to 32 when a ring needs more, at creation or in a run) */
     int32_t repair_rounds;  /* max test/repair rounds per step, device and host together (0: 16, max 32) */
     int32_t device_rounds;  /* repair rounds run on the device inside each step: round 0 over the whole
                                grid, later ones in one block (0: 8) */
@@ -170,6 +170,13 @@ spv_status spv_step(spv_sys* s, int64_t nsteps);
 
 /* Number of systems and total number of cells of the handle. */
 spv_status spv_get_size(spv_sys* s, int32_t* S, int64_t* N);
+
+/* Current ring capacity (16 or 32).  With kcap 0 the handle starts at 16 and
+ * moves to 32 when a ring needs more: at creation, or during spv_step, where
+ * the step whose repair overflowed is finished by rebuilding the topology of
+ * its positions at capacity 32 (statistics then restart as after
+ * spv_load_state; the handle pointer stays valid). */
+spv_status spv_get_kcap(spv_sys* s, int32_t* kcap);
 
 /* First cell (in tag order) and cell count of system sys. */
 spv_status spv_get_system_range(spv_sys* s, int32_t sys, int64_t* first, int64_t* n);

@@ -2070,11 +2070,72 @@ spv_status spv_batch_create(spv_sys** out, int32_t S, const int64_t* N_s, const 
     return create_regrow(a, Ntot, out);
 }
 
+// kcap 0: a ring that outgrows 16 entries during a run.  The step that
+// failed has moved the cells but not finished its topology; the state is
+// saved as it is (the sticky error set aside), a handle with kcap 32 and the
+// same knobs is built from it, and the state is loaded there, which rebuilds
+// the topology of those positions from scratch -- the finished step.  The
+// new handle's contents then replace this one's (the caller's pointer stays
+// valid; statistics restart as after spv_load_state).
+spv_status regrow_capacity(spv_sys* s)
+{
+    std::vector<char> buf((size_t)state_bytes(s));
+    const spv_status sticky = s->sticky;
+    const std::string sticky_msg = s->sticky_msg;
+    s->sticky = SPV_OK;
+    spv_status st = save_state(s, buf.data(), (int64_t)buf.size(), nullptr);
+    s->sticky = sticky;
+    s->sticky_msg = sticky_msg;
+    ST_TRY(st);
+    StateHeader h;
+    std::memcpy(&h, buf.data(), sizeof h);
+    CreateArgs a;
+    a.stream = s->stream;
+    const char* p = buf.data() + sizeof h;
+    for (int k = 0; k < h.S; k++) {
+        StateSystem r;
+        std::memcpy(&r, p, sizeof r);
+        p += sizeof r;
+        a.in.push_back({r.n, r.Lx, r.Ly, r.v0, r.seed});
+    }
+    const size_t N = (size_t)h.N;
+    const double* arr = reinterpret_cast<const double*>(p);
+    a.x.assign(arr, arr + N);
+    a.y.assign(arr + N, arr + 2 * N);
+    a.th.assign(arr + 2 * N, arr + 3 * N);
+    a.A0.assign(arr + 3 * N, arr + 4 * N);
+    a.P0.assign(arr + 4 * N, arr + 5 * N);
+    spv_params prm = with_knobs(s->prm, knobs_of(s));
+    prm.kcap = 32;
+    ST_TRY(check_ring_extent((int64_t)N, 32));
+    spv_sys* t = nullptr;
+    ST_TRY(build_handle(a, prm, &t));
+    st = load_state(t, buf.data(), (int64_t)buf.size());
+    if (st != SPV_OK) {
+        destroy_all(t);
+        return st;
+    }
+    t->prm.kcap = 0;  // still the caller's setting
+    t->tune_source = s->tune_source;
+    t->tune_ms = s->tune_ms;
+    const bool timing = s->timing;
+    std::swap(*s, *t);
+    destroy_all(t);  // the old arrays, graphs and streams
+    if (timing) ST_TRY(spv_set_timing(s, 1));
+    return SPV_OK;
+}
+
 spv_status spv_step(spv_sys* s, int64_t nsteps)
 {
     if (!s || nsteps < 0) return fail(SPV_EINVAL, "bad handle or nsteps");
     s->traj_valid = false;  // the recorded trajectory no longer ends at the current state
-    return run_steps(s, nsteps);
+    const uint64_t target = s->step + (uint64_t)nsteps;
+    spv_status st = run_steps(s, nsteps);
+    if (st == SPV_ECAPACITY && s->prm.kcap == 0 && s->KC == 16 && (s->h_st->err & ERR_CAPACITY)) {
+        ST_TRY(regrow_capacity(s));
+        st = run_steps(s, (int64_t)(target - s->step));
+    }
+    return st;
 }
 
 spv_status spv_save_state(spv_sys* s, void* buf, int64_t cap, int64_t* needed)
@@ -2101,6 +2162,13 @@ spv_status spv_get_tuning(spv_sys* s, spv_tuning* out)
     out->source = s->tune_source;
     out->bin_factor = s->bin_factor;
     out->ms_per_step = s->tune_ms;
+    return SPV_OK;
+}
+
+spv_status spv_get_kcap(spv_sys* s, int32_t* kcap)
+{
+    if (!s || !kcap) return fail(SPV_EINVAL, "bad argument");
+    *kcap = s->KC;
     return SPV_OK;
 }
 

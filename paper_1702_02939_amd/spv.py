@@ -91,6 +91,7 @@ _SIGS = {
     "spv_save_state": [_H, _P, _i64, ctypes.POINTER(_i64)],
     "spv_load_state": [_H, _P, _i64],
     "spv_get_size": [_H, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
+    "spv_get_kcap": [_H, ctypes.POINTER(_i32)],
     "spv_get_system_range": [_H, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "spv_get_box": [_H, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)],
     "spv_get_system_box": [_H, _i32, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_i32)],
@@ -202,6 +203,12 @@ def spv_get_size(h):
     S, N = _i32(), _i64()
     _check(_lib.spv_get_size(h, ctypes.byref(S), ctypes.byref(N)), "spv_get_size")
     return S.value, N.value
+
+
+def spv_get_kcap(h):
+    k = _i32()
+    _check(_lib.spv_get_kcap(h, ctypes.byref(k)), "spv_get_kcap")
+    return k.value
 
 
 def spv_get_system_range(h, s):
@@ -356,6 +363,9 @@ class System:
 
     def size(self):
         return spv_get_size(self.h)
+
+    def kcap(self):
+        return spv_get_kcap(self.h)
 
     def system_range(self, s):
         return spv_get_system_range(self.h, s)

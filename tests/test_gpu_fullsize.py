@@ -178,3 +178,58 @@ def test_ring_capacity(spv):
         goff, gring = s.neighbors()
         assert np.array_equal(goff, o2) and np.array_equal(gring, r2)
         s.close()
+
+
+def _intruder_case():
+    """16 cells on a circle of radius 3 around one cell, a 17th at radius 3.9
+    in the gap between two of them, the rest uniform beyond radius 6; the
+    17th cell's director points at the centre, every other director the
+    opposite way."""
+    L = 40.0
+    rng = np.random.default_rng(11)
+    xs, ys = [20.0], [20.0]
+    for t in range(16):
+        a = 2 * math.pi * t / 16 + rng.uniform(-0.02, 0.02)
+        r = 3.0 + rng.uniform(-0.05, 0.05)
+        xs.append(20.0 + r * math.cos(a))
+        ys.append(20.0 + r * math.sin(a))
+    ga = math.pi / 16
+    xs.append(20.0 + 3.9 * math.cos(ga))
+    ys.append(20.0 + 3.9 * math.sin(ga))
+    bx, by = inputs.uniform_positions(1600, L, L, 6)
+    keep = np.hypot(bx - 20.0, by - 20.0) > 6.0
+    x = np.concatenate([xs, bx[keep]])
+    y = np.concatenate([ys, by[keep]])
+    th = np.full(len(x), ga)
+    th[17] = ga + math.pi
+    return x, y, L, th
+
+
+def test_ring_capacity_regrows_in_a_run(spv):
+    """K_A = K_P = 0, D_r = 0: every cell moves straight with its director,
+    so the 17th cell of `_intruder_case` closes in on the centre relative to
+    the others and the centre's degree reaches 17 (oracle: steps 45-54).
+    kcap 16 stops the run with SPV_ECAPACITY; the default capacity regrows
+    to 32 in the run, and the topology equals the oracle's triangulation of
+    the device positions at every check, before and after."""
+    x, y, L, th = _intruder_case()
+    prm = dict(KA=0.0, KP=0.0, v0=1.0, Dr=0.0, dt=0.01, seed=1)
+    s16 = spv.System(x, y, L, L, theta0=th, params=spv.Params(kcap=16, **prm))
+    with pytest.raises(spv.SPVError) as ei:
+        s16.step(60)
+    assert ei.value.status == spv.SPV_ECAPACITY
+    s16.close()
+    s = spv.System(x, y, L, L, theta0=th, params=spv.Params(**prm))
+    assert s.kcap() == 16
+    Lx, Ly, q = s.box()
+    longest = 0
+    for _ in range(14):
+        s.step(5)
+        gx, gy = s.positions()
+        off, ring, _, _ = oracle.triangulate(gx, gy, Lx, Ly, q)
+        goff, gring = s.neighbors()
+        assert np.array_equal(goff, off) and np.array_equal(gring, ring)
+        longest = max(longest, int(np.diff(off).max()))
+    assert longest == 17 and s.kcap() == 32
+    assert s.observables()[3][0] == 70
+    s.close()
