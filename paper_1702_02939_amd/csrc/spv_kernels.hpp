@@ -1018,15 +1018,17 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
                              int* s_tmp, double scale, bool& closed)
 {
     const int lane = threadIdx.x & 63;
-    // G lanes per candidate split the loop over the other candidates
-    const int G = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
+    // G lanes per candidate split the loop over the other candidates (three
+    // for 17 to 21 candidates: 51 to 63 lanes busy instead of 34 to 42)
+    const int G = n <= 16 ? 4 : (n <= 21 ? 3 : (n <= 32 ? 2 : 1));
     const int per_pass = 64 / G;
+    const bool act = lane < per_pass * G;  // lane 63 idles when G = 3
     int unsure = 0, k = 0;
     for (int base = 0; base < n; base += per_pass) {
         const int pi = base + lane / G, r = lane % G;
         bool mem = false, blocked = false;
         double ulo = INFINITY, uhi = INFINITY, llo = -INFINITY, lhi = -INFINITY;
-        if (pi < n) {
+        if (act && pi < n) {
             const double px = sx[pi], py = sy[pi];
 #pragma unroll 4
             for (int q = r; q < n; q += G) {
@@ -1067,14 +1069,32 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
             }
         }
         // combine the G lanes of each candidate (aligned groups)
-        for (int off = 1; off < G; off <<= 1) {
-            ulo = fmin(ulo, __shfl_xor(ulo, off));
-            uhi = fmin(uhi, __shfl_xor(uhi, off));
-            llo = fmax(llo, __shfl_xor(llo, off));
-            lhi = fmax(lhi, __shfl_xor(lhi, off));
-            blocked = __shfl_xor((int)blocked, off) != 0 || blocked;
+        if (G == 3) {
+            const int g0 = lane - r;  // the group's lanes g0 .. g0 + 2
+            double a = ulo, b = uhi, c = llo, d = lhi;
+            int bl = blocked ? 1 : 0;
+            for (int j = 0; j < 3; j++) {
+                a = fmin(a, __shfl(ulo, g0 + j));
+                b = fmin(b, __shfl(uhi, g0 + j));
+                c = fmax(c, __shfl(llo, g0 + j));
+                d = fmax(d, __shfl(lhi, g0 + j));
+                bl |= __shfl(blocked ? 1 : 0, g0 + j);
+            }
+            ulo = a;
+            uhi = b;
+            llo = c;
+            lhi = d;
+            blocked = bl != 0;
+        } else {
+            for (int off = 1; off < G; off <<= 1) {
+                ulo = fmin(ulo, __shfl_xor(ulo, off));
+                uhi = fmin(uhi, __shfl_xor(uhi, off));
+                llo = fmax(llo, __shfl_xor(llo, off));
+                lhi = fmax(lhi, __shfl_xor(lhi, off));
+                blocked = __shfl_xor((int)blocked, off) != 0 || blocked;
+            }
         }
-        if (pi < n && r == 0 && !blocked) {
+        if (act && pi < n && r == 0 && !blocked) {
             if (ulo > lhi) mem = true;           // certainly a non-empty interval
             else if (!(llo > uhi)) unsure = 1;  // and not certainly empty either
         }
