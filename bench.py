@@ -74,12 +74,12 @@ def class_bytes(cls, r):
 # source they were taken on (digest of the device headers): any later change
 # of the kernels nulls roofline.traffic.
 MEASURED_TRAFFIC = {
-    ("spv_n100k", "repair", 1): {"bytes_per_launch": 17.210e6, "source_sha256":
-                                 "7b183ec57a21d088bee681a42088f87dc1e189278ee75338b48126cff6ebc42c"},
-    ("spv_n100k", "force_update", 1): {"bytes_per_launch": 17.328e6, "source_sha256":
-                                       "7b183ec57a21d088bee681a42088f87dc1e189278ee75338b48126cff6ebc42c"},
+    ("spv_n100k", "repair", 1): {"bytes_per_launch": 18.297e6, "source_sha256":
+                                 "a382cd4b05eb0d17b4c7e5b523e9e01f630b53fbc037442ef4dd1831fbe7495a"},
+    ("spv_n100k", "force_update", 1): {"bytes_per_launch": 17.324e6, "source_sha256":
+                                       "a382cd4b05eb0d17b4c7e5b523e9e01f630b53fbc037442ef4dd1831fbe7495a"},
     ("spv_n100k", "geometry_test", 1): {"bytes_per_launch": 15.310e6, "source_sha256":
-                                        "7b183ec57a21d088bee681a42088f87dc1e189278ee75338b48126cff6ebc42c"},
+                                        "a382cd4b05eb0d17b4c7e5b523e9e01f630b53fbc037442ef4dd1831fbe7495a"},
 }
 
 

@@ -1021,14 +1021,18 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
     // G lanes per candidate split the loop over the other candidates (three
     // for 17 to 21 candidates: 51 to 63 lanes busy instead of 34 to 42)
     const int G = n <= 16 ? 4 : (n <= 21 ? 3 : (n <= 32 ? 2 : 1));
-    const int per_pass = 64 / G;
-    const bool act = lane < per_pass * G;  // lane 63 idles when G = 3
+    const int per_pass = G == 3 ? 21 : 64 / G;
+    // lane / G and lane % G without a division (lane * 21846 >> 16 is
+    // lane / 3 for lane < 64)
+    const int gl = G == 3 ? (lane * 21846) >> 16 : lane >> (G == 4 ? 2 : G == 2 ? 1 : 0);
+    const int r = lane - gl * G;
     int unsure = 0, k = 0;
     for (int base = 0; base < n; base += per_pass) {
-        const int pi = base + lane / G, r = lane % G;
+        // (lane 63 idles when G = 3: its candidate index is past the end)
+        const int pi = gl < per_pass ? base + gl : n;
         bool mem = false, blocked = false;
         double ulo = INFINITY, uhi = INFINITY, llo = -INFINITY, lhi = -INFINITY;
-        if (act && pi < n) {
+        if (pi < n) {
             const double px = sx[pi], py = sy[pi];
 #pragma unroll 4
             for (int q = r; q < n; q += G) {
@@ -1070,21 +1074,14 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
         }
         // combine the G lanes of each candidate (aligned groups)
         if (G == 3) {
-            const int g0 = lane - r;  // the group's lanes g0 .. g0 + 2
-            double a = ulo, b = uhi, c = llo, d = lhi;
-            int bl = blocked ? 1 : 0;
-            for (int j = 0; j < 3; j++) {
-                a = fmin(a, __shfl(ulo, g0 + j));
-                b = fmin(b, __shfl(uhi, g0 + j));
-                c = fmax(c, __shfl(llo, g0 + j));
-                d = fmax(d, __shfl(lhi, g0 + j));
-                bl |= __shfl(blocked ? 1 : 0, g0 + j);
-            }
-            ulo = a;
-            uhi = b;
-            llo = c;
-            lhi = d;
-            blocked = bl != 0;
+            // only the group's first lane (r = 0) uses the result: it reads
+            // lanes + 1 and + 2, the rest of its group
+            ulo = fmin(ulo, fmin(__shfl_down(ulo, 1), __shfl_down(ulo, 2)));
+            uhi = fmin(uhi, fmin(__shfl_down(uhi, 1), __shfl_down(uhi, 2)));
+            llo = fmax(llo, fmax(__shfl_down(llo, 1), __shfl_down(llo, 2)));
+            lhi = fmax(lhi, fmax(__shfl_down(lhi, 1), __shfl_down(lhi, 2)));
+            const int bl = blocked ? 1 : 0;
+            blocked = (bl | __shfl_down(bl, 1) | __shfl_down(bl, 2)) != 0;
         } else {
             for (int off = 1; off < G; off <<= 1) {
                 ulo = fmin(ulo, __shfl_xor(ulo, off));
@@ -1094,7 +1091,7 @@ __device__ int star_parallel(const double* __restrict__ sx, const double* __rest
                 blocked = __shfl_xor((int)blocked, off) != 0 || blocked;
             }
         }
-        if (act && pi < n && r == 0 && !blocked) {
+        if (pi < n && r == 0 && !blocked) {
             if (ulo > lhi) mem = true;           // certainly a non-empty interval
             else if (!(llo > uhi)) unsure = 1;  // and not certainly empty either
         }
