@@ -580,3 +580,36 @@ def test_corrupted_ring_is_detected_and_repaired(spv, repair_mode):
     o3, r3 = s.neighbors()
     assert np.array_equal(o3, o2) and np.array_equal(r3, r2)
     s.close()
+
+
+def test_corrupted_ring_in_a_batch(spv):
+    """The fault-injection hook on a batch: a ring of the third system (a
+    global index) with one neighbour dropped is rebuilt by the next step;
+    every system's rings equal the oracle's triangulation of its positions,
+    and a ring naming a cell of another system is rejected."""
+    S = 4
+    N_s, L_s, xs, ys, p0_s, v0_s, seed_s = _batch_inputs(S, 64)
+    b = spv.System.batch(N_s, L_s, np.concatenate(xs), np.concatenate(ys), p0_s, v0_s=v0_s, seed_s=seed_s,
+                         params=spv.Params(Dr=1.0, dt=0.01, resort_every=8))
+    b.step(40)
+    off, ring = b.neighbors()
+    first, n2 = b.system_range(2)
+    t = first + int(np.argmax(np.diff(off)[first:first + n2]))
+    r = list(ring[off[t]:off[t + 1]])
+    assert len(r) >= 5
+    b.debug_set_ring(t, r[:1] + r[2:])
+    other = b.system_range(1)[0]
+    with pytest.raises(spv.SPVError) as ei:
+        b.debug_set_ring(t, [other] + r[1:])
+    assert ei.value.status == spv.SPV_EINVAL
+    b.step(1)
+    gx, gy = b.positions()
+    off, ring = b.neighbors()
+    for k in range(S):
+        f, nk = b.system_range(k)
+        Lx, Ly, q = b.system_box(k)
+        o, rr, _, _ = oracle.triangulate(gx[f:f + nk], gy[f:f + nk], Lx, Ly, q)
+        go = off[f:f + nk + 1] - off[f]
+        assert np.array_equal(go, o)
+        assert np.array_equal(ring[off[f]:off[f + nk]] - f, rr)
+    b.close()
