@@ -240,6 +240,12 @@ def test_invalid_inputs(spv):
     with pytest.raises(spv.SPVError) as ei:
         spv.System(x3, y3, Lx, Ly)
     assert ei.value.status == spv.SPV_EINVAL
+    for bad in (float("nan"), float("inf"), -0.5):
+        x4 = x.copy()
+        x4[7] = bad
+        with pytest.raises(spv.SPVError) as ei:
+            spv.System(x4, y, Lx, Ly)
+        assert ei.value.status == spv.SPV_EINVAL
 
 
 def test_device_pointer_inputs_and_outputs(spv):
